@@ -1,0 +1,165 @@
+"""CPU oracle for triangle listing under a vertex ordering -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product path (the HIP library and its binding)
+never does.  The C source, ``oracle.c``, is a plain single-threaded
+statement of Algorithms 1 (A++) and 2 (A+-) of Lecuyer et al., "Tailored
+vertex ordering for faster triangle listing in large graphs", with the
+boolean array B of the paper, a work counter, and Definition 1's costs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+APP, APM, AMM = 0, 1, 2
+ALGOS = {"A++": APP, "A+-": APM, "A--": AMM}
+
+u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+
+
+def build() -> str:
+    """Compile oracle.c (plain -O2, no vectorisation flags, single thread)."""
+    tmp = _SO + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp,
+                           os.path.join(_HERE, "oracle.c")])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    u64, u32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+    lib.orc_list.restype = ctypes.c_int
+    lib.orc_list.argtypes = [u32, u64, u32p, u32p, u32p, ctypes.c_int, u32, u32, vp, u64, u64p]
+    lib.orc_cost.restype = ctypes.c_int
+    lib.orc_cost.argtypes = [u32, u64, u32p, u32p, u32p, u64p]
+    lib.orc_oriented_csr.restype = ctypes.c_int
+    lib.orc_oriented_csr.argtypes = [u32, u64, u32p, u32p, u32p, u64p, u32p, u64p, u32p, u32p]
+    lib.orc_triangle_hash.restype = u64
+    lib.orc_triangle_hash.argtypes = [u32, u32, u32]
+    lib.orc_mix64.restype = u64
+    lib.orc_mix64.argtypes = [u64]
+    _lib = lib
+    return lib
+
+
+class OracleError(ValueError):
+    pass
+
+
+def _check(rc):
+    if rc == -1:
+        raise OracleError("invalid input (vertex id >= n or rank not a permutation)")
+    if rc == -2:
+        raise MemoryError("oracle: out of host memory")
+
+
+@dataclass
+class Listing:
+    count: int
+    hash: int
+    work: int
+    m: int
+    triangles: np.ndarray | None  # (count, 3) uint32, canonical, discovery order
+
+    def sorted_triangles(self) -> np.ndarray:
+        t = self.triangles
+        if t is None or len(t) == 0:
+            return np.zeros((0, 3), np.uint32)
+        order = np.lexsort((t[:, 2], t[:, 1], t[:, 0]))
+        return t[order]
+
+
+def _arrs(src, dst, rank):
+    return (np.ascontiguousarray(src, np.uint32), np.ascontiguousarray(dst, np.uint32),
+            np.ascontiguousarray(rank, np.uint32))
+
+
+def list_triangles(n, src, dst, rank, algo="A++", pivot_lo=0, pivot_hi=None,
+                   want_triangles=True, cap=None) -> Listing:
+    """Run Algorithm 1 (A++), 2 (A+-) or the S2 variant (A--) over pivots
+    with rank in [pivot_lo, pivot_hi)."""
+    lib = _load()
+    s, d, r = _arrs(src, dst, rank)
+    if pivot_hi is None:
+        pivot_hi = n
+    out = np.zeros(4, np.uint64)
+    tri = None
+    if want_triangles:
+        if cap is None:
+            # first pass for the size, then list
+            _check(lib.orc_list(n, len(s), s, d, r, ALGOS[algo], pivot_lo, pivot_hi, None, 0, out))
+            cap = int(out[0])
+        tri = np.zeros((max(cap, 1), 3), np.uint32)
+        _check(lib.orc_list(n, len(s), s, d, r, ALGOS[algo], pivot_lo, pivot_hi,
+                            tri.ctypes.data, cap, out))
+        tri = tri[:min(cap, int(out[0]))]
+    else:
+        _check(lib.orc_list(n, len(s), s, d, r, ALGOS[algo], pivot_lo, pivot_hi, None, 0, out))
+    return Listing(int(out[0]), int(out[1]), int(out[2]), int(out[3]), tri)
+
+
+@dataclass
+class Cost:
+    cpp: int   # C++ = sum d+ d+
+    cpm: int   # C+- = sum d+ d-
+    cmm: int   # sum d- d-
+    m: int
+    sum_dplus: int
+    sum_dminus: int
+
+    def for_algo(self, algo: str) -> int:
+        return {"A++": self.cpp, "A+-": self.cpm, "A--": self.cmm}[algo]
+
+
+def cost(n, src, dst, rank) -> Cost:
+    lib = _load()
+    s, d, r = _arrs(src, dst, rank)
+    out = np.zeros(6, np.uint64)
+    _check(lib.orc_cost(n, len(s), s, d, r, out))
+    return Cost(*[int(x) for x in out])
+
+
+def oriented_csr(n, src, dst, rank):
+    """(fwd_off, fwd_adj, bwd_off, bwd_adj, inv) in rank space."""
+    lib = _load()
+    s, d, r = _arrs(src, dst, rank)
+    c = cost(n, s, d, r)
+    fo = np.zeros(n + 1, np.uint64)
+    bo = np.zeros(n + 1, np.uint64)
+    fa = np.zeros(max(c.m, 1), np.uint32)
+    ba = np.zeros(max(c.m, 1), np.uint32)
+    inv = np.zeros(max(n, 1), np.uint32)
+    _check(lib.orc_oriented_csr(n, len(s), s, d, r, fo, fa, bo, ba, inv))
+    return fo, fa[:c.m], bo, ba[:c.m], inv[:n]
+
+
+def triangle_hash(a: int, b: int, c: int) -> int:
+    return int(_load().orc_triangle_hash(a, b, c))
+
+
+def mix64(z: int) -> int:
+    return int(_load().orc_mix64(z))
+
+
+def hash_of(triangles) -> int:
+    """Wrapping 64-bit sum of the per-triangle digest (canonical input)."""
+    h = 0
+    for a, b, c in np.asarray(triangles).reshape(-1, 3):
+        h = (h + triangle_hash(int(a), int(b), int(c))) & 0xFFFFFFFFFFFFFFFF
+    return h

@@ -1,0 +1,329 @@
+/*
+ * CPU ORACLE -- test infrastructure only.
+ *
+ * A plain, single-threaded, deliberately unoptimised statement of what the
+ * GPU triangle-listing path computes.  Only the test-suite, the smoke check
+ * and the benchmark's CPU-baseline leg may load it; the product path never
+ * does.  It shares no code, header or table with the GPU library.
+ *
+ * Paper: Lecuyer, Jachiet, Magnien, Tabourier, "Tailored vertex ordering for
+ * faster triangle listing in large graphs" (arXiv 2203.04774).
+ *
+ *   graph model        Section 1.3 (Notations): simple undirected G=(V,E),
+ *                      ordering pi, DAG G_pi with (u,v) in E_pi iff
+ *                      pi_u < pi_v, successors N+ and predecessors N-.
+ *                      Input loops and duplicate pairs are dropped, as the
+ *                      experimental setup does with its datasets (Sec. 4.1.1).
+ *   A++                Algorithm 1: for each vertex w, mark N-_w in a boolean
+ *                      array B; for each u in N-_w scan all of N+_u and report
+ *                      {u,v,w} for every v with B[v]; unmark.
+ *   A+-                Algorithm 2: for each vertex u, mark N+_u; for each v
+ *                      in N+_u scan all of N+_v and report {u,v,w} for every
+ *                      marked w; unmark.
+ *   cost               Definition 1: C++ = sum_u d+_u d+_u,
+ *                      C+- = sum_u d+_u d-_u.
+ *   work               one unit per element scanned in the innermost loop of
+ *                      Algorithms 1/2; by Property 1 it sums to C++ (A++) or
+ *                      C+- (A+-), which the tests check.
+ *
+ * Output convention (not fixed by the paper): a triangle is reported as its
+ * three original vertex ids sorted ascending, a < b < c.  The 64-bit
+ * order-independent digest is the wrapping sum over triangles of
+ *   h(a,b,c) = f(f((a << 32) | b) + c),
+ * f = the splitmix64 output function (Steele, Lea, Flood, OOPSLA 2014).
+ * Parity of the digest is unpinned by the paper; the tests pin f against
+ * splitmix64's published output sequence and the sum against hashing the
+ * brute-force triangle set.
+ *
+ * Restricting the outer loop to pivots whose rank lies in [lo, hi) lists
+ * exactly the triangles whose pivot (w for A++, u for A+-, v for A--) has
+ * such a rank;
+ * the outer iterations are independent (Section 4.1.2), so ranges partition
+ * the output.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+enum { ORC_APP = 0, ORC_APM = 1, ORC_AMM = 2 };
+
+static u64 orc_f(u64 z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+u64 orc_mix64(u64 z) { return orc_f(z); }
+
+u64 orc_triangle_hash(u32 a, u32 b, u32 c) {
+    return orc_f(orc_f(((u64)a << 32) | (u64)b) + (u64)c);
+}
+
+/* ------------------------------------------------------------ the graph */
+
+/* Undirected simple graph as adjacency lists in original ids, plus the
+ * oriented lists N+ and N- under a given rank. */
+typedef struct {
+    u32 n;
+    u64 m;         /* undirected edges after dropping loops and duplicates */
+    u64 *off;      /* n+1, into adj */
+    u32 *adj;      /* 2m neighbour ids, each list sorted by id, no repeats */
+    const u32 *rank;
+    u64 *poff, *moff;  /* n+1 each */
+    u32 *plus, *minus; /* N+_u and N-_u, in id order */
+} graph;
+
+static int cmp_u32(const void *a, const void *b) {
+    u32 x = *(const u32 *)a, y = *(const u32 *)b;
+    return (x > y) - (x < y);
+}
+
+static void graph_free(graph *g) {
+    free(g->off); free(g->adj); free(g->poff); free(g->moff); free(g->plus); free(g->minus);
+    memset(g, 0, sizeof *g);
+}
+
+/* Returns 0 on success, -1 on bad input (id >= n, rank not a permutation),
+ * -2 on allocation failure. */
+static int graph_build(graph *g, u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank) {
+    memset(g, 0, sizeof *g);
+    g->n = n;
+    g->rank = rank;
+    /* rank must be a permutation of [0, n) */
+    unsigned char *seen = (unsigned char *)calloc((size_t)n + 1, 1);
+    if (!seen) return -2;
+    for (u32 u = 0; u < n; u++) {
+        if (rank[u] >= n || seen[rank[u]]) { free(seen); return -1; }
+        seen[rank[u]] = 1;
+    }
+    free(seen);
+    for (u64 i = 0; i < m_in; i++)
+        if (src[i] >= n || dst[i] >= n) return -1;
+
+    /* symmetric adjacency with loops removed */
+    u64 *cnt = (u64 *)calloc((size_t)n + 1, sizeof(u64));
+    if (!cnt) return -2;
+    for (u64 i = 0; i < m_in; i++) {
+        if (src[i] == dst[i]) continue;
+        cnt[src[i]]++;
+        cnt[dst[i]]++;
+    }
+    u64 *raw_off = (u64 *)calloc((size_t)n + 1, sizeof(u64));
+    for (u32 u = 0; u < n; u++) raw_off[u + 1] = raw_off[u] + cnt[u];
+    u32 *raw = (u32 *)malloc(raw_off[n] * sizeof(u32) + 4);
+    if (!raw_off || !raw) { free(cnt); free(raw_off); free(raw); return -2; }
+    memset(cnt, 0, ((size_t)n + 1) * sizeof(u64));
+    for (u64 i = 0; i < m_in; i++) {
+        u32 a = src[i], b = dst[i];
+        if (a == b) continue;
+        raw[raw_off[a] + cnt[a]++] = b;
+        raw[raw_off[b] + cnt[b]++] = a;
+    }
+    /* sort each list and drop repeated neighbours (duplicate edges) */
+    g->off = (u64 *)calloc((size_t)n + 1, sizeof(u64));
+    u64 w = 0;
+    for (u32 u = 0; u < n; u++) {
+        u32 *row = raw + raw_off[u];
+        u64 len = raw_off[u + 1] - raw_off[u];
+        qsort(row, len, sizeof(u32), cmp_u32);
+        g->off[u] = w;
+        for (u64 j = 0; j < len; j++)
+            if (j == 0 || row[j] != row[j - 1]) raw[w++] = row[j];
+    }
+    g->off[n] = w;
+    g->adj = raw; /* compacted in place */
+    g->m = w / 2;
+    free(raw_off);
+    free(cnt);
+
+    /* orientation by rank: N+_u = {v : pi_v > pi_u}, N-_u = {v : pi_v < pi_u} */
+    g->poff = (u64 *)calloc((size_t)n + 1, sizeof(u64));
+    g->moff = (u64 *)calloc((size_t)n + 1, sizeof(u64));
+    g->plus = (u32 *)malloc(g->m * sizeof(u32) + 4);
+    g->minus = (u32 *)malloc(g->m * sizeof(u32) + 4);
+    if (!g->off || !g->poff || !g->moff || !g->plus || !g->minus) { graph_free(g); return -2; }
+    u64 pw = 0, mw = 0;
+    for (u32 u = 0; u < n; u++) {
+        g->poff[u] = pw;
+        g->moff[u] = mw;
+        for (u64 j = g->off[u]; j < g->off[u + 1]; j++) {
+            u32 v = g->adj[j];
+            if (rank[v] > rank[u]) g->plus[pw++] = v;
+            else g->minus[mw++] = v;
+        }
+    }
+    g->poff[n] = pw;
+    g->moff[n] = mw;
+    return 0;
+}
+
+#define DPLUS(g, u) ((g)->poff[(u) + 1] - (g)->poff[(u)])
+#define DMINUS(g, u) ((g)->moff[(u) + 1] - (g)->moff[(u)])
+
+/* ------------------------------------------------------------ reporting */
+
+typedef struct {
+    u64 count, hash, work;
+    u32 *tri;      /* optional: 3*cap slots */
+    u64 cap;
+} sink;
+
+static void report(sink *s, u32 x, u32 y, u32 z) {
+    /* canonical form: ids sorted ascending */
+    u32 t;
+    if (x > y) { t = x; x = y; y = t; }
+    if (y > z) { t = y; y = z; z = t; }
+    if (x > y) { t = x; x = y; y = t; }
+    if (s->tri && s->count < s->cap) {
+        s->tri[3 * s->count + 0] = x;
+        s->tri[3 * s->count + 1] = y;
+        s->tri[3 * s->count + 2] = z;
+    }
+    s->count++;
+    s->hash += orc_triangle_hash(x, y, z);
+}
+
+/* ------------------------------------------------------------ Algorithm 1 */
+
+static void list_app(const graph *g, u32 lo, u32 hi, unsigned char *B, sink *s) {
+    for (u32 w = 0; w < g->n; w++) {
+        if (g->rank[w] < lo || g->rank[w] >= hi) continue;
+        for (u64 j = g->moff[w]; j < g->moff[w + 1]; j++) B[g->minus[j]] = 1;
+        for (u64 j = g->moff[w]; j < g->moff[w + 1]; j++) {
+            u32 u = g->minus[j];
+            for (u64 k = g->poff[u]; k < g->poff[u + 1]; k++) {
+                u32 v = g->plus[k];
+                s->work++;
+                if (B[v]) report(s, u, v, w);
+            }
+        }
+        for (u64 j = g->moff[w]; j < g->moff[w + 1]; j++) B[g->minus[j]] = 0;
+    }
+}
+
+/* ------------------------------------------------------------ Algorithm 2 */
+
+static void list_apm(const graph *g, u32 lo, u32 hi, unsigned char *B, sink *s) {
+    for (u32 u = 0; u < g->n; u++) {
+        if (g->rank[u] < lo || g->rank[u] >= hi) continue;
+        for (u64 j = g->poff[u]; j < g->poff[u + 1]; j++) B[g->plus[j]] = 1;
+        for (u64 j = g->poff[u]; j < g->poff[u + 1]; j++) {
+            u32 v = g->plus[j];
+            for (u64 k = g->poff[v]; k < g->poff[v + 1]; k++) {
+                u32 w = g->plus[k];
+                s->work++;
+                if (B[w]) report(s, u, v, w);
+            }
+        }
+        for (u64 j = g->poff[u]; j < g->poff[u + 1]; j++) B[g->plus[j]] = 0;
+    }
+}
+
+/* ---------------------------------------------------- A-- (S2 seed edge)
+ * The third variant named in the footnote to Algorithms 1/2, whose seed edge
+ * is the second short edge S2 = (v,w) of Figure 1.  Reading taken here: the
+ * pivot is the middle vertex v; mark N-_v; for each successor w of v (seed
+ * edge S2) scan all of N-_w and report {u,v,w} for every marked u.  Each w is
+ * scanned once per predecessor, d-_w long, so the work is sum_w d-_w d-_w:
+ * the C++ of the reversed ordering, which is the footnote's "equivalent to
+ * A++". */
+static void list_amm(const graph *g, u32 lo, u32 hi, unsigned char *B, sink *s) {
+    for (u32 v = 0; v < g->n; v++) {
+        if (g->rank[v] < lo || g->rank[v] >= hi) continue;
+        for (u64 j = g->moff[v]; j < g->moff[v + 1]; j++) B[g->minus[j]] = 1;
+        for (u64 j = g->poff[v]; j < g->poff[v + 1]; j++) {
+            u32 w = g->plus[j];
+            for (u64 k = g->moff[w]; k < g->moff[w + 1]; k++) {
+                u32 u = g->minus[k];
+                s->work++;
+                if (B[u]) report(s, u, v, w);
+            }
+        }
+        for (u64 j = g->moff[v]; j < g->moff[v + 1]; j++) B[g->minus[j]] = 0;
+    }
+}
+
+/* ================================================================ ABI */
+
+/*
+ * Lists the triangles of the simple graph underlying (src, dst) under the
+ * ordering `rank`, with Algorithm 1 (algo 0), Algorithm 2 (algo 1) or the
+ * S2 variant (algo 2), restricted to pivots with rank in [lo, hi).
+ * out[0..2] = count, hash, work; out[3] = m after simplification.
+ * If tri != NULL, the first min(count, cap) canonical triangles are written
+ * there (3 ids each) in discovery order.
+ * Returns 0, -1 (invalid input) or -2 (out of memory).
+ */
+int orc_list(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank, int algo,
+             u32 lo, u32 hi, u32 *tri, u64 cap, u64 *out) {
+    graph g;
+    int rc = graph_build(&g, n, m_in, src, dst, rank);
+    if (rc) return rc;
+    unsigned char *B = (unsigned char *)calloc((size_t)n + 1, 1);
+    if (!B) { graph_free(&g); return -2; }
+    sink s = {0, 0, 0, tri, cap};
+    if (algo == ORC_APP) list_app(&g, lo, hi, B, &s);
+    else if (algo == ORC_APM) list_apm(&g, lo, hi, B, &s);
+    else if (algo == ORC_AMM) list_amm(&g, lo, hi, B, &s);
+    else { free(B); graph_free(&g); return -1; }
+    out[0] = s.count;
+    out[1] = s.hash;
+    out[2] = s.work;
+    out[3] = g.m;
+    free(B);
+    graph_free(&g);
+    return 0;
+}
+
+/*
+ * Definition 1 costs.  out[0] = C++ = sum d+ d+, out[1] = C+- = sum d+ d-,
+ * out[2] = sum d- d-, out[3] = m, out[4] = sum d+, out[5] = sum d-.
+ */
+int orc_cost(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank, u64 *out) {
+    graph g;
+    int rc = graph_build(&g, n, m_in, src, dst, rank);
+    if (rc) return rc;
+    u64 cpp = 0, cpm = 0, cmm = 0, sp = 0, sm = 0;
+    for (u32 u = 0; u < n; u++) {
+        u64 dp = DPLUS(&g, u), dm = DMINUS(&g, u);
+        cpp += dp * dp;
+        cpm += dp * dm;
+        cmm += dm * dm;
+        sp += dp;
+        sm += dm;
+    }
+    out[0] = cpp; out[1] = cpm; out[2] = cmm; out[3] = g.m; out[4] = sp; out[5] = sm;
+    graph_free(&g);
+    return 0;
+}
+
+/*
+ * The oriented graph in rank space, for comparing CSR arrays: row r holds
+ * the ranks of the successors of the vertex of rank r, ascending.
+ * fwd_off has n+1 entries, fwd_adj m entries (caller sizes it with m from
+ * orc_cost); bwd_* likewise hold the predecessors.  inv[r] = vertex of rank r.
+ */
+int orc_oriented_csr(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank,
+                     u64 *fwd_off, u32 *fwd_adj, u64 *bwd_off, u32 *bwd_adj, u32 *inv) {
+    graph g;
+    int rc = graph_build(&g, n, m_in, src, dst, rank);
+    if (rc) return rc;
+    for (u32 u = 0; u < n; u++) inv[rank[u]] = u;
+    u64 pw = 0, mw = 0;
+    for (u32 r = 0; r < n; r++) {
+        u32 u = inv[r];
+        fwd_off[r] = pw;
+        for (u64 j = g.poff[u]; j < g.poff[u + 1]; j++) fwd_adj[pw++] = rank[g.plus[j]];
+        qsort(fwd_adj + fwd_off[r], pw - fwd_off[r], sizeof(u32), cmp_u32);
+        bwd_off[r] = mw;
+        for (u64 j = g.moff[u]; j < g.moff[u + 1]; j++) bwd_adj[mw++] = rank[g.minus[j]];
+        qsort(bwd_adj + bwd_off[r], mw - bwd_off[r], sizeof(u32), cmp_u32);
+    }
+    fwd_off[n] = pw;
+    bwd_off[n] = mw;
+    graph_free(&g);
+    return 0;
+}

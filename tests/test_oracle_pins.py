@@ -1,0 +1,255 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each check is independent of the oracle's own code: brute-force enumeration,
+trace(A^3)/6, closed forms, the printed values of the Figure 2 example and
+the Split example (Section 3.3.3), the costs stated for the gadget graphs of
+Appendices A and B, the linear-cost property of Appendix B, and splitmix64's
+published output sequence for the digest's mixing function.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import graphs as G
+import oracle
+
+ALGOS = ["A++", "A+-", "A--"]
+MASK = (1 << 64) - 1
+
+
+def rand_graph(seed, n=None, p=None):
+    rs = np.random.default_rng(seed)
+    n = n if n is not None else int(rs.integers(3, 45))
+    p = p if p is not None else float(rs.uniform(0.05, 0.6))
+    return G.erdos_renyi(n, p, seed)
+
+
+def rand_rank(n, seed):
+    rs = np.random.default_rng(seed + 99991)
+    return rs.permutation(n).astype(np.uint32)
+
+
+# ---------------------------------------------------------------- digest
+
+def test_mix64_matches_published_splitmix64_sequence():
+    # splitmix64 from state 0 outputs f(k * 0x9e3779b97f4a7c15), k = 1, 2, 3;
+    # these three values are the generator's published first outputs.
+    golden = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for k, want in enumerate(golden, start=1):
+        assert oracle.mix64((k * 0x9E3779B97F4A7C15) & MASK) == want
+
+
+def test_digest_is_sum_over_bruteforce_set():
+    n, s, d = rand_graph(7, n=30, p=0.4)
+    bf = G.brute_force_triangles(n, s, d)
+    res = oracle.list_triangles(n, s, d, rand_rank(n, 7), "A+-")
+    assert res.hash == oracle.hash_of(bf)
+    # a duplicated triangle changes the digest (add, not xor, combination)
+    dup = np.vstack([bf, bf[:1]])
+    assert oracle.hash_of(dup) != res.hash
+
+
+# ------------------------------------------------------ triangle set pins
+
+@pytest.mark.parametrize("seed", range(25))
+@pytest.mark.parametrize("algo", ALGOS)
+def test_matches_brute_force(seed, algo):
+    n, s, d = rand_graph(seed)
+    bf = G.brute_force_triangles(n, s, d)
+    res = oracle.list_triangles(n, s, d, rand_rank(n, seed), algo)
+    assert res.count == len(bf)
+    assert np.array_equal(res.sorted_triangles(), bf)
+    # every listed triple is canonical and unique
+    t = res.triangles
+    assert np.all(t[:, 0] < t[:, 1]) and np.all(t[:, 1] < t[:, 2])
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_count_matches_trace_a3(seed):
+    n, s, d = rand_graph(100 + seed, n=60)
+    assert oracle.list_triangles(n, s, d, rand_rank(n, seed), "A++",
+                                 want_triangles=False).count == G.trace_count(n, s, d)
+
+
+@pytest.mark.parametrize("nv", range(3, 10))
+def test_complete_graph_closed_forms(nv):
+    n, s, d = G.complete(nv)
+    for seed in range(3):
+        r = rand_rank(n, seed)
+        for algo in ALGOS:
+            assert oracle.list_triangles(n, s, d, r, algo).count == math.comb(nv, 3)
+        c = oracle.cost(n, s, d, r)
+        # every order gives out-degrees 0..n-1 once each
+        assert c.cpp == (nv - 1) * nv * (2 * nv - 1) // 6
+        assert c.cpm == math.comb(nv, 3)
+
+
+@pytest.mark.parametrize("nv", range(4, 14))
+def test_wheel(nv):
+    n, s, d = G.wheel(nv)
+    want = 4 if nv == 4 else nv - 1   # W_4 is K_4
+    for algo in ALGOS:
+        assert oracle.list_triangles(n, s, d, rand_rank(n, nv), algo).count == want
+
+
+@pytest.mark.parametrize("builder", [lambda: G.grid(7, 9), lambda: G.complete_bipartite(6, 8),
+                                     lambda: G.random_bipartite(15, 20, 0.4, 3),
+                                     lambda: G.cycle(10), lambda: G.star(12)])
+def test_triangle_free(builder):
+    n, s, d = builder()
+    for algo in ALGOS:
+        res = oracle.list_triangles(n, s, d, rand_rank(n, 1), algo)
+        assert res.count == 0 and res.hash == 0
+
+
+def test_fig2_triangles_and_printed_costs():
+    n, s, d, orders, names = G.fig2()
+    bf = G.brute_force_triangles(n, s, d)
+    as_names = sorted("".join(names[i] for i in t) for t in bf.tolist())
+    assert as_names == ["abe", "ade", "bcg"]
+    for order, cpm in orders:
+        r = G.order_to_rank(order)
+        assert oracle.cost(n, s, d, r).cpm == cpm
+        for algo in ALGOS:
+            assert np.array_equal(oracle.list_triangles(n, s, d, r, algo).sorted_triangles(), bf)
+
+
+@pytest.mark.parametrize("dd,want", G.ld_golden())
+def test_ld_gadget_cost(dd, want):
+    n, s, d, order = G.ld_gadget(dd)
+    r = G.order_to_rank(order)
+    c = oracle.cost(n, s, d, r)
+    assert c.cpp == want
+    # triangles of L_d: inside the clique K (d+1 vertices) and each v_i with
+    # any two clique vertices
+    res = oracle.list_triangles(n, s, d, r, "A++")
+    assert res.count == math.comb(dd + 1, 3) + dd * math.comb(dd + 1, 2)
+    assert res.count == len(G.brute_force_triangles(n, s, d))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_gphi_gadget(seed):
+    n, s, d, order = G.gphi_gadget(n_vars=6 + seed, n_clauses=4 + 2 * seed, seed=seed)
+    m_clauses = 4 + 2 * seed
+    r = G.order_to_rank(order)
+    assert oracle.cost(n, s, d, r).cpm == 2 * m_clauses
+    for k in range(20):
+        assert oracle.cost(n, s, d, rand_rank(n, 1000 * seed + k)).cpm >= 2 * m_clauses
+    assert oracle.list_triangles(n, s, d, r, "A+-").count == m_clauses
+
+
+# ------------------------------------------------------- cost and work
+
+@pytest.mark.parametrize("seed", range(15))
+def test_work_equals_cost(seed):
+    n, s, d = rand_graph(200 + seed)
+    r = rand_rank(n, seed)
+    c = oracle.cost(n, s, d, r)
+    for algo in ALGOS:
+        assert oracle.list_triangles(n, s, d, r, algo, want_triangles=False).work == c.for_algo(algo)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_linear_cost_invariant(seed):
+    # Appendix B property: the successor counts sum to |E| for every order
+    n, s, d = rand_graph(300 + seed)
+    m = len({(min(a, b), max(a, b)) for a, b in zip(s.tolist(), d.tolist()) if a != b})
+    for k in range(5):
+        c = oracle.cost(n, s, d, rand_rank(n, k))
+        assert c.sum_dplus == m and c.sum_dminus == m and c.m == m
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_reversal_identities(seed):
+    n, s, d = rand_graph(400 + seed)
+    r = rand_rank(n, seed)
+    rev = (n - 1 - r.astype(np.int64)).astype(np.uint32)
+    c, cr = oracle.cost(n, s, d, r), oracle.cost(n, s, d, rev)
+    assert cr.cpm == c.cpm
+    assert cr.cpp == c.cmm and cr.cmm == c.cpp
+
+
+# ---------------------------------------------------------- invariance
+
+@pytest.mark.parametrize("seed", range(5))
+def test_invariance_over_orders_and_algorithms(seed):
+    n, s, d = rand_graph(500 + seed, n=40, p=0.3)
+    ref = oracle.list_triangles(n, s, d, np.arange(n, dtype=np.uint32), "A++")
+    for k in range(20):
+        r = rand_rank(n, 37 * seed + k)
+        for algo in ALGOS:
+            res = oracle.list_triangles(n, s, d, r, algo)
+            assert (res.count, res.hash) == (ref.count, ref.hash)
+            assert np.array_equal(res.sorted_triangles(), ref.sorted_triangles())
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_pivot_ranges_partition(algo):
+    n, s, d = rand_graph(77, n=40, p=0.35)
+    r = rand_rank(n, 5)
+    full = oracle.list_triangles(n, s, d, r, algo)
+    cuts = [0, 3, 11, 12, 25, n]
+    cnt = hsh = wrk = 0
+    parts = []
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        p = oracle.list_triangles(n, s, d, r, algo, lo, hi)
+        cnt += p.count
+        hsh = (hsh + p.hash) & MASK
+        wrk += p.work
+        parts.append(p.triangles)
+    assert (cnt, hsh, wrk) == (full.count, full.hash, full.work)
+    allp = np.vstack(parts)
+    assert np.array_equal(allp[np.lexsort((allp[:, 2], allp[:, 1], allp[:, 0]))],
+                          full.sorted_triangles())
+
+
+# ------------------------------------------------------------- inputs
+
+def test_loops_and_duplicates_dropped():
+    n, s, d = G.complete(6)
+    s2 = np.concatenate([s, d, np.arange(6, dtype=np.uint32), s[:4]])
+    d2 = np.concatenate([d, s, np.arange(6, dtype=np.uint32), d[:4]])
+    r = rand_rank(n, 3)
+    a = oracle.list_triangles(n, s, d, r, "A+-")
+    b = oracle.list_triangles(n, s2, d2, r, "A+-")
+    assert (a.count, a.hash, a.m) == (b.count, b.hash, b.m) == (20, a.hash, 15)
+
+
+def test_invalid_inputs_rejected():
+    n, s, d = G.complete(5)
+    with pytest.raises(oracle.OracleError):
+        oracle.list_triangles(n, s, d, np.array([0, 1, 1, 2, 3], np.uint32))
+    with pytest.raises(oracle.OracleError):
+        oracle.list_triangles(n, s, d, np.array([0, 1, 2, 3, 5], np.uint32))
+    bad = s.copy()
+    bad[0] = 9
+    with pytest.raises(oracle.OracleError):
+        oracle.list_triangles(n, bad, d, np.arange(5, dtype=np.uint32))
+
+
+def test_empty_and_tiny_graphs():
+    for nv in range(0, 4):
+        n, s, d = G.complete(nv)
+        r = np.arange(nv, dtype=np.uint32)
+        res = oracle.list_triangles(n, s, d, r, "A++")
+        assert res.count == (1 if nv == 3 else 0)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_oriented_csr_rows(seed):
+    n, s, d = rand_graph(600 + seed)
+    r = rand_rank(n, seed)
+    fo, fa, bo, ba, inv = oracle.oriented_csr(n, s, d, r)
+    _, pairs = G.simple_degrees(n, s, d)
+    want_f = [[] for _ in range(n)]
+    want_b = [[] for _ in range(n)]
+    for a, b in pairs:
+        lo, hi = sorted((int(r[a]), int(r[b])))
+        want_f[lo].append(hi)
+        want_b[hi].append(lo)
+    for x in range(n):
+        assert fa[fo[x]:fo[x + 1]].tolist() == sorted(want_f[x])
+        assert ba[bo[x]:bo[x + 1]].tolist() == sorted(want_b[x])
+        assert r[inv[x]] == x

@@ -1,0 +1,172 @@
+/*
+ * tl.h -- triangle listing under a given vertex ordering, on one AMD
+ * Instinct MI355X (gfx950) GPU.
+ *
+ * Method: Lecuyer, Jachiet, Magnien, Tabourier, "Tailored vertex ordering
+ * for faster triangle listing in large graphs" (arXiv 2203.04774).
+ *
+ * Problem statement (Section 1.3 and Section 2.1): given a simple undirected
+ * graph G = (V, E) and an ordering pi of V, orient every edge from the lower
+ * to the higher index (the DAG G_pi) and report every triangle {u, v, w}
+ * exactly once, as the triple with pi_u < pi_v < pi_w.  Algorithm 1 (A++)
+ * seeds on the long edge (u, w) and scans N+_u against the marked N-_w;
+ * Algorithm 2 (A+-) seeds on the first short edge (u, v) and scans N+_v
+ * against the marked N+_u; the footnote's third form (A--) seeds on the
+ * second short edge.  Definition 1 gives the costs C++ = sum d+ d+ and
+ * C+- = sum d+ d-.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Vertex ids and ranks are uint32 in [0, n); rank is 0-based (the paper's
+ *   pi_u is 1-based).  Offsets, counts, costs and digests are uint64.
+ * - Pointers documented as "device" must point to memory on the current HIP
+ *   device; "host" pointers to ordinary host memory.  `stream` is a
+ *   hipStream_t passed as void* (NULL = the null stream).  All GPU work is
+ *   ordered on that stream; a call returns after its host outputs are filled.
+ * - Every function returns TL_OK or an error code and never throws or aborts.
+ *   tl_strerror() names a code; tl_last_error() gives the calling thread's
+ *   most recent detailed message.
+ * - A tl_csr is used from one stream at a time.
+ */
+#ifndef TL_H
+#define TL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque oriented graph, library-owned device memory. */
+typedef struct tl_csr tl_csr;
+
+/* Listing algorithm: A++ = Algorithm 1 (seed edge L, cost C++),
+ * A+- = Algorithm 2 (seed edge S1, cost C+-), A-- = the S2-seeded variant
+ * of the footnote in Section 2.1 (cost sum d- d-). */
+typedef enum { TL_APP = 0, TL_APM = 1, TL_AMM = 2 } tl_algo;
+
+enum {
+    TL_OK = 0,
+    TL_EINVAL = 1,    /* bad argument: NULL pointer, id >= n, rank not a permutation, size limit */
+    TL_ENOMEM = 2,    /* device allocation failed */
+    TL_ECAPACITY = 3, /* output buffer too small; summary->count holds the size needed */
+    TL_EHIP = 4,      /* a HIP runtime call failed */
+    TL_EABORT = 5     /* the chunk callback asked to stop */
+};
+
+/* Result of a listing call.
+ *   count    triangles listed
+ *   hash     wrapping 64-bit sum over listed triangles (a<b<c original ids)
+ *            of f(f((a<<32)|b) + c), f = the splitmix64 output function;
+ *            order independent, so it identifies the set (with count)
+ *   work     the paper's work: elements of the scanned lists over the
+ *            listed pivots' seed edges (Property 1); for a full listing it
+ *            equals tl_cost for the same algorithm
+ *   scanned  elements the kernels actually tested after range pruning */
+typedef struct {
+    uint64_t count;
+    uint64_t hash;
+    uint64_t work;
+    uint64_t scanned;
+} tl_summary;
+
+/* Chunk sink: receives `k` triangles (3*k uint32 in device memory, valid
+ * until the callback returns).  A non-zero return stops the listing with
+ * TL_EABORT. */
+typedef int (*tl_chunk_fn)(const uint32_t *tri_dev, uint64_t k, void *user);
+
+/*
+ * tl_orient -- build the oriented graph G_pi (Section 1.3).
+ *   n          vertex count, 0 <= n < 2^32 - 1
+ *   src, dst   device, m_in uint32 each: undirected edges {src[i], dst[i]};
+ *              each edge may appear once or in both directions; self-loops
+ *              and repeated pairs are dropped (the paper's datasets are
+ *              simplified the same way, Section 4.1.1)
+ *   m_in       input edge count, < 2^32
+ *   rank       device, n uint32: rank[u] = pi_u - 1; must be a permutation
+ *   out        host: receives the new handle (release with tl_csr_free)
+ * The handle holds, in rank space, the forward CSR (row r = ranks of the
+ * successors of the vertex of rank r, ascending), the backward CSR (the
+ * predecessors), their row ids, and the inverse permutation.  Inputs are
+ * not retained.  Errors: TL_EINVAL for NULL pointers with non-zero sizes,
+ * an id >= n or a rank that is not a permutation (nothing allocated).
+ */
+int tl_orient(uint32_t n, const uint32_t *src, const uint32_t *dst, uint64_t m_in,
+              const uint32_t *rank, void *stream, tl_csr **out);
+
+/*
+ * tl_cost -- Definition 1 for the handle's ordering: C++ = sum_u d+_u d+_u
+ * (TL_APP), C+- = sum_u d+_u d-_u (TL_APM), sum_u d-_u d-_u (TL_AMM).
+ *   cost  host, receives the value.
+ */
+int tl_cost(const tl_csr *g, tl_algo a, void *stream, uint64_t *cost);
+
+/*
+ * tl_list -- list every triangle once with the chosen algorithm
+ * (Algorithms 1 and 2), all pivots.  Output modes:
+ *   tri_dev != NULL: triangles are written to tri_dev (device, 3*cap
+ *     uint32, row i = (a, b, c), a < b < c, original ids), in unspecified
+ *     order.  If more than cap exist, TL_ECAPACITY is returned with
+ *     out->count = the number needed (the buffer holds cap of them).
+ *   tri_dev == NULL, cb != NULL: triangles are streamed through cb in
+ *     library-owned device chunks (see tl_set_chunk_triangles).
+ *   both NULL: count, digest and work only.
+ *   out  host, receives the summary (filled in every mode, also on
+ *        TL_ECAPACITY).
+ */
+int tl_list(const tl_csr *g, tl_algo a, uint32_t *tri_dev, uint64_t cap_triangles,
+            tl_chunk_fn cb, void *user, void *stream, tl_summary *out);
+
+/*
+ * tl_list_range -- as tl_list, restricted to pivots whose rank lies in
+ * [pivot_lo, pivot_hi).  The pivot is the vertex whose list the paper marks
+ * in B: w for A++ (Algorithm 1), u for A+- (Algorithm 2), v for A--.  The
+ * outer iterations are independent (Section 4.1.2), so disjoint ranges
+ * partition the triangles, and counts, digests and work add up.
+ */
+int tl_list_range(const tl_csr *g, tl_algo a, uint32_t pivot_lo, uint32_t pivot_hi,
+                  uint32_t *tri_dev, uint64_t cap_triangles, tl_chunk_fn cb, void *user,
+                  void *stream, tl_summary *out);
+
+/* Size of the oriented graph: n and m (undirected edges after dropping
+ * loops and duplicates).  Host outputs. */
+int tl_csr_size(const tl_csr *g, uint32_t *n, uint64_t *m);
+
+/*
+ * tl_csr_copy_to_host -- copy the oriented graph into host buffers (for
+ * inspection and tests).  Any pointer may be NULL to skip that array.
+ *   off_fwd, off_bwd  n+1 uint64     adj_fwd, adj_bwd  m uint32
+ *   inv               n uint32, inv[r] = vertex of rank r
+ */
+int tl_csr_copy_to_host(const tl_csr *g, uint64_t *off_fwd, uint32_t *adj_fwd,
+                        uint64_t *off_bwd, uint32_t *adj_bwd, uint32_t *inv);
+
+/* Release a handle and its device memory (NULL is a no-op). */
+void tl_csr_free(tl_csr *g);
+
+/* Triangles per library-owned chunk in callback mode (default 2^24, i.e.
+ * 192 MiB of uint32 triples).  Applies to later calls in this process. */
+int tl_set_chunk_triangles(uint64_t k);
+
+/*
+ * Kernel-phase timing, for measurement.  While enabled, the library records
+ * HIP events on the caller's stream around each phase's kernels and, when
+ * the call synchronises, adds the elapsed time to a per-phase total.
+ *   phase  TL_PHASE_ORIENT (all of tl_orient's kernels), TL_PHASE_PLAN
+ *          (per-seed-edge windows, compaction, work prefix), TL_PHASE_PROBE
+ *          (the intersection/emit kernel), TL_PHASE_COST (tl_cost)
+ *   ms, calls  host outputs: accumulated milliseconds and timed launches
+ */
+enum { TL_PHASE_ORIENT = 0, TL_PHASE_PLAN = 1, TL_PHASE_PROBE = 2, TL_PHASE_COST = 3, TL_NUM_PHASES = 4 };
+int tl_timing_enable(int on);
+int tl_timing_reset(void);
+int tl_timing_read(int phase, double *ms, uint64_t *calls);
+
+const char *tl_strerror(int code);
+const char *tl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TL_H */

@@ -1,0 +1,10 @@
+"""MI355X-native triangle listing under a given vertex ordering.
+
+Implements the listing path of Lecuyer, Jachiet, Magnien, Tabourier,
+"Tailored vertex ordering for faster triangle listing in large graphs"
+(arXiv 2203.04774): orientation by an ordering (Section 1.3), Algorithms 1
+(A++) and 2 (A+-) and the S2 variant (A--), and Definition 1's costs, in HIP
+kernels for gfx950 behind the C-ABI of include/tl.h.
+"""
+from .tl import (ALGOS, Csr, Summary, TLError, cost, list_triangles, orient,  # noqa: F401
+                 raw_lib, set_chunk_triangles)

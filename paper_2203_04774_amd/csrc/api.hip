@@ -1,0 +1,187 @@
+// C-ABI entry points of libtl (declared in include/tl.h).  Each call
+// validates its arguments on the host, runs the HIP pipeline on the
+// caller's stream and converts every failure into a status code.
+#include <mutex>
+#include <string>
+
+#include "tl_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int g_num_cus = 0;
+std::once_flag g_pool_once;
+
+void configure_pool() {
+    // keep freed stream-ordered scratch cached in the device pool instead of
+    // returning it to the driver at every synchronisation
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        std::call_once(g_pool_once, configure_pool);
+        return f();
+    } catch (const TlError &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return TL_ENOMEM;
+    } catch (...) {
+        g_last_error = "unexpected exception";
+        return TL_EHIP;
+    }
+}
+
+}  // namespace
+
+void tl_set_error(const std::string &msg) { g_last_error = msg; }
+
+int tl_num_cus() {
+    if (!g_num_cus) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            g_num_cus = cus;
+        else
+            g_num_cus = 256;
+    }
+    return g_num_cus;
+}
+
+void DevBuf::alloc() {
+    if (!bytes) return;
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        throw TlError{TL_ENOMEM, "device scratch allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+}
+
+void *tl_dev_alloc(size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 1;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw TlError{TL_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
+    return p;
+}
+
+void tl_dev_free(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+extern "C" {
+
+int tl_orient(uint32_t n, const uint32_t *src, const uint32_t *dst, uint64_t m_in, const uint32_t *rank,
+              void *stream, tl_csr **out) {
+    return guarded([&] {
+        TL_REQUIRE(out, TL_EINVAL, "out is NULL");
+        *out = nullptr;
+        *out = orient_impl(n, src, dst, m_in, rank, (hipStream_t)stream);
+        return TL_OK;
+    });
+}
+
+int tl_cost(const tl_csr *g, tl_algo a, void *stream, uint64_t *cost) {
+    return guarded([&] {
+        TL_REQUIRE(g && cost, TL_EINVAL, "NULL argument");
+        TL_REQUIRE(a == TL_APP || a == TL_APM || a == TL_AMM, TL_EINVAL, "unknown algorithm");
+        *cost = cost_impl(g, (int)a, (hipStream_t)stream);
+        return TL_OK;
+    });
+}
+
+int tl_list_range(const tl_csr *g, tl_algo a, uint32_t pivot_lo, uint32_t pivot_hi, uint32_t *tri_dev,
+                  uint64_t cap_triangles, tl_chunk_fn cb, void *user, void *stream, tl_summary *out) {
+    return guarded([&] {
+        TL_REQUIRE(g && out, TL_EINVAL, "NULL argument");
+        TL_REQUIRE(a == TL_APP || a == TL_APM || a == TL_AMM, TL_EINVAL, "unknown algorithm");
+        TL_REQUIRE(!(tri_dev && cb), TL_EINVAL, "give either an output buffer or a chunk callback");
+        return list_impl(g, (int)a, pivot_lo, pivot_hi, tri_dev, cap_triangles, cb, user, (hipStream_t)stream, out);
+    });
+}
+
+int tl_list(const tl_csr *g, tl_algo a, uint32_t *tri_dev, uint64_t cap_triangles, tl_chunk_fn cb, void *user,
+            void *stream, tl_summary *out) {
+    return tl_list_range(g, a, 0u, 0xffffffffu, tri_dev, cap_triangles, cb, user, stream, out);
+}
+
+int tl_csr_size(const tl_csr *g, uint32_t *n, uint64_t *m) {
+    return guarded([&] {
+        TL_REQUIRE(g, TL_EINVAL, "NULL handle");
+        if (n) *n = g->n;
+        if (m) *m = g->m;
+        return TL_OK;
+    });
+}
+
+int tl_csr_copy_to_host(const tl_csr *g, uint64_t *off_fwd, uint32_t *adj_fwd, uint64_t *off_bwd, uint32_t *adj_bwd,
+                        uint32_t *inv) {
+    return guarded([&] {
+        TL_REQUIRE(g, TL_EINVAL, "NULL handle");
+        TL_HIP(hipDeviceSynchronize());
+        const size_t no = ((size_t)g->n + 1) * sizeof(uint64_t), na = (size_t)g->m * sizeof(uint32_t);
+        if (off_fwd) TL_HIP(hipMemcpy(off_fwd, g->off_f, no, hipMemcpyDeviceToHost));
+        if (off_bwd) TL_HIP(hipMemcpy(off_bwd, g->off_b, no, hipMemcpyDeviceToHost));
+        if (adj_fwd && na) TL_HIP(hipMemcpy(adj_fwd, g->adj_f, na, hipMemcpyDeviceToHost));
+        if (adj_bwd && na) TL_HIP(hipMemcpy(adj_bwd, g->adj_b, na, hipMemcpyDeviceToHost));
+        if (inv && g->n) TL_HIP(hipMemcpy(inv, g->inv, (size_t)g->n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        return TL_OK;
+    });
+}
+
+void tl_csr_free(tl_csr *g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    tl_dev_free(g->off_f);
+    tl_dev_free(g->adj_f);
+    tl_dev_free(g->row_f);
+    tl_dev_free(g->off_b);
+    tl_dev_free(g->adj_b);
+    tl_dev_free(g->row_b);
+    tl_dev_free(g->inv);
+    delete g;
+}
+
+int tl_set_chunk_triangles(uint64_t k) {
+    if (k == 0 || k > (1ull << 32)) {
+        g_last_error = "chunk size must be in [1, 2^32]";
+        return TL_EINVAL;
+    }
+    set_chunk_triangles(k);
+    return TL_OK;
+}
+
+const char *tl_strerror(int code) {
+    switch (code) {
+        case TL_OK: return "ok";
+        case TL_EINVAL: return "invalid argument";
+        case TL_ENOMEM: return "out of device memory";
+        case TL_ECAPACITY: return "output buffer too small";
+        case TL_EHIP: return "HIP runtime error";
+        case TL_EABORT: return "aborted by chunk callback";
+        default: return "unknown error code";
+    }
+}
+
+const char *tl_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

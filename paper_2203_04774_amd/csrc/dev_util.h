@@ -1,0 +1,124 @@
+// Device-side helpers for 64-lane CDNA wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define WAVE 64
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    int l = lane_id();
+    return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    uint32_t lo = __shfl((uint32_t)v, src, WAVE);
+    uint32_t hi = __shfl((uint32_t)(v >> 32), src, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
+    uint32_t lo = __shfl_up((uint32_t)v, d, WAVE);
+    uint32_t hi = __shfl_up((uint32_t)(v >> 32), d, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    uint32_t lo = __shfl_xor((uint32_t)v, m, WAVE);
+    uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += shfl_xor_u64(v, m);
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+    int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint64_t t = shfl_up_u64(v, d);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one u64 per thread.  `lds` must hold
+// BLOCK/64 entries.  Returns the exclusive prefix; `total` gets the block sum.
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t *lds, uint64_t &total) {
+    const int l = lane_id(), w = threadIdx.x / WAVE;
+    uint64_t inc = wave_incl_scan_u64(v);
+    if (l == WAVE - 1) lds[w] = inc;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / WAVE; i++) {
+        uint64_t s = lds[i];
+        off += (i < w) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *lds) {
+    const int l = lane_id(), w = threadIdx.x / WAVE;
+    v = wave_sum_u64(v);
+    if (l == 0) lds[w] = v;
+    __syncthreads();
+    uint64_t tot = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / WAVE; i++) tot += lds[i];
+    __syncthreads();
+    return tot;
+}
+
+// first index i in [lo, hi) with a[i] >= x (hi if none)
+template <class T>
+__device__ __forceinline__ uint64_t lower_bound_dev(const T *a, uint64_t lo, uint64_t hi, T x) {
+    while (lo < hi) {
+        uint64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// first index i in [lo, hi) with a[i] > x (hi if none)
+template <class T>
+__device__ __forceinline__ uint64_t upper_bound_dev(const T *a, uint64_t lo, uint64_t hi, T x) {
+    while (lo < hi) {
+        uint64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// splitmix64 output function (Steele, Lea, Flood, OOPSLA 2014)
+__device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// digest of a triangle given as three original ids in any order
+__device__ __forceinline__ void canon3(uint32_t &a, uint32_t &b, uint32_t &c) {
+    uint32_t t;
+    if (a > b) { t = a; a = b; b = t; }
+    if (b > c) { t = b; b = c; c = t; }
+    if (a > b) { t = a; a = b; b = t; }
+}
+
+__device__ __forceinline__ uint64_t tri_digest(uint32_t a, uint32_t b, uint32_t c) {
+    return sm64_mix(sm64_mix(((uint64_t)a << 32) | b) + c);
+}
+
+#define GRID_STRIDE(i, n)                                                                \
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)(n); \
+         i += (uint64_t)gridDim.x * blockDim.x)

@@ -1,0 +1,208 @@
+// Orientation of an undirected edge list by a vertex ordering (Section 1.3:
+// (u,v) is in E_pi iff pi_u < pi_v) into rank-space forward and backward
+// CSR arrays.
+//
+// Pipeline, all on the caller's stream:
+//   1. validate: rank is a permutation of [0,n) and every endpoint id < n
+//   2. relabel + orient: edge {a,b} -> (lo,hi) = (min, max)(rank[a], rank[b]);
+//      self-loops dropped; per-row counts of lo
+//   3. scan -> raw row offsets; scatter hi into row lo
+//   4. sort each row, drop repeated pairs; compact only if some were repeated
+//   5. backward CSR: count by target, scan, scatter, sort rows
+//   6. inverse permutation inv[rank[u]] = u
+#include "tl_internal.h"
+#include "dev_util.h"
+#include "timing.h"
+
+namespace {
+
+__global__ void k_rank_count(const u32 *rank, u32 n, u32 *cnt, u32 *flag) {
+    GRID_STRIDE(i, n) {
+        u32 r = rank[i];
+        if (r >= n) atomicOr(flag, 1u);
+        else atomicAdd(&cnt[r], 1u);
+    }
+}
+
+__global__ void k_rank_verify(const u32 *cnt, u32 n, u32 *flag) {
+    GRID_STRIDE(i, n) {
+        if (cnt[i] != 1u) atomicOr(flag, 1u);
+    }
+}
+
+__global__ void k_edge_verify(const u32 *src, const u32 *dst, u64 m_in, u32 n, u32 *flag) {
+    GRID_STRIDE(i, m_in) {
+        if (src[i] >= n || dst[i] >= n) atomicOr(flag, 2u);
+    }
+}
+
+// rank and ids are validated before this runs
+__global__ void k_row_count(const u32 *src, const u32 *dst, u64 m_in, const u32 *rank, u32 *cnt) {
+    GRID_STRIDE(i, m_in) {
+        u32 ra = rank[src[i]], rb = rank[dst[i]];
+        if (ra != rb) atomicAdd(&cnt[ra < rb ? ra : rb], 1u);
+    }
+}
+
+__global__ void k_row_scatter(const u32 *src, const u32 *dst, u64 m_in, const u32 *rank, const u64 *off,
+                              u32 *cursor, u32 *adj, u32 *row) {
+    GRID_STRIDE(i, m_in) {
+        u32 ra = rank[src[i]], rb = rank[dst[i]];
+        if (ra == rb) continue;
+        u32 lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+        u64 pos = off[lo] + atomicAdd(&cursor[lo], 1u);
+        adj[pos] = hi;
+        row[pos] = lo;
+    }
+}
+
+// keep the first uniq[row] entries of each raw row, at their new offsets
+__global__ void k_compact_rows(const u64 *raw_off, const u32 *raw_adj, const u32 *raw_row, u64 nnz_raw,
+                               const u32 *uniq, const u64 *off, u32 *adj, u32 *row) {
+    GRID_STRIDE(j, nnz_raw) {
+        u32 r = raw_row[j];
+        u64 k = j - raw_off[r];
+        if (k < uniq[r]) {
+            adj[off[r] + k] = raw_adj[j];
+            row[off[r] + k] = r;
+        }
+    }
+}
+
+__global__ void k_count_targets(const u32 *adj, u64 m, u32 *cnt) {
+    GRID_STRIDE(j, m) { atomicAdd(&cnt[adj[j]], 1u); }
+}
+
+__global__ void k_transpose_scatter(const u32 *adj_f, const u32 *row_f, u64 m, const u64 *off_b, u32 *cursor,
+                                    u32 *adj_b, u32 *row_b) {
+    GRID_STRIDE(j, m) {
+        u32 v = adj_f[j];
+        u64 pos = off_b[v] + atomicAdd(&cursor[v], 1u);
+        adj_b[pos] = row_f[j];
+        row_b[pos] = v;
+    }
+}
+
+__global__ void k_inverse(const u32 *rank, u32 n, u32 *inv) {
+    GRID_STRIDE(i, n) { inv[rank[i]] = (u32)i; }
+}
+
+unsigned grid_n(u64 items) { return grid_for(items, 256, (unsigned)tl_num_cus() * 16); }
+
+struct CsrOwner {
+    tl_csr *g;
+    explicit CsrOwner(tl_csr *p) : g(p) {}
+    ~CsrOwner() { if (g) tl_csr_free(g); }
+    tl_csr *release() { tl_csr *p = g; g = nullptr; return p; }
+};
+
+}  // namespace
+
+tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *rank, hipStream_t s) {
+    TL_REQUIRE(n < 0xffffffffu, TL_EINVAL, "n must be below 2^32 - 1");
+    TL_REQUIRE(m_in < (1ull << 32), TL_EINVAL, "m_in must be below 2^32");
+    TL_REQUIRE(n == 0 || rank, TL_EINVAL, "rank is NULL");
+    TL_REQUIRE(m_in == 0 || (src && dst), TL_EINVAL, "src/dst is NULL");
+    TL_REQUIRE(n > 0 || m_in == 0, TL_EINVAL, "edges given for an empty vertex set");
+
+    PhaseTimer timer(TL_PHASE_ORIENT, s);
+    // ---- 1. validation
+    DevBuf cnt((u64)(n + 1) * sizeof(u32), s);
+    DevBuf flag(sizeof(u32), s);
+    TL_HIP(hipMemsetAsync(flag.p, 0, sizeof(u32), s));
+    if (n) {
+        TL_HIP(hipMemsetAsync(cnt.p, 0, (u64)n * sizeof(u32), s));
+        hipLaunchKernelGGL(k_rank_count, dim3(grid_n(n)), dim3(256), 0, s, rank, n, cnt.as<u32>(), flag.as<u32>());
+        TL_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_rank_verify, dim3(grid_n(n)), dim3(256), 0, s, cnt.as<u32>(), n, flag.as<u32>());
+        TL_HIP(hipGetLastError());
+    }
+    if (m_in) {
+        hipLaunchKernelGGL(k_edge_verify, dim3(grid_n(m_in)), dim3(256), 0, s, src, dst, m_in, n, flag.as<u32>());
+        TL_HIP(hipGetLastError());
+    }
+    u32 h_flag = 0;
+    TL_HIP(hipMemcpyAsync(&h_flag, flag.p, sizeof(u32), hipMemcpyDeviceToHost, s));
+    TL_HIP(hipStreamSynchronize(s));
+    TL_REQUIRE(!(h_flag & 1u), TL_EINVAL, "rank is not a permutation of [0, n)");
+    TL_REQUIRE(!(h_flag & 2u), TL_EINVAL, "an edge endpoint is >= n");
+
+    CsrOwner own(new tl_csr());
+    tl_csr *g = own.g;
+    g->n = n;
+    TL_HIP(hipGetDevice(&g->device));
+    g->off_f = (u64 *)tl_dev_alloc((u64)(n + 1) * sizeof(u64));
+    g->off_b = (u64 *)tl_dev_alloc((u64)(n + 1) * sizeof(u64));
+    g->inv = (u32 *)tl_dev_alloc((u64)(n ? n : 1) * sizeof(u32));
+
+    // ---- 2-3. count rows, scan, scatter
+    u32 *rowcnt = cnt.as<u32>();
+    if (n) TL_HIP(hipMemsetAsync(rowcnt, 0, (u64)n * sizeof(u32), s));
+    if (m_in) {
+        hipLaunchKernelGGL(k_row_count, dim3(grid_n(m_in)), dim3(256), 0, s, src, dst, m_in, rank, rowcnt);
+        TL_HIP(hipGetLastError());
+    }
+    DevBuf raw_off((u64)(n + 1) * sizeof(u64), s);
+    scan_u32_to_u64(rowcnt, raw_off.as<u64>(), n, s);
+    u64 nnz_raw = 0;
+    TL_HIP(hipMemcpyAsync(&nnz_raw, raw_off.as<u64>() + n, sizeof(u64), hipMemcpyDeviceToHost, s));
+    TL_HIP(hipStreamSynchronize(s));
+
+    u32 *raw_adj = (u32 *)tl_dev_alloc((nnz_raw ? nnz_raw : 1) * sizeof(u32));
+    u32 *raw_row = (u32 *)tl_dev_alloc((nnz_raw ? nnz_raw : 1) * sizeof(u32));
+    g->adj_f = raw_adj;  // owned by g from here (freed on error)
+    g->row_f = raw_row;
+    if (nnz_raw) {
+        TL_HIP(hipMemsetAsync(rowcnt, 0, (u64)n * sizeof(u32), s));
+        hipLaunchKernelGGL(k_row_scatter, dim3(grid_n(m_in)), dim3(256), 0, s, src, dst, m_in, rank,
+                           raw_off.as<u64>(), rowcnt, raw_adj, raw_row);
+        TL_HIP(hipGetLastError());
+    }
+
+    // ---- 4. sort rows, drop repeated pairs
+    DevBuf uniq((u64)(n + 1) * sizeof(u32), s);
+    segmented_sort_unique(raw_off.as<u64>(), n, raw_adj, nnz_raw, n, uniq.as<u32>(), s);
+    scan_u32_to_u64(uniq.as<u32>(), g->off_f, n, s);
+    u64 m = 0;
+    TL_HIP(hipMemcpyAsync(&m, g->off_f + n, sizeof(u64), hipMemcpyDeviceToHost, s));
+    TL_HIP(hipStreamSynchronize(s));
+    g->m = m;
+    if (m != nnz_raw) {
+        u32 *adj = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32));
+        u32 *row = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32));
+        hipLaunchKernelGGL(k_compact_rows, dim3(grid_n(nnz_raw)), dim3(256), 0, s, raw_off.as<u64>(), raw_adj,
+                           raw_row, nnz_raw, uniq.as<u32>(), g->off_f, adj, row);
+        TL_HIP(hipGetLastError());
+        TL_HIP(hipStreamSynchronize(s));
+        tl_dev_free(raw_adj);
+        tl_dev_free(raw_row);
+        g->adj_f = adj;
+        g->row_f = row;
+    }
+
+    // ---- 5. backward CSR (predecessor lists)
+    g->adj_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32));
+    g->row_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32));
+    if (n) TL_HIP(hipMemsetAsync(rowcnt, 0, (u64)n * sizeof(u32), s));
+    if (m) {
+        hipLaunchKernelGGL(k_count_targets, dim3(grid_n(m)), dim3(256), 0, s, g->adj_f, m, rowcnt);
+        TL_HIP(hipGetLastError());
+    }
+    scan_u32_to_u64(rowcnt, g->off_b, n, s);
+    if (m) {
+        TL_HIP(hipMemsetAsync(rowcnt, 0, (u64)n * sizeof(u32), s));
+        hipLaunchKernelGGL(k_transpose_scatter, dim3(grid_n(m)), dim3(256), 0, s, g->adj_f, g->row_f, m, g->off_b,
+                           rowcnt, g->adj_b, g->row_b);
+        TL_HIP(hipGetLastError());
+        segmented_sort_unique(g->off_b, n, g->adj_b, m, n, uniq.as<u32>(), s);
+    }
+
+    // ---- 6. inverse permutation
+    if (n) {
+        hipLaunchKernelGGL(k_inverse, dim3(grid_n(n)), dim3(256), 0, s, rank, n, g->inv);
+        TL_HIP(hipGetLastError());
+    }
+    timer.stop();
+    TL_HIP(hipStreamSynchronize(s));
+    return own.release();
+}

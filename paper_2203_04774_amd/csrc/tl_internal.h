@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP translation units of libtl.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "tl.h"
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+// ------------------------------------------------------------ error plumbing
+
+struct TlError {
+    int code;
+    std::string msg;
+};
+
+void tl_set_error(const std::string &msg);
+
+#define TL_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw TlError{TL_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)};   \
+        } while (0)
+
+#define TL_REQUIRE(cond, code, text)                                                     \
+    do {                                                                                 \
+        if (!(cond)) throw TlError{(code), (text)};                                      \
+    } while (0)
+
+// ------------------------------------------------------------ device memory
+
+// Stream-ordered scratch allocation: freed on the same stream when the
+// object goes out of scope.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(size_t b, hipStream_t st) : bytes(b), s(st) { alloc(); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), s(o.s) { o.p = nullptr; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        release();
+        p = o.p; bytes = o.bytes; s = o.s; o.p = nullptr;
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc();
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+    void *detach() { void *q = p; p = nullptr; return q; }
+};
+
+// Long-lived allocation (graph storage).
+void *tl_dev_alloc(size_t bytes);
+void tl_dev_free(void *p);
+
+// ------------------------------------------------------------ the handle
+
+struct tl_csr {
+    u32 n = 0;
+    u64 m = 0;
+    int device = 0;
+    u64 *off_f = nullptr;  // n+1: forward CSR offsets (rank space)
+    u32 *adj_f = nullptr;  // m:   successor ranks, rows ascending
+    u32 *row_f = nullptr;  // m:   row (source rank) of each forward entry
+    u64 *off_b = nullptr;  // n+1: backward CSR offsets
+    u32 *adj_b = nullptr;  // m:   predecessor ranks, rows ascending
+    u32 *row_b = nullptr;  // m:   row (target rank) of each backward entry
+    u32 *inv = nullptr;    // n:   inv[r] = vertex of rank r
+};
+
+// ------------------------------------------------------------ launch helpers
+
+int tl_num_cus();
+
+inline unsigned grid_for(u64 items, unsigned block, unsigned max_blocks = 65535u * 4u) {
+    u64 g = (items + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > max_blocks) g = max_blocks;
+    return (unsigned)g;
+}
+
+// exclusive scan: out[i] = sum_{j<i} in[j] for i in [0, n]; out[n] = total.
+void scan_u32_to_u64(const u32 *in, u64 *out, u64 n, hipStream_t s);
+void scan_u64_to_u64(const u64 *in, u64 *out, u64 n, hipStream_t s);
+
+// Sort every row of a CSR ascending and drop repeated values inside a row;
+// uniq[r] receives the row's distinct count and the distinct values are
+// packed at the start of the row.  Values must be < n_values.
+void segmented_sort_unique(const u64 *off, u32 nrows, u32 *adj, u64 nnz, u32 n_values, u32 *uniq,
+                           hipStream_t s);
+
+// Orientation and listing drivers (orient.hip, list.hip).
+tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *rank, hipStream_t s);
+u64 cost_impl(const tl_csr *g, int algo, hipStream_t s);
+int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl_chunk_fn cb, void *user,
+              hipStream_t s, tl_summary *out);
+u64 chunk_triangles();
+void set_chunk_triangles(u64 k);

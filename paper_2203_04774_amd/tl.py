@@ -1,0 +1,189 @@
+"""ctypes binding of libtl (include/tl.h): argument marshalling only.
+
+Device buffers are torch tensors on the current HIP device; their raw
+pointers and the current stream are handed to the C-ABI.  Every step of the
+listing path runs in the library's HIP kernels.  If libtl.so is missing the
+import fails: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtl.so")
+
+TL_OK, TL_EINVAL, TL_ENOMEM, TL_ECAPACITY, TL_EHIP, TL_EABORT = range(6)
+ALGOS = {"A++": 0, "A+-": 1, "A--": 2}
+
+
+class TLError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_lib.tl_strerror(code).decode()} ({_lib.tl_last_error().decode()})")
+        self.code = code
+
+
+class Summary(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("hash", ctypes.c_uint64),
+                ("work", ctypes.c_uint64), ("scanned", ctypes.c_uint64)]
+
+    def __repr__(self):
+        return (f"Summary(count={self.count}, hash=0x{self.hash:016x}, work={self.work}, "
+                f"scanned={self.scanned})")
+
+
+CHUNK_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(or python -m paper_2203_04774_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    lib.tl_orient.argtypes = [u32, vp, vp, u64, vp, vp, ctypes.POINTER(vp)]
+    lib.tl_cost.argtypes = [vp, i32, vp, ctypes.POINTER(u64)]
+    lib.tl_list.argtypes = [vp, i32, vp, u64, CHUNK_FN, vp, vp, ctypes.POINTER(Summary)]
+    lib.tl_list_range.argtypes = [vp, i32, u32, u32, vp, u64, CHUNK_FN, vp, vp, ctypes.POINTER(Summary)]
+    lib.tl_csr_size.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u64)]
+    lib.tl_csr_copy_to_host.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.tl_csr_free.argtypes = [vp]
+    lib.tl_csr_free.restype = None
+    lib.tl_set_chunk_triangles.argtypes = [u64]
+    lib.tl_strerror.argtypes = [i32]
+    lib.tl_strerror.restype = ctypes.c_char_p
+    lib.tl_last_error.restype = ctypes.c_char_p
+    for f in ("tl_orient", "tl_cost", "tl_list", "tl_list_range", "tl_csr_size",
+              "tl_csr_copy_to_host", "tl_set_chunk_triangles"):
+        getattr(lib, f).restype = i32
+    return lib
+
+
+_lib = _load()
+_NULL_CB = CHUNK_FN()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t: torch.Tensor | None, what: str):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise ValueError(f"{what} must be int32/uint32")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(rc, what):
+    if rc != TL_OK:
+        raise TLError(rc, what)
+
+
+class Csr:
+    """Oriented graph handle returned by :func:`orient` (owns device memory)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        n, m = ctypes.c_uint32(), ctypes.c_uint64()
+        _check(_lib.tl_csr_size(handle, ctypes.byref(n), ctypes.byref(m)), "tl_csr_size")
+        self.n, self.m = int(n.value), int(m.value)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("handle already freed")
+        return self._h
+
+    def free(self):
+        if self._h is not None:
+            _lib.tl_csr_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def to_host(self):
+        """(off_fwd, adj_fwd, off_bwd, adj_bwd, inv) as numpy arrays."""
+        import numpy as np
+        fo = np.zeros(self.n + 1, np.uint64)
+        bo = np.zeros(self.n + 1, np.uint64)
+        fa = np.zeros(max(self.m, 1), np.uint32)
+        ba = np.zeros(max(self.m, 1), np.uint32)
+        inv = np.zeros(max(self.n, 1), np.uint32)
+        _check(_lib.tl_csr_copy_to_host(self.handle, fo.ctypes.data, fa.ctypes.data, bo.ctypes.data,
+                                        ba.ctypes.data, inv.ctypes.data), "tl_csr_copy_to_host")
+        return fo, fa[:self.m], bo, ba[:self.m], inv[:self.n]
+
+
+def orient(n: int, src: torch.Tensor, dst: torch.Tensor, rank: torch.Tensor, stream=None) -> Csr:
+    """tl_orient: edges (src[i], dst[i]) and rank (device int32 tensors)."""
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in length")
+    h = ctypes.c_void_p()
+    _check(_lib.tl_orient(n, _dptr(src, "src"), _dptr(dst, "dst"), src.numel(), _dptr(rank, "rank"),
+                          _stream_ptr(stream), ctypes.byref(h)), "tl_orient")
+    return Csr(h)
+
+
+def cost(g: Csr, algo: str = "A++", stream=None) -> int:
+    out = ctypes.c_uint64()
+    _check(_lib.tl_cost(g.handle, ALGOS[algo], _stream_ptr(stream), ctypes.byref(out)), "tl_cost")
+    return int(out.value)
+
+
+def list_triangles(g: Csr, algo: str = "A++", out: torch.Tensor | None = None, on_chunk=None,
+                   pivot_range=None, stream=None, allow_capacity_error=False) -> Summary:
+    """tl_list / tl_list_range.
+
+    out       optional device int32 tensor of shape (cap, 3): receives the
+              triangles (original ids, a < b < c)
+    on_chunk  optional callable(ptr: int, k: int) -> bool|None; return True
+              to stop; receives library-owned device chunks
+    """
+    s = Summary()
+    cap = 0
+    if out is not None:
+        if out.dim() != 2 or out.shape[1] != 3:
+            raise ValueError("out must have shape (cap, 3)")
+        cap = out.shape[0]
+    cb = _NULL_CB
+    if on_chunk is not None:
+        def _tramp(ptr, k, user):
+            try:
+                return 1 if on_chunk(int(ptr), int(k)) else 0
+            except Exception:
+                return 1
+        cb = CHUNK_FN(_tramp)
+    optr = _dptr(out, "out") if out is not None else None
+    if pivot_range is None:
+        rc = _lib.tl_list(g.handle, ALGOS[algo], optr, cap, cb, None, _stream_ptr(stream), ctypes.byref(s))
+    else:
+        lo, hi = pivot_range
+        rc = _lib.tl_list_range(g.handle, ALGOS[algo], lo, hi, optr, cap, cb, None, _stream_ptr(stream),
+                                ctypes.byref(s))
+    if rc == TL_ECAPACITY and allow_capacity_error:
+        return s
+    _check(rc, "tl_list")
+    return s
+
+
+def set_chunk_triangles(k: int):
+    _check(_lib.tl_set_chunk_triangles(k), "tl_set_chunk_triangles")
+
+
+def raw_lib():
+    """The loaded ctypes library (for callers that marshal pointers themselves)."""
+    return _lib

@@ -115,6 +115,7 @@ def main():
     src, dst = dev(g.src), dev(g.dst)
     dranks = {k: dev(r) for k, r in ranks.items()}
     lib = tl.raw_lib()
+    lib.tl_timing_read.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
 
     # size the output buffer from a count-only pass
     csr = tl.orient(g.n, src, dst, dranks[wl["orders"][0]])
@@ -124,15 +125,30 @@ def main():
 
     runs = [(k, a) for k in wl["orders"] for a in wl["algos"]]
 
+    def phase_ms():
+        vals = []
+        for ph in range(4):
+            ms = ctypes.c_double()
+            lib.tl_timing_read(ph, ctypes.byref(ms), None)
+            vals.append(ms.value)
+        return vals
+
     def step(record=None):
         for kind in wl["orders"]:
+            t_or = phase_ms()[0] if record is not None else 0.0
             csr = tl.orient(g.n, src, dst, dranks[kind])
+            if record is not None:
+                t_or = phase_ms()[0] - t_or
             for algo in wl["algos"]:
+                before = phase_ms() if record is not None else None
                 c = tl.cost(csr, algo)
                 s = tl.list_triangles(csr, algo, out=out)
                 if record is not None:
+                    after = phase_ms()
                     record.append(dict(order=kind, algo=algo, T=int(s.count), C=int(c), work=int(s.work),
-                                       scanned=int(s.scanned), hash=f"0x{s.hash:016x}", m=csr.m))
+                                       scanned=int(s.scanned), hash=f"0x{s.hash:016x}", m=csr.m,
+                                       orient_ms=t_or, plan_ms=after[1] - before[1],
+                                       probe_ms=after[2] - before[2]))
             csr.free()
 
     for i in range(args.warmup):
@@ -155,7 +171,6 @@ def main():
     phases = {}
     for ph, name in enumerate(["orient", "plan", "probe", "cost"]):
         ms, calls = ctypes.c_double(), ctypes.c_uint64()
-        lib.tl_timing_read.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         lib.tl_timing_read(ph, ctypes.byref(ms), ctypes.byref(calls))
         phases[name] = {"ms": ms.value, "launches": int(calls.value)}
 

@@ -10,10 +10,22 @@
 // Lists are sorted ranks, so only the part of S inside [min, max] of the
 // candidate part of T can match; for A++ and A+- the candidates are the
 // entries of T after x itself (a triangle needs the third vertex on the far
-// side of x).  The plan step computes that window per seed edge, compacts
-// the non-empty ones and prefix-sums their lengths; the probe step then
-// gives every lane exactly one scanned element (perfect load balance over
-// the flattened work), which it looks up in T by binary search.
+// side of x, and every element of S_x already lies there).
+//
+// Plan (per listing): a window per seed edge; per-pivot work W_p; pivots with
+// enough work become "heavy"; non-empty seed edges are compacted with the
+// light pivots' ones first, then the heavy ones (pivot-major), and their
+// window lengths prefix-summed into one flattened work space.
+// Probe: light items are spread evenly over wavefronts, one scanned element
+// per lane, tested by binary search in T (global memory).  Heavy pivots are
+// cut into tasks of item slices; a 1024-thread workgroup per task stages T in
+// LDS -- as the paper's boolean array B (a bitmap over T's rank window) when
+// that window fits, else as a sorted array -- and then tests each scanned
+// element with one (or log |T|) LDS reads.
+#include <cstdio>
+#include <cstdlib>
+#include <mutex>
+
 #include "tl_internal.h"
 #include "dev_util.h"
 #include "timing.h"
@@ -51,51 +63,249 @@ struct Seed {
     }
 };
 
-constexpr int PB = 256;
-
+// Arrays that index seeds, scanned lists and pivot lists for a form.
 template <int ALGO>
-__global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len, u32 *start, u32 *flag,
-                                             u64 *acc) {
+struct Form {
+    // seed edges are the entries of this CSR (pivot-major)
+    static __device__ __forceinline__ const u64 *seed_off(const GView &g) { return ALGO == 0 ? g.off_b : g.off_f; }
+    static __device__ __forceinline__ const u32 *seed_adj(const GView &g) { return ALGO == 0 ? g.adj_b : g.adj_f; }
+    // scanned lists
+    static __device__ __forceinline__ const u32 *scan_adj(const GView &g) { return ALGO == 2 ? g.adj_b : g.adj_f; }
+    // pivot (marked) list
+    static __device__ __forceinline__ const u64 *piv_off(const GView &g) { return ALGO == 1 ? g.off_f : g.off_b; }
+    static __device__ __forceinline__ const u32 *piv_adj(const GView &g) { return ALGO == 1 ? g.adj_f : g.adj_b; }
+};
+
+constexpr int PB = 256;        // threads per block, light kernels
+constexpr int HB = 1024;       // threads per block, heavy-pivot kernel
+constexpr u32 LDS_BYTES = 128 * 1024;
+constexpr u32 LDS_WORDS = LDS_BYTES / 4;
+constexpr u64 LDS_BITS = (u64)LDS_BYTES * 8;
+constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + (HB / 64) * 3 * 128 * 4;  // + per-wavefront emit stages
+constexpr u64 HEAVY_MIN = 4096;    // items of a pivot before it gets a workgroup
+constexpr u64 SLICE_MIN = 16384;   // items per heavy task, at least
+
+enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2 };
+
+struct Task {
+    u64 a, b;    // item range
+    u64 cb, ce;  // compacted seed range of the pivot
+    u32 p;       // pivot
+    u32 mode;
+};
+
+// ---------------------------------------------------------------- plan
+
+// Window of every seed edge; per-pivot work W_p (segmented by pivot, since
+// seeds are pivot-major); the paper's work for the listed pivots.
+template <int ALGO>
+__global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len, u64 *sabs, u64 *wp, u64 *acc) {
     __shared__ u64 lds[PB / WAVE];
     u64 work = 0;
-    GRID_STRIDE(e, g.m) {
-        Seed<ALGO> sd(g, e);
-        u32 l = 0, st = 0;
-        if (sd.p >= plo && sd.p < phi) {
-            work += sd.s_hi - sd.s_lo;
-            if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
-                u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
-                u64 a = lower_bound_dev<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
-                u64 b = upper_bound_dev<u32>(sd.S, a, sd.s_hi, tmax);
-                l = (u32)(b - a);
-                st = (u32)(a - sd.s_lo);
+    const int lane = lane_id();
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 iters = g.m > first - lane ? (g.m - (first - lane) + stride - 1) / stride : 0;  // wave-uniform
+    for (u64 it = 0; it < iters; it++) {
+        const u64 e = first + it * stride;
+        const bool valid = e < g.m;
+        u32 l = 0, p = 0xffffffffu;
+        u64 abs = 0;
+        if (valid) {
+            Seed<ALGO> sd(g, e);
+            p = sd.p;
+            if (sd.p >= plo && sd.p < phi) {
+                work += sd.s_hi - sd.s_lo;
+                if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
+                    u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
+                    u64 a = lower_bound_dev<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
+                    u64 b = upper_bound_dev<u32>(sd.S, a, sd.s_hi, tmax);
+                    l = (u32)(b - a);
+                    abs = a;
+                }
             }
+            len[e] = l;
+            sabs[e] = abs;
         }
-        len[e] = l;
-        start[e] = st;
-        flag[e] = l ? 1u : 0u;
+        // segmented sum of l over runs of equal pivot within the wavefront
+        u64 v = l;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            u64 t = shfl_up_u64(v, d);
+            u32 q = __shfl_up(p, d, WAVE);
+            if (lane >= d && q == p) v += t;
+        }
+        const u32 pn = __shfl_down(p, 1, WAVE);
+        const bool last = valid && (lane == WAVE - 1 || pn != p || !(e + 1 < g.m));
+        if (last && v) atomicAdd((unsigned long long *)&wp[p], (unsigned long long)v);
     }
     u64 tot = block_sum_u64<PB>(work, lds);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&acc[2], (unsigned long long)tot);
 }
 
-__global__ void k_compact_seeds(const u32 *len, const u32 *start, const u64 *pos, u64 m, u32 *cseed, u32 *cstart,
-                                u32 *clen) {
+// Heavy/light decision and task count per pivot.
+template <int ALGO>
+__global__ void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask, u64 *slice) {
+    GRID_STRIDE(p, n) {
+        const u64 w = wp[p];
+        u32 md = 0xffffffffu, nt = 0;
+        u64 sl = 0;
+        if (w >= HEAVY_MIN) {
+            const u64 *po = Form<ALGO>::piv_off(g);
+            const u32 *pa = Form<ALGO>::piv_adj(g);
+            const u64 t0 = po[p], t1 = po[p + 1];
+            const u64 tlen = t1 - t0;
+            const u64 range = (u64)pa[t1 - 1] - pa[t0] + 1;
+            const u64 words = (range + 31) / 32;
+            const bool bm_ok = range <= LDS_BITS;
+            const bool arr_ok = tlen <= LDS_WORDS;
+            u64 stage;
+            if (bm_ok && (words <= 4 * tlen || words * 16 <= w)) { md = MODE_BITMAP; stage = words + tlen; }
+            else if (arr_ok) { md = MODE_ARRAY; stage = tlen; }
+            else if (bm_ok) { md = MODE_BITMAP; stage = words + tlen; }
+            else { md = MODE_GLOBAL; stage = 0; }
+            sl = 16 * stage;
+            if (sl < SLICE_MIN) sl = SLICE_MIN;
+            nt = (u32)((w + sl - 1) / sl);
+        }
+        mode[p] = md;
+        ntask[p] = nt;
+        slice[p] = sl;
+    }
+}
+
+// Class flag per seed, packed for one scan: low half light, high half heavy.
+template <int ALGO>
+__global__ void k_seed_class(GView g, const u32 *len, const u32 *mode, u64 *flags) {
+    GRID_STRIDE(e, g.m) {
+        u64 f = 0;
+        if (len[e]) {
+            const u32 p = ALGO == 0 ? g.row_b[e] : g.row_f[e];
+            f = mode[p] == 0xffffffffu ? 1ull : (1ull << 32);
+        }
+        flags[e] = f;
+    }
+}
+
+// Light seeds first, then heavy seeds, both in seed (pivot-major) order.
+__global__ void k_compact(u64 m, const u32 *len, const u64 *sabs, const u64 *pos, u32 *cseed, u64 *cabs, u32 *clen) {
+    const u64 nl = pos[m] & 0xffffffffull;
     GRID_STRIDE(e, m) {
-        u32 l = len[e];
+        const u32 l = len[e];
         if (l) {
-            u64 p = pos[e];
-            cseed[p] = (u32)e;
-            cstart[p] = start[e];
-            clen[p] = l;
+            const u64 ps = pos[e];
+            const bool heavy = ((ps >> 32) != (pos[e + 1] >> 32));
+            const u64 d = heavy ? nl + (ps >> 32) : (ps & 0xffffffffull);
+            cseed[d] = (u32)e;
+            cabs[d] = sabs[e];
+            clen[d] = l;
         }
     }
 }
 
+template <int ALGO>
+__global__ void k_make_tasks(GView g, u32 n, const u32 *mode, const u32 *ntask, const u64 *slice, const u64 *tpos,
+                             const u64 *pos, const u64 *cpre, u64 m, Task *tasks) {
+    const u64 nl = pos[m] & 0xffffffffull;
+    GRID_STRIDE(p, n) {
+        const u32 nt = ntask[p];
+        if (!nt) continue;
+        const u64 *so = Form<ALGO>::seed_off(g);
+        const u64 cb = nl + (pos[so[p]] >> 32), ce = nl + (pos[so[p + 1]] >> 32);
+        const u64 a = cpre[cb], b = cpre[ce];
+        const u64 sl = slice[p];
+        for (u32 i = 0; i < nt; i++) {
+            Task t;
+            t.a = a + (u64)i * sl;
+            t.b = (t.a + sl < b) ? t.a + sl : b;
+            t.cb = cb;
+            t.ce = ce;
+            t.p = (u32)p;
+            t.mode = mode[p];
+            tasks[tpos[p] + i] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- probe
+
+// Finds, for each lane's item k in [kb, kb+64), the compacted seed c with
+// cpre[c] <= k < cpre[c+1], given c_lo = seed of item kb.  Returns c and
+// writes the item's offset inside the seed's window to rel.
+__device__ __forceinline__ u64 seed_of_item(const u64 *cpre, u64 ncap, u64 c_lo, u64 k, u64 &rel) {
+    const int lane = lane_id();
+    const u64 P = (c_lo + lane <= ncap) ? cpre[c_lo + lane] : ~0ull;
+    int lo = 0;
+#pragma unroll
+    for (int st = 32; st > 0; st >>= 1) {
+        u64 pv = shfl_u64(P, lo + st);
+        if (pv <= k) lo += st;
+    }
+    rel = k - shfl_u64(P, lo);
+    return c_lo + lo;
+}
+
+// Per-wavefront staging of listed triangles in LDS: hits are appended with
+// a ballot, and a full stage is flushed with ONE cursor atomic and
+// coalesced stores, instead of one global atomic per iteration with a hit.
+constexpr u32 STAGE_TRI = 128;  // triangles per wavefront stage (>= 2 * 64)
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool EMIT>
+struct WaveEmitter {
+    u32 *stage;  // 3 * STAGE_TRI words of this wavefront's LDS
+    u32 fill = 0;
+    __device__ __forceinline__ explicit WaveEmitter(u32 *st) : stage(st) {}
+
+    __device__ __forceinline__ void flush(u32 *tri, u64 cap, u64 *acc) {
+        if (!EMIT || fill == 0) return;
+        wave_lds_sync();
+        u64 base = 0;
+        if (lane_id() == 0) base = atomicAdd((unsigned long long *)&acc[3], (unsigned long long)fill);
+        base = shfl_u64(base, 0);
+        const u32 words = 3 * fill;
+        for (u32 i = lane_id(); i < words; i += WAVE) {
+            const u64 w = 3 * base + i;
+            if (w < 3 * cap) tri[w] = stage[i];
+        }
+        wave_lds_sync();
+        fill = 0;
+    }
+
+    __device__ __forceinline__ void push(bool hit, u32 a, u32 b, u32 c, u32 *tri, u64 cap, u64 *acc) {
+        if (!EMIT) return;
+        const u64 bal = __ballot(hit);
+        if (!bal) return;
+        if (hit) {
+            const u32 i = 3 * (fill + __popcll(bal & lanemask_lt()));
+            stage[i + 0] = a;
+            stage[i + 1] = b;
+            stage[i + 2] = c;
+        }
+        fill += __popcll(bal);
+        if (fill >= STAGE_TRI - WAVE) flush(tri, cap, acc);
+    }
+};
+
+__device__ __forceinline__ void flush_counts(u64 cnt, u64 hsh, u64 *acc) {
+    cnt = wave_sum_u64(cnt);
+    hsh = wave_sum_u64(hsh);
+    if (lane_id() == 0 && cnt) {
+        atomicAdd((unsigned long long *)&acc[0], (unsigned long long)cnt);
+        atomicAdd((unsigned long long *)&acc[1], (unsigned long long)hsh);
+    }
+}
+
+// Light items [k0, k1): each wavefront takes a contiguous run of items.
 // acc: [0] count, [1] digest, [2] paper work, [3] output cursor
 template <int ALGO, bool EMIT>
-__global__ __launch_bounds__(PB) void k_probe(GView g, const u32 *cseed, const u32 *cstart, const u64 *cpre,
-                                              u64 ncap, u64 k0, u64 k1, u32 *tri, u64 cap, u64 *acc) {
+__global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, const u64 *cabs, const u64 *cpre,
+                                                    u64 ncap, u64 k0, u64 k1, u32 *tri, u64 cap, u64 *acc) {
     const int lane = lane_id();
     const u64 gw = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
@@ -103,54 +313,39 @@ __global__ __launch_bounds__(PB) void k_probe(GView g, const u32 *cseed, const u
     const u64 per = (((span + nw - 1) / nw) + WAVE - 1) & ~(u64)(WAVE - 1);
     const u64 wb = k0 + gw * per;
     const u64 we = (wb + per < k1) ? wb + per : k1;
+    const u32 *SA = Form<ALGO>::scan_adj(g);
+    __shared__ u32 stage_lds[PB / WAVE][3 * STAGE_TRI];
+    WaveEmitter<EMIT> em(stage_lds[threadIdx.x / WAVE]);
     u64 cnt = 0, hsh = 0;
     if (wb < we) {
-        // seed of the wave's first item: last c with cpre[c] <= wb
         u64 c_lo = upper_bound_dev<u64>(cpre, 0, ncap + 1, wb) - 1;
         for (u64 kb = wb; kb < we; kb += WAVE) {
             const u64 k = kb + lane;
             const bool act = k < we;
-            const u64 P = (c_lo + lane <= ncap) ? cpre[c_lo + lane] : ~0ull;
-            int lo = 0;
-#pragma unroll
-            for (int st = 32; st > 0; st >>= 1) {
-                u64 pv = shfl_u64(P, lo + st);
-                if (pv <= k) lo += st;
-            }
-            const u64 c = c_lo + lo;
-            const u64 rel = k - shfl_u64(P, lo);
+            u64 rel;
+            const u64 c = seed_of_item(cpre, ncap, c_lo, k, rel);
             bool hit = false;
             u32 a = 0, b = 0, cc = 0;
             if (act) {
-                const u64 e = cseed[c];
-                Seed<ALGO> sd(g, e);
-                const u32 y = sd.S[sd.s_lo + cstart[c] + rel];
-                const u64 j = lower_bound_dev<u32>(sd.T, sd.t_lo, sd.t_hi, y);
-                if (j < sd.t_hi && sd.T[j] == y) {
+                const u32 e = cseed[c];
+                const u32 y = SA[cabs[c] + rel];
+                u32 p;
+                u64 t_lo, t_hi;
+                const u32 *T;
+                if (ALGO == 0) { p = g.row_b[e]; T = g.adj_b; t_lo = e + 1; t_hi = g.off_b[p + 1]; }
+                else if (ALGO == 1) { p = g.row_f[e]; T = g.adj_f; t_lo = e + 1; t_hi = g.off_f[p + 1]; }
+                else { p = g.row_f[e]; T = g.adj_b; t_lo = g.off_b[p]; t_hi = g.off_b[p + 1]; }
+                const u64 j = lower_bound_dev<u32>(T, t_lo, t_hi, y);
+                if (j < t_hi && T[j] == y) {
                     hit = true;
-                    a = g.inv[sd.p]; b = g.inv[sd.x]; cc = g.inv[y];
+                    const u32 x = Form<ALGO>::seed_adj(g)[e];
+                    a = g.inv[p]; b = g.inv[x]; cc = g.inv[y];
                     canon3(a, b, cc);
                     cnt += 1;
                     hsh += tri_digest(a, b, cc);
                 }
             }
-            if (EMIT) {
-                const u64 bal = __ballot(hit);
-                if (bal) {
-                    u64 base = 0;
-                    if (lane == 0) base = atomicAdd((unsigned long long *)&acc[3], (unsigned long long)__popcll(bal));
-                    base = shfl_u64(base, 0);
-                    if (hit) {
-                        const u64 pos = base + __popcll(bal & lanemask_lt());
-                        if (pos < cap) {
-                            tri[3 * pos + 0] = a;
-                            tri[3 * pos + 1] = b;
-                            tri[3 * pos + 2] = cc;
-                        }
-                    }
-                }
-            }
-            // seed of the next chunk's first item
+            em.push(hit, a, b, cc, tri, cap, acc);
             const u64 c_last = shfl_u64(c, WAVE - 1);
             const u64 nk = kb + WAVE;
             if (nk < we) {
@@ -159,12 +354,91 @@ __global__ __launch_bounds__(PB) void k_probe(GView g, const u32 *cseed, const u
             }
         }
     }
-    cnt = wave_sum_u64(cnt);
-    hsh = wave_sum_u64(hsh);
-    if (lane == 0 && cnt) {
-        atomicAdd((unsigned long long *)&acc[0], (unsigned long long)cnt);
-        atomicAdd((unsigned long long *)&acc[1], (unsigned long long)hsh);
+    em.flush(tri, cap, acc);
+    flush_counts(cnt, hsh, acc);
+}
+
+// Heavy tasks: one workgroup stages the pivot's list in LDS, then its
+// wavefronts share the task's items.  Items are clipped to [k0, k1).
+template <int ALGO, bool EMIT>
+__global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, u64 ntasks, const u32 *cseed,
+                                                    const u64 *cabs, const u64 *cpre, u64 k0, u64 k1, u32 *tri,
+                                                    u64 cap, u64 *acc) {
+    extern __shared__ u32 lds[];  // LDS_WORDS for the pivot list, then one stage per wavefront
+    const int lane = lane_id(), wid = threadIdx.x / WAVE, nwv = blockDim.x / WAVE;
+    WaveEmitter<EMIT> em(lds + LDS_WORDS + wid * 3 * STAGE_TRI);
+    const u32 *SA = Form<ALGO>::scan_adj(g);
+    const u64 *po = Form<ALGO>::piv_off(g);
+    const u32 *pa = Form<ALGO>::piv_adj(g);
+    u64 cnt = 0, hsh = 0;
+    for (u64 ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+        const Task tk = tasks[ti];
+        const u64 a = tk.a > k0 ? tk.a : k0;
+        const u64 b = tk.b < k1 ? tk.b : k1;
+        if (a >= b) continue;  // uniform across the block
+        const u32 p = tk.p;
+        const u64 t0 = po[p], t1 = po[p + 1];
+        const u32 tmin = pa[t0], tmax = pa[t1 - 1];
+        const u32 tlen = (u32)(t1 - t0);
+        if (tk.mode == MODE_BITMAP) {
+            const u32 words = ((tmax - tmin) >> 5) + 1;
+            for (u32 i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0u;
+            __syncthreads();
+            for (u64 i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+                const u32 v = pa[i] - tmin;
+                atomicOr(&lds[v >> 5], 1u << (v & 31));
+            }
+            __syncthreads();
+        } else if (tk.mode == MODE_ARRAY) {
+            for (u32 i = threadIdx.x; i < tlen; i += blockDim.x) lds[i] = pa[t0 + i];
+            __syncthreads();
+        }
+        const u64 span = b - a;
+        const u64 per = (((span + nwv - 1) / nwv) + WAVE - 1) & ~(u64)(WAVE - 1);
+        const u64 wb = a + (u64)wid * per;
+        const u64 we = (wb + per < b) ? wb + per : b;
+        if (wb < we) {
+            u64 c_lo = upper_bound_dev<u64>(cpre, tk.cb, tk.ce + 1, wb) - 1;
+            for (u64 kb = wb; kb < we; kb += WAVE) {
+                const u64 k = kb + lane;
+                const bool act = k < we;
+                u64 rel;
+                const u64 c = seed_of_item(cpre, tk.ce, c_lo, k, rel);
+                bool hit = false;
+                u32 xa = 0, xb = 0, xc = 0;
+                if (act) {
+                    const u32 y = SA[cabs[c] + rel];
+                    if (tk.mode == MODE_BITMAP) {
+                        const u32 v = y - tmin;
+                        hit = y >= tmin && y <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
+                    } else if (tk.mode == MODE_ARRAY) {
+                        const u64 j = lower_bound_dev<u32>(lds, 0, tlen, y);
+                        hit = j < tlen && lds[j] == y;
+                    } else {
+                        const u64 j = lower_bound_dev<u32>(pa, t0, t1, y);
+                        hit = j < t1 && pa[j] == y;
+                    }
+                    if (hit) {
+                        const u32 x = Form<ALGO>::seed_adj(g)[cseed[c]];
+                        xa = g.inv[p]; xb = g.inv[x]; xc = g.inv[y];
+                        canon3(xa, xb, xc);
+                        cnt += 1;
+                        hsh += tri_digest(xa, xb, xc);
+                    }
+                }
+                em.push(hit, xa, xb, xc, tri, cap, acc);
+                const u64 c_last = shfl_u64(c, WAVE - 1);
+                const u64 nk = kb + WAVE;
+                if (nk < we) {
+                    c_lo = c_last;
+                    if (c_lo + 1 <= tk.ce && cpre[c_lo + 1] <= nk) c_lo++;
+                }
+            }
+        }
+        __syncthreads();  // the next task overwrites LDS
     }
+    em.flush(tri, cap, acc);
+    flush_counts(cnt, hsh, acc);
 }
 
 __global__ __launch_bounds__(PB) void k_cost(const u64 *off_f, const u64 *off_b, u32 n, int algo, u64 *out) {
@@ -184,28 +458,122 @@ GView view_of(const tl_csr *g) {
     return GView{g->off_f, g->off_b, g->adj_f, g->adj_b, g->row_f, g->row_b, g->inv, g->m};
 }
 
+// Everything a listing's probe phase needs, produced by the plan.
+struct Plan {
+    DevBuf cseed, cabs, cpre, tasks;
+    u64 ncomp = 0;    // compacted seeds
+    u64 w_light = 0;  // light items [0, w_light)
+    u64 w_total = 0;  // all items
+    u64 ntasks = 0;
+};
+
 template <int ALGO>
-void launch_plan(const GView &v, u32 plo, u32 phi, u32 *len, u32 *start, u32 *flag, u64 *acc, hipStream_t s) {
-    hipLaunchKernelGGL((k_plan<ALGO>), dim3(grid_for(v.m, PB, (unsigned)tl_num_cus() * 16)), dim3(PB), 0, s, v, plo,
-                       phi, len, start, flag, acc);
+void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t s, Plan &P) {
+    const u64 m = v.m;
+    const unsigned gm = grid_for(m, PB, (unsigned)tl_num_cus() * 16);
+    const unsigned gn = grid_for(n, PB, (unsigned)tl_num_cus() * 16);
+    DevBuf len(m * sizeof(u32), s), sabs(m * sizeof(u64), s), wp((u64)n * sizeof(u64), s);
+    TL_HIP(hipMemsetAsync(wp.p, 0, (u64)n * sizeof(u64), s));
+    hipLaunchKernelGGL((k_plan<ALGO>), dim3(gm), dim3(PB), 0, s, v, plo, phi, len.as<u32>(), sabs.as<u64>(),
+                       wp.as<u64>(), d_acc);
     TL_HIP(hipGetLastError());
+    DevBuf mode((u64)n * sizeof(u32), s), ntask((u64)n * sizeof(u32), s), slice((u64)n * sizeof(u64), s);
+    hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), mode.as<u32>(),
+                       ntask.as<u32>(), slice.as<u64>());
+    TL_HIP(hipGetLastError());
+    DevBuf flags(m * sizeof(u64), s), pos((m + 1) * sizeof(u64), s);
+    hipLaunchKernelGGL((k_seed_class<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), mode.as<u32>(),
+                       flags.as<u64>());
+    TL_HIP(hipGetLastError());
+    scan_u64_to_u64(flags.as<u64>(), pos.as<u64>(), m, s);
+    P.cseed = DevBuf(m * sizeof(u32), s);
+    P.cabs = DevBuf(m * sizeof(u64), s);
+    u32 *clen = (u32 *)flags.p;  // the flags are consumed by the scan: reuse them as lengths
+    TL_HIP(hipMemsetAsync(clen, 0, m * sizeof(u32), s));
+    hipLaunchKernelGGL(k_compact, dim3(gm), dim3(PB), 0, s, m, len.as<u32>(), sabs.as<u64>(), pos.as<u64>(),
+                       P.cseed.as<u32>(), P.cabs.as<u64>(), clen);
+    TL_HIP(hipGetLastError());
+    P.cpre = DevBuf((m + 1) * sizeof(u64), s);
+    scan_u32_to_u64(clen, P.cpre.as<u64>(), m, s);
+    DevBuf tpos(((u64)n + 1) * sizeof(u64), s);
+    scan_u32_to_u64(ntask.as<u32>(), tpos.as<u64>(), n, s);
+    u64 h_pos = 0, h_nt = 0;
+    TL_HIP(hipMemcpyAsync(&h_pos, pos.as<u64>() + m, sizeof(u64), hipMemcpyDeviceToHost, s));
+    TL_HIP(hipMemcpyAsync(&h_nt, tpos.as<u64>() + n, sizeof(u64), hipMemcpyDeviceToHost, s));
+    TL_HIP(hipStreamSynchronize(s));
+    const u64 nl = h_pos & 0xffffffffull, nh = h_pos >> 32;
+    P.ncomp = nl + nh;
+    P.ntasks = h_nt;
+    if (h_nt) {
+        P.tasks = DevBuf(h_nt * sizeof(Task), s);
+        hipLaunchKernelGGL((k_make_tasks<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, mode.as<u32>(), ntask.as<u32>(),
+                           slice.as<u64>(), tpos.as<u64>(), pos.as<u64>(), P.cpre.as<u64>(), m,
+                           P.tasks.as<Task>());
+        TL_HIP(hipGetLastError());
+    }
+    u64 h_w[2] = {0, 0};
+    TL_HIP(hipMemcpyAsync(&h_w[0], P.cpre.as<u64>() + nl, sizeof(u64), hipMemcpyDeviceToHost, s));
+    TL_HIP(hipMemcpyAsync(&h_w[1], P.cpre.as<u64>() + m, sizeof(u64), hipMemcpyDeviceToHost, s));
+    TL_HIP(hipStreamSynchronize(s));
+    P.w_light = h_w[0];
+    P.w_total = h_w[1];
 }
 
 template <int ALGO>
-void launch_probe(const GView &v, const u32 *cseed, const u32 *cstart, const u64 *cpre, u64 k0, u64 k1, u32 *tri,
-                  u64 cap, bool emit, u64 *acc, hipStream_t s) {
-    const u64 waves_needed = (k1 - k0 + WAVE - 1) / WAVE;
-    const unsigned max_blocks = (unsigned)tl_num_cus() * 8;
-    u64 blocks = (waves_needed + (PB / WAVE) - 1) / (PB / WAVE);
-    if (blocks > max_blocks) blocks = max_blocks;
-    if (blocks < 1) blocks = 1;
-    if (emit)
-        hipLaunchKernelGGL((k_probe<ALGO, true>), dim3((unsigned)blocks), dim3(PB), 0, s, v, cseed, cstart, cpre,
-                           v.m, k0, k1, tri, cap, acc);
-    else
-        hipLaunchKernelGGL((k_probe<ALGO, false>), dim3((unsigned)blocks), dim3(PB), 0, s, v, cseed, cstart, cpre,
-                           v.m, k0, k1, tri, cap, acc);
-    TL_HIP(hipGetLastError());
+void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, u32 *tri, u64 cap, bool emit, u64 *acc,
+                  hipStream_t s) {
+    // light part
+    const u64 l0 = k0, l1 = k1 < P.w_light ? k1 : P.w_light;
+    if (l0 < l1) {
+        const u64 waves_needed = (l1 - l0 + WAVE - 1) / WAVE;
+        u64 blocks = (waves_needed + (PB / WAVE) - 1) / (PB / WAVE);
+        const u64 max_blocks = (u64)tl_num_cus() * 8;
+        if (blocks > max_blocks) blocks = max_blocks;
+        if (blocks < 1) blocks = 1;
+        if (emit)
+            hipLaunchKernelGGL((k_probe_light<ALGO, true>), dim3((unsigned)blocks), dim3(PB), 0, s, v,
+                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(), P.ncomp, l0, l1, tri, cap, acc);
+        else
+            hipLaunchKernelGGL((k_probe_light<ALGO, false>), dim3((unsigned)blocks), dim3(PB), 0, s, v,
+                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(), P.ncomp, l0, l1, tri, cap, acc);
+        TL_HIP(hipGetLastError());
+    }
+    // heavy part
+    const u64 h0 = k0 > P.w_light ? k0 : P.w_light, h1 = k1;
+    if (h0 < h1 && P.ntasks) {
+        u64 blocks = P.ntasks;
+        const u64 max_blocks = (u64)tl_num_cus() * 2;
+        if (blocks > max_blocks) blocks = max_blocks;
+        if (emit)
+            hipLaunchKernelGGL((k_probe_heavy<ALGO, true>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
+                               P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(),
+                               h0, h1, tri, cap, acc);
+        else
+            hipLaunchKernelGGL((k_probe_heavy<ALGO, false>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
+                               P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(),
+                               h0, h1, tri, cap, acc);
+        TL_HIP(hipGetLastError());
+    }
+}
+
+bool debug_enabled() {
+    static const bool on = [] {
+        const char *e = getenv("TL_DEBUG");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
+// Allow the heavy-pivot kernels their full dynamic LDS (once per process).
+void prepare_kernels() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const void *fns[] = {(const void *)k_probe_heavy<0, true>, (const void *)k_probe_heavy<0, false>,
+                             (const void *)k_probe_heavy<1, true>, (const void *)k_probe_heavy<1, false>,
+                             (const void *)k_probe_heavy<2, true>, (const void *)k_probe_heavy<2, false>};
+        for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, HEAVY_LDS_BYTES);
+        (void)hipGetLastError();
+    });
 }
 
 }  // namespace
@@ -236,40 +604,36 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     if (phi > g->n) phi = g->n;
     if (m == 0 || plo >= phi) return TL_OK;
     const GView v = view_of(g);
+    prepare_kernels();
 
     DevBuf acc(4 * sizeof(u64), s);
     TL_HIP(hipMemsetAsync(acc.p, 0, 4 * sizeof(u64), s));
     u64 *d_acc = acc.as<u64>();
 
-    // ---- plan: window per seed edge, compaction, work prefix
-    PhaseTimer plan_timer(TL_PHASE_PLAN, s);
-    DevBuf len(m * sizeof(u32), s), start(m * sizeof(u32), s), flag(m * sizeof(u32), s);
-    DevBuf pos((m + 1) * sizeof(u64), s);
-    if (algo == 0) launch_plan<0>(v, plo, phi, len.as<u32>(), start.as<u32>(), flag.as<u32>(), d_acc, s);
-    else if (algo == 1) launch_plan<1>(v, plo, phi, len.as<u32>(), start.as<u32>(), flag.as<u32>(), d_acc, s);
-    else launch_plan<2>(v, plo, phi, len.as<u32>(), start.as<u32>(), flag.as<u32>(), d_acc, s);
-    scan_u32_to_u64(flag.as<u32>(), pos.as<u64>(), m, s);
-    DevBuf cseed(m * sizeof(u32), s), cstart(m * sizeof(u32), s);
-    u32 *clen = flag.as<u32>();  // flags are consumed by the scan above; reuse as compacted lengths
-    TL_HIP(hipMemsetAsync(clen, 0, m * sizeof(u32), s));
-    hipLaunchKernelGGL(k_compact_seeds, dim3(grid_for(m, 256, (unsigned)tl_num_cus() * 16)), dim3(256), 0, s,
-                       len.as<u32>(), start.as<u32>(), pos.as<u64>(), m, cseed.as<u32>(), cstart.as<u32>(), clen);
-    TL_HIP(hipGetLastError());
-    DevBuf cpre((m + 1) * sizeof(u64), s);
-    scan_u32_to_u64(clen, cpre.as<u64>(), m, s);
-    plan_timer.stop();
-    u64 h_total = 0, h_work = 0;
-    TL_HIP(hipMemcpyAsync(&h_total, cpre.as<u64>() + m, sizeof(u64), hipMemcpyDeviceToHost, s));
+    // ---- plan: windows, heavy/light classes, compaction, work prefix, tasks
+    Plan P;
+    {
+        PhaseTimer plan_timer(TL_PHASE_PLAN, s);
+        if (algo == 0) make_plan<0>(v, g->n, plo, phi, d_acc, s, P);
+        else if (algo == 1) make_plan<1>(v, g->n, plo, phi, d_acc, s, P);
+        else make_plan<2>(v, g->n, plo, phi, d_acc, s, P);
+    }
+    u64 h_work = 0;
     TL_HIP(hipMemcpyAsync(&h_work, d_acc + 2, sizeof(u64), hipMemcpyDeviceToHost, s));
     TL_HIP(hipStreamSynchronize(s));
     out->work = h_work;
-    out->scanned = h_total;
+    out->scanned = P.w_total;
+    const u64 h_total = P.w_total;
+    if (debug_enabled())
+        fprintf(stderr, "[tl] list algo=%d m=%llu compacted=%llu light_items=%llu heavy_items=%llu tasks=%llu\n", algo,
+                (unsigned long long)m, (unsigned long long)P.ncomp, (unsigned long long)P.w_light,
+                (unsigned long long)(P.w_total - P.w_light), (unsigned long long)P.ntasks);
 
     auto probe = [&](u64 k0, u64 k1, u32 *dst, u64 dcap, bool emit) {
         PhaseTimer t(TL_PHASE_PROBE, s);
-        if (algo == 0) launch_probe<0>(v, cseed.as<u32>(), cstart.as<u32>(), cpre.as<u64>(), k0, k1, dst, dcap, emit, d_acc, s);
-        else if (algo == 1) launch_probe<1>(v, cseed.as<u32>(), cstart.as<u32>(), cpre.as<u64>(), k0, k1, dst, dcap, emit, d_acc, s);
-        else launch_probe<2>(v, cseed.as<u32>(), cstart.as<u32>(), cpre.as<u64>(), k0, k1, dst, dcap, emit, d_acc, s);
+        if (algo == 0) launch_probe<0>(v, P, k0, k1, dst, dcap, emit, d_acc, s);
+        else if (algo == 1) launch_probe<1>(v, P, k0, k1, dst, dcap, emit, d_acc, s);
+        else launch_probe<2>(v, P, k0, k1, dst, dcap, emit, d_acc, s);
     };
 
     int rc = TL_OK;

@@ -40,14 +40,26 @@ __global__ void k_bin_count(const u64 *off, u32 nrows, u32 *counts, u32 *uniq) {
     if (threadIdx.x < NBINS && c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], c[threadIdx.x]);
 }
 
-__global__ void k_bin_fill(const u64 *off, u32 nrows, const u32 *bin_start, u32 *cursor, u32 *rows) {
-    GRID_STRIDE(r, nrows) {
-        u64 len = off[r + 1] - off[r];
-        int b = bin_of(len);
-        if (b) {
-            u32 pos = atomicAdd(&cursor[b], 1u);
-            rows[bin_start[b] + pos] = (u32)r;
+// Block-aggregated: one global atomic per bin per block.
+__global__ __launch_bounds__(256) void k_bin_fill(const u64 *off, u32 nrows, const u32 *bin_start, u32 *cursor,
+                                                  u32 *rows) {
+    __shared__ u32 cnt[NBINS], base[NBINS];
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    for (u64 r0 = (u64)blockIdx.x * blockDim.x; r0 < nrows; r0 += stride) {  // block-uniform
+        if (threadIdx.x < NBINS) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        const u64 r = r0 + threadIdx.x;
+        int b = 0;
+        u32 local = 0;
+        if (r < nrows) {
+            b = bin_of(off[r + 1] - off[r]);
+            if (b) local = atomicAdd(&cnt[b], 1u);
         }
+        __syncthreads();
+        if (threadIdx.x < NBINS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+        __syncthreads();
+        if (r < nrows && b) rows[bin_start[b] + base[b] + local] = (u32)r;
+        __syncthreads();
     }
 }
 

@@ -82,7 +82,7 @@ constexpr u32 LDS_BYTES = 128 * 1024;
 constexpr u32 LDS_WORDS = LDS_BYTES / 4;
 constexpr u64 LDS_BITS = (u64)LDS_BYTES * 8;
 constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + (HB / 64) * 3 * 128 * 4;  // + per-wavefront emit stages
-constexpr u64 HEAVY_MIN = 4096;    // items of a pivot before it gets a workgroup
+constexpr u64 HEAVY_MIN = 2048;    // items of a pivot before it gets a workgroup
 constexpr u64 SLICE_MIN = 16384;   // items per heavy task, at least
 
 enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2 };
@@ -156,13 +156,13 @@ __global__ void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *nta
             const u64 t0 = po[p], t1 = po[p + 1];
             const u64 tlen = t1 - t0;
             const u64 range = (u64)pa[t1 - 1] - pa[t0] + 1;
-            const u64 words = (range + 31) / 32;
             const bool bm_ok = range <= LDS_BITS;
             const bool arr_ok = tlen <= LDS_WORDS;
+            // the bitmap is kept clear between tasks, so marking and
+            // unmarking cost 2 |T| (the paper's set/reset of B)
             u64 stage;
-            if (bm_ok && (words <= 4 * tlen || words * 16 <= w)) { md = MODE_BITMAP; stage = words + tlen; }
-            else if (arr_ok) { md = MODE_ARRAY; stage = tlen; }
-            else if (bm_ok) { md = MODE_BITMAP; stage = words + tlen; }
+            if (bm_ok) { md = MODE_BITMAP; stage = 2 * tlen; }
+            else if (arr_ok) { md = MODE_ARRAY; stage = 2 * tlen; }
             else { md = MODE_GLOBAL; stage = 0; }
             sl = 16 * stage;
             if (sl < SLICE_MIN) sl = SLICE_MIN;
@@ -371,6 +371,8 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
     const u64 *po = Form<ALGO>::piv_off(g);
     const u32 *pa = Form<ALGO>::piv_adj(g);
     u64 cnt = 0, hsh = 0;
+    for (u32 i = threadIdx.x; i < LDS_WORDS; i += blockDim.x) lds[i] = 0u;  // B starts all false
+    __syncthreads();
     for (u64 ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
         const Task tk = tasks[ti];
         const u64 a = tk.a > k0 ? tk.a : k0;
@@ -381,9 +383,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         const u32 tmin = pa[t0], tmax = pa[t1 - 1];
         const u32 tlen = (u32)(t1 - t0);
         if (tk.mode == MODE_BITMAP) {
-            const u32 words = ((tmax - tmin) >> 5) + 1;
-            for (u32 i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0u;
-            __syncthreads();
             for (u64 i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
                 const u32 v = pa[i] - tmin;
                 atomicOr(&lds[v >> 5], 1u << (v & 31));
@@ -435,7 +434,15 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                 }
             }
         }
-        __syncthreads();  // the next task overwrites LDS
+        __syncthreads();  // every wavefront is done with the staged list
+        // reset B (or the staged array) so that LDS is all zero again
+        if (tk.mode == MODE_BITMAP) {
+            for (u64 i = t0 + threadIdx.x; i < t1; i += blockDim.x) lds[(pa[i] - tmin) >> 5] = 0u;
+            __syncthreads();
+        } else if (tk.mode == MODE_ARRAY) {
+            for (u32 i = threadIdx.x; i < tlen; i += blockDim.x) lds[i] = 0u;
+            __syncthreads();
+        }
     }
     em.flush(tri, cap, acc);
     flush_counts(cnt, hsh, acc);

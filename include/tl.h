@@ -107,7 +107,9 @@ int tl_cost(const tl_csr *g, tl_algo a, void *stream, uint64_t *cost);
  *   tri_dev != NULL: triangles are written to tri_dev (device, 3*cap
  *     uint32, row i = (a, b, c), a < b < c, original ids), in unspecified
  *     order.  If more than cap exist, TL_ECAPACITY is returned with
- *     out->count = the number needed (the buffer holds cap of them).
+ *     out->count = the number needed; the buffer's contents are then
+ *     unspecified.  The library also allocates a spill area of its own
+ *     (bounded by the launch shape, not by the graph) while listing.
  *   tri_dev == NULL, cb != NULL: triangles are streamed through cb in
  *     library-owned device chunks (see tl_set_chunk_triangles).
  *   both NULL: count, digest and work only.

@@ -22,13 +22,16 @@
 // LDS -- as the paper's boolean array B (a bitmap over T's rank window) when
 // that window fits, else as a sorted array -- and then tests each scanned
 // element with one (or log |T|) LDS reads.
+#include <algorithm>
 #include <cstdio>
+#include <vector>
 #include <cstdlib>
 #include <mutex>
 
 #include "tl_internal.h"
 #include "dev_util.h"
 #include "timing.h"
+#include "holes.h"
 
 namespace {
 
@@ -81,7 +84,7 @@ constexpr int HB = 1024;       // threads per block, heavy-pivot kernel
 constexpr u32 LDS_BYTES = 128 * 1024;
 constexpr u32 LDS_WORDS = LDS_BYTES / 4;
 constexpr u64 LDS_BITS = (u64)LDS_BYTES * 8;
-constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + (HB / 64) * 3 * 128 * 4;  // + per-wavefront emit stages
+constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES;
 constexpr u64 HEAVY_MIN = 2048;    // items of a pivot before it gets a workgroup
 constexpr u64 SLICE_MIN = 16384;   // items per heavy task, at least
 
@@ -229,66 +232,111 @@ __global__ void k_make_tasks(GView g, u32 n, const u32 *mode, const u32 *ntask, 
 
 // ---------------------------------------------------------------- probe
 
-// Finds, for each lane's item k in [kb, kb+64), the compacted seed c with
-// cpre[c] <= k < cpre[c+1], given c_lo = seed of item kb.  Returns c and
-// writes the item's offset inside the seed's window to rel.
-__device__ __forceinline__ u64 seed_of_item(const u64 *cpre, u64 ncap, u64 c_lo, u64 k, u64 &rel) {
-    const int lane = lane_id();
-    const u64 P = (c_lo + lane <= ncap) ? cpre[c_lo + lane] : ~0ull;
-    int lo = 0;
-#pragma unroll
-    for (int st = 32; st > 0; st >>= 1) {
-        u64 pv = shfl_u64(P, lo + st);
-        if (pv <= k) lo += st;
+// Walks a run of the flattened work space 64 items at a time and gives each
+// lane the compacted seed c with cpre[c] <= k < cpre[c+1] of its item k, and
+// the item's offset inside that seed's window.  When the whole chunk lies in
+// one seed (long windows) no search is needed; otherwise the chunk spans at
+// most 64 seeds starting at the current one, found by a binary search over
+// a 64-entry window of cpre held one entry per lane.
+struct SeedCursor {
+    const u64 *cpre;
+    u64 ncap;         // cpre[0..ncap] is readable
+    u64 c_lo;         // seed of the chunk's first item
+    u64 base, end;    // cpre[c_lo], cpre[c_lo + 1]
+
+    __device__ __forceinline__ SeedCursor(const u64 *cp, u64 lo, u64 nc, u64 first_item) : cpre(cp), ncap(nc) {
+        c_lo = upper_bound_dev<u64>(cpre, lo, ncap + 1, first_item) - 1;
+        base = cpre[c_lo];
+        end = cpre[c_lo + 1];
     }
-    rel = k - shfl_u64(P, lo);
-    return c_lo + lo;
-}
 
-// Per-wavefront staging of listed triangles in LDS: hits are appended with
-// a ballot, and a full stage is flushed with ONE cursor atomic and
-// coalesced stores, instead of one global atomic per iteration with a hit.
-constexpr u32 STAGE_TRI = 128;  // triangles per wavefront stage (>= 2 * 64)
+    __device__ __forceinline__ u64 locate(u64 kb, u64 k, u64 &rel) const {
+        if (end >= kb + WAVE) {  // wave-uniform
+            rel = k - base;
+            return c_lo;
+        }
+        const int lane = lane_id();
+        const u64 P = (c_lo + lane <= ncap) ? cpre[c_lo + lane] : ~0ull;
+        int lo = 0;
+#pragma unroll
+        for (int st = 32; st > 0; st >>= 1) {
+            u64 pv = shfl_u64(P, lo + st);
+            if (pv <= k) lo += st;
+        }
+        rel = k - shfl_u64(P, lo);
+        return c_lo + lo;
+    }
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+    // move to the seed of item nk, given c = seed of the last lane's item
+    __device__ __forceinline__ void advance(u64 nk, u64 c) {
+        if (nk < end) return;
+        c_lo = shfl_u64(c, WAVE - 1);
+        if (cpre[c_lo + 1] <= nk) c_lo++;
+        base = cpre[c_lo];
+        end = cpre[c_lo + 1];
+    }
+};
+
+// Where listed triangles go.  Positions come from a global cursor in blocks
+// of RESERVE triangles per wavefront (one atomic per block, not per hit).
+// Positions below cap land in the caller's buffer; the next spill_cap
+// positions in a library spill area; the unused tail of each wavefront's
+// last block is recorded as a hole, and a fix-up step moves spilled
+// triangles into the holes so that the output is exactly [0, count).
+constexpr u64 RESERVE = 1024;
+
+struct Out {
+    u32 *tri;
+    u64 cap;
+    u32 *spill;
+    u64 spill_cap;
+    u64 *acc;      // [0] count, [1] digest, [2] work, [3] cursor, [4] holes
+    Hole *holes;
+    u64 hole_cap;
+
+    __device__ __forceinline__ void put(u64 pos, u32 a, u32 b, u32 c) const {
+        u32 *d;
+        if (pos < cap) d = tri + 3 * pos;
+        else if (pos - cap < spill_cap) d = spill + 3 * (pos - cap);
+        else return;
+        d[0] = a;
+        d[1] = b;
+        d[2] = c;
+    }
+};
 
 template <bool EMIT>
 struct WaveEmitter {
-    u32 *stage;  // 3 * STAGE_TRI words of this wavefront's LDS
-    u32 fill = 0;
-    __device__ __forceinline__ explicit WaveEmitter(u32 *st) : stage(st) {}
+    u64 rb = 0, re = 0;  // wave-uniform reservation [rb, re)
 
-    __device__ __forceinline__ void flush(u32 *tri, u64 cap, u64 *acc) {
-        if (!EMIT || fill == 0) return;
-        wave_lds_sync();
-        u64 base = 0;
-        if (lane_id() == 0) base = atomicAdd((unsigned long long *)&acc[3], (unsigned long long)fill);
-        base = shfl_u64(base, 0);
-        const u32 words = 3 * fill;
-        for (u32 i = lane_id(); i < words; i += WAVE) {
-            const u64 w = 3 * base + i;
-            if (w < 3 * cap) tri[w] = stage[i];
-        }
-        wave_lds_sync();
-        fill = 0;
-    }
-
-    __device__ __forceinline__ void push(bool hit, u32 a, u32 b, u32 c, u32 *tri, u64 cap, u64 *acc) {
+    __device__ __forceinline__ void push(bool hit, u32 a, u32 b, u32 c, const Out &o) {
         if (!EMIT) return;
         const u64 bal = __ballot(hit);
         if (!bal) return;
-        if (hit) {
-            const u32 i = 3 * (fill + __popcll(bal & lanemask_lt()));
-            stage[i + 0] = a;
-            stage[i + 1] = b;
-            stage[i + 2] = c;
+        const u64 k = __popcll(bal);
+        const u64 idx = __popcll(bal & lanemask_lt());
+        const u64 avail = re - rb;
+        u64 pos;
+        if (avail >= k) {
+            pos = rb + idx;
+            rb += k;
+        } else {
+            u64 nb = 0;
+            if (lane_id() == 0) nb = atomicAdd((unsigned long long *)&o.acc[3], (unsigned long long)RESERVE);
+            nb = shfl_u64(nb, 0);
+            pos = idx < avail ? rb + idx : nb + (idx - avail);
+            rb = nb + (k - avail);
+            re = nb + RESERVE;
         }
-        fill += __popcll(bal);
-        if (fill >= STAGE_TRI - WAVE) flush(tri, cap, acc);
+        if (hit) o.put(pos, a, b, c);
+    }
+
+    __device__ __forceinline__ void finish(const Out &o) {
+        if (!EMIT || re == rb) return;
+        if (lane_id() == 0) {
+            const u64 h = atomicAdd((unsigned long long *)&o.acc[4], 1ull);
+            if (h < o.hole_cap) o.holes[h] = Hole{rb, re - rb};
+        }
     }
 };
 
@@ -302,10 +350,9 @@ __device__ __forceinline__ void flush_counts(u64 cnt, u64 hsh, u64 *acc) {
 }
 
 // Light items [k0, k1): each wavefront takes a contiguous run of items.
-// acc: [0] count, [1] digest, [2] paper work, [3] output cursor
 template <int ALGO, bool EMIT>
 __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, const u64 *cabs, const u64 *cpre,
-                                                    u64 ncap, u64 k0, u64 k1, u32 *tri, u64 cap, u64 *acc) {
+                                                    u64 ncap, u64 k0, u64 k1, Out o) {
     const int lane = lane_id();
     const u64 gw = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
@@ -314,16 +361,15 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, c
     const u64 wb = k0 + gw * per;
     const u64 we = (wb + per < k1) ? wb + per : k1;
     const u32 *SA = Form<ALGO>::scan_adj(g);
-    __shared__ u32 stage_lds[PB / WAVE][3 * STAGE_TRI];
-    WaveEmitter<EMIT> em(stage_lds[threadIdx.x / WAVE]);
+    WaveEmitter<EMIT> em;
     u64 cnt = 0, hsh = 0;
     if (wb < we) {
-        u64 c_lo = upper_bound_dev<u64>(cpre, 0, ncap + 1, wb) - 1;
+        SeedCursor cur(cpre, 0, ncap, wb);
         for (u64 kb = wb; kb < we; kb += WAVE) {
             const u64 k = kb + lane;
             const bool act = k < we;
             u64 rel;
-            const u64 c = seed_of_item(cpre, ncap, c_lo, k, rel);
+            const u64 c = cur.locate(kb, k, rel);
             bool hit = false;
             u32 a = 0, b = 0, cc = 0;
             if (act) {
@@ -345,31 +391,25 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, c
                     hsh += tri_digest(a, b, cc);
                 }
             }
-            em.push(hit, a, b, cc, tri, cap, acc);
-            const u64 c_last = shfl_u64(c, WAVE - 1);
-            const u64 nk = kb + WAVE;
-            if (nk < we) {
-                c_lo = c_last;
-                if (c_lo + 1 <= ncap && cpre[c_lo + 1] <= nk) c_lo++;
-            }
+            em.push(hit, a, b, cc, o);
+            cur.advance(kb + WAVE, c);
         }
     }
-    em.flush(tri, cap, acc);
-    flush_counts(cnt, hsh, acc);
+    em.finish(o);
+    flush_counts(cnt, hsh, o.acc);
 }
 
 // Heavy tasks: one workgroup stages the pivot's list in LDS, then its
 // wavefronts share the task's items.  Items are clipped to [k0, k1).
 template <int ALGO, bool EMIT>
 __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, u64 ntasks, const u32 *cseed,
-                                                    const u64 *cabs, const u64 *cpre, u64 k0, u64 k1, u32 *tri,
-                                                    u64 cap, u64 *acc) {
-    extern __shared__ u32 lds[];  // LDS_WORDS for the pivot list, then one stage per wavefront
+                                                    const u64 *cabs, const u64 *cpre, u64 k0, u64 k1, Out o) {
+    extern __shared__ u32 lds[];  // the pivot list: B as a bitmap, or a sorted array
     const int lane = lane_id(), wid = threadIdx.x / WAVE, nwv = blockDim.x / WAVE;
-    WaveEmitter<EMIT> em(lds + LDS_WORDS + wid * 3 * STAGE_TRI);
     const u32 *SA = Form<ALGO>::scan_adj(g);
     const u64 *po = Form<ALGO>::piv_off(g);
     const u32 *pa = Form<ALGO>::piv_adj(g);
+    WaveEmitter<EMIT> em;
     u64 cnt = 0, hsh = 0;
     for (u32 i = threadIdx.x; i < LDS_WORDS; i += blockDim.x) lds[i] = 0u;  // B starts all false
     __syncthreads();
@@ -397,12 +437,12 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         const u64 wb = a + (u64)wid * per;
         const u64 we = (wb + per < b) ? wb + per : b;
         if (wb < we) {
-            u64 c_lo = upper_bound_dev<u64>(cpre, tk.cb, tk.ce + 1, wb) - 1;
+            SeedCursor cur(cpre, tk.cb, tk.ce, wb);
             for (u64 kb = wb; kb < we; kb += WAVE) {
                 const u64 k = kb + lane;
                 const bool act = k < we;
                 u64 rel;
-                const u64 c = seed_of_item(cpre, tk.ce, c_lo, k, rel);
+                const u64 c = cur.locate(kb, k, rel);
                 bool hit = false;
                 u32 xa = 0, xb = 0, xc = 0;
                 if (act) {
@@ -425,13 +465,8 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                         hsh += tri_digest(xa, xb, xc);
                     }
                 }
-                em.push(hit, xa, xb, xc, tri, cap, acc);
-                const u64 c_last = shfl_u64(c, WAVE - 1);
-                const u64 nk = kb + WAVE;
-                if (nk < we) {
-                    c_lo = c_last;
-                    if (c_lo + 1 <= tk.ce && cpre[c_lo + 1] <= nk) c_lo++;
-                }
+                em.push(hit, xa, xb, xc, o);
+                cur.advance(kb + WAVE, c);
             }
         }
         __syncthreads();  // every wavefront is done with the staged list
@@ -444,8 +479,21 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             __syncthreads();
         }
     }
-    em.flush(tri, cap, acc);
-    flush_counts(cnt, hsh, acc);
+    em.finish(o);
+    flush_counts(cnt, hsh, o.acc);
+}
+
+// Copies spilled (or misplaced) triangles into holes: one move per block.
+
+__global__ void k_apply_moves(const Move *mv, u64 nmv, u32 *tri, u64 cap, const u32 *spill) {
+    for (u64 i = blockIdx.x; i < nmv; i += gridDim.x) {
+        const Move m = mv[i];
+        for (u64 w = threadIdx.x; w < 3 * m.len; w += blockDim.x) {
+            const u64 sp = 3 * m.src + w;
+            const u32 v = (sp < 3 * cap) ? tri[sp] : spill[sp - 3 * cap];
+            tri[3 * m.dst + w] = v;
+        }
+    }
 }
 
 __global__ __launch_bounds__(PB) void k_cost(const u64 *off_f, const u64 *off_b, u32 n, int algo, u64 *out) {
@@ -526,41 +574,69 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
     P.w_total = h_w[1];
 }
 
+// Largest grids the probe kernels are launched with; they bound the number
+// of wavefronts, hence of holes, per launch.
+inline u64 light_max_blocks() { return (u64)tl_num_cus() * 8; }
+inline u64 heavy_max_blocks() { return (u64)tl_num_cus() * 2; }
+inline u64 max_holes_per_probe() { return light_max_blocks() * (PB / WAVE) + heavy_max_blocks() * (HB / WAVE); }
+
 template <int ALGO>
-void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, u32 *tri, u64 cap, bool emit, u64 *acc,
-                  hipStream_t s) {
+void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, const Out &o, hipStream_t s) {
     // light part
     const u64 l0 = k0, l1 = k1 < P.w_light ? k1 : P.w_light;
     if (l0 < l1) {
         const u64 waves_needed = (l1 - l0 + WAVE - 1) / WAVE;
         u64 blocks = (waves_needed + (PB / WAVE) - 1) / (PB / WAVE);
-        const u64 max_blocks = (u64)tl_num_cus() * 8;
-        if (blocks > max_blocks) blocks = max_blocks;
+        if (blocks > light_max_blocks()) blocks = light_max_blocks();
         if (blocks < 1) blocks = 1;
         if (emit)
             hipLaunchKernelGGL((k_probe_light<ALGO, true>), dim3((unsigned)blocks), dim3(PB), 0, s, v,
-                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(), P.ncomp, l0, l1, tri, cap, acc);
+                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(), P.ncomp, l0, l1, o);
         else
             hipLaunchKernelGGL((k_probe_light<ALGO, false>), dim3((unsigned)blocks), dim3(PB), 0, s, v,
-                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(), P.ncomp, l0, l1, tri, cap, acc);
+                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(), P.ncomp, l0, l1, o);
         TL_HIP(hipGetLastError());
     }
     // heavy part
     const u64 h0 = k0 > P.w_light ? k0 : P.w_light, h1 = k1;
     if (h0 < h1 && P.ntasks) {
         u64 blocks = P.ntasks;
-        const u64 max_blocks = (u64)tl_num_cus() * 2;
-        if (blocks > max_blocks) blocks = max_blocks;
+        if (blocks > heavy_max_blocks()) blocks = heavy_max_blocks();
         if (emit)
             hipLaunchKernelGGL((k_probe_heavy<ALGO, true>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
                                P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(),
-                               h0, h1, tri, cap, acc);
+                               h0, h1, o);
         else
             hipLaunchKernelGGL((k_probe_heavy<ALGO, false>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
                                P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(),
-                               h0, h1, tri, cap, acc);
+                               h0, h1, o);
         TL_HIP(hipGetLastError());
     }
+}
+
+// After a probe with emission: count = triangles listed, reserved = cursor.
+// Triangles occupy [0, reserved) minus the holes; move the ones at or above
+// count into the holes below count so that the output is exactly [0, count).
+void fix_holes(const Out &o, u64 count, u64 reserved, u64 nholes, hipStream_t s) {
+    if (nholes == 0 || reserved == count) return;
+    TL_REQUIRE(nholes <= o.hole_cap, TL_EHIP, "internal: hole list overflow");
+    std::vector<Hole> holes(nholes);
+    TL_HIP(hipMemcpyAsync(holes.data(), o.holes, nholes * sizeof(Hole), hipMemcpyDeviceToHost, s));
+    TL_HIP(hipStreamSynchronize(s));
+    std::vector<Move> mv;
+    try {
+        mv = plan_hole_moves(std::move(holes), count, reserved);
+    } catch (const std::runtime_error &e) {
+        throw TlError{TL_EHIP, std::string("internal: ") + e.what()};
+    }
+    if (mv.empty()) return;
+    DevBuf dmv(mv.size() * sizeof(Move), s);
+    TL_HIP(hipMemcpyAsync(dmv.p, mv.data(), mv.size() * sizeof(Move), hipMemcpyHostToDevice, s));
+    const unsigned blocks = (unsigned)std::min<u64>(mv.size(), (u64)tl_num_cus() * 4);
+    hipLaunchKernelGGL(k_apply_moves, dim3(blocks), dim3(256), 0, s, dmv.as<Move>(), (u64)mv.size(), o.tri, o.cap,
+                       o.spill);
+    TL_HIP(hipGetLastError());
+    TL_HIP(hipStreamSynchronize(s));
 }
 
 bool debug_enabled() {
@@ -613,8 +689,9 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     const GView v = view_of(g);
     prepare_kernels();
 
-    DevBuf acc(4 * sizeof(u64), s);
-    TL_HIP(hipMemsetAsync(acc.p, 0, 4 * sizeof(u64), s));
+    constexpr int NACC = 8;
+    DevBuf acc(NACC * sizeof(u64), s);
+    TL_HIP(hipMemsetAsync(acc.p, 0, NACC * sizeof(u64), s));
     u64 *d_acc = acc.as<u64>();
 
     // ---- plan: windows, heavy/light classes, compaction, work prefix, tasks
@@ -636,40 +713,61 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
                 (unsigned long long)m, (unsigned long long)P.ncomp, (unsigned long long)P.w_light,
                 (unsigned long long)(P.w_total - P.w_light), (unsigned long long)P.ntasks);
 
-    auto probe = [&](u64 k0, u64 k1, u32 *dst, u64 dcap, bool emit) {
+    // output plumbing shared by the emitting modes
+    const bool emitting = (tri || cb) && h_total;
+    const u64 hole_cap = max_holes_per_probe();
+    DevBuf holes, spill, chunk;
+    Out o{nullptr, 0, nullptr, 0, d_acc, nullptr, hole_cap};
+    if (emitting) {
+        holes = DevBuf(hole_cap * sizeof(Hole), s);
+        o.holes = holes.as<Hole>();
+        o.spill_cap = hole_cap * RESERVE;
+        spill = DevBuf(o.spill_cap * 3 * sizeof(u32), s);
+        o.spill = spill.as<u32>();
+    }
+
+    auto probe = [&](u64 k0, u64 k1, bool emit) {
         PhaseTimer t(TL_PHASE_PROBE, s);
-        if (algo == 0) launch_probe<0>(v, P, k0, k1, dst, dcap, emit, d_acc, s);
-        else if (algo == 1) launch_probe<1>(v, P, k0, k1, dst, dcap, emit, d_acc, s);
-        else launch_probe<2>(v, P, k0, k1, dst, dcap, emit, d_acc, s);
+        if (algo == 0) launch_probe<0>(v, P, k0, k1, emit, o, s);
+        else if (algo == 1) launch_probe<1>(v, P, k0, k1, emit, o, s);
+        else launch_probe<2>(v, P, k0, k1, emit, o, s);
     };
 
     int rc = TL_OK;
-    u64 h_acc[4] = {0, 0, 0, 0};
+    u64 h_acc[NACC] = {0};
     if (h_total == 0) {
         // nothing to scan
     } else if (tri) {
-        probe(0, h_total, tri, cap, true);
+        o.tri = tri;
+        o.cap = cap;
+        probe(0, h_total, true);
         TL_HIP(hipMemcpyAsync(h_acc, d_acc, sizeof h_acc, hipMemcpyDeviceToHost, s));
         TL_HIP(hipStreamSynchronize(s));
         if (h_acc[0] > cap) rc = TL_ECAPACITY;
+        else fix_holes(o, h_acc[0], h_acc[3], h_acc[4], s);
     } else if (cb) {
         // each scanned element yields at most one triangle, so a slice of K
         // work items always fits a chunk of K triangles
         const u64 K = g_chunk_triangles;
-        DevBuf chunk(K * 3 * sizeof(u32), s);
+        chunk = DevBuf(K * 3 * sizeof(u32), s);
+        o.tri = chunk.as<u32>();
+        o.cap = K;
+        u64 prev_count = 0;
         for (u64 k0 = 0; k0 < h_total; k0 += K) {
             const u64 k1 = (h_total - k0 > K) ? k0 + K : h_total;
-            TL_HIP(hipMemsetAsync(d_acc + 3, 0, sizeof(u64), s));
-            probe(k0, k1, chunk.as<u32>(), K, true);
-            u64 got = 0;
-            TL_HIP(hipMemcpyAsync(&got, d_acc + 3, sizeof(u64), hipMemcpyDeviceToHost, s));
+            TL_HIP(hipMemsetAsync(d_acc + 3, 0, 2 * sizeof(u64), s));  // cursor and holes
+            probe(k0, k1, true);
+            TL_HIP(hipMemcpyAsync(h_acc, d_acc, sizeof h_acc, hipMemcpyDeviceToHost, s));
             TL_HIP(hipStreamSynchronize(s));
-            if (got && cb(chunk.as<u32>(), got, user) != 0) { rc = TL_EABORT; break; }
+            const u64 got = h_acc[0] - prev_count;
+            prev_count = h_acc[0];
+            fix_holes(o, got, h_acc[3], h_acc[4], s);
+            if (got && cb(o.tri, got, user) != 0) { rc = TL_EABORT; break; }
         }
         TL_HIP(hipMemcpyAsync(h_acc, d_acc, sizeof h_acc, hipMemcpyDeviceToHost, s));
         TL_HIP(hipStreamSynchronize(s));
     } else {
-        probe(0, h_total, nullptr, 0, false);
+        probe(0, h_total, false);
         TL_HIP(hipMemcpyAsync(h_acc, d_acc, sizeof h_acc, hipMemcpyDeviceToHost, s));
         TL_HIP(hipStreamSynchronize(s));
     }

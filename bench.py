@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--workload", default="chunglu20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -111,6 +113,15 @@ def main():
 
     def dev(a):
         return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to("cuda")
+
+    if args.copy_calibration_mib:
+        n_words = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n_words, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
+        del a, b
 
     src, dst = dev(g.src), dev(g.dst)
     dranks = {k: dev(r) for k, r in ranks.items()}

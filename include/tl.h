@@ -146,6 +146,11 @@ int tl_csr_copy_to_host(const tl_csr *g, uint64_t *off_fwd, uint32_t *adj_fwd,
 /* Release a handle and its device memory (NULL is a no-op). */
 void tl_csr_free(tl_csr *g);
 
+/* Device memory for handles and per-call scratch is cached by the library
+ * (one free list per stream) and reused by later calls.  This returns every
+ * cached block that is not in use to the driver; it waits for the device. */
+int tl_release_cached_memory(void);
+
 /* Triangles per library-owned chunk in callback mode (default 2^24, i.e.
  * 192 MiB of uint32 triples).  Applies to later calls in this process. */
 int tl_set_chunk_triangles(uint64_t k);

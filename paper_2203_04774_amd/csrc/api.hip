@@ -1,8 +1,12 @@
 // C-ABI entry points of libtl (declared in include/tl.h).  Each call
 // validates its arguments on the host, runs the HIP pipeline on the
 // caller's stream and converts every failure into a status code.
+#include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
+#include <vector>
 
 #include "tl_internal.h"
 
@@ -11,24 +15,10 @@ namespace {
 thread_local std::string g_last_error;
 
 int g_num_cus = 0;
-std::once_flag g_pool_once;
-
-void configure_pool() {
-    // keep freed stream-ordered scratch cached in the device pool instead of
-    // returning it to the driver at every synchronisation
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = ~0ull;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-}
 
 template <class F>
 int guarded(F &&f) {
     try {
-        std::call_once(g_pool_once, configure_pool);
         return f();
     } catch (const TlError &e) {
         g_last_error = e.msg;
@@ -58,34 +48,155 @@ int tl_num_cus() {
     return g_num_cus;
 }
 
-void DevBuf::alloc() {
-    if (!bytes) return;
-    hipError_t e = hipMallocAsync(&p, bytes, s);
-    if (e != hipSuccess) {
-        p = nullptr;
-        (void)hipGetLastError();
-        throw TlError{TL_ENOMEM, "device scratch allocation of " + std::to_string(bytes) + " bytes failed"};
+// ---------------------------------------------------------------- pool
+
+namespace {
+
+struct Pool {
+    std::mutex mu;
+    std::map<hipStream_t, std::multimap<size_t, void *>> free_;   // per stream, by size
+    std::unordered_map<void *, std::pair<size_t, hipStream_t>> live_;
+    std::vector<std::pair<void *, size_t>> all_;
+};
+
+Pool &pool_of(int dev) {
+    static std::mutex mu;
+    static std::map<int, Pool *> pools;
+    std::lock_guard<std::mutex> lk(mu);
+    Pool *&p = pools[dev];
+    if (!p) p = new Pool();  // lives until process exit
+    return *p;
+}
+
+size_t round_bytes(size_t b) {
+    const size_t g = b < (1u << 20) ? 256 : (size_t)2 << 20;
+    return (b + g - 1) / g * g;
+}
+
+}  // namespace
+
+void *pool_get(size_t bytes, hipStream_t s) {
+    int dev = 0;
+    TL_HIP(hipGetDevice(&dev));
+    Pool &P = pool_of(dev);
+    bytes = round_bytes(bytes ? bytes : 1);
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto &fl = P.free_[s];
+    auto it = fl.lower_bound(bytes);
+    if (it != fl.end() && it->first <= 2 * bytes) {
+        void *p = it->second;
+        P.live_[p] = {it->first, s};
+        fl.erase(it);
+        return p;
     }
-}
-
-void DevBuf::release() {
-    if (p) (void)hipFreeAsync(p, s);
-    p = nullptr;
-}
-
-void *tl_dev_alloc(size_t bytes) {
     void *p = nullptr;
-    if (bytes == 0) bytes = 1;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
+        // give cached blocks of every stream back to the driver and retry
         (void)hipGetLastError();
-        throw TlError{TL_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+        (void)hipDeviceSynchronize();
+        for (auto &kv : P.free_)
+            for (auto &blk : kv.second) {
+                (void)hipFree(blk.second);
+                for (size_t i = 0; i < P.all_.size(); i++)
+                    if (P.all_[i].first == blk.second) { P.all_.erase(P.all_.begin() + i); break; }
+            }
+        P.free_.clear();
+        e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw TlError{TL_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+        }
     }
+    P.live_[p] = {bytes, s};
+    P.all_.push_back({p, bytes});
     return p;
 }
 
-void tl_dev_free(void *p) {
-    if (p) (void)hipFree(p);
+void pool_put(void *p) {
+    if (!p) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    Pool &P = pool_of(dev);
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto it = P.live_.find(p);
+    if (it == P.live_.end()) return;
+    P.free_[it->second.second].insert({it->second.first, p});
+    P.live_.erase(it);
+}
+
+void pool_trim() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    Pool &P = pool_of(dev);
+    std::lock_guard<std::mutex> lk(P.mu);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : P.free_)
+        for (auto &blk : kv.second) {
+            (void)hipFree(blk.second);
+            for (size_t i = 0; i < P.all_.size(); i++)
+                if (P.all_[i].first == blk.second) { P.all_.erase(P.all_.begin() + i); break; }
+        }
+    P.free_.clear();
+}
+
+void *tl_dev_alloc(size_t bytes, hipStream_t s) { return pool_get(bytes, s); }
+void tl_dev_free(void *p) { pool_put(p); }
+
+// ------------------------------------------------------- pinned staging
+
+namespace {
+constexpr size_t STAGE_BYTES = 4u << 20;
+
+char *stage_buffer() {
+    thread_local char *buf = nullptr;
+    if (!buf) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, STAGE_BYTES, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            throw TlError{TL_ENOMEM, "pinned staging allocation failed"};
+        }
+        buf = static_cast<char *>(p);  // kept for the thread's lifetime
+    }
+    return buf;
+}
+}  // namespace
+
+void d2h_sync(hipStream_t s, std::initializer_list<D2H> copies) {
+    size_t total = 0;
+    for (const D2H &c : copies) total += (c.bytes + 15) & ~size_t(15);
+    if (total > STAGE_BYTES) {
+        for (const D2H &c : copies)
+            if (c.bytes) TL_HIP(hipMemcpyAsync(c.host, c.dev, c.bytes, hipMemcpyDeviceToHost, s));
+        TL_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    char *st = stage_buffer();
+    size_t off = 0;
+    for (const D2H &c : copies) {
+        if (c.bytes) TL_HIP(hipMemcpyAsync(st + off, c.dev, c.bytes, hipMemcpyDeviceToHost, s));
+        off += (c.bytes + 15) & ~size_t(15);
+    }
+    TL_HIP(hipStreamSynchronize(s));
+    off = 0;
+    for (const D2H &c : copies) {
+        if (c.bytes) memcpy(c.host, st + off, c.bytes);
+        off += (c.bytes + 15) & ~size_t(15);
+    }
+}
+
+void h2d_sync(void *dev, const void *host, size_t bytes, hipStream_t s) {
+    if (!bytes) return;
+    if (bytes > STAGE_BYTES) {
+        TL_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s));
+        TL_HIP(hipStreamSynchronize(s));
+        return;
+    }
+    char *st = stage_buffer();
+    TL_HIP(hipStreamSynchronize(s));  // staging may still feed an earlier copy
+    memcpy(st, host, bytes);
+    TL_HIP(hipMemcpyAsync(dev, st, bytes, hipMemcpyHostToDevice, s));
+    TL_HIP(hipStreamSynchronize(s));
 }
 
 extern "C" {
@@ -150,7 +261,6 @@ int tl_csr_copy_to_host(const tl_csr *g, uint64_t *off_fwd, uint32_t *adj_fwd, u
 
 void tl_csr_free(tl_csr *g) {
     if (!g) return;
-    (void)hipDeviceSynchronize();
     tl_dev_free(g->off_f);
     tl_dev_free(g->adj_f);
     tl_dev_free(g->row_f);
@@ -159,6 +269,13 @@ void tl_csr_free(tl_csr *g) {
     tl_dev_free(g->row_b);
     tl_dev_free(g->inv);
     delete g;
+}
+
+int tl_release_cached_memory(void) {
+    return guarded([&] {
+        pool_trim();
+        return TL_OK;
+    });
 }
 
 int tl_set_chunk_triangles(uint64_t k) {

@@ -520,6 +520,7 @@ struct Plan {
     u64 w_light = 0;  // light items [0, w_light)
     u64 w_total = 0;  // all items
     u64 ntasks = 0;
+    u64 work = 0;     // the paper's work over the listed pivots
 };
 
 template <int ALGO>
@@ -553,9 +554,7 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
     DevBuf tpos(((u64)n + 1) * sizeof(u64), s);
     scan_u32_to_u64(ntask.as<u32>(), tpos.as<u64>(), n, s);
     u64 h_pos = 0, h_nt = 0;
-    TL_HIP(hipMemcpyAsync(&h_pos, pos.as<u64>() + m, sizeof(u64), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipMemcpyAsync(&h_nt, tpos.as<u64>() + n, sizeof(u64), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipStreamSynchronize(s));
+    d2h_sync(s, {{&h_pos, pos.as<u64>() + m, sizeof(u64)}, {&h_nt, tpos.as<u64>() + n, sizeof(u64)}});
     const u64 nl = h_pos & 0xffffffffull, nh = h_pos >> 32;
     P.ncomp = nl + nh;
     P.ntasks = h_nt;
@@ -566,10 +565,11 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
                            P.tasks.as<Task>());
         TL_HIP(hipGetLastError());
     }
-    u64 h_w[2] = {0, 0};
-    TL_HIP(hipMemcpyAsync(&h_w[0], P.cpre.as<u64>() + nl, sizeof(u64), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipMemcpyAsync(&h_w[1], P.cpre.as<u64>() + m, sizeof(u64), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipStreamSynchronize(s));
+    u64 h_w[3] = {0, 0, 0};
+    d2h_sync(s, {{&h_w[0], P.cpre.as<u64>() + nl, sizeof(u64)},
+                 {&h_w[1], P.cpre.as<u64>() + m, sizeof(u64)},
+                 {&h_w[2], d_acc + 2, sizeof(u64)}});
+    P.work = h_w[2];
     P.w_light = h_w[0];
     P.w_total = h_w[1];
 }
@@ -621,8 +621,7 @@ void fix_holes(const Out &o, u64 count, u64 reserved, u64 nholes, hipStream_t s)
     if (nholes == 0 || reserved == count) return;
     TL_REQUIRE(nholes <= o.hole_cap, TL_EHIP, "internal: hole list overflow");
     std::vector<Hole> holes(nholes);
-    TL_HIP(hipMemcpyAsync(holes.data(), o.holes, nholes * sizeof(Hole), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipStreamSynchronize(s));
+    d2h_sync(s, {{holes.data(), o.holes, nholes * sizeof(Hole)}});
     std::vector<Move> mv;
     try {
         mv = plan_hole_moves(std::move(holes), count, reserved);
@@ -631,7 +630,7 @@ void fix_holes(const Out &o, u64 count, u64 reserved, u64 nholes, hipStream_t s)
     }
     if (mv.empty()) return;
     DevBuf dmv(mv.size() * sizeof(Move), s);
-    TL_HIP(hipMemcpyAsync(dmv.p, mv.data(), mv.size() * sizeof(Move), hipMemcpyHostToDevice, s));
+    h2d_sync(dmv.p, mv.data(), mv.size() * sizeof(Move), s);
     const unsigned blocks = (unsigned)std::min<u64>(mv.size(), (u64)tl_num_cus() * 4);
     hipLaunchKernelGGL(k_apply_moves, dim3(blocks), dim3(256), 0, s, dmv.as<Move>(), (u64)mv.size(), o.tri, o.cap,
                        o.spill);
@@ -675,8 +674,7 @@ u64 cost_impl(const tl_csr *g, int algo, hipStream_t s) {
     }
     timer.stop();
     u64 h = 0;
-    TL_HIP(hipMemcpyAsync(&h, out.p, sizeof(u64), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipStreamSynchronize(s));
+    d2h_sync(s, {{&h, out.p, sizeof(u64)}});
     return h;
 }
 
@@ -702,10 +700,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
         else if (algo == 1) make_plan<1>(v, g->n, plo, phi, d_acc, s, P);
         else make_plan<2>(v, g->n, plo, phi, d_acc, s, P);
     }
-    u64 h_work = 0;
-    TL_HIP(hipMemcpyAsync(&h_work, d_acc + 2, sizeof(u64), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipStreamSynchronize(s));
-    out->work = h_work;
+    out->work = P.work;
     out->scanned = P.w_total;
     const u64 h_total = P.w_total;
     if (debug_enabled())
@@ -741,8 +736,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
         o.tri = tri;
         o.cap = cap;
         probe(0, h_total, true);
-        TL_HIP(hipMemcpyAsync(h_acc, d_acc, sizeof h_acc, hipMemcpyDeviceToHost, s));
-        TL_HIP(hipStreamSynchronize(s));
+        d2h_sync(s, {{h_acc, d_acc, sizeof h_acc}});
         if (h_acc[0] > cap) rc = TL_ECAPACITY;
         else fix_holes(o, h_acc[0], h_acc[3], h_acc[4], s);
     } else if (cb) {
@@ -757,19 +751,16 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
             const u64 k1 = (h_total - k0 > K) ? k0 + K : h_total;
             TL_HIP(hipMemsetAsync(d_acc + 3, 0, 2 * sizeof(u64), s));  // cursor and holes
             probe(k0, k1, true);
-            TL_HIP(hipMemcpyAsync(h_acc, d_acc, sizeof h_acc, hipMemcpyDeviceToHost, s));
-            TL_HIP(hipStreamSynchronize(s));
+            d2h_sync(s, {{h_acc, d_acc, sizeof h_acc}});
             const u64 got = h_acc[0] - prev_count;
             prev_count = h_acc[0];
             fix_holes(o, got, h_acc[3], h_acc[4], s);
             if (got && cb(o.tri, got, user) != 0) { rc = TL_EABORT; break; }
         }
-        TL_HIP(hipMemcpyAsync(h_acc, d_acc, sizeof h_acc, hipMemcpyDeviceToHost, s));
-        TL_HIP(hipStreamSynchronize(s));
+        d2h_sync(s, {{h_acc, d_acc, sizeof h_acc}});
     } else {
         probe(0, h_total, false);
-        TL_HIP(hipMemcpyAsync(h_acc, d_acc, sizeof h_acc, hipMemcpyDeviceToHost, s));
-        TL_HIP(hipStreamSynchronize(s));
+        d2h_sync(s, {{h_acc, d_acc, sizeof h_acc}});
     }
     out->count = h_acc[0];
     out->hash = h_acc[1];

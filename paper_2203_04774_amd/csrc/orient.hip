@@ -122,8 +122,7 @@ tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *
         TL_HIP(hipGetLastError());
     }
     u32 h_flag = 0;
-    TL_HIP(hipMemcpyAsync(&h_flag, flag.p, sizeof(u32), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipStreamSynchronize(s));
+    d2h_sync(s, {{&h_flag, flag.p, sizeof(u32)}});
     TL_REQUIRE(!(h_flag & 1u), TL_EINVAL, "rank is not a permutation of [0, n)");
     TL_REQUIRE(!(h_flag & 2u), TL_EINVAL, "an edge endpoint is >= n");
 
@@ -131,9 +130,9 @@ tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *
     tl_csr *g = own.g;
     g->n = n;
     TL_HIP(hipGetDevice(&g->device));
-    g->off_f = (u64 *)tl_dev_alloc((u64)(n + 1) * sizeof(u64));
-    g->off_b = (u64 *)tl_dev_alloc((u64)(n + 1) * sizeof(u64));
-    g->inv = (u32 *)tl_dev_alloc((u64)(n ? n : 1) * sizeof(u32));
+    g->off_f = (u64 *)tl_dev_alloc((u64)(n + 1) * sizeof(u64), s);
+    g->off_b = (u64 *)tl_dev_alloc((u64)(n + 1) * sizeof(u64), s);
+    g->inv = (u32 *)tl_dev_alloc((u64)(n ? n : 1) * sizeof(u32), s);
 
     // ---- 2-3. count rows, scan, scatter
     u32 *rowcnt = cnt.as<u32>();
@@ -145,11 +144,10 @@ tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *
     DevBuf raw_off((u64)(n + 1) * sizeof(u64), s);
     scan_u32_to_u64(rowcnt, raw_off.as<u64>(), n, s);
     u64 nnz_raw = 0;
-    TL_HIP(hipMemcpyAsync(&nnz_raw, raw_off.as<u64>() + n, sizeof(u64), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipStreamSynchronize(s));
+    d2h_sync(s, {{&nnz_raw, raw_off.as<u64>() + n, sizeof(u64)}});
 
-    u32 *raw_adj = (u32 *)tl_dev_alloc((nnz_raw ? nnz_raw : 1) * sizeof(u32));
-    u32 *raw_row = (u32 *)tl_dev_alloc((nnz_raw ? nnz_raw : 1) * sizeof(u32));
+    u32 *raw_adj = (u32 *)tl_dev_alloc((nnz_raw ? nnz_raw : 1) * sizeof(u32), s);
+    u32 *raw_row = (u32 *)tl_dev_alloc((nnz_raw ? nnz_raw : 1) * sizeof(u32), s);
     g->adj_f = raw_adj;  // owned by g from here (freed on error)
     g->row_f = raw_row;
     if (nnz_raw) {
@@ -164,25 +162,23 @@ tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *
     segmented_sort_unique(raw_off.as<u64>(), n, raw_adj, nnz_raw, n, uniq.as<u32>(), s);
     scan_u32_to_u64(uniq.as<u32>(), g->off_f, n, s);
     u64 m = 0;
-    TL_HIP(hipMemcpyAsync(&m, g->off_f + n, sizeof(u64), hipMemcpyDeviceToHost, s));
-    TL_HIP(hipStreamSynchronize(s));
+    d2h_sync(s, {{&m, g->off_f + n, sizeof(u64)}});
     g->m = m;
     if (m != nnz_raw) {
-        u32 *adj = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32));
-        u32 *row = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32));
+        u32 *adj = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
+        u32 *row = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
         hipLaunchKernelGGL(k_compact_rows, dim3(grid_n(nnz_raw)), dim3(256), 0, s, raw_off.as<u64>(), raw_adj,
                            raw_row, nnz_raw, uniq.as<u32>(), g->off_f, adj, row);
         TL_HIP(hipGetLastError());
-        TL_HIP(hipStreamSynchronize(s));
-        tl_dev_free(raw_adj);
+        tl_dev_free(raw_adj);  // stream-ordered reuse only
         tl_dev_free(raw_row);
         g->adj_f = adj;
         g->row_f = row;
     }
 
     // ---- 5. backward CSR (predecessor lists)
-    g->adj_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32));
-    g->row_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32));
+    g->adj_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
+    g->row_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
     if (n) TL_HIP(hipMemsetAsync(rowcnt, 0, (u64)n * sizeof(u32), s));
     if (m) {
         hipLaunchKernelGGL(k_count_targets, dim3(grid_n(m)), dim3(256), 0, s, g->adj_f, m, rowcnt);

@@ -194,14 +194,13 @@ void segmented_sort_unique(const u64 *off, u32 nrows, u32 *adj, u64 nnz, u32 n_v
     hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(256), 0, s, off, nrows, d_counts, uniq);
     TL_HIP(hipGetLastError());
     u32 h_counts[NBINS];
-    TL_HIP(hipMemcpyAsync(h_counts, d_counts, sizeof h_counts, hipMemcpyDeviceToHost, s));
-    TL_HIP(hipStreamSynchronize(s));
+    d2h_sync(s, {{h_counts, d_counts, sizeof h_counts}});
     u32 h_start[NBINS];
     u64 total = 0;
     for (int b = 0; b < NBINS; b++) { h_start[b] = (u32)total; total += h_counts[b]; }
     if (total == 0) return;
     DevBuf rows(total * sizeof(u32), s), starts(NBINS * sizeof(u32), s);
-    TL_HIP(hipMemcpyAsync(starts.p, h_start, sizeof h_start, hipMemcpyHostToDevice, s));
+    h2d_sync(starts.p, h_start, sizeof h_start, s);
     hipLaunchKernelGGL(k_bin_fill, dim3(g), dim3(256), 0, s, off, nrows, starts.as<u32>(), d_cursor,
                        rows.as<u32>());
     TL_HIP(hipGetLastError());

@@ -1,10 +1,28 @@
 // Per-phase kernel timing with HIP events on the caller's stream.
 #include <mutex>
+#include <vector>
 
 #include "tl_internal.h"
 #include "timing.h"
 
 namespace {
+// events are reused: creating and destroying them per call costs host time
+thread_local std::vector<hipEvent_t> t_events;
+
+hipEvent_t take_event() {
+    if (!t_events.empty()) {
+        hipEvent_t e = t_events.back();
+        t_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
 std::mutex g_mu;
 bool g_on = false;
 double g_ms[TL_NUM_PHASES] = {0, 0, 0, 0};
@@ -16,10 +34,9 @@ PhaseTimer::PhaseTimer(int phase, hipStream_t s) : phase_(phase), s_(s) {
         std::lock_guard<std::mutex> lk(g_mu);
         if (!g_on) return;
     }
-    if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
-        (void)hipGetLastError();
-        return;
-    }
+    a_ = take_event();
+    b_ = take_event();
+    if (!a_ || !b_) return;
     if (hipEventRecord(a_, s_) != hipSuccess) return;
     armed_ = true;
 }
@@ -38,8 +55,8 @@ PhaseTimer::~PhaseTimer() {
             g_calls[phase_] += 1;
         }
     }
-    if (a_) (void)hipEventDestroy(a_);
-    if (b_) (void)hipEventDestroy(b_);
+    if (a_) t_events.push_back(a_);
+    if (b_) t_events.push_back(b_);
 }
 
 extern "C" {

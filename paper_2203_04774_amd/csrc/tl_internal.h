@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <initializer_list>
 #include <string>
 
 #include "tl.h"
@@ -33,8 +34,15 @@ void tl_set_error(const std::string &msg);
 
 // ------------------------------------------------------------ device memory
 
-// Stream-ordered scratch allocation: freed on the same stream when the
-// object goes out of scope.
+// Device memory comes from a caching pool with one free list per stream: a
+// block returned while kernels on stream s may still use it is only handed
+// out again to work on the same stream, which runs after those kernels.
+// Blocks are released to the driver only by tl_release_cached_memory().
+void *pool_get(size_t bytes, hipStream_t s);
+void pool_put(void *p);
+void pool_trim();
+
+// Scratch owned by one library call, returned to the pool at scope exit.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
@@ -50,15 +58,25 @@ struct DevBuf {
         return *this;
     }
     ~DevBuf() { release(); }
-    void alloc();
-    void release();
+    void alloc() { if (bytes) p = pool_get(bytes, s); }
+    void release() { if (p) pool_put(p); p = nullptr; }
     template <class T> T *as() const { return static_cast<T *>(p); }
-    void *detach() { void *q = p; p = nullptr; return q; }
 };
 
-// Long-lived allocation (graph storage).
-void *tl_dev_alloc(size_t bytes);
+// Long-lived allocation (graph storage), also pooled.
+void *tl_dev_alloc(size_t bytes, hipStream_t s);
 void tl_dev_free(void *p);
+
+// Small host<->device transfers through a pinned staging area.
+struct D2H {
+    void *host;
+    const void *dev;
+    size_t bytes;
+};
+// Enqueue the copies on s, wait for the stream, then fill the host buffers.
+void d2h_sync(hipStream_t s, std::initializer_list<D2H> copies);
+// Copy host bytes to the device through pinned staging (waits for s).
+void h2d_sync(void *dev, const void *host, size_t bytes, hipStream_t s);
 
 // ------------------------------------------------------------ the handle
 

@@ -277,6 +277,30 @@ struct SeedCursor {
     }
 };
 
+constexpr int UN = 4;  // chunks per iteration when they share one seed window
+
+// UN independent branchless membership tests of y[j] in the sorted list
+// T[lo, hi) (the same list for all j), so their loads overlap.
+__device__ __forceinline__ void member_multi(const u32 *T, u64 lo, u64 hi, const u32 (&y)[UN], bool (&hit)[UN]) {
+    u64 n = hi - lo;
+    if (n == 0) {
+#pragma unroll
+        for (int j = 0; j < UN; j++) hit[j] = false;
+        return;
+    }
+    u64 b[UN];
+#pragma unroll
+    for (int j = 0; j < UN; j++) b[j] = lo;
+    while (n > 1) {
+        const u64 half = n >> 1;
+#pragma unroll
+        for (int j = 0; j < UN; j++) b[j] = (T[b[j] + half] <= y[j]) ? b[j] + half : b[j];
+        n -= half;
+    }
+#pragma unroll
+    for (int j = 0; j < UN; j++) hit[j] = T[b[j]] == y[j];
+}
+
 // Where listed triangles go.  Positions come from a global cursor in blocks
 // of RESERVE triangles per wavefront (one atomic per block, not per hit).
 // Positions below cap land in the caller's buffer; the next spill_cap
@@ -365,7 +389,48 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, c
     u64 cnt = 0, hsh = 0;
     if (wb < we) {
         SeedCursor cur(cpre, 0, ncap, wb);
-        for (u64 kb = wb; kb < we; kb += WAVE) {
+        u64 kb = wb;
+        while (kb < we) {
+            if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
+                // UN full chunks inside one seed window: one pivot list, UN
+                // overlapped searches
+                const u32 e = cseed[cur.c_lo];
+                const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
+                u32 p;
+                u64 t_lo, t_hi;
+                const u32 *T;
+                if (ALGO == 0) { p = g.row_b[e]; T = g.adj_b; t_lo = e + 1; t_hi = g.off_b[p + 1]; }
+                else if (ALGO == 1) { p = g.row_f[e]; T = g.adj_f; t_lo = e + 1; t_hi = g.off_f[p + 1]; }
+                else { p = g.row_f[e]; T = g.adj_b; t_lo = g.off_b[p]; t_hi = g.off_b[p + 1]; }
+                u32 y[UN];
+                bool h[UN];
+#pragma unroll
+                for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
+                member_multi(T, t_lo, t_hi, y, h);
+                u32 pinv = 0, xinv = 0;
+                bool have = false;
+#pragma unroll
+                for (int j = 0; j < UN; j++) {
+                    u32 a = 0, b = 0, cc = 0;
+                    if (__ballot(h[j])) {
+                        if (!have) {
+                            pinv = g.inv[p];
+                            xinv = g.inv[Form<ALGO>::seed_adj(g)[e]];
+                            have = true;
+                        }
+                        if (h[j]) {
+                            a = pinv; b = xinv; cc = g.inv[y[j]];
+                            canon3(a, b, cc);
+                            cnt += 1;
+                            hsh += tri_digest(a, b, cc);
+                        }
+                    }
+                    em.push(h[j], a, b, cc, o);
+                }
+                kb += UN * WAVE;
+                cur.advance(kb, cur.c_lo);
+                continue;
+            }
             const u64 k = kb + lane;
             const bool act = k < we;
             u64 rel;
@@ -392,7 +457,8 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, c
                 }
             }
             em.push(hit, a, b, cc, o);
-            cur.advance(kb + WAVE, c);
+            kb += WAVE;
+            cur.advance(kb, c);
         }
     }
     em.finish(o);
@@ -438,7 +504,50 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         const u64 we = (wb + per < b) ? wb + per : b;
         if (wb < we) {
             SeedCursor cur(cpre, tk.cb, tk.ce, wb);
-            for (u64 kb = wb; kb < we; kb += WAVE) {
+            const u32 pinv = g.inv[p];
+            auto member = [&](u32 y) -> bool {
+                if (tk.mode == MODE_BITMAP) {
+                    const u32 v = y - tmin;
+                    return y >= tmin && y <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
+                } else if (tk.mode == MODE_ARRAY) {
+                    const u64 j = lower_bound_dev<u32>(lds, 0, tlen, y);
+                    return j < tlen && lds[j] == y;
+                }
+                const u64 j = lower_bound_dev<u32>(pa, t0, t1, y);
+                return j < t1 && pa[j] == y;
+            };
+            u64 kb = wb;
+            while (kb < we) {
+                if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
+                    // UN full chunks inside one seed window: overlapped loads
+                    const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
+                    u32 y[UN];
+#pragma unroll
+                    for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
+                    u32 xinv = 0;
+                    bool have = false;
+#pragma unroll
+                    for (int j = 0; j < UN; j++) {
+                        const bool hit = member(y[j]);
+                        u32 xa = 0, xb = 0, xc = 0;
+                        if (__ballot(hit)) {
+                            if (!have) {
+                                xinv = g.inv[Form<ALGO>::seed_adj(g)[cseed[cur.c_lo]]];
+                                have = true;
+                            }
+                            if (hit) {
+                                xa = pinv; xb = xinv; xc = g.inv[y[j]];
+                                canon3(xa, xb, xc);
+                                cnt += 1;
+                                hsh += tri_digest(xa, xb, xc);
+                            }
+                        }
+                        em.push(hit, xa, xb, xc, o);
+                    }
+                    kb += UN * WAVE;
+                    cur.advance(kb, cur.c_lo);
+                    continue;
+                }
                 const u64 k = kb + lane;
                 const bool act = k < we;
                 u64 rel;
@@ -447,26 +556,18 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                 u32 xa = 0, xb = 0, xc = 0;
                 if (act) {
                     const u32 y = SA[cabs[c] + rel];
-                    if (tk.mode == MODE_BITMAP) {
-                        const u32 v = y - tmin;
-                        hit = y >= tmin && y <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
-                    } else if (tk.mode == MODE_ARRAY) {
-                        const u64 j = lower_bound_dev<u32>(lds, 0, tlen, y);
-                        hit = j < tlen && lds[j] == y;
-                    } else {
-                        const u64 j = lower_bound_dev<u32>(pa, t0, t1, y);
-                        hit = j < t1 && pa[j] == y;
-                    }
+                    hit = member(y);
                     if (hit) {
                         const u32 x = Form<ALGO>::seed_adj(g)[cseed[c]];
-                        xa = g.inv[p]; xb = g.inv[x]; xc = g.inv[y];
+                        xa = pinv; xb = g.inv[x]; xc = g.inv[y];
                         canon3(xa, xb, xc);
                         cnt += 1;
                         hsh += tri_digest(xa, xb, xc);
                     }
                 }
                 em.push(hit, xa, xb, xc, o);
-                cur.advance(kb + WAVE, c);
+                kb += WAVE;
+                cur.advance(kb, c);
             }
         }
         __syncthreads();  // every wavefront is done with the staged list

@@ -146,6 +146,23 @@ int tl_csr_copy_to_host(const tl_csr *g, uint64_t *off_fwd, uint32_t *adj_fwd,
 /* Release a handle and its device memory (NULL is a no-op). */
 void tl_csr_free(tl_csr *g);
 
+/*
+ * Launch tuning (results never depend on it).  Keys:
+ *   heavy_min            items of a pivot before it gets a workgroup (>= 1)
+ *   slice_min            items per heavy-pivot task, at least (>= 64)
+ *   slice_mult           tasks are also >= this many times the pivot's
+ *                        staging cost (>= 1)
+ *   heavy_blocks_per_cu  heavy-pivot workgroups launched per CU (1..64)
+ *   light_blocks_per_cu  light-pivot workgroups launched per CU (1..64)
+ *   queue                1: heavy tasks handed out by an atomic queue
+ *   splits               1: wavefront start seeds precomputed per task
+ * Values apply to later calls in this process; TL_TUNE_<KEY> environment
+ * variables (upper case) set the initial values.  Unknown keys or values
+ * out of range give TL_EINVAL.
+ */
+int tl_set_tuning(const char *key, uint64_t value);
+int tl_get_tuning(const char *key, uint64_t *value);
+
 /* Device memory for handles and per-call scratch is cached by the library
  * (one free list per stream) and reused by later calls.  This returns every
  * cached block that is not in use to the driver; it waits for the device. */

@@ -271,6 +271,24 @@ void tl_csr_free(tl_csr *g) {
     delete g;
 }
 
+int tl_set_tuning(const char *key, uint64_t value) {
+    return guarded([&] {
+        TL_REQUIRE(key, TL_EINVAL, "NULL key");
+        const int rc = set_tuning(key, value);
+        TL_REQUIRE(rc == TL_OK, TL_EINVAL, std::string("unknown tuning key or value out of range: ") + key);
+        return TL_OK;
+    });
+}
+
+int tl_get_tuning(const char *key, uint64_t *value) {
+    return guarded([&] {
+        TL_REQUIRE(key && value, TL_EINVAL, "NULL argument");
+        const int rc = get_tuning(key, value);
+        TL_REQUIRE(rc == TL_OK, TL_EINVAL, std::string("unknown tuning key: ") + key);
+        return TL_OK;
+    });
+}
+
 int tl_release_cached_memory(void) {
     return guarded([&] {
         pool_trim();

@@ -85,17 +85,39 @@ constexpr u32 LDS_BYTES = 128 * 1024;
 constexpr u32 LDS_WORDS = LDS_BYTES / 4;
 constexpr u64 LDS_BITS = (u64)LDS_BYTES * 8;
 constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES;
-constexpr u64 HEAVY_MIN = 2048;    // items of a pivot before it gets a workgroup
-constexpr u64 SLICE_MIN = 16384;   // items per heavy task, at least
+// Tunable launch parameters (defaults; tl_set_tuning or TL_TUNE_* env vars).
+struct Tuning {
+    // defaults from sweeps on the Chung-Lu 2^20 workload (random and degree
+    // orders, A++ and A+-) on MI355X
+    u64 heavy_min = 16384;       // items of a pivot before it gets a workgroup
+    u64 slice_min = 262144;      // items per heavy task, at least
+    u64 slice_mult = 16;         // ... and at least this many times its staging cost
+    u64 heavy_blocks_per_cu = 1; // heavy grid = this many workgroups per CU
+    u64 queue = 1;               // 1: heavy tasks handed out by an atomic queue
+    u64 splits = 1;              // 1: wavefront start seeds precomputed at plan time
+    u64 light_blocks_per_cu = 8; // light grid cap
+};
+Tuning &tuning();
 
 enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2 };
 
+constexpr int HW = HB / 64;    // wavefronts per heavy workgroup
+
 struct Task {
-    u64 a, b;    // item range
-    u64 cb, ce;  // compacted seed range of the pivot
-    u32 p;       // pivot
+    u64 a, b;      // item range
+    u64 cb, ce;    // compacted seed range of the pivot
+    u32 p;         // pivot
     u32 mode;
+    u32 ws[HW];    // seed (relative to cb) of each wavefront's first item
 };
+
+// Item range of wavefront w when a workgroup shares [a, b) (64-aligned runs).
+__host__ __device__ __forceinline__ void wave_share(u64 a, u64 b, u32 nwv, u32 w, u64 &wb, u64 &we) {
+    const u64 span = b - a;
+    const u64 per = (((span + nwv - 1) / nwv) + 63) & ~(u64)63;
+    wb = a + (u64)w * per;
+    we = (wb + per < b) ? wb + per : b;
+}
 
 // ---------------------------------------------------------------- plan
 
@@ -148,12 +170,13 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len
 
 // Heavy/light decision and task count per pivot.
 template <int ALGO>
-__global__ void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask, u64 *slice) {
+__global__ void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask, u64 *slice, u64 heavy_min,
+                              u64 slice_min, u64 slice_mult) {
     GRID_STRIDE(p, n) {
         const u64 w = wp[p];
         u32 md = 0xffffffffu, nt = 0;
         u64 sl = 0;
-        if (w >= HEAVY_MIN) {
+        if (w >= heavy_min) {
             const u64 *po = Form<ALGO>::piv_off(g);
             const u32 *pa = Form<ALGO>::piv_adj(g);
             const u64 t0 = po[p], t1 = po[p + 1];
@@ -167,8 +190,8 @@ __global__ void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *nta
             if (bm_ok) { md = MODE_BITMAP; stage = 2 * tlen; }
             else if (arr_ok) { md = MODE_ARRAY; stage = 2 * tlen; }
             else { md = MODE_GLOBAL; stage = 0; }
-            sl = 16 * stage;
-            if (sl < SLICE_MIN) sl = SLICE_MIN;
+            sl = slice_mult * stage;
+            if (sl < slice_min) sl = slice_min;
             nt = (u32)((w + sl - 1) / sl);
         }
         mode[p] = md;
@@ -225,8 +248,24 @@ __global__ void k_make_tasks(GView g, u32 n, const u32 *mode, const u32 *ntask, 
             t.ce = ce;
             t.p = (u32)p;
             t.mode = mode[p];
+            for (int w = 0; w < HW; w++) t.ws[w] = 0;
             tasks[tpos[p] + i] = t;
         }
+    }
+}
+
+// Seed of every heavy wavefront's first item, found once at plan time (in
+// parallel over tasks) instead of by a dependent search at task start.
+__global__ void k_task_splits(Task *tasks, u64 ntasks, const u64 *cpre) {
+    GRID_STRIDE(i, ntasks * HW) {
+        const u64 ti = i / HW;
+        const u32 w = (u32)(i % HW);
+        const Task &t = tasks[ti];
+        u64 wb, we;
+        wave_share(t.a, t.b, HW, w, wb, we);
+        u32 rel = 0;
+        if (wb < we) rel = (u32)(upper_bound_dev<u64>(cpre, t.cb, t.ce + 1, wb) - 1 - t.cb);
+        tasks[ti].ws[w] = rel;
     }
 }
 
@@ -246,6 +285,11 @@ struct SeedCursor {
 
     __device__ __forceinline__ SeedCursor(const u64 *cp, u64 lo, u64 nc, u64 first_item) : cpre(cp), ncap(nc) {
         c_lo = upper_bound_dev<u64>(cpre, lo, ncap + 1, first_item) - 1;
+        base = cpre[c_lo];
+        end = cpre[c_lo + 1];
+    }
+    // when the seed of the first item is already known
+    __device__ __forceinline__ SeedCursor(const u64 *cp, u64 nc, u64 c) : cpre(cp), ncap(nc), c_lo(c) {
         base = cpre[c_lo];
         end = cpre[c_lo + 1];
     }
@@ -314,7 +358,7 @@ struct Out {
     u64 cap;
     u32 *spill;
     u64 spill_cap;
-    u64 *acc;      // [0] count, [1] digest, [2] work, [3] cursor, [4] holes
+    u64 *acc;      // [0] count, [1] digest, [2] work, [3] cursor, [4] holes, [5] task queue
     Hole *holes;
     u64 hole_cap;
 
@@ -469,7 +513,8 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, c
 // wavefronts share the task's items.  Items are clipped to [k0, k1).
 template <int ALGO, bool EMIT>
 __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, u64 ntasks, const u32 *cseed,
-                                                    const u64 *cabs, const u64 *cpre, u64 k0, u64 k1, Out o) {
+                                                    const u64 *cabs, const u64 *cpre, u64 k0, u64 k1, Out o,
+                                                    int use_queue, int use_splits) {
     extern __shared__ u32 lds[];  // the pivot list: B as a bitmap, or a sorted array
     const int lane = lane_id(), wid = threadIdx.x / WAVE, nwv = blockDim.x / WAVE;
     const u32 *SA = Form<ALGO>::scan_adj(g);
@@ -477,9 +522,21 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
     const u32 *pa = Form<ALGO>::piv_adj(g);
     WaveEmitter<EMIT> em;
     u64 cnt = 0, hsh = 0;
+    __shared__ u64 next_task;
     for (u32 i = threadIdx.x; i < LDS_WORDS; i += blockDim.x) lds[i] = 0u;  // B starts all false
     __syncthreads();
-    for (u64 ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    for (u64 it = 0;; it++) {
+        u64 ti;
+        if (use_queue) {
+            // tasks handed out dynamically: one atomic per task per workgroup
+            if (threadIdx.x == 0) next_task = atomicAdd((unsigned long long *)&o.acc[5], 1ull);
+            __syncthreads();
+            ti = next_task;
+            __syncthreads();
+        } else {
+            ti = blockIdx.x + it * gridDim.x;
+        }
+        if (ti >= ntasks) break;
         const Task tk = tasks[ti];
         const u64 a = tk.a > k0 ? tk.a : k0;
         const u64 b = tk.b < k1 ? tk.b : k1;
@@ -498,12 +555,11 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             for (u32 i = threadIdx.x; i < tlen; i += blockDim.x) lds[i] = pa[t0 + i];
             __syncthreads();
         }
-        const u64 span = b - a;
-        const u64 per = (((span + nwv - 1) / nwv) + WAVE - 1) & ~(u64)(WAVE - 1);
-        const u64 wb = a + (u64)wid * per;
-        const u64 we = (wb + per < b) ? wb + per : b;
+        u64 wb, we;
+        wave_share(a, b, (u32)nwv, (u32)wid, wb, we);
         if (wb < we) {
-            SeedCursor cur(cpre, tk.cb, tk.ce, wb);
+            const bool exact = use_splits && a == tk.a && b == tk.b;  // not clipped by a chunk slice
+            SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tk.ws[wid]) : SeedCursor(cpre, tk.cb, tk.ce, wb);
             const u32 pinv = g.inv[p];
             auto member = [&](u32 y) -> bool {
                 if (tk.mode == MODE_BITMAP) {
@@ -635,8 +691,9 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
                        wp.as<u64>(), d_acc);
     TL_HIP(hipGetLastError());
     DevBuf mode((u64)n * sizeof(u32), s), ntask((u64)n * sizeof(u32), s), slice((u64)n * sizeof(u64), s);
+    const Tuning &tu = tuning();
     hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), mode.as<u32>(),
-                       ntask.as<u32>(), slice.as<u64>());
+                       ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult);
     TL_HIP(hipGetLastError());
     DevBuf flags(m * sizeof(u64), s), pos((m + 1) * sizeof(u64), s);
     hipLaunchKernelGGL((k_seed_class<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), mode.as<u32>(),
@@ -665,6 +722,11 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
                            slice.as<u64>(), tpos.as<u64>(), pos.as<u64>(), P.cpre.as<u64>(), m,
                            P.tasks.as<Task>());
         TL_HIP(hipGetLastError());
+        if (tuning().splits) {
+            hipLaunchKernelGGL(k_task_splits, dim3(grid_for(h_nt * HW, PB, (unsigned)tl_num_cus() * 16)), dim3(PB), 0,
+                               s, P.tasks.as<Task>(), h_nt, P.cpre.as<u64>());
+            TL_HIP(hipGetLastError());
+        }
     }
     u64 h_w[3] = {0, 0, 0};
     d2h_sync(s, {{&h_w[0], P.cpre.as<u64>() + nl, sizeof(u64)},
@@ -677,8 +739,8 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
 
 // Largest grids the probe kernels are launched with; they bound the number
 // of wavefronts, hence of holes, per launch.
-inline u64 light_max_blocks() { return (u64)tl_num_cus() * 8; }
-inline u64 heavy_max_blocks() { return (u64)tl_num_cus() * 2; }
+inline u64 light_max_blocks() { return (u64)tl_num_cus() * tuning().light_blocks_per_cu; }
+inline u64 heavy_max_blocks() { return (u64)tl_num_cus() * tuning().heavy_blocks_per_cu; }
 inline u64 max_holes_per_probe() { return light_max_blocks() * (PB / WAVE) + heavy_max_blocks() * (HB / WAVE); }
 
 template <int ALGO>
@@ -706,11 +768,11 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
         if (emit)
             hipLaunchKernelGGL((k_probe_heavy<ALGO, true>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
                                P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(),
-                               h0, h1, o);
+                               h0, h1, o, (int)tuning().queue, (int)tuning().splits);
         else
             hipLaunchKernelGGL((k_probe_heavy<ALGO, false>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
                                P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(),
-                               h0, h1, o);
+                               h0, h1, o, (int)tuning().queue, (int)tuning().splits);
         TL_HIP(hipGetLastError());
     }
 }
@@ -739,6 +801,25 @@ void fix_holes(const Out &o, u64 count, u64 reserved, u64 nholes, hipStream_t s)
     TL_HIP(hipStreamSynchronize(s));
 }
 
+Tuning &tuning() {
+    static Tuning t = [] {
+        Tuning d;
+        auto env = [](const char *k, u64 &v) {
+            const char *e = getenv(k);
+            if (e && *e) v = strtoull(e, nullptr, 10);
+        };
+        env("TL_TUNE_HEAVY_MIN", d.heavy_min);
+        env("TL_TUNE_SLICE_MIN", d.slice_min);
+        env("TL_TUNE_SLICE_MULT", d.slice_mult);
+        env("TL_TUNE_HEAVY_BLOCKS_PER_CU", d.heavy_blocks_per_cu);
+        env("TL_TUNE_QUEUE", d.queue);
+        env("TL_TUNE_SPLITS", d.splits);
+        env("TL_TUNE_LIGHT_BLOCKS_PER_CU", d.light_blocks_per_cu);
+        return d;
+    }();
+    return t;
+}
+
 bool debug_enabled() {
     static const bool on = [] {
         const char *e = getenv("TL_DEBUG");
@@ -762,6 +843,34 @@ void prepare_kernels() {
 }  // namespace
 
 u64 chunk_triangles() { return g_chunk_triangles; }
+
+int set_tuning(const char *key, u64 value) {
+    Tuning &t = tuning();
+    const std::string k(key ? key : "");
+    if (k == "heavy_min" && value >= 1) t.heavy_min = value;
+    else if (k == "slice_min" && value >= 64) t.slice_min = value;
+    else if (k == "slice_mult" && value >= 1) t.slice_mult = value;
+    else if (k == "heavy_blocks_per_cu" && value >= 1 && value <= 64) t.heavy_blocks_per_cu = value;
+    else if (k == "queue" && value <= 1) t.queue = value;
+    else if (k == "splits" && value <= 1) t.splits = value;
+    else if (k == "light_blocks_per_cu" && value >= 1 && value <= 64) t.light_blocks_per_cu = value;
+    else return TL_EINVAL;
+    return TL_OK;
+}
+
+int get_tuning(const char *key, u64 *value) {
+    const Tuning &t = tuning();
+    const std::string k(key ? key : "");
+    if (k == "heavy_min") *value = t.heavy_min;
+    else if (k == "slice_min") *value = t.slice_min;
+    else if (k == "slice_mult") *value = t.slice_mult;
+    else if (k == "heavy_blocks_per_cu") *value = t.heavy_blocks_per_cu;
+    else if (k == "queue") *value = t.queue;
+    else if (k == "splits") *value = t.splits;
+    else if (k == "light_blocks_per_cu") *value = t.light_blocks_per_cu;
+    else return TL_EINVAL;
+    return TL_OK;
+}
 void set_chunk_triangles(u64 k) { g_chunk_triangles = k; }
 
 u64 cost_impl(const tl_csr *g, int algo, hipStream_t s) {
@@ -813,7 +922,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     const bool emitting = (tri || cb) && h_total;
     const u64 hole_cap = max_holes_per_probe();
     DevBuf holes, spill, chunk;
-    Out o{nullptr, 0, nullptr, 0, d_acc, nullptr, hole_cap};
+    Out o{nullptr, 0, nullptr, 0, d_acc, nullptr, hole_cap};  // acc[5] = heavy task queue
     if (emitting) {
         holes = DevBuf(hole_cap * sizeof(Hole), s);
         o.holes = holes.as<Hole>();
@@ -850,7 +959,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
         u64 prev_count = 0;
         for (u64 k0 = 0; k0 < h_total; k0 += K) {
             const u64 k1 = (h_total - k0 > K) ? k0 + K : h_total;
-            TL_HIP(hipMemsetAsync(d_acc + 3, 0, 2 * sizeof(u64), s));  // cursor and holes
+            TL_HIP(hipMemsetAsync(d_acc + 3, 0, 3 * sizeof(u64), s));  // cursor, holes, task queue
             probe(k0, k1, true);
             d2h_sync(s, {{h_acc, d_acc, sizeof h_acc}});
             const u64 got = h_acc[0] - prev_count;

@@ -120,4 +120,6 @@ u64 cost_impl(const tl_csr *g, int algo, hipStream_t s);
 int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl_chunk_fn cb, void *user,
               hipStream_t s, tl_summary *out);
 u64 chunk_triangles();
+int set_tuning(const char *key, u64 value);
+int get_tuning(const char *key, u64 *value);
 void set_chunk_triangles(u64 k);

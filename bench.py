@@ -61,6 +61,31 @@ def alg_bytes(C, m, n, T, emit=True):
     return 4 * C + 4 * m + 16 * m + 16 * n + (12 * T if emit else 0)
 
 
+def heavy_alg_bytes(st):
+    """Algorithmic bytes of the heavy-pivot kernel's share of a listing: 4 B
+    per element of the paper's work over its seed edges, 4 B per staged
+    pivot-list element, 16 B of offsets per seed edge and per pivot, 12 B per
+    written triangle."""
+    return (4 * st["heavy_work"] + 4 * st["heavy_staged"] + 16 * st["heavy_seeds"] + 16 * st["heavy_pivots"]
+            + 12 * st["heavy_triangles"])
+
+
+def measured_traffic(workload, launches_per_step):
+    """HBM bytes per heavy-probe launch from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None if there is none for this workload or the kernel source changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    from paper_2203_04774_amd.profiling import list_source_digest
+    if t.get("source_digest") != list_source_digest():
+        return None
+    return t.get("heavy_bytes_per_launch")
+
+
 def cpu_baseline(g, ranks, budget_s=20.0):
     """The oracle, single-threaded on the host, over a bounded sample of the
     step's listings (whole listings, taken in order until the budget)."""
@@ -136,9 +161,14 @@ def main():
 
     runs = [(k, a) for k in wl["orders"] for a in wl["algos"]]
 
+    class Stats(ctypes.Structure):
+        _fields_ = [(k, ctypes.c_uint64) for k in (
+            "light_items", "heavy_items", "light_seeds", "heavy_seeds", "heavy_work", "heavy_pivots",
+            "heavy_staged", "heavy_triangles", "tasks")]
+
     def phase_ms():
         vals = []
-        for ph in range(4):
+        for ph in range(6):
             ms = ctypes.c_double()
             lib.tl_timing_read(ph, ctypes.byref(ms), None)
             vals.append(ms.value)
@@ -156,10 +186,14 @@ def main():
                 s = tl.list_triangles(csr, algo, out=out)
                 if record is not None:
                     after = phase_ms()
+                    st = Stats()
+                    lib.tl_last_list_stats(ctypes.byref(st))
                     record.append(dict(order=kind, algo=algo, T=int(s.count), C=int(c), work=int(s.work),
                                        scanned=int(s.scanned), hash=f"0x{s.hash:016x}", m=csr.m,
                                        orient_ms=t_or, plan_ms=after[1] - before[1],
-                                       probe_ms=after[2] - before[2]))
+                                       probe_ms=after[2] - before[2], light_ms=after[4] - before[4],
+                                       heavy_ms=after[5] - before[5],
+                                       stats={k: int(getattr(st, k)) for k, _ in Stats._fields_}))
             csr.free()
 
     for i in range(args.warmup):
@@ -180,19 +214,24 @@ def main():
     log(f"[bench] {args.steps} timed steps in {elapsed:.3f}s")
 
     phases = {}
-    for ph, name in enumerate(["orient", "plan", "probe", "cost"]):
+    for ph, name in enumerate(["orient", "plan", "probe", "cost", "probe_light", "probe_heavy"]):
         ms, calls = ctypes.c_double(), ctypes.c_uint64()
         lib.tl_timing_read(ph, ctypes.byref(ms), ctypes.byref(calls))
         phases[name] = {"ms": ms.value, "launches": int(calls.value)}
 
     tri_per_step = sum(r["T"] for r in rec)
     work_per_step = sum(r["work"] for r in rec)
-    bytes_per_step = sum(alg_bytes(r["C"], r["m"], g.n, r["T"]) for r in rec)
     value = tri_per_step * args.steps / elapsed
+    # roofline of the dominant kernel, the heavy-pivot probe: algorithmic
+    # bytes of its share of the work over its own HIP-event time
+    heavy_bytes = sum(heavy_alg_bytes(r["stats"]) for r in rec) * args.steps
+    heavy_s = phases["probe_heavy"]["ms"] / 1e3
+    achieved = heavy_bytes / heavy_s / 1e9 if heavy_s > 0 else 0.0
     probe_s = phases["probe"]["ms"] / 1e3
-    achieved = bytes_per_step * args.steps / probe_s / 1e9 if probe_s > 0 else 0.0
-    scanned_bytes = sum(4 * r["scanned"] + 20 * r["m"] + 16 * g.n + 12 * r["T"] for r in rec) * args.steps
-    dominant = max(phases, key=lambda k: phases[k]["ms"])
+    probe_bytes = sum(alg_bytes(r["C"], r["m"], g.n, r["T"]) for r in rec) * args.steps
+    heavy_launches = phases["probe_heavy"]["launches"]
+    traffic = measured_traffic(args.workload, heavy_launches / max(args.steps, 1))
+    dominant = max(("orient", "plan", "probe_light", "probe_heavy", "cost"), key=lambda k: phases[k]["ms"])
 
     res = {
         "metric": "triangles listed/s + intersect elems/s (%HBM peak); batched vs plain; p99 job ms",
@@ -211,10 +250,14 @@ def main():
                    "orders": wl["orders"], "algos": wl["algos"], "emit": "full list to device",
                    "listings_per_step": len(runs)},
         "intersect_elems_per_s": work_per_step * args.steps / elapsed,
-        "roofline": {"bound": "hbm", "kernel": "k_probe (intersection + emit)",
+        "roofline": {"bound": "hbm", "kernel": "k_probe_heavy",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "achieved_on_scanned_elements": scanned_bytes / probe_s / 1e9 if probe_s else 0.0},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_ms": phases["probe_heavy"]["ms"] / max(heavy_launches, 1),
+                     "launches": heavy_launches,
+                     "alg_bytes_per_launch": heavy_bytes / max(heavy_launches, 1)},
+        "probe_phase": {"achieved_GBps": probe_bytes / probe_s / 1e9 if probe_s else 0.0,
+                        "ms_per_step": phases["probe"]["ms"] / args.steps},
         "phases_ms_per_step": {k: v["ms"] / args.steps for k, v in phases.items()},
         "dominant_phase": dominant,
         "runs": rec,

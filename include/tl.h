@@ -176,12 +176,33 @@ int tl_set_chunk_triangles(uint64_t k);
  * Kernel-phase timing, for measurement.  While enabled, the library records
  * HIP events on the caller's stream around each phase's kernels and, when
  * the call synchronises, adds the elapsed time to a per-phase total.
- *   phase  TL_PHASE_ORIENT (all of tl_orient's kernels), TL_PHASE_PLAN
- *          (per-seed-edge windows, compaction, work prefix), TL_PHASE_PROBE
- *          (the intersection/emit kernel), TL_PHASE_COST (tl_cost)
+ *   phase  one of the TL_PHASE_* values below
  *   ms, calls  host outputs: accumulated milliseconds and timed launches
  */
-enum { TL_PHASE_ORIENT = 0, TL_PHASE_PLAN = 1, TL_PHASE_PROBE = 2, TL_PHASE_COST = 3, TL_NUM_PHASES = 4 };
+/*
+ * Work split of the calling thread's most recent listing (for measurement):
+ * items are scanned-list elements after pruning; "heavy" pivots are the ones
+ * listed by workgroup tasks with their list staged in LDS; heavy_work is the
+ * paper's work of those pivots' seed edges, heavy_staged the total length of
+ * their staged lists.
+ */
+typedef struct {
+    uint64_t light_items, heavy_items;
+    uint64_t light_seeds, heavy_seeds;
+    uint64_t heavy_work, heavy_pivots, heavy_staged, heavy_triangles;
+    uint64_t tasks;
+} tl_list_stats;
+int tl_last_list_stats(tl_list_stats *out);
+
+enum {
+    TL_PHASE_ORIENT = 0,      /* all of tl_orient */
+    TL_PHASE_PLAN = 1,        /* windows, classes, compaction, prefix, tasks */
+    TL_PHASE_PROBE = 2,       /* both probe kernels */
+    TL_PHASE_COST = 3,        /* tl_cost */
+    TL_PHASE_PROBE_LIGHT = 4, /* the light-pivot probe kernel alone */
+    TL_PHASE_PROBE_HEAVY = 5, /* the heavy-pivot probe kernel alone */
+    TL_NUM_PHASES = 6
+};
 int tl_timing_enable(int on);
 int tl_timing_reset(void);
 int tl_timing_read(int phase, double *ms, uint64_t *calls);

@@ -289,6 +289,12 @@ int tl_get_tuning(const char *key, uint64_t *value) {
     });
 }
 
+int tl_last_list_stats(tl_list_stats *out) {
+    if (!out) return TL_EINVAL;
+    *out = last_stats();
+    return TL_OK;
+}
+
 int tl_release_cached_memory(void) {
     return guarded([&] {
         pool_trim();

@@ -170,8 +170,11 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len
 
 // Heavy/light decision and task count per pivot.
 template <int ALGO>
-__global__ void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask, u64 *slice, u64 heavy_min,
-                              u64 slice_min, u64 slice_mult) {
+__global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask,
+                                                    u64 *slice, u64 heavy_min, u64 slice_min, u64 slice_mult,
+                                                    u64 *acc) {
+    __shared__ u64 lds[PB / WAVE];
+    u64 hp = 0, staged = 0;
     GRID_STRIDE(p, n) {
         const u64 w = wp[p];
         u32 md = 0xffffffffu, nt = 0;
@@ -193,24 +196,43 @@ __global__ void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *nta
             sl = slice_mult * stage;
             if (sl < slice_min) sl = slice_min;
             nt = (u32)((w + sl - 1) / sl);
+            hp += 1;
+            staged += tlen;
         }
         mode[p] = md;
         ntask[p] = nt;
         slice[p] = sl;
     }
+    hp = block_sum_u64<PB>(hp, lds);
+    staged = block_sum_u64<PB>(staged, lds);
+    if (threadIdx.x == 0 && hp) {
+        atomicAdd((unsigned long long *)&acc[7], (unsigned long long)hp);
+        atomicAdd((unsigned long long *)&acc[9], (unsigned long long)staged);
+    }
 }
 
 // Class flag per seed, packed for one scan: low half light, high half heavy.
+// Also sums the paper's work of the heavy pivots' seed edges (measurement).
 template <int ALGO>
-__global__ void k_seed_class(GView g, const u32 *len, const u32 *mode, u64 *flags) {
+__global__ __launch_bounds__(PB) void k_seed_class(GView g, const u32 *len, const u32 *mode, u64 *flags, u64 *acc) {
+    __shared__ u64 lds[PB / WAVE];
+    u64 hw = 0;
     GRID_STRIDE(e, g.m) {
         u64 f = 0;
         if (len[e]) {
             const u32 p = ALGO == 0 ? g.row_b[e] : g.row_f[e];
-            f = mode[p] == 0xffffffffu ? 1ull : (1ull << 32);
+            if (mode[p] == 0xffffffffu) {
+                f = 1ull;
+            } else {
+                f = 1ull << 32;
+                Seed<ALGO> sd(g, e);
+                hw += sd.s_hi - sd.s_lo;
+            }
         }
         flags[e] = f;
     }
+    hw = block_sum_u64<PB>(hw, lds);
+    if (threadIdx.x == 0 && hw) atomicAdd((unsigned long long *)&acc[6], (unsigned long long)hw);
 }
 
 // Light seeds first, then heavy seeds, both in seed (pivot-major) order.
@@ -358,7 +380,8 @@ struct Out {
     u64 cap;
     u32 *spill;
     u64 spill_cap;
-    u64 *acc;      // [0] count, [1] digest, [2] work, [3] cursor, [4] holes, [5] task queue
+    u64 *acc;      // [0] count, [1] digest, [2] work, [3] cursor, [4] holes, [5] task queue,
+                   // [6] heavy work, [7] heavy pivots, [8] heavy triangles, [9] heavy staged elements
     Hole *holes;
     u64 hole_cap;
 
@@ -537,7 +560,13 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             ti = blockIdx.x + it * gridDim.x;
         }
         if (ti >= ntasks) break;
-        const Task tk = tasks[ti];
+        // fields are read one by one: copying the struct and indexing its
+        // per-wavefront array would put it in scratch memory
+        const Task &tg = tasks[ti];
+        struct {
+            u64 a, b, cb, ce;
+            u32 p, mode;
+        } tk{tg.a, tg.b, tg.cb, tg.ce, tg.p, tg.mode};
         const u64 a = tk.a > k0 ? tk.a : k0;
         const u64 b = tk.b < k1 ? tk.b : k1;
         if (a >= b) continue;  // uniform across the block
@@ -559,7 +588,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         wave_share(a, b, (u32)nwv, (u32)wid, wb, we);
         if (wb < we) {
             const bool exact = use_splits && a == tk.a && b == tk.b;  // not clipped by a chunk slice
-            SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tk.ws[wid]) : SeedCursor(cpre, tk.cb, tk.ce, wb);
+            SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tg.ws[wid]) : SeedCursor(cpre, tk.cb, tk.ce, wb);
             const u32 pinv = g.inv[p];
             auto member = [&](u32 y) -> bool {
                 if (tk.mode == MODE_BITMAP) {
@@ -637,6 +666,10 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         }
     }
     em.finish(o);
+    {
+        const u64 c8 = wave_sum_u64(cnt);
+        if (lane_id() == 0 && c8) atomicAdd((unsigned long long *)&o.acc[8], (unsigned long long)c8);
+    }
     flush_counts(cnt, hsh, o.acc);
 }
 
@@ -674,6 +707,7 @@ GView view_of(const tl_csr *g) {
 struct Plan {
     DevBuf cseed, cabs, cpre, tasks;
     u64 ncomp = 0;    // compacted seeds
+    u64 nlight = 0;   // ... of which light
     u64 w_light = 0;  // light items [0, w_light)
     u64 w_total = 0;  // all items
     u64 ntasks = 0;
@@ -693,11 +727,11 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
     DevBuf mode((u64)n * sizeof(u32), s), ntask((u64)n * sizeof(u32), s), slice((u64)n * sizeof(u64), s);
     const Tuning &tu = tuning();
     hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), mode.as<u32>(),
-                       ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult);
+                       ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult, d_acc);
     TL_HIP(hipGetLastError());
     DevBuf flags(m * sizeof(u64), s), pos((m + 1) * sizeof(u64), s);
     hipLaunchKernelGGL((k_seed_class<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), mode.as<u32>(),
-                       flags.as<u64>());
+                       flags.as<u64>(), d_acc);
     TL_HIP(hipGetLastError());
     scan_u64_to_u64(flags.as<u64>(), pos.as<u64>(), m, s);
     P.cseed = DevBuf(m * sizeof(u32), s);
@@ -715,6 +749,7 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
     d2h_sync(s, {{&h_pos, pos.as<u64>() + m, sizeof(u64)}, {&h_nt, tpos.as<u64>() + n, sizeof(u64)}});
     const u64 nl = h_pos & 0xffffffffull, nh = h_pos >> 32;
     P.ncomp = nl + nh;
+    P.nlight = nl;
     P.ntasks = h_nt;
     if (h_nt) {
         P.tasks = DevBuf(h_nt * sizeof(Task), s);
@@ -748,6 +783,7 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
     // light part
     const u64 l0 = k0, l1 = k1 < P.w_light ? k1 : P.w_light;
     if (l0 < l1) {
+        PhaseTimer tlight(TL_PHASE_PROBE_LIGHT, s);
         const u64 waves_needed = (l1 - l0 + WAVE - 1) / WAVE;
         u64 blocks = (waves_needed + (PB / WAVE) - 1) / (PB / WAVE);
         if (blocks > light_max_blocks()) blocks = light_max_blocks();
@@ -763,6 +799,7 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
     // heavy part
     const u64 h0 = k0 > P.w_light ? k0 : P.w_light, h1 = k1;
     if (h0 < h1 && P.ntasks) {
+        PhaseTimer theavy(TL_PHASE_PROBE_HEAVY, s);
         u64 blocks = P.ntasks;
         if (blocks > heavy_max_blocks()) blocks = heavy_max_blocks();
         if (emit)
@@ -844,6 +881,11 @@ void prepare_kernels() {
 
 u64 chunk_triangles() { return g_chunk_triangles; }
 
+tl_list_stats &last_stats() {
+    thread_local tl_list_stats st{};
+    return st;
+}
+
 int set_tuning(const char *key, u64 value) {
     Tuning &t = tuning();
     const std::string k(key ? key : "");
@@ -897,7 +939,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     const GView v = view_of(g);
     prepare_kernels();
 
-    constexpr int NACC = 8;
+    constexpr int NACC = 10;
     DevBuf acc(NACC * sizeof(u64), s);
     TL_HIP(hipMemsetAsync(acc.p, 0, NACC * sizeof(u64), s));
     u64 *d_acc = acc.as<u64>();
@@ -974,5 +1016,15 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     }
     out->count = h_acc[0];
     out->hash = h_acc[1];
+    tl_list_stats &st = last_stats();
+    st.light_items = P.w_light;
+    st.heavy_items = P.w_total - P.w_light;
+    st.light_seeds = P.nlight;
+    st.heavy_seeds = P.ncomp - P.nlight;
+    st.heavy_work = h_acc[6];
+    st.heavy_pivots = h_acc[7];
+    st.heavy_triangles = h_acc[8];
+    st.heavy_staged = h_acc[9];
+    st.tasks = P.ntasks;
     return rc;
 }

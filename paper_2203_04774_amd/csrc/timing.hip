@@ -25,8 +25,8 @@ hipEvent_t take_event() {
 
 std::mutex g_mu;
 bool g_on = false;
-double g_ms[TL_NUM_PHASES] = {0, 0, 0, 0};
-uint64_t g_calls[TL_NUM_PHASES] = {0, 0, 0, 0};
+double g_ms[TL_NUM_PHASES] = {};
+uint64_t g_calls[TL_NUM_PHASES] = {};
 }  // namespace
 
 PhaseTimer::PhaseTimer(int phase, hipStream_t s) : phase_(phase), s_(s) {

@@ -121,5 +121,6 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
               hipStream_t s, tl_summary *out);
 u64 chunk_triangles();
 int set_tuning(const char *key, u64 value);
+tl_list_stats &last_stats();
 int get_tuning(const char *key, u64 *value);
 void set_chunk_triangles(u64 k);

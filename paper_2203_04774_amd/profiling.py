@@ -1,0 +1,111 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+    python -m paper_2203_04774_amd.profiling stats  <kernel_stats.csv> <out.md> <command...>
+    python -m paper_2203_04774_amd.profiling traffic <fetch_counter_collection.csv> \
+        <write_counter_collection.csv> <calibration MiB> <workload> <out.json> <command...>
+
+`stats` turns a `--kernel-trace --stats` kernel_stats.csv into a short
+markdown table.  `traffic` combines two `--pmc FETCH_SIZE` / `--pmc
+WRITE_SIZE` runs of `bench.py --steps 1 --warmup 0 --copy-calibration-mib N`:
+the plain device copy of N MiB at the start of the run calibrates the
+counters (bytes the copy must move / bytes the counter reports), and the
+heavy-pivot probe kernel's per-dispatch bytes are scaled by that factor.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def short_name(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
+    return name.split("(")[0] if not name.startswith("void ") else name[5:].split("(")[0]
+
+
+def list_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("list.hip", "dev_util.h"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stats(csv_path: str, out_md: str, command: str, top: int = 25) -> None:
+    rows = list(csv.DictReader(open(csv_path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics", "", "Command:", "", "```", command, "```", "",
+             f"Total kernel time {total / 1e6:.2f} ms over {sum(int(r['Calls']) for r in rows)} dispatches.", "",
+             "| kernel | calls | avg ms | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.1f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _per_dispatch(path: str):
+    """{dispatch_id: (kernel, value_kib)} summed over counter instances."""
+    out = {}
+    for r in csv.DictReader(open(path)):
+        d = int(r["Dispatch_Id"])
+        k, v = out.get(d, (r["Kernel_Name"], 0.0))
+        out[d] = (k, v + float(r["Counter_Value"]))
+    return out
+
+
+def traffic(fetch_csv: str, write_csv: str, calib_mib: float, workload: str, out_json: str, command: str) -> dict:
+    fetch, write = _per_dispatch(fetch_csv), _per_dispatch(write_csv)
+    calib_bytes = calib_mib * (1 << 20)
+
+    def copy_factor(d):
+        # the calibration copy is the first rocclr copy kernel of about the calibration size
+        for _, (k, v) in sorted(d.items()):
+            if "copyBuffer" in k and v * 1024 > 0.25 * calib_bytes:
+                return calib_bytes / (v * 1024), v * 1024
+        raise SystemExit("no calibration copy found")
+
+    f_fac, f_raw = copy_factor(fetch)
+    w_fac, w_raw = copy_factor(write)
+    per_kernel = defaultdict(lambda: {"launches": 0, "fetch": 0.0, "write": 0.0})
+    for src, key, fac in ((fetch, "fetch", f_fac), (write, "write", w_fac)):
+        for _, (k, v) in src.items():
+            name = short_name(k)
+            per_kernel[name][key] += v * 1024 * fac
+            if key == "fetch":
+                per_kernel[name]["launches"] += 1
+    heavy = [n for n in per_kernel if n.startswith("k_probe_heavy") and n.endswith("true>")]
+    hb = sum(per_kernel[n]["fetch"] + per_kernel[n]["write"] for n in heavy)
+    hl = sum(per_kernel[n]["launches"] for n in heavy)
+    res = {
+        "workload": workload,
+        "command": command,
+        "source_digest": list_source_digest(),
+        "calibration": {"copy_bytes": calib_bytes, "fetch_counter_bytes": f_raw, "write_counter_bytes": w_raw,
+                        "fetch_factor": f_fac, "write_factor": w_fac},
+        "heavy_kernels": heavy,
+        "heavy_launches": hl,
+        "heavy_bytes_per_launch": hb / hl if hl else None,
+        "per_kernel_bytes_per_launch": {n: {"fetch": v["fetch"] / max(v["launches"], 1),
+                                            "write": v["write"] / max(v["launches"], 1),
+                                            "launches": v["launches"]}
+                                        for n, v in sorted(per_kernel.items(), key=lambda kv: -kv[1]["fetch"])[:20]},
+    }
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6], " ".join(sys.argv[7:]))
+    else:
+        raise SystemExit(__doc__)

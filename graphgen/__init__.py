@@ -94,7 +94,8 @@ def rmat(scale: int, edge_factor: int = 8, a=0.57, b=0.19, c=0.19, seed: int = 1
     src = np.empty(samples, np.uint32)
     dst = np.empty(samples, np.uint32)
     m = lib.gg_rmat(scale, samples, a, b, c, seed, src, dst)
-    return Graph(1 << scale, src[:m].copy(), dst[:m].copy(), f"rmat{scale}-ef{edge_factor}-s{seed}")
+    # prefix views, not copies: at scale 26 a copy would cost another 8 GB
+    return Graph(1 << scale, src[:m], dst[:m], f"rmat{scale}-ef{edge_factor}-s{seed}")
 
 
 def chung_lu(n: int, gamma: float = 2.1, mean_degree: float = 20.0, seed: int = 1,
@@ -107,7 +108,7 @@ def chung_lu(n: int, gamma: float = 2.1, mean_degree: float = 20.0, seed: int = 
     src = np.empty(max(samples, 1), np.uint32)
     dst = np.empty(max(samples, 1), np.uint32)
     m = lib.gg_chung_lu(n, gamma, i0, samples, seed, src, dst) if samples else 0
-    return Graph(n, src[:m].copy(), dst[:m].copy(), f"chunglu-n{n}-g{gamma}-k{mean_degree}-s{seed}")
+    return Graph(n, src[:m], dst[:m], f"chunglu-n{n}-g{gamma}-k{mean_degree}-s{seed}")
 
 
 def simplify(n: int, src, dst, name="") -> Graph:

@@ -50,6 +50,14 @@ def _load():
     lib.orc_cost.argtypes = [u32, u64, u32p, u32p, u32p, u64p]
     lib.orc_oriented_csr.restype = ctypes.c_int
     lib.orc_oriented_csr.argtypes = [u32, u64, u32p, u32p, u32p, u64p, u32p, u64p, u32p, u32p]
+    lib.orc_list_ranges.restype = ctypes.c_int
+    lib.orc_list_ranges.argtypes = [u32, u64, u32p, u32p, u32p, ctypes.c_int, u32, u32p, u32p, vp, vp, u64p]
+    lib.orc_graph_new.restype = vp
+    lib.orc_graph_new.argtypes = [u32, u64, u32p, u32p, u32p, ctypes.POINTER(ctypes.c_int)]
+    lib.orc_graph_list.restype = ctypes.c_int
+    lib.orc_graph_list.argtypes = [vp, ctypes.c_int, u32, u32, vp, u64, u64p]
+    lib.orc_graph_free.restype = None
+    lib.orc_graph_free.argtypes = [vp]
     lib.orc_triangle_hash.restype = u64
     lib.orc_triangle_hash.argtypes = [u32, u32, u32]
     lib.orc_mix64.restype = u64
@@ -112,6 +120,66 @@ def list_triangles(n, src, dst, rank, algo="A++", pivot_lo=0, pivot_hi=None,
     else:
         _check(lib.orc_list(n, len(s), s, d, r, ALGOS[algo], pivot_lo, pivot_hi, None, 0, out))
     return Listing(int(out[0]), int(out[1]), int(out[2]), int(out[3]), tri)
+
+
+def list_ranges(n, src, dst, rank, algo, ranges, caps=None):
+    """Algorithm 1/2 over several pivot ranges with one graph build.
+
+    ranges: list of (lo, hi); caps: None (counts only) or a list of
+    capacities, in which case each range's triangles are returned too.
+    Returns a list of Listing."""
+    lib = _load()
+    s, d, r = _arrs(src, dst, rank)
+    nr = len(ranges)
+    lo = np.ascontiguousarray([a for a, _ in ranges], np.uint32)
+    hi = np.ascontiguousarray([b for _, b in ranges], np.uint32)
+    out = np.zeros(4 * nr, np.uint64)
+    bufs, ptrs, capa = None, None, None
+    if caps is not None:
+        bufs = [np.zeros((max(int(c), 1), 3), np.uint32) for c in caps]
+        ptrs = (ctypes.c_void_p * nr)(*[b.ctypes.data for b in bufs])
+        capa = np.ascontiguousarray(caps, np.uint64)
+    _check(lib.orc_list_ranges(n, len(s), s, d, r, ALGOS[algo], nr, lo, hi,
+                               ctypes.cast(ptrs, ctypes.c_void_p) if ptrs is not None else None,
+                               capa.ctypes.data if capa is not None else None, out))
+    res = []
+    for i in range(nr):
+        c = int(out[4 * i])
+        tri = bufs[i][:min(c, int(caps[i]))] if bufs is not None else None
+        res.append(Listing(c, int(out[4 * i + 1]), int(out[4 * i + 2]), int(out[4 * i + 3]), tri))
+    return res
+
+
+class BuiltGraph:
+    """A graph built once by the oracle, listed over many pivot ranges."""
+
+    def __init__(self, n, src, dst, rank):
+        lib = _load()
+        s, d, r = _arrs(src, dst, rank)
+        rc = ctypes.c_int(0)
+        self.n = n
+        self._h = lib.orc_graph_new(n, len(s), s, d, r, ctypes.byref(rc))
+        _check(rc.value)
+
+    def list(self, algo="A++", lo=0, hi=None, cap=0) -> Listing:
+        lib = _load()
+        hi = self.n if hi is None else hi
+        out = np.zeros(4, np.uint64)
+        tri = np.zeros((max(cap, 1), 3), np.uint32) if cap else None
+        _check(lib.orc_graph_list(self._h, ALGOS[algo], lo, hi, tri.ctypes.data if cap else None, cap, out))
+        c = int(out[0])
+        return Listing(c, int(out[1]), int(out[2]), int(out[3]), tri[:min(c, cap)] if cap else None)
+
+    def close(self):
+        if self._h:
+            _load().orc_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @dataclass

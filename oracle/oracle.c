@@ -279,6 +279,72 @@ int orc_list(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank, i
 }
 
 /*
+ * As orc_list, for nr pivot ranges [lo[i], hi[i]) over one graph build.
+ * tri[i] (may be NULL) receives up to cap[i] triangles of range i;
+ * out[4*i .. 4*i+3] = count, hash, work, m for range i.
+ */
+int orc_list_ranges(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank, int algo, u32 nr,
+                    const u32 *lo, const u32 *hi, u32 **tri, const u64 *cap, u64 *out) {
+    graph g;
+    int rc = graph_build(&g, n, m_in, src, dst, rank);
+    if (rc) return rc;
+    unsigned char *B = (unsigned char *)calloc((size_t)n + 1, 1);
+    if (!B) { graph_free(&g); return -2; }
+    for (u32 i = 0; i < nr; i++) {
+        sink s = {0, 0, 0, tri ? tri[i] : 0, cap ? cap[i] : 0};
+        if (algo == ORC_APP) list_app(&g, lo[i], hi[i], B, &s);
+        else if (algo == ORC_APM) list_apm(&g, lo[i], hi[i], B, &s);
+        else if (algo == ORC_AMM) list_amm(&g, lo[i], hi[i], B, &s);
+        else { free(B); graph_free(&g); return -1; }
+        out[4 * i + 0] = s.count;
+        out[4 * i + 1] = s.hash;
+        out[4 * i + 2] = s.work;
+        out[4 * i + 3] = g.m;
+    }
+    free(B);
+    graph_free(&g);
+    return 0;
+}
+
+/* A built graph kept between calls (for listing many pivot ranges). */
+void *orc_graph_new(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank, int *rc) {
+    graph *g = (graph *)calloc(1, sizeof(graph));
+    if (!g) { *rc = -2; return 0; }
+    /* the rank array must outlive the handle; keep a private copy */
+    u32 *rk = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    if (!rk) { free(g); *rc = -2; return 0; }
+    memcpy(rk, rank, (size_t)n * sizeof(u32));
+    *rc = graph_build(g, n, m_in, src, dst, rk);
+    if (*rc) { free(rk); free(g); return 0; }
+    return g;
+}
+
+int orc_graph_list(void *h, int algo, u32 lo, u32 hi, u32 *tri, u64 cap, u64 *out) {
+    graph *g = (graph *)h;
+    unsigned char *B = (unsigned char *)calloc((size_t)g->n + 1, 1);
+    if (!B) return -2;
+    sink s = {0, 0, 0, tri, cap};
+    if (algo == ORC_APP) list_app(g, lo, hi, B, &s);
+    else if (algo == ORC_APM) list_apm(g, lo, hi, B, &s);
+    else if (algo == ORC_AMM) list_amm(g, lo, hi, B, &s);
+    else { free(B); return -1; }
+    out[0] = s.count;
+    out[1] = s.hash;
+    out[2] = s.work;
+    out[3] = g->m;
+    free(B);
+    return 0;
+}
+
+void orc_graph_free(void *h) {
+    graph *g = (graph *)h;
+    if (!g) return;
+    free((void *)g->rank);
+    graph_free(g);
+    free(g);
+}
+
+/*
  * Definition 1 costs.  out[0] = C++ = sum d+ d+, out[1] = C+- = sum d+ d-,
  * out[2] = sum d- d-, out[3] = m, out[4] = sum d+, out[5] = sum d-.
  */

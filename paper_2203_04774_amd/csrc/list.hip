@@ -96,10 +96,26 @@ struct Tuning {
     u64 queue = 1;               // 1: heavy tasks handed out by an atomic queue
     u64 splits = 1;              // 1: wavefront start seeds precomputed at plan time
     u64 light_blocks_per_cu = 8; // light grid cap
+    u64 reverse = 1;             // 1: REVERSE instead of ARRAY/GLOBAL when B does not fit LDS
+    u64 force_mode = 255;        // testing: use this MODE_* for every heavy pivot where it fits
 };
 Tuning &tuning();
 
-enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2 };
+// How a heavy task tests "y is marked" (y in the pivot's list T):
+//   BITMAP   T's rank window fits LDS: one LDS read (the paper's B)
+//   ARRAY    T itself fits LDS: binary search in LDS
+//   GLOBAL   binary search of T in global memory
+//   REVERSE  test the same edge from y's side: for A++ and A--, y in N-_p
+//            iff p in N+_y; for A+-, y in N+_p iff p in N-_y -- a search of
+//            y's own (short, under degree-like orders) sorted list
+enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2, MODE_REVERSE = 3 };
+
+// the list searched by MODE_REVERSE for an element y of the scanned list
+template <int ALGO>
+struct Reverse {
+    static __device__ __forceinline__ const u64 *off(const GView &g) { return ALGO == 1 ? g.off_b : g.off_f; }
+    static __device__ __forceinline__ const u32 *adj(const GView &g) { return ALGO == 1 ? g.adj_b : g.adj_f; }
+};
 
 constexpr int HW = HB / 64;    // wavefronts per heavy workgroup
 
@@ -172,7 +188,7 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len
 template <int ALGO>
 __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask,
                                                     u64 *slice, u64 heavy_min, u64 slice_min, u64 slice_mult,
-                                                    u64 *acc) {
+                                                    u64 reverse, u64 force_mode, u64 *acc) {
     __shared__ u64 lds[PB / WAVE];
     u64 hp = 0, staged = 0;
     GRID_STRIDE(p, n) {
@@ -190,7 +206,12 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             // the bitmap is kept clear between tasks, so marking and
             // unmarking cost 2 |T| (the paper's set/reset of B)
             u64 stage;
-            if (bm_ok) { md = MODE_BITMAP; stage = 2 * tlen; }
+            if (force_mode == MODE_BITMAP && bm_ok) { md = MODE_BITMAP; stage = 2 * tlen; }
+            else if (force_mode == MODE_ARRAY && arr_ok) { md = MODE_ARRAY; stage = 2 * tlen; }
+            else if (force_mode == MODE_GLOBAL) { md = MODE_GLOBAL; stage = 0; }
+            else if (force_mode == MODE_REVERSE) { md = MODE_REVERSE; stage = 0; }
+            else if (bm_ok) { md = MODE_BITMAP; stage = 2 * tlen; }
+            else if (reverse) { md = MODE_REVERSE; stage = 0; }
             else if (arr_ok) { md = MODE_ARRAY; stage = 2 * tlen; }
             else { md = MODE_GLOBAL; stage = 0; }
             sl = slice_mult * stage;
@@ -560,6 +581,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             ti = blockIdx.x + it * gridDim.x;
         }
         if (ti >= ntasks) break;
+        if (use_queue && tasks[ti].a >= k1) break;  // sorted: no later task overlaps [k0, k1)
         // fields are read one by one: copying the struct and indexing its
         // per-wavefront array would put it in scratch memory
         const Task &tg = tasks[ti];
@@ -597,6 +619,12 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                 } else if (tk.mode == MODE_ARRAY) {
                     const u64 j = lower_bound_dev<u32>(lds, 0, tlen, y);
                     return j < tlen && lds[j] == y;
+                } else if (tk.mode == MODE_REVERSE) {
+                    const u64 *ro = Reverse<ALGO>::off(g);
+                    const u32 *ra = Reverse<ALGO>::adj(g);
+                    const u64 r0 = ro[y], r1 = ro[y + 1];
+                    const u64 j = lower_bound_dev<u32>(ra, r0, r1, p);
+                    return j < r1 && ra[j] == p;
                 }
                 const u64 j = lower_bound_dev<u32>(pa, t0, t1, y);
                 return j < t1 && pa[j] == y;
@@ -673,6 +701,17 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
     flush_counts(cnt, hsh, o.acc);
 }
 
+// Heavy tasks are ordered by item range: start the queue at the first task
+// that reaches past k0 (chunked listings probe one item slice at a time).
+__global__ void k_task_first(const Task *tasks, u64 ntasks, u64 k0, u64 *queue) {
+    u64 lo = 0, hi = ntasks;
+    while (lo < hi) {
+        const u64 mid = lo + (hi - lo) / 2;
+        if (tasks[mid].b <= k0) lo = mid + 1; else hi = mid;
+    }
+    *queue = lo;
+}
+
 // Copies spilled (or misplaced) triangles into holes: one move per block.
 
 __global__ void k_apply_moves(const Move *mv, u64 nmv, u32 *tri, u64 cap, const u32 *spill) {
@@ -727,7 +766,8 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
     DevBuf mode((u64)n * sizeof(u32), s), ntask((u64)n * sizeof(u32), s), slice((u64)n * sizeof(u64), s);
     const Tuning &tu = tuning();
     hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), mode.as<u32>(),
-                       ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult, d_acc);
+                       ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult,
+                       tu.reverse, tu.force_mode, d_acc);
     TL_HIP(hipGetLastError());
     DevBuf flags(m * sizeof(u64), s), pos((m + 1) * sizeof(u64), s);
     hipLaunchKernelGGL((k_seed_class<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), mode.as<u32>(),
@@ -800,6 +840,10 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
     const u64 h0 = k0 > P.w_light ? k0 : P.w_light, h1 = k1;
     if (h0 < h1 && P.ntasks) {
         PhaseTimer theavy(TL_PHASE_PROBE_HEAVY, s);
+        if (tuning().queue) {
+            hipLaunchKernelGGL(k_task_first, dim3(1), dim3(1), 0, s, P.tasks.as<Task>(), P.ntasks, h0, o.acc + 5);
+            TL_HIP(hipGetLastError());
+        }
         u64 blocks = P.ntasks;
         if (blocks > heavy_max_blocks()) blocks = heavy_max_blocks();
         if (emit)
@@ -852,6 +896,8 @@ Tuning &tuning() {
         env("TL_TUNE_QUEUE", d.queue);
         env("TL_TUNE_SPLITS", d.splits);
         env("TL_TUNE_LIGHT_BLOCKS_PER_CU", d.light_blocks_per_cu);
+        env("TL_TUNE_REVERSE", d.reverse);
+        env("TL_TUNE_FORCE_MODE", d.force_mode);
         return d;
     }();
     return t;
@@ -896,6 +942,8 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "queue" && value <= 1) t.queue = value;
     else if (k == "splits" && value <= 1) t.splits = value;
     else if (k == "light_blocks_per_cu" && value >= 1 && value <= 64) t.light_blocks_per_cu = value;
+    else if (k == "reverse" && value <= 1) t.reverse = value;
+    else if (k == "force_mode" && (value <= MODE_REVERSE || value == 255)) t.force_mode = value;
     else return TL_EINVAL;
     return TL_OK;
 }
@@ -910,6 +958,8 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "queue") *value = t.queue;
     else if (k == "splits") *value = t.splits;
     else if (k == "light_blocks_per_cu") *value = t.light_blocks_per_cu;
+    else if (k == "reverse") *value = t.reverse;
+    else if (k == "force_mode") *value = t.force_mode;
     else return TL_EINVAL;
     return TL_OK;
 }
@@ -1001,7 +1051,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
         u64 prev_count = 0;
         for (u64 k0 = 0; k0 < h_total; k0 += K) {
             const u64 k1 = (h_total - k0 > K) ? k0 + K : h_total;
-            TL_HIP(hipMemsetAsync(d_acc + 3, 0, 3 * sizeof(u64), s));  // cursor, holes, task queue
+            TL_HIP(hipMemsetAsync(d_acc + 3, 0, 2 * sizeof(u64), s));  // cursor and holes
             probe(k0, k1, true);
             d2h_sync(s, {{h_acc, d_acc, sizeof h_acc}});
             const u64 got = h_acc[0] - prev_count;

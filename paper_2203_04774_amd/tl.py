@@ -53,11 +53,13 @@ def _load():
     lib.tl_csr_free.argtypes = [vp]
     lib.tl_csr_free.restype = None
     lib.tl_set_chunk_triangles.argtypes = [u64]
+    lib.tl_set_tuning.argtypes = [ctypes.c_char_p, u64]
+    lib.tl_get_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(u64)]
     lib.tl_strerror.argtypes = [i32]
     lib.tl_strerror.restype = ctypes.c_char_p
     lib.tl_last_error.restype = ctypes.c_char_p
     for f in ("tl_orient", "tl_cost", "tl_list", "tl_list_range", "tl_csr_size",
-              "tl_csr_copy_to_host", "tl_set_chunk_triangles"):
+              "tl_csr_copy_to_host", "tl_set_chunk_triangles", "tl_set_tuning", "tl_get_tuning"):
         getattr(lib, f).restype = i32
     return lib
 
@@ -182,6 +184,17 @@ def list_triangles(g: Csr, algo: str = "A++", out: torch.Tensor | None = None, o
 
 def set_chunk_triangles(k: int):
     _check(_lib.tl_set_chunk_triangles(k), "tl_set_chunk_triangles")
+
+
+def set_tuning(key: str, value: int):
+    """tl_set_tuning: launch parameters (results never depend on them)."""
+    _check(_lib.tl_set_tuning(key.encode(), int(value)), f"tl_set_tuning({key})")
+
+
+def get_tuning(key: str) -> int:
+    v = ctypes.c_uint64()
+    _check(_lib.tl_get_tuning(key.encode(), ctypes.byref(v)), f"tl_get_tuning({key})")
+    return int(v.value)
 
 
 def raw_lib():

@@ -322,3 +322,69 @@ def test_chunglu20_full_sorted_list(tl, chunglu20, algo):
     ref = oracle.list_triangles(gr.n, gr.src, gr.dst, r, algo)
     assert (st.count, st.hash, st.work) == (ref.count, ref.hash, ref.work)
     assert np.array_equal(packed_sorted(tri), packed_sorted(ref.triangles))
+
+
+# ---------------------------------------------------- every probe path
+
+TUNINGS = {
+    "all-light": {"heavy_min": 1 << 40},
+    "bitmap": {"heavy_min": 1, "force_mode": 0},
+    "array": {"heavy_min": 1, "force_mode": 1},
+    "global": {"heavy_min": 1, "force_mode": 2},
+    "reverse": {"heavy_min": 1, "force_mode": 3},
+    "tiny-tasks-static": {"heavy_min": 1, "slice_min": 64, "slice_mult": 1, "queue": 0, "splits": 0},
+    "tiny-tasks-queue": {"heavy_min": 1, "slice_min": 64, "slice_mult": 1, "queue": 1, "splits": 1},
+}
+
+
+@pytest.fixture
+def tuned(tl, request):
+    cfg = TUNINGS[request.param]
+    saved = {k: tl.get_tuning(k) for k in cfg}
+    for k, v in cfg.items():
+        tl.set_tuning(k, v)
+    yield request.param
+    for k, v in saved.items():
+        tl.set_tuning(k, v)
+
+
+@pytest.mark.parametrize("tuned", list(TUNINGS), indirect=True)
+@pytest.mark.parametrize("algo", ALGOS)
+def test_probe_paths(tl, tuned, algo):
+    """Each membership mode and task schedule, forced, against the oracle:
+    random graphs (short and long windows), closed forms, RMAT-12 under the
+    three orderings, and a chunked listing whose slices clip tasks."""
+    for seed in range(6):
+        n, s, d, r = rand_case(700 + seed)
+        assert_same(tl, n, s, d, r, algo)
+    n, s, d = G.complete(150)
+    assert_same(tl, n, s, d, np.random.default_rng(3).permutation(n).astype(np.uint32), algo)
+    n, s, d = G.wheel(3000)
+    assert_same(tl, n, s, d, np.arange(n, dtype=np.uint32)[::-1].copy(), algo)
+    gr = graphgen.config_rmat12(seed=3)
+    for kind in ["degree", "random"]:
+        assert_same(tl, gr.n, gr.src, gr.dst, graphgen.ordering(gr, kind, seed=2), algo)
+    # chunked: slices of 5000 items cut through heavy tasks
+    import torch
+    r = graphgen.degree_order(gr)
+    ref = oracle.list_triangles(gr.n, gr.src, gr.dst, r, algo)
+    g = tl.orient(gr.n, dev(gr.src), dev(gr.dst), dev(r))
+    tl.set_chunk_triangles(5000)
+    try:
+        parts = []
+        import ctypes
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+
+        def sink(ptr, k):
+            buf = torch.empty((k, 3), dtype=torch.int32, device="cuda")
+            assert hip.hipMemcpy(buf.data_ptr(), ptr, k * 12, 3) == 0
+            parts.append(buf.cpu().numpy().view(np.uint32))
+            return False
+
+        st = tl.list_triangles(g, algo, on_chunk=sink)
+        assert (st.count, st.hash, st.work) == (ref.count, ref.hash, ref.work)
+        assert np.array_equal(sort_rows(np.vstack(parts)), ref.sorted_triangles())
+    finally:
+        tl.set_chunk_triangles(1 << 24)
+        g.free()

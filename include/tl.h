@@ -156,11 +156,15 @@ void tl_csr_free(tl_csr *g);
  *   light_blocks_per_cu  light-pivot workgroups launched per CU (1..64)
  *   queue                1: heavy tasks handed out by an atomic queue
  *   splits               1: wavefront start seeds precomputed per task
- *   reverse              1: when a heavy pivot's list is too wide for the
- *                        LDS bitmap, test each edge (y, pivot) by searching
- *                        y's own sorted list instead of the pivot's
- *   force_mode           testing: 0 bitmap, 1 array, 2 global, 3 reverse
- *                        for every heavy pivot where it fits; 255 = auto
+ *   hash                 1: a heavy pivot whose list's rank window is too
+ *                        wide for the LDS bitmap keeps the list in an LDS
+ *                        hash table when it fits
+ *   reverse              1: a heavy pivot whose list fits no LDS form tests
+ *                        each edge (y, pivot) by searching y's own sorted
+ *                        list instead of the pivot's
+ *   force_mode           testing: 0 bitmap, 1 array, 2 global, 3 reverse,
+ *                        4 hash for every heavy pivot where it fits;
+ *                        255 = automatic
  * Values apply to later calls in this process; TL_TUNE_<KEY> environment
  * variables (upper case) set the initial values.  Unknown keys or values
  * out of range give TL_EINVAL.

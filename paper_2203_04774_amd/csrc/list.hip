@@ -96,7 +96,8 @@ struct Tuning {
     u64 queue = 1;               // 1: heavy tasks handed out by an atomic queue
     u64 splits = 1;              // 1: wavefront start seeds precomputed at plan time
     u64 light_blocks_per_cu = 8; // light grid cap
-    u64 reverse = 1;             // 1: REVERSE instead of ARRAY/GLOBAL when B does not fit LDS
+    u64 reverse = 0;             // 1: REVERSE instead of GLOBAL for lists that fit no LDS form
+    u64 hash = 0;                // 1: HASH before ARRAY when B's window does not fit LDS
     u64 force_mode = 255;        // testing: use this MODE_* for every heavy pivot where it fits
 };
 Tuning &tuning();
@@ -107,8 +108,19 @@ Tuning &tuning();
 //   GLOBAL   binary search of T in global memory
 //   REVERSE  test the same edge from y's side: for A++ and A--, y in N-_p
 //            iff p in N+_y; for A+-, y in N+_p iff p in N-_y -- a search of
-//            y's own (short, under degree-like orders) sorted list
-enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2, MODE_REVERSE = 3 };
+//            y's own sorted list
+//   HASH     T in an LDS open-addressing table (linear probing, load <= 1/2)
+enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2, MODE_REVERSE = 3, MODE_HASH = 4 };
+
+constexpr u32 HASH_MAX = LDS_WORDS / 2;  // list entries a task's hash table holds
+
+__device__ __forceinline__ u32 hash_bits_for(u32 tlen) {
+    u32 k = 1;
+    while ((1u << k) < 2 * tlen) k++;
+    return k;  // table of 2^k slots, 2^k >= 2 |T|
+}
+
+__device__ __forceinline__ u32 hash_slot(u32 y, u32 k) { return (y * 2654435761u) >> (32 - k); }
 
 // the list searched by MODE_REVERSE for an element y of the scanned list
 template <int ALGO>
@@ -188,7 +200,7 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len
 template <int ALGO>
 __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask,
                                                     u64 *slice, u64 heavy_min, u64 slice_min, u64 slice_mult,
-                                                    u64 reverse, u64 force_mode, u64 *acc) {
+                                                    u64 reverse, u64 use_hash, u64 force_mode, u64 *acc) {
     __shared__ u64 lds[PB / WAVE];
     u64 hp = 0, staged = 0;
     GRID_STRIDE(p, n) {
@@ -210,9 +222,11 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             else if (force_mode == MODE_ARRAY && arr_ok) { md = MODE_ARRAY; stage = 2 * tlen; }
             else if (force_mode == MODE_GLOBAL) { md = MODE_GLOBAL; stage = 0; }
             else if (force_mode == MODE_REVERSE) { md = MODE_REVERSE; stage = 0; }
+            else if (force_mode == MODE_HASH && tlen <= HASH_MAX) { md = MODE_HASH; stage = 2 * tlen + 2 * tlen; }
             else if (bm_ok) { md = MODE_BITMAP; stage = 2 * tlen; }
-            else if (reverse) { md = MODE_REVERSE; stage = 0; }
+            else if (use_hash && tlen <= HASH_MAX) { md = MODE_HASH; stage = 4 * tlen; }
             else if (arr_ok) { md = MODE_ARRAY; stage = 2 * tlen; }
+            else if (reverse) { md = MODE_REVERSE; stage = 0; }
             else { md = MODE_GLOBAL; stage = 0; }
             sl = slice_mult * stage;
             if (sl < slice_min) sl = slice_min;
@@ -495,25 +509,26 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, c
 #pragma unroll
                 for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
                 member_multi(T, t_lo, t_hi, y, h);
-                u32 pinv = 0, xinv = 0;
-                bool have = false;
+                bool any = false;
 #pragma unroll
-                for (int j = 0; j < UN; j++) {
-                    u32 a = 0, b = 0, cc = 0;
-                    if (__ballot(h[j])) {
-                        if (!have) {
-                            pinv = g.inv[p];
-                            xinv = g.inv[Form<ALGO>::seed_adj(g)[e]];
-                            have = true;
-                        }
+                for (int j = 0; j < UN; j++) any |= h[j];
+                if (__ballot(any)) {
+                    const u32 pinv = g.inv[p];
+                    const u32 xinv = g.inv[Form<ALGO>::seed_adj(g)[e]];
+                    u32 yi[UN];
+#pragma unroll
+                    for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+#pragma unroll
+                    for (int j = 0; j < UN; j++) {
+                        u32 a = 0, b = 0, cc = 0;
                         if (h[j]) {
-                            a = pinv; b = xinv; cc = g.inv[y[j]];
+                            a = pinv; b = xinv; cc = yi[j];
                             canon3(a, b, cc);
                             cnt += 1;
                             hsh += tri_digest(a, b, cc);
                         }
+                        em.push(h[j], a, b, cc, o);
                     }
-                    em.push(h[j], a, b, cc, o);
                 }
                 kb += UN * WAVE;
                 cur.advance(kb, cur.c_lo);
@@ -605,6 +620,15 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         } else if (tk.mode == MODE_ARRAY) {
             for (u32 i = threadIdx.x; i < tlen; i += blockDim.x) lds[i] = pa[t0 + i];
             __syncthreads();
+        } else if (tk.mode == MODE_HASH) {
+            // keys stored as value + 1 so that the all-zero LDS reads as empty
+            const u32 hk = hash_bits_for(tlen), hmask = (1u << hk) - 1;
+            for (u64 i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+                const u32 key = pa[i] + 1;
+                u32 h = hash_slot(key - 1, hk);
+                while (atomicCAS(&lds[h], 0u, key) != 0u) h = (h + 1) & hmask;
+            }
+            __syncthreads();
         }
         u64 wb, we;
         wave_share(a, b, (u32)nwv, (u32)wid, wb, we);
@@ -612,6 +636,8 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             const bool exact = use_splits && a == tk.a && b == tk.b;  // not clipped by a chunk slice
             SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tg.ws[wid]) : SeedCursor(cpre, tk.cb, tk.ce, wb);
             const u32 pinv = g.inv[p];
+            u32 xinv = 0;
+            u64 xinv_c = ~0ull;
             auto member = [&](u32 y) -> bool {
                 if (tk.mode == MODE_BITMAP) {
                     const u32 v = y - tmin;
@@ -619,6 +645,15 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                 } else if (tk.mode == MODE_ARRAY) {
                     const u64 j = lower_bound_dev<u32>(lds, 0, tlen, y);
                     return j < tlen && lds[j] == y;
+                } else if (tk.mode == MODE_HASH) {
+                    const u32 hk = hash_bits_for(tlen), hmask = (1u << hk) - 1;
+                    u32 h = hash_slot(y, hk);
+                    for (;;) {  // ends: the table is at most half full
+                        const u32 v = lds[h];
+                        if (v == y + 1) return true;
+                        if (v == 0u) return false;
+                        h = (h + 1) & hmask;
+                    }
                 } else if (tk.mode == MODE_REVERSE) {
                     const u64 *ro = Reverse<ALGO>::off(g);
                     const u32 *ra = Reverse<ALGO>::adj(g);
@@ -632,30 +667,43 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             u64 kb = wb;
             while (kb < we) {
                 if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
-                    // UN full chunks inside one seed window: overlapped loads
+                    // UN full chunks inside one seed window: all loads of the
+                    // group are issued before any of their results is used
                     const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
                     u32 y[UN];
+                    bool h[UN];
 #pragma unroll
                     for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
-                    u32 xinv = 0;
-                    bool have = false;
+                    bool any = false;
+                    if (tk.mode == MODE_ARRAY) {
+                        member_multi(lds, 0, tlen, y, h);  // UN searches interleaved
+                    } else if (tk.mode == MODE_GLOBAL) {
+                        member_multi(pa, t0, t1, y, h);
+                    } else {
 #pragma unroll
-                    for (int j = 0; j < UN; j++) {
-                        const bool hit = member(y[j]);
-                        u32 xa = 0, xb = 0, xc = 0;
-                        if (__ballot(hit)) {
-                            if (!have) {
-                                xinv = g.inv[Form<ALGO>::seed_adj(g)[cseed[cur.c_lo]]];
-                                have = true;
-                            }
-                            if (hit) {
-                                xa = pinv; xb = xinv; xc = g.inv[y[j]];
+                        for (int j = 0; j < UN; j++) h[j] = member(y[j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < UN; j++) any |= h[j];
+                    if (__ballot(any)) {
+                        if (xinv_c != cur.c_lo) {  // inverse of the seed's other endpoint, once per seed
+                            xinv = g.inv[Form<ALGO>::seed_adj(g)[cseed[cur.c_lo]]];
+                            xinv_c = cur.c_lo;
+                        }
+                        u32 yi[UN];
+#pragma unroll
+                        for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+#pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            u32 xa = 0, xb = 0, xc = 0;
+                            if (h[j]) {
+                                xa = pinv; xb = xinv; xc = yi[j];
                                 canon3(xa, xb, xc);
                                 cnt += 1;
                                 hsh += tri_digest(xa, xb, xc);
                             }
+                            em.push(h[j], xa, xb, xc, o);
                         }
-                        em.push(hit, xa, xb, xc, o);
                     }
                     kb += UN * WAVE;
                     cur.advance(kb, cur.c_lo);
@@ -690,6 +738,10 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             __syncthreads();
         } else if (tk.mode == MODE_ARRAY) {
             for (u32 i = threadIdx.x; i < tlen; i += blockDim.x) lds[i] = 0u;
+            __syncthreads();
+        } else if (tk.mode == MODE_HASH) {
+            const u32 slots = 1u << hash_bits_for(tlen);
+            for (u32 i = threadIdx.x; i < slots; i += blockDim.x) lds[i] = 0u;
             __syncthreads();
         }
     }
@@ -767,7 +819,7 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
     const Tuning &tu = tuning();
     hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), mode.as<u32>(),
                        ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult,
-                       tu.reverse, tu.force_mode, d_acc);
+                       tu.reverse, tu.hash, tu.force_mode, d_acc);
     TL_HIP(hipGetLastError());
     DevBuf flags(m * sizeof(u64), s), pos((m + 1) * sizeof(u64), s);
     hipLaunchKernelGGL((k_seed_class<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), mode.as<u32>(),
@@ -897,6 +949,7 @@ Tuning &tuning() {
         env("TL_TUNE_SPLITS", d.splits);
         env("TL_TUNE_LIGHT_BLOCKS_PER_CU", d.light_blocks_per_cu);
         env("TL_TUNE_REVERSE", d.reverse);
+        env("TL_TUNE_HASH", d.hash);
         env("TL_TUNE_FORCE_MODE", d.force_mode);
         return d;
     }();
@@ -943,7 +996,8 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "splits" && value <= 1) t.splits = value;
     else if (k == "light_blocks_per_cu" && value >= 1 && value <= 64) t.light_blocks_per_cu = value;
     else if (k == "reverse" && value <= 1) t.reverse = value;
-    else if (k == "force_mode" && (value <= MODE_REVERSE || value == 255)) t.force_mode = value;
+    else if (k == "hash" && value <= 1) t.hash = value;
+    else if (k == "force_mode" && (value <= MODE_HASH || value == 255)) t.force_mode = value;
     else return TL_EINVAL;
     return TL_OK;
 }
@@ -959,6 +1013,7 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "splits") *value = t.splits;
     else if (k == "light_blocks_per_cu") *value = t.light_blocks_per_cu;
     else if (k == "reverse") *value = t.reverse;
+    else if (k == "hash") *value = t.hash;
     else if (k == "force_mode") *value = t.force_mode;
     else return TL_EINVAL;
     return TL_OK;

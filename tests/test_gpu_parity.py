@@ -332,6 +332,7 @@ TUNINGS = {
     "array": {"heavy_min": 1, "force_mode": 1},
     "global": {"heavy_min": 1, "force_mode": 2},
     "reverse": {"heavy_min": 1, "force_mode": 3},
+    "hash": {"heavy_min": 1, "force_mode": 4},
     "tiny-tasks-static": {"heavy_min": 1, "slice_min": 64, "slice_mult": 1, "queue": 0, "splits": 0},
     "tiny-tasks-queue": {"heavy_min": 1, "slice_min": 64, "slice_mult": 1, "queue": 1, "splits": 1},
 }

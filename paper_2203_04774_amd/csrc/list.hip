@@ -271,7 +271,13 @@ __global__ __launch_bounds__(PB) void k_seed_class(GView g, const u32 *len, cons
 }
 
 // Light seeds first, then heavy seeds, both in seed (pivot-major) order.
-__global__ void k_compact(u64 m, const u32 *len, const u64 *sabs, const u64 *pos, u32 *cseed, u64 *cabs, u32 *clen) {
+// Also records, per compacted seed, the original id of the seed edge's other
+// endpoint, so that a hit needs no dependent lookups to name it.
+// Light seeds also get their candidate range of T and the pivot's id.
+template <int ALGO>
+__global__ void k_compact(GView g, const u32 *len, const u64 *sabs, const u64 *pos, u32 *cseed, u64 *cabs,
+                          u32 *cxinv, u32 *clen, u32 *ctlo, u32 *cthi, u32 *cpinv) {
+    const u64 m = g.m;
     const u64 nl = pos[m] & 0xffffffffull;
     GRID_STRIDE(e, m) {
         const u32 l = len[e];
@@ -281,7 +287,14 @@ __global__ void k_compact(u64 m, const u32 *len, const u64 *sabs, const u64 *pos
             const u64 d = heavy ? nl + (ps >> 32) : (ps & 0xffffffffull);
             cseed[d] = (u32)e;
             cabs[d] = sabs[e];
+            cxinv[d] = g.inv[Form<ALGO>::seed_adj(g)[e]];
             clen[d] = l;
+            if (!heavy) {
+                Seed<ALGO> sd(g, e);
+                ctlo[d] = (u32)sd.t_lo;
+                cthi[d] = (u32)sd.t_hi;
+                cpinv[d] = g.inv[sd.p];
+            }
         }
     }
 }
@@ -368,6 +381,13 @@ struct SeedCursor {
         return c_lo + lo;
     }
 
+    // continue from seed c (known to hold the next item)
+    __device__ __forceinline__ void reset(u64 c) {
+        c_lo = c;
+        base = cpre[c_lo];
+        end = cpre[c_lo + 1];
+    }
+
     // move to the seed of item nk, given c = seed of the last lane's item
     __device__ __forceinline__ void advance(u64 nk, u64 c) {
         if (nk < end) return;
@@ -400,6 +420,33 @@ __device__ __forceinline__ void member_multi(const u32 *T, u64 lo, u64 hi, const
     }
 #pragma unroll
     for (int j = 0; j < UN; j++) hit[j] = T[b[j]] == y[j];
+}
+
+// As member_multi, with a different list T[lo[j], hi[j]) per element.
+__device__ __forceinline__ void member_multi_var(const u32 *T, const u64 (&lo)[UN], const u64 (&hi)[UN],
+                                                 const u32 (&y)[UN], bool (&hit)[UN]) {
+    u64 b[UN], n[UN];
+    u64 nmax = 0;
+#pragma unroll
+    for (int j = 0; j < UN; j++) {
+        b[j] = lo[j];
+        n[j] = hi[j] > lo[j] ? hi[j] - lo[j] : 0;
+        nmax = n[j] > nmax ? n[j] : nmax;
+    }
+    while (nmax > 1) {
+        nmax = 0;
+#pragma unroll
+        for (int j = 0; j < UN; j++) {
+            if (n[j] > 1) {
+                const u64 half = n[j] >> 1;
+                b[j] = (T[b[j] + half] <= y[j]) ? b[j] + half : b[j];
+                n[j] -= half;
+            }
+            nmax = n[j] > nmax ? n[j] : nmax;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < UN; j++) hit[j] = n[j] == 1 && T[b[j]] == y[j];
 }
 
 // Where listed triangles go.  Positions come from a global cursor in blocks
@@ -475,10 +522,18 @@ __device__ __forceinline__ void flush_counts(u64 cnt, u64 hsh, u64 *acc) {
     }
 }
 
-// Light items [k0, k1): each wavefront takes a contiguous run of items.
+// Per-seed arrays of the light items.
+struct LightSeeds {
+    const u64 *cpre, *cabs;
+    const u32 *cxinv, *ctlo, *cthi, *cpinv;
+};
+
+// Light items [k0, k1): each wavefront takes a contiguous run of items and
+// tests each scanned element by binary search in the pivot's list, UN
+// chunks of 64 items at a time whenever they fall in one seed window or in
+// the 64 seeds starting at the current one.
 template <int ALGO, bool EMIT>
-__global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, const u64 *cabs, const u64 *cpre,
-                                                    u64 ncap, u64 k0, u64 k1, Out o) {
+__global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 ncap, u64 k0, u64 k1, Out o) {
     const int lane = lane_id();
     const u64 gw = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
@@ -487,52 +542,94 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, c
     const u64 wb = k0 + gw * per;
     const u64 we = (wb + per < k1) ? wb + per : k1;
     const u32 *SA = Form<ALGO>::scan_adj(g);
+    const u32 *T = Form<ALGO>::piv_adj(g);
     WaveEmitter<EMIT> em;
     u64 cnt = 0, hsh = 0;
+    auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&pv)[UN], const u32 (&xv)[UN]) {
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < UN; j++) any |= h[j];
+        if (!__ballot(any)) return;
+        u32 yi[UN];
+#pragma unroll
+        for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+#pragma unroll
+        for (int j = 0; j < UN; j++) {
+            u32 a = 0, b = 0, c = 0;
+            if (h[j]) {
+                a = pv[j]; b = xv[j]; c = yi[j];
+                canon3(a, b, c);
+                cnt += 1;
+                hsh += tri_digest(a, b, c);
+            }
+            em.push(h[j], a, b, c, o);
+        }
+    };
     if (wb < we) {
-        SeedCursor cur(cpre, 0, ncap, wb);
+        SeedCursor cur(L.cpre, 0, ncap, wb);
         u64 kb = wb;
         while (kb < we) {
             if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
-                // UN full chunks inside one seed window: one pivot list, UN
-                // overlapped searches
-                const u32 e = cseed[cur.c_lo];
-                const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
-                u32 p;
-                u64 t_lo, t_hi;
-                const u32 *T;
-                if (ALGO == 0) { p = g.row_b[e]; T = g.adj_b; t_lo = e + 1; t_hi = g.off_b[p + 1]; }
-                else if (ALGO == 1) { p = g.row_f[e]; T = g.adj_f; t_lo = e + 1; t_hi = g.off_f[p + 1]; }
-                else { p = g.row_f[e]; T = g.adj_b; t_lo = g.off_b[p]; t_hi = g.off_b[p + 1]; }
-                u32 y[UN];
+                // UN full chunks inside one seed window
+                const u64 c = cur.c_lo;
+                const u64 sab = L.cabs[c] + (kb - cur.base) + lane;
+                const u64 t_lo = L.ctlo[c], t_hi = L.cthi[c];
+                u32 y[UN], pv[UN], xv[UN];
                 bool h[UN];
 #pragma unroll
                 for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
                 member_multi(T, t_lo, t_hi, y, h);
-                bool any = false;
+                const u32 pi = L.cpinv[c], xi = L.cxinv[c];
 #pragma unroll
-                for (int j = 0; j < UN; j++) any |= h[j];
-                if (__ballot(any)) {
-                    const u32 pinv = g.inv[p];
-                    const u32 xinv = g.inv[Form<ALGO>::seed_adj(g)[e]];
-                    u32 yi[UN];
-#pragma unroll
-                    for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+                for (int j = 0; j < UN; j++) { pv[j] = pi; xv[j] = xi; }
+                report(y, h, pv, xv);
+                kb += UN * WAVE;
+                cur.advance(kb, c);
+                continue;
+            }
+            if (kb + UN * WAVE <= we) {
+                const u64 ci = cur.c_lo + lane;
+                const bool inw = ci < ncap;
+                const u64 P = inw ? L.cpre[ci] : ~0ull;
+                const u64 pend = (cur.c_lo + WAVE <= ncap) ? L.cpre[cur.c_lo + WAVE] : ~0ull;
+                if (pend >= kb + UN * WAVE) {
+                    // the next UN chunks lie in the 64 seeds from the current one
+                    const u64 A = inw ? L.cabs[ci] : 0ull;
+                    const u32 X = inw ? L.cxinv[ci] : 0u, PI = inw ? L.cpinv[ci] : 0u;
+                    const u32 TL = inw ? L.ctlo[ci] : 0u, TH = inw ? L.cthi[ci] : 0u;
+                    const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                    u32 y[UN], pv[UN], xv[UN];
+                    u64 tl[UN], th[UN];
+                    bool h[UN];
+                    int lo_last = 0;
 #pragma unroll
                     for (int j = 0; j < UN; j++) {
-                        u32 a = 0, b = 0, cc = 0;
-                        if (h[j]) {
-                            a = pinv; b = xinv; cc = yi[j];
-                            canon3(a, b, cc);
-                            cnt += 1;
-                            hsh += tri_digest(a, b, cc);
+                        const u32 kr = (u32)(j * WAVE + lane);
+                        int lo = 0;
+#pragma unroll
+                        for (int st = 32; st > 0; st >>= 1) {
+                            const u32 q = __shfl(Q, lo + st, WAVE);
+                            if (q <= kr) lo += st;
                         }
-                        em.push(h[j], a, b, cc, o);
+                        const u64 rel = (kb + kr) - shfl_u64(P, lo);
+                        y[j] = SA[shfl_u64(A, lo) + rel];
+                        xv[j] = __shfl(X, lo, WAVE);
+                        pv[j] = __shfl(PI, lo, WAVE);
+                        tl[j] = __shfl(TL, lo, WAVE);
+                        th[j] = __shfl(TH, lo, WAVE);
+                        if (j == UN - 1) lo_last = __shfl(lo, WAVE - 1, WAVE);
                     }
+                    member_multi_var(T, tl, th, y, h);
+                    report(y, h, pv, xv);
+                    kb += UN * WAVE;
+                    if (kb < we) {
+                        u64 c = cur.c_lo + (u64)lo_last;
+                        const u64 pn = (lo_last + 1 < WAVE) ? shfl_u64(P, lo_last + 1) : pend;
+                        if (pn <= kb) c++;
+                        cur.reset(c);
+                    }
+                    continue;
                 }
-                kb += UN * WAVE;
-                cur.advance(kb, cur.c_lo);
-                continue;
             }
             const u64 k = kb + lane;
             const bool act = k < we;
@@ -541,19 +638,12 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, c
             bool hit = false;
             u32 a = 0, b = 0, cc = 0;
             if (act) {
-                const u32 e = cseed[c];
-                const u32 y = SA[cabs[c] + rel];
-                u32 p;
-                u64 t_lo, t_hi;
-                const u32 *T;
-                if (ALGO == 0) { p = g.row_b[e]; T = g.adj_b; t_lo = e + 1; t_hi = g.off_b[p + 1]; }
-                else if (ALGO == 1) { p = g.row_f[e]; T = g.adj_f; t_lo = e + 1; t_hi = g.off_f[p + 1]; }
-                else { p = g.row_f[e]; T = g.adj_b; t_lo = g.off_b[p]; t_hi = g.off_b[p + 1]; }
+                const u32 y = SA[L.cabs[c] + rel];
+                const u64 t_lo = L.ctlo[c], t_hi = L.cthi[c];
                 const u64 j = lower_bound_dev<u32>(T, t_lo, t_hi, y);
                 if (j < t_hi && T[j] == y) {
                     hit = true;
-                    const u32 x = Form<ALGO>::seed_adj(g)[e];
-                    a = g.inv[p]; b = g.inv[x]; cc = g.inv[y];
+                    a = L.cpinv[c]; b = L.cxinv[c]; cc = g.inv[y];
                     canon3(a, b, cc);
                     cnt += 1;
                     hsh += tri_digest(a, b, cc);
@@ -572,8 +662,8 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u32 *cseed, c
 // wavefronts share the task's items.  Items are clipped to [k0, k1).
 template <int ALGO, bool EMIT>
 __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, u64 ntasks, const u32 *cseed,
-                                                    const u64 *cabs, const u64 *cpre, u64 k0, u64 k1, Out o,
-                                                    int use_queue, int use_splits) {
+                                                    const u64 *cabs, const u32 *cxinv, const u64 *cpre, u64 k0,
+                                                    u64 k1, Out o, int use_queue, int use_splits) {
     extern __shared__ u32 lds[];  // the pivot list: B as a bitmap, or a sorted array
     const int lane = lane_id(), wid = threadIdx.x / WAVE, nwv = blockDim.x / WAVE;
     const u32 *SA = Form<ALGO>::scan_adj(g);
@@ -664,50 +754,101 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                 const u64 j = lower_bound_dev<u32>(pa, t0, t1, y);
                 return j < t1 && pa[j] == y;
             };
+            // membership of UN elements at once (interleaved where it is a search)
+            auto member_all = [&](const u32 (&y)[UN], bool (&h)[UN]) {
+                if (tk.mode == MODE_ARRAY) {
+                    member_multi(lds, 0, tlen, y, h);
+                } else if (tk.mode == MODE_GLOBAL) {
+                    member_multi(pa, t0, t1, y, h);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < UN; j++) h[j] = member(y[j]);
+                }
+            };
+            // listed triangles of a group: yi gathers issued together
+            auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
+                bool any = false;
+#pragma unroll
+                for (int j = 0; j < UN; j++) any |= h[j];
+                if (!__ballot(any)) return;
+                u32 yi[UN];
+#pragma unroll
+                for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+#pragma unroll
+                for (int j = 0; j < UN; j++) {
+                    u32 xa = 0, xb = 0, xc = 0;
+                    if (h[j]) {
+                        xa = pinv; xb = xv[j]; xc = yi[j];
+                        canon3(xa, xb, xc);
+                        cnt += 1;
+                        hsh += tri_digest(xa, xb, xc);
+                    }
+                    em.push(h[j], xa, xb, xc, o);
+                }
+            };
             u64 kb = wb;
             while (kb < we) {
                 if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
-                    // UN full chunks inside one seed window: all loads of the
-                    // group are issued before any of their results is used
+                    // UN full chunks inside one seed window
                     const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
-                    u32 y[UN];
+                    u32 y[UN], xv[UN];
                     bool h[UN];
 #pragma unroll
                     for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
-                    bool any = false;
-                    if (tk.mode == MODE_ARRAY) {
-                        member_multi(lds, 0, tlen, y, h);  // UN searches interleaved
-                    } else if (tk.mode == MODE_GLOBAL) {
-                        member_multi(pa, t0, t1, y, h);
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < UN; j++) h[j] = member(y[j]);
+                    if (xinv_c != cur.c_lo) {  // once per seed
+                        xinv = cxinv[cur.c_lo];
+                        xinv_c = cur.c_lo;
                     }
 #pragma unroll
-                    for (int j = 0; j < UN; j++) any |= h[j];
-                    if (__ballot(any)) {
-                        if (xinv_c != cur.c_lo) {  // inverse of the seed's other endpoint, once per seed
-                            xinv = g.inv[Form<ALGO>::seed_adj(g)[cseed[cur.c_lo]]];
-                            xinv_c = cur.c_lo;
-                        }
-                        u32 yi[UN];
-#pragma unroll
-                        for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
-#pragma unroll
-                        for (int j = 0; j < UN; j++) {
-                            u32 xa = 0, xb = 0, xc = 0;
-                            if (h[j]) {
-                                xa = pinv; xb = xinv; xc = yi[j];
-                                canon3(xa, xb, xc);
-                                cnt += 1;
-                                hsh += tri_digest(xa, xb, xc);
-                            }
-                            em.push(h[j], xa, xb, xc, o);
-                        }
-                    }
+                    for (int j = 0; j < UN; j++) xv[j] = xinv;
+                    member_all(y, h);
+                    report(y, h, xv);
                     kb += UN * WAVE;
                     cur.advance(kb, cur.c_lo);
                     continue;
+                }
+                if (kb + UN * WAVE <= we) {
+                    // short windows: if the next UN chunks lie in the 64 seeds
+                    // starting at the current one, one load of their prefix,
+                    // scan start and endpoint id serves all UN chunks
+                    const u64 ci = cur.c_lo + lane;
+                    const bool inw = ci < tk.ce;
+                    const u64 P = inw ? cpre[ci] : ~0ull;
+                    const u64 pend = (cur.c_lo + WAVE <= tk.ce) ? cpre[cur.c_lo + WAVE] : ~0ull;
+                    if (pend >= kb + UN * WAVE) {
+                        const u64 A = inw ? cabs[ci] : 0ull;
+                        const u32 X = inw ? cxinv[ci] : 0u;
+                        // prefixes relative to kb (those at or below kb read as 0)
+                        const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                        u32 y[UN], xv[UN];
+                        bool h[UN];
+                        int lo_last = 0;
+#pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            const u32 kr = (u32)(j * WAVE + lane);
+                            int lo = 0;
+#pragma unroll
+                            for (int st = 32; st > 0; st >>= 1) {
+                                const u32 q = __shfl(Q, lo + st, WAVE);
+                                if (q <= kr) lo += st;
+                            }
+                            const u64 rel = (kb + kr) - shfl_u64(P, lo);
+                            y[j] = SA[shfl_u64(A, lo) + rel];
+                            xv[j] = __shfl(X, lo, WAVE);
+                            if (j == UN - 1) lo_last = __shfl(lo, WAVE - 1, WAVE);
+                        }
+                        member_all(y, h);
+                        report(y, h, xv);
+                        kb += UN * WAVE;
+                        if (kb < we) {
+                            // seed of item kb: the last lane's seed, or the next one
+                            u64 c = cur.c_lo + (u64)lo_last;
+                            const u64 pn = (lo_last + 1 < WAVE) ? shfl_u64(P, lo_last + 1) : pend;
+                            if (pn <= kb) c++;
+                            cur.reset(c);
+                        }
+                        continue;
+                    }
                 }
                 const u64 k = kb + lane;
                 const bool act = k < we;
@@ -719,8 +860,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                     const u32 y = SA[cabs[c] + rel];
                     hit = member(y);
                     if (hit) {
-                        const u32 x = Form<ALGO>::seed_adj(g)[cseed[c]];
-                        xa = pinv; xb = g.inv[x]; xc = g.inv[y];
+                        xa = pinv; xb = cxinv[c]; xc = g.inv[y];
                         canon3(xa, xb, xc);
                         cnt += 1;
                         hsh += tri_digest(xa, xb, xc);
@@ -796,7 +936,8 @@ GView view_of(const tl_csr *g) {
 
 // Everything a listing's probe phase needs, produced by the plan.
 struct Plan {
-    DevBuf cseed, cabs, cpre, tasks;
+    DevBuf cseed, cabs, cxinv, cpre, tasks;
+    DevBuf ctlo, cthi, cpinv;  // light seeds only
     u64 ncomp = 0;    // compacted seeds
     u64 nlight = 0;   // ... of which light
     u64 w_light = 0;  // light items [0, w_light)
@@ -830,8 +971,13 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
     P.cabs = DevBuf(m * sizeof(u64), s);
     u32 *clen = (u32 *)flags.p;  // the flags are consumed by the scan: reuse them as lengths
     TL_HIP(hipMemsetAsync(clen, 0, m * sizeof(u32), s));
-    hipLaunchKernelGGL(k_compact, dim3(gm), dim3(PB), 0, s, m, len.as<u32>(), sabs.as<u64>(), pos.as<u64>(),
-                       P.cseed.as<u32>(), P.cabs.as<u64>(), clen);
+    P.cxinv = DevBuf(m * sizeof(u32), s);
+    P.ctlo = DevBuf(m * sizeof(u32), s);
+    P.cthi = DevBuf(m * sizeof(u32), s);
+    P.cpinv = DevBuf(m * sizeof(u32), s);
+    hipLaunchKernelGGL((k_compact<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), sabs.as<u64>(), pos.as<u64>(),
+                       P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(), clen, P.ctlo.as<u32>(),
+                       P.cthi.as<u32>(), P.cpinv.as<u32>());
     TL_HIP(hipGetLastError());
     P.cpre = DevBuf((m + 1) * sizeof(u64), s);
     scan_u32_to_u64(clen, P.cpre.as<u64>(), m, s);
@@ -870,6 +1016,11 @@ inline u64 light_max_blocks() { return (u64)tl_num_cus() * tuning().light_blocks
 inline u64 heavy_max_blocks() { return (u64)tl_num_cus() * tuning().heavy_blocks_per_cu; }
 inline u64 max_holes_per_probe() { return light_max_blocks() * (PB / WAVE) + heavy_max_blocks() * (HB / WAVE); }
 
+inline LightSeeds light_seeds(const Plan &P) {
+    return LightSeeds{P.cpre.as<u64>(), P.cabs.as<u64>(), P.cxinv.as<u32>(), P.ctlo.as<u32>(), P.cthi.as<u32>(),
+                      P.cpinv.as<u32>()};
+}
+
 template <int ALGO>
 void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, const Out &o, hipStream_t s) {
     // light part
@@ -881,11 +1032,11 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
         if (blocks > light_max_blocks()) blocks = light_max_blocks();
         if (blocks < 1) blocks = 1;
         if (emit)
-            hipLaunchKernelGGL((k_probe_light<ALGO, true>), dim3((unsigned)blocks), dim3(PB), 0, s, v,
-                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(), P.ncomp, l0, l1, o);
+            hipLaunchKernelGGL((k_probe_light<ALGO, true>), dim3((unsigned)blocks), dim3(PB), 0, s, v, light_seeds(P),
+                               P.nlight, l0, l1, o);
         else
-            hipLaunchKernelGGL((k_probe_light<ALGO, false>), dim3((unsigned)blocks), dim3(PB), 0, s, v,
-                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(), P.ncomp, l0, l1, o);
+            hipLaunchKernelGGL((k_probe_light<ALGO, false>), dim3((unsigned)blocks), dim3(PB), 0, s, v, light_seeds(P),
+                               P.nlight, l0, l1, o);
         TL_HIP(hipGetLastError());
     }
     // heavy part
@@ -900,11 +1051,13 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
         if (blocks > heavy_max_blocks()) blocks = heavy_max_blocks();
         if (emit)
             hipLaunchKernelGGL((k_probe_heavy<ALGO, true>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
-                               P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(),
+                               P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(),
+                               P.cpre.as<u64>(),
                                h0, h1, o, (int)tuning().queue, (int)tuning().splits);
         else
             hipLaunchKernelGGL((k_probe_heavy<ALGO, false>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
-                               P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cpre.as<u64>(),
+                               P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(),
+                               P.cpre.as<u64>(),
                                h0, h1, o, (int)tuning().queue, (int)tuning().splits);
         TL_HIP(hipGetLastError());
     }

@@ -35,6 +35,9 @@ WORKLOADS = {
                    orders=["degree"], algos=["A++"]),
     "rmat26": dict(desc="RMAT scale 26 edge factor 16 a/b/c/d=.57/.19/.19/.05 seed 1",
                    orders=["degree"], algos=["A++"], emit="chunks", chunk=1 << 30),
+    "batch": dict(desc="independent Chung-Lu graphs i = 0..K-1, n log-uniform in [100, 50000], "
+                       "gamma U(2.0, 2.8), mean degree U(8, 40), seed 1000+i, degree order",
+                  orders=["degree"], algos=["A++"]),
 }
 
 
@@ -107,6 +110,152 @@ def cpu_baseline(g, ranks, budget_s=20.0):
             "intersect_elems_per_s": work / spent}
 
 
+def bench_batch(args):
+    """Batched form: K graphs oriented as one union and listed by one
+    captured pass (per-graph count, digest, work), against the plain form
+    (tl_orient + tl_list per graph) on the same resident inputs."""
+    import ctypes
+
+    import torch
+
+    import graphgen
+    import paper_2203_04774_amd as tl
+
+    K = args.batch_graphs
+    t0 = time.time()
+    B = graphgen.batch(K)
+    M = int(B.ebase[-1])
+    log(f"[bench] {K} graphs, {int(B.n.sum())} vertices, {M} edges generated in {time.time() - t0:.1f}s")
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to("cuda")
+
+    src, dst, rank = dev(B.src), dev(B.dst), dev(B.rank)
+    torch.cuda.synchronize()
+    lib = tl.raw_lib()
+    lib.tl_timing_read.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+
+    def phase(ph):
+        ms, calls = ctypes.c_double(), ctypes.c_uint64()
+        lib.tl_timing_read(ph, ctypes.byref(ms), ctypes.byref(calls))
+        return ms.value, int(calls.value)
+
+    def batched_step():
+        b = tl.batch_orient(B.n, B.m, src, dst, rank)
+        try:
+            table = b.list("A++", use_graph=True)
+            # a second replay of the captured pass (listing only)
+            t = time.perf_counter()
+            table2 = b.list("A++", use_graph=True)
+            replay = time.perf_counter() - t
+            assert np.array_equal(table, table2)
+        finally:
+            b.free()
+        return table, replay
+
+    for i in range(args.warmup):
+        batched_step()
+        log(f"[bench] batched warmup {i + 1}/{args.warmup} done")
+    lib.tl_timing_reset()
+    lib.tl_timing_enable(1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    replays = []
+    for i in range(args.steps):
+        table, rp = batched_step()
+        replays.append(rp)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    lib.tl_timing_enable(0)
+    orient_ms, _ = phase(0)
+    list_ms, list_calls = phase(6)
+    T = int(table[:, 0].sum())
+    W = int(table[:, 2].sum())
+    log(f"[bench] batched: {args.steps} steps in {elapsed:.3f}s, T={T}")
+
+    # plain form over the same resident inputs, one graph at a time
+    tl.release_cached_memory()
+    n_plain = min(K, args.plain_graphs) if args.plain_graphs else K
+    plain = np.zeros((n_plain, 3), np.uint64)
+    views = []
+    for i in range(n_plain):
+        a, b_ = int(B.ebase[i]), int(B.ebase[i + 1])
+        va, vb = int(B.vbase[i]), int(B.vbase[i + 1])
+        views.append((int(B.n[i]), src[a:b_], dst[a:b_], rank[va:vb]))
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for i, (n, s_, d_, r_) in enumerate(views):
+        g = tl.orient(n, s_, d_, r_)
+        x = tl.list_triangles(g, "A++")
+        g.free()
+        plain[i] = (x.count, x.hash, x.work)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - tp
+    same = bool(np.array_equal(plain, table[:n_plain]))
+    T_plain = int(plain[:, 0].sum())
+    log(f"[bench] plain: {n_plain} graphs in {plain_s:.3f}s, equal to batched rows: {same}")
+
+    value = T * args.steps / elapsed
+    plain_value = T_plain / plain_s
+    import hashlib
+    table_sha = hashlib.sha256(np.ascontiguousarray(table, "<u8").tobytes()).hexdigest()
+    expected = None
+    gpath = os.path.join(ROOT, "tests", "golden", "oracle_batch.json")
+    if os.path.exists(gpath):
+        with open(gpath) as f:
+            gold = json.load(f)
+        if gold.get("k") == K:
+            expected = gold["table_sha256"] == table_sha
+    # the listing pass's algorithmic bytes: 4 B per scanned-list element of
+    # the paper's work plus 32 B of seed geometry per edge and 8 B per triangle
+    pass_bytes = 4 * W + 32 * M + 8 * T
+    list_s = list_ms / 1e3 / max(list_calls, 1)
+    res = {
+        "metric": "triangles listed/s + intersect elems/s (%HBM peak); batched vs plain; p99 job ms",
+        "value": value,
+        "unit": "triangles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "batch", "graph": WORKLOADS["batch"]["desc"], "graphs": K,
+                   "n": int(B.n.sum()), "m": M, "algos": ["A++"],
+                   "step": "tl_batch_orient + tl_batch_list (captured HIP graph) + a replay"},
+        "intersect_elems_per_s": W * args.steps / elapsed,
+        "plain": {"value": plain_value, "unit": "triangles/s", "graphs": n_plain, "seconds": plain_s,
+                  "per_graph_equal_to_batched": same},
+        "batched_vs_plain": value / plain_value if plain_value else None,
+        "batched_list_only": {"ms": list_s * 1e3, "triangles_per_s": T / list_s if list_s else None,
+                              "replay_ms": 1e3 * float(np.median(replays))},
+        "orient_ms_per_step": orient_ms / args.steps,
+        "roofline": {"bound": "hbm", "kernel": "tl_batch_list pass", "achieved": pass_bytes / list_s / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pass_bytes / list_s / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None},
+        "table_sha256": table_sha,
+        "oracle_table_match": expected,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        spent, tri, done = 0.0, 0, 0
+        for i in range(K):
+            gi = B.graph(i)
+            t1 = time.perf_counter()
+            L = oracle.list_triangles(gi.n, gi.src, gi.dst, B.ranks(i), "A++", want_triangles=False)
+            spent += time.perf_counter() - t1
+            tri += L.count
+            done += 1
+            if spent > args.cpu_budget:
+                break
+        res["cpu_baseline"] = {"value": tri / spent, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+                               "sample": f"graphs 0..{done - 1} of the batch, one at a time ({spent:.1f} s)"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,11 +266,17 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--batch-graphs", type=int, default=20000, help="graphs in the batch workload")
+    ap.add_argument("--plain-graphs", type=int, default=0,
+                    help="graphs timed one by one for the plain form (0: all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     import ctypes
 

@@ -61,6 +61,10 @@ def _load():
     lib.gg_core_order.restype = None
     lib.gg_core_order.argtypes = [u32, u64, u32p, u32p, u32p, ctypes.c_void_p]
     lib.gg_num_threads.restype = ctypes.c_int
+    f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+    u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+    lib.gg_chung_lu_batch.restype = None
+    lib.gg_chung_lu_batch.argtypes = [u32, u32p, f64p, u64p, u64p, dbl, u64p, u32p, u32p, u32p]
     _lib = lib
     return lib
 
@@ -205,6 +209,54 @@ def batch_graph_params(i: int, base_seed: int = 1000):
 def batch_graph(i: int, base_seed: int = 1000) -> Graph:
     n, gamma, k, seed = batch_graph_params(i, base_seed)
     return chung_lu(n, gamma, k, seed=seed)
+
+
+class GraphBatch:
+    """k graphs stored back to back: graph i has n[i] vertices, its edges
+    (local ids) at [ebase[i], ebase[i+1]) of src/dst and its ordering at
+    [vbase[i], vbase[i+1]) of rank."""
+
+    def __init__(self, n, ebase, src, dst, rank, first=0, base_seed=1000):
+        self.n = np.ascontiguousarray(n, np.uint32)
+        self.ebase = np.ascontiguousarray(ebase, np.uint64)
+        self.vbase = np.zeros(len(self.n) + 1, np.uint64)
+        np.cumsum(self.n, out=self.vbase[1:])
+        self.src, self.dst, self.rank = src, dst, rank
+        self.first, self.base_seed = first, base_seed
+
+    @property
+    def k(self) -> int:
+        return len(self.n)
+
+    @property
+    def m(self) -> np.ndarray:
+        return np.diff(self.ebase)
+
+    def graph(self, i) -> Graph:
+        a, b = int(self.ebase[i]), int(self.ebase[i + 1])
+        return Graph(int(self.n[i]), self.src[a:b], self.dst[a:b], f"batch{self.first + i}")
+
+    def ranks(self, i) -> np.ndarray:
+        return self.rank[int(self.vbase[i]):int(self.vbase[i + 1])]
+
+
+def batch(k: int, first: int = 0, base_seed: int = 1000) -> GraphBatch:
+    """Graphs first .. first+k-1 of the batched workload (each equal to
+    batch_graph(i)) with their degree orders, generated in parallel."""
+    lib = _load()
+    params = [batch_graph_params(first + i, base_seed) for i in range(k)]
+    n = np.array([p[0] for p in params], np.uint32)
+    gamma = np.array([p[1] for p in params], np.float64)
+    samples = np.array([int(round(p[0] * p[2] / 2.0)) for p in params], np.uint64)
+    seeds = np.array([p[3] for p in params], np.uint64)
+    total = int(samples.sum())
+    src = np.empty(max(total, 1), np.uint32)
+    dst = np.empty(max(total, 1), np.uint32)
+    rank = np.empty(max(int(n.sum()), 1), np.uint32)
+    ebase = np.empty(k + 1, np.uint64)
+    lib.gg_chung_lu_batch(k, n, gamma, samples, seeds, 10.0, ebase, src, dst, rank)
+    m = int(ebase[-1])
+    return GraphBatch(n, ebase, src[:m], dst[:m], rank[:int(n.sum())], first, base_seed)
 
 
 def num_threads() -> int:

@@ -158,15 +158,18 @@ u64 gg_rmat(int scale, u64 samples, double a, double b, double c, u64 seed, u32 
 /* Draws `samples` endpoint pairs, each endpoint independently with
  * probability proportional to w_i = (i + i0)^(-1/(gamma-1)), i in [0,n),
  * then simplifies.  Returns m. */
-u64 gg_chung_lu(u32 n, double gamma, double i0, u64 samples, u64 seed, u32 *src, u32 *dst) {
+/* Chung-Lu endpoint pairs: each endpoint is vertex i with probability
+ * proportional to (i + i0)^(-1/(gamma-1)); keys[i] = packed pair (loops as
+ * sentinels).  Threads split the samples when `parallel` is set; the keys do
+ * not depend on it. */
+static void chung_lu_keys(u32 n, double gamma, double i0, u64 samples, u64 seed, u64 *keys, int parallel) {
     u64 key = stream_key(seed, 0x43484c55ULL /* "CHLU" */);
     double *cdf = (double *)malloc((size_t)n * sizeof(double) + 8);
     double ex = -1.0 / (gamma - 1.0), run = 0.0;
     for (u32 i = 0; i < n; i++) { run += pow((double)i + i0, ex); cdf[i] = run; }
     for (u32 i = 0; i < n; i++) cdf[i] /= run;
     cdf[n - 1] = 1.0;
-    u64 *keys = (u64 *)malloc(samples * sizeof(u64) + 8);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (parallel)
     for (long long i = 0; i < (long long)samples; i++) {
         u32 e[2];
         for (int s = 0; s < 2; s++) {
@@ -182,9 +185,114 @@ u64 gg_chung_lu(u32 n, double gamma, double i0, u64 samples, u64 seed, u32 *src,
         keys[i] = pack_edge(e[0], e[1]);
     }
     free(cdf);
+}
+
+u64 gg_chung_lu(u32 n, double gamma, double i0, u64 samples, u64 seed, u32 *src, u32 *dst) {
+    u64 *keys = (u64 *)malloc(samples * sizeof(u64) + 8);
+    chung_lu_keys(n, gamma, i0, samples, seed, keys, 1);
     u64 m = finish_simple(keys, samples, n, src, dst);
     free(keys);
     return m;
+}
+
+static int cmp_u32(const void *a, const void *b) {
+    u32 x = *(const u32 *)a, y = *(const u32 *)b;
+    return x < y ? -1 : x > y;
+}
+
+void gg_degrees(u32 n, u64 m, const u32 *src, const u32 *dst, u32 *deg);
+void gg_degree_order(u32 n, const u32 *deg, u32 *rank);
+
+/* Single-threaded finish_simple: bucket the pairs by smaller endpoint,
+ * sort and deduplicate each bucket.  Same output as finish_simple. */
+static u64 finish_simple_serial(const u64 *keys, u64 nk, u32 n, u32 *src, u32 *dst) {
+    u64 *off = (u64 *)calloc((size_t)n + 1, sizeof(u64));
+    u32 *col = (u32 *)malloc(nk * sizeof(u32) + 4);
+    for (u64 i = 0; i < nk; i++) if (keys[i] != UINT64_MAX) off[(keys[i] >> 32) + 1]++;
+    for (u32 v = 0; v < n; v++) off[v + 1] += off[v];
+    u64 *fill = (u64 *)malloc(((size_t)n + 1) * sizeof(u64));
+    memcpy(fill, off, ((size_t)n + 1) * sizeof(u64));
+    for (u64 i = 0; i < nk; i++)
+        if (keys[i] != UINT64_MAX) col[fill[keys[i] >> 32]++] = (u32)(keys[i] & 0xffffffffu);
+    free(fill);
+    u64 m = 0;
+    for (u32 v = 0; v < n; v++) {
+        u32 *r = col + off[v];
+        u64 len = off[v + 1] - off[v];
+        if (len > 1) qsort(r, len, sizeof(u32), cmp_u32);
+        for (u64 j = 0; j < len; j++) {
+            if (j && r[j] == r[j - 1]) continue;
+            src[m] = v;
+            dst[m] = r[j];
+            m++;
+        }
+    }
+    free(col);
+    free(off);
+    return m;
+}
+
+/* k Chung-Lu graphs generated side by side (one thread per graph), each the
+ * same as gg_chung_lu(n[i], gamma[i], i0, samples[i], seed[i]), followed by
+ * its degree order.  Graph i's edges (local ids, src < dst, sorted) go to
+ * [ebase[i], ebase[i+1]) of src/dst, which must hold sum(samples) entries;
+ * its ranks go to rank[vbase[i] .. + n[i]) with vbase the prefix of n. */
+void gg_chung_lu_batch(u32 k, const u32 *n, const double *gamma, const u64 *samples, const u64 *seed, double i0,
+                       u64 *ebase, u32 *src, u32 *dst, u32 *rank) {
+    u64 *cap = (u64 *)malloc(((size_t)k + 1) * sizeof(u64));
+    u64 *vb = (u64 *)malloc(((size_t)k + 1) * sizeof(u64));
+    u64 *mm = (u64 *)malloc(((size_t)k + 1) * sizeof(u64));
+    cap[0] = 0;
+    vb[0] = 0;
+    for (u32 i = 0; i < k; i++) {
+        cap[i + 1] = cap[i] + samples[i];
+        vb[i + 1] = vb[i] + n[i];
+    }
+#pragma omp parallel
+    {
+        u64 kcap = 0;
+        u64 *keys = NULL;
+        u32 *deg = NULL;
+        u32 dcap = 0;
+#pragma omp for schedule(dynamic, 1)
+        for (long long ii = 0; ii < (long long)k; ii++) {
+            u32 i = (u32)ii;
+            if (samples[i] + 1 > kcap) {
+                free(keys);
+                kcap = samples[i] + 1;
+                keys = (u64 *)malloc(kcap * sizeof(u64));
+            }
+            if (n[i] + 1 > dcap) {
+                free(deg);
+                dcap = n[i] + 1;
+                deg = (u32 *)malloc((size_t)dcap * sizeof(u32));
+            }
+            u64 m = 0;
+            if (n[i] && samples[i]) {
+                chung_lu_keys(n[i], gamma[i], i0, samples[i], seed[i], keys, 0);
+                m = finish_simple_serial(keys, samples[i], n[i], src + cap[i], dst + cap[i]);
+            }
+            mm[i] = m;
+            if (n[i]) {
+                gg_degrees(n[i], m, src + cap[i], dst + cap[i], deg);
+                gg_degree_order(n[i], deg, rank + vb[i]);
+            }
+        }
+        free(keys);
+        free(deg);
+    }
+    /* close the gaps between graphs (each moves toward lower addresses) */
+    ebase[0] = 0;
+    for (u32 i = 0; i < k; i++) {
+        ebase[i + 1] = ebase[i] + mm[i];
+        if (mm[i] && ebase[i] != cap[i]) {
+            memmove(src + ebase[i], src + cap[i], mm[i] * sizeof(u32));
+            memmove(dst + ebase[i], dst + cap[i], mm[i] * sizeof(u32));
+        }
+    }
+    free(cap);
+    free(vb);
+    free(mm);
 }
 
 /* Simplifies an arbitrary edge list (drops loops, dedups undirected pairs).

@@ -147,6 +147,55 @@ int tl_csr_copy_to_host(const tl_csr *g, uint64_t *off_fwd, uint32_t *adj_fwd,
 void tl_csr_free(tl_csr *g);
 
 /*
+ * Batched listing: many independent graphs listed by one pass.
+ *
+ * The problem solved for each graph is the one of tl_orient + tl_list
+ * (Section 1.3 for the orientation, Algorithms 1 and 2 for the listing);
+ * the batch is the disjoint union of the graphs, oriented once, and its
+ * listing attributes every triangle to its graph.  A listing pass allocates
+ * nothing and never waits for the host before its end: with use_graph = 1
+ * it is captured once per algorithm as a HIP graph and replayed.
+ *
+ * tl_batch_orient
+ *   k        number of graphs (>= 1)
+ *   n, m     host arrays of k entries: graph i has n[i] vertices and m[i]
+ *            input edges (any order, loops and duplicates allowed, as for
+ *            tl_orient)
+ *   src,dst  device uint32 arrays of sum(m) entries: graph i's edges occupy
+ *            [m[0] + .. + m[i-1], + m[i]) and use its local ids [0, n[i])
+ *   rank     device uint32 array of sum(n) entries: graph i's permutation of
+ *            [0, n[i]) at [n[0] + .. + n[i-1], + n[i])
+ *   out      receives the handle (owns all device memory of the batch:
+ *            the union's CSR plus listing scratch of about 48 bytes per
+ *            edge, sized once here)
+ *   The inputs are read only during the call.  TL_EINVAL if sum(n) >=
+ *   2^32 - 1, sum(m) >= 2^32, a rank is out of its graph's range or an edge
+ *   endpoint is >= its graph's n (a rank array that is not a permutation
+ *   gives TL_EINVAL as in tl_orient).  TL_ENOMEM if the device is full.
+ *
+ * tl_batch_list
+ *   algo       TL_APP, TL_APM or TL_AMM
+ *   use_graph  1: replay the pass as a captured HIP graph (captured on the
+ *              first call for this algo); 0: launch its kernels directly
+ *   per_graph  host array of 3 * k uint64 (or NULL): for graph i, entries
+ *              3i, 3i+1, 3i+2 receive its triangle count, its digest (as
+ *              tl_list's hash, over the graph's local ids) and its work
+ *   per_graph_dev  device array of 3 * k uint64 (or NULL): the same table,
+ *              written on the stream
+ *   Returns after the pass has finished on the stream.  Calls on one
+ *   handle must not overlap.
+ */
+typedef struct tl_batch tl_batch;
+int tl_batch_orient(uint32_t k, const uint32_t *n, const uint64_t *m, const uint32_t *src, const uint32_t *dst,
+                    const uint32_t *rank, void *stream, tl_batch **out);
+int tl_batch_list(tl_batch *b, tl_algo algo, int use_graph, uint64_t *per_graph, uint64_t *per_graph_dev,
+                  void *stream);
+/* k, the union's vertex count and its simple-edge count (host outputs, any may be NULL). */
+int tl_batch_size(const tl_batch *b, uint32_t *k, uint32_t *n, uint64_t *m);
+/* Releases the batch (NULL is ignored); waits for the device. */
+void tl_batch_free(tl_batch *b);
+
+/*
  * Launch tuning (results never depend on it).  Keys:
  *   heavy_min            items of a pivot before it gets a workgroup (>= 1)
  *   slice_min            items per heavy-pivot task, at least (>= 64)
@@ -210,7 +259,8 @@ enum {
     TL_PHASE_COST = 3,        /* tl_cost */
     TL_PHASE_PROBE_LIGHT = 4, /* the light-pivot probe kernel alone */
     TL_PHASE_PROBE_HEAVY = 5, /* the heavy-pivot probe kernel alone */
-    TL_NUM_PHASES = 6
+    TL_PHASE_BATCH = 6,       /* one tl_batch_list pass (all of its kernels) */
+    TL_NUM_PHASES = 7
 };
 int tl_timing_enable(int on);
 int tl_timing_reset(void);

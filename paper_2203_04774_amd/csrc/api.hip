@@ -325,4 +325,40 @@ const char *tl_strerror(int code) {
 
 const char *tl_last_error(void) { return g_last_error.c_str(); }
 
+int tl_batch_orient(uint32_t k, const uint32_t *n, const uint64_t *m, const uint32_t *src, const uint32_t *dst,
+                    const uint32_t *rank, void *stream, tl_batch **out) {
+    return guarded([&] {
+        TL_REQUIRE(out, TL_EINVAL, "out is NULL");
+        *out = nullptr;
+        *out = batch_orient_impl(k, n, m, src, dst, rank, (hipStream_t)stream);
+        return TL_OK;
+    });
+}
+
+int tl_batch_list(tl_batch *b, tl_algo a, int use_graph, uint64_t *per_graph, uint64_t *per_graph_dev,
+                  void *stream) {
+    return guarded([&] {
+        TL_REQUIRE(b, TL_EINVAL, "NULL handle");
+        TL_REQUIRE(a == TL_APP || a == TL_APM || a == TL_AMM, TL_EINVAL, "unknown algorithm");
+        batch_list_impl(b, (int)a, (hipStream_t)stream, use_graph ? 1 : 0, per_graph, per_graph_dev);
+        return TL_OK;
+    });
+}
+
+int tl_batch_size(const tl_batch *b, uint32_t *k, uint32_t *n, uint64_t *m) {
+    return guarded([&] {
+        TL_REQUIRE(b, TL_EINVAL, "NULL handle");
+        batch_sizes(b, k, n, m);
+        return TL_OK;
+    });
+}
+
+void tl_batch_free(tl_batch *b) {
+    if (!b) return;
+    (void)guarded([&] {
+        batch_free_impl(b);
+        return TL_OK;
+    });
+}
+
 }  // extern "C"

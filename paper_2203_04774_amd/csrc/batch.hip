@@ -1,0 +1,465 @@
+// Batched listing: many independent graphs listed as one.
+//
+// The batch is the disjoint union of its graphs: graph i's vertex v becomes
+// vbase[i] + v and its rank vbase[i] + rank_i[v], so the union's ordering
+// keeps every graph's vertices contiguous in rank space and its triangles
+// are exactly the graphs' triangles.  One orientation builds the union's
+// CSR; one listing pass attributes every triangle (and every seed edge's
+// work) to the graph owning its pivot and accumulates per-graph count,
+// digest (over local ids) and paper work.
+//
+// The listing pipeline allocates nothing and never waits for the host: all
+// of its buffers belong to the batch and all sizes are fixed by the union's
+// n and m, so it is captured once per algorithm as a HIP graph and replayed.
+#include <cstring>
+#include <vector>
+
+#include "tl_internal.h"
+#include "dev_util.h"
+#include "probe_common.h"
+#include "timing.h"
+
+namespace {
+
+constexpr int BB = 256;
+
+__global__ void k_fill_u64(u64 *p, u64 n, u64 v) {
+    GRID_STRIDE(i, n) { p[i] = v; }
+}
+__global__ void k_fill_u32(u32 *p, u64 n, u32 v) {
+    GRID_STRIDE(i, n) { p[i] = v; }
+}
+
+// graph of vertex v: last i with vbase[i] <= v
+__device__ __forceinline__ u32 graph_of(const u32 *vbase, u32 k, u32 v) {
+    return (u32)(upper_bound_dev<u32>(vbase, 0, (u64)k + 1, v) - 1);
+}
+
+__global__ void k_union_vertices(const u32 *rank, const u32 *vbase, u32 k, u32 N, u32 *gid, u32 *urank, u32 *flag) {
+    GRID_STRIDE(v, N) {
+        const u32 g = graph_of(vbase, k, (u32)v);
+        const u32 ng = vbase[g + 1] - vbase[g];
+        const u32 r = rank[v];
+        if (r >= ng) atomicOr(flag, 1u);
+        gid[v] = g;
+        urank[v] = vbase[g] + (r < ng ? r : 0u);
+    }
+}
+
+__global__ void k_union_edges(const u32 *src, const u32 *dst, const u64 *ebase, const u32 *vbase, u32 k, u64 M,
+                              u32 *usrc, u32 *udst, u32 *flag) {
+    GRID_STRIDE(i, M) {
+        const u32 g = (u32)(upper_bound_dev<u64>(ebase, 0, (u64)k + 1, i) - 1);
+        const u32 ng = vbase[g + 1] - vbase[g];
+        u32 a = src[i], b = dst[i];
+        if (a >= ng || b >= ng) {
+            atomicOr(flag, 2u);
+            a = 0;
+            b = 0;  // a self-loop: dropped by the orientation
+        }
+        usrc[i] = vbase[g] + a;
+        udst[i] = vbase[g] + b;
+    }
+}
+
+// Adds v to dest[key] for runs of equal key across the lanes of a wavefront
+// (keys are non-decreasing along lanes); one atomic per run.
+__device__ __forceinline__ void wave_segmented_add(bool valid, u32 key, u64 v, u64 *dest, int stride) {
+    const int lane = lane_id();
+    const u32 kk = valid ? key : 0xffffffffu;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const u64 t = shfl_up_u64(v, d);
+        const u32 q = __shfl_up(kk, d, WAVE);
+        if (lane >= d && q == kk) v += t;
+    }
+    const u32 nk = __shfl_down(kk, 1, WAVE);
+    const bool last = valid && (lane == WAVE - 1 || nk != kk);
+    if (last && v) atomicAdd((unsigned long long *)&dest[(u64)kk * stride], (unsigned long long)v);
+}
+
+// The window of seed e in its scanned list: the part of S between the
+// smallest and the largest candidate of T (no other element can match).
+template <int ALGO>
+__device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u64 &abs) {
+    abs = 0;
+    if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
+        const u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
+        const u64 a = lower_bound_dev<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
+        const u64 b = upper_bound_dev<u32>(sd.S, a, sd.s_hi, tmax);
+        abs = a;
+        return (u32)(b - a);
+    }
+    return 0;
+}
+
+// Per seed edge: whether its window is non-empty, and the paper's work
+// (the scanned list's length) added to the pivot's graph.  pg holds
+// (count, digest, work) per graph.
+template <int ALGO>
+__global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *flag, u64 *pg) {
+    const int lane = lane_id();
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 iters = g.m > first - lane ? (g.m - (first - lane) + stride - 1) / stride : 0;  // wave-uniform
+    for (u64 it = 0; it < iters; it++) {
+        const u64 e = first + it * stride;
+        const bool valid = e < g.m;
+        u32 gr = 0;
+        u64 w = 0;
+        if (valid) {
+            Seed<ALGO> sd(g, e);
+            gr = gid[sd.p];
+            w = sd.s_hi - sd.s_lo;
+            u64 abs;
+            flag[e] = seed_window<ALGO>(sd, abs) ? 1u : 0u;
+        }
+        wave_segmented_add(valid, gr, w, pg + 2, 3);
+    }
+}
+
+struct BSeeds {
+    const u64 *cpre, *cabs;
+    const u32 *cxinv, *ctlo, *cthi, *cpinv, *cgid;
+};
+
+// Seeds with a non-empty window, packed in seed order (pos = prefix of the
+// flags); the window is found again rather than stored for every seed.
+template <int ALGO>
+__global__ void k_bcompact(GView g, const u32 *gid, const u64 *pos, u64 *cabs, u32 *cxinv, u32 *ctlo, u32 *cthi,
+                           u32 *cpinv, u32 *cgid, u32 *clen) {
+    GRID_STRIDE(e, g.m) {
+        const u64 d = pos[e];
+        if (pos[e + 1] != d) {
+            Seed<ALGO> sd(g, e);
+            u64 abs;
+            const u32 l = seed_window<ALGO>(sd, abs);
+            cabs[d] = abs;
+            cxinv[d] = g.inv[sd.x];
+            ctlo[d] = (u32)sd.t_lo;
+            cthi[d] = (u32)sd.t_hi;
+            cpinv[d] = g.inv[sd.p];
+            cgid[d] = gid[sd.p];
+            clen[d] = l;
+        }
+    }
+}
+
+// Per-lane accumulator of (count, digest) for the graph of the lane's
+// current items; graphs only grow along a wavefront's run, so each lane
+// flushes once per graph it leaves.
+struct GraphAcc {
+    u32 gcur = 0xffffffffu;
+    u64 cnt = 0, hsh = 0;
+    __device__ __forceinline__ void add(u32 gr, u64 h, u64 *pg) {
+        if (gr != gcur) {
+            flush(pg);
+            gcur = gr;
+        }
+        cnt += 1;
+        hsh += h;
+    }
+    __device__ __forceinline__ void flush(u64 *pg) {
+        if (cnt) {
+            atomicAdd((unsigned long long *)&pg[3 * (u64)gcur + 0], (unsigned long long)cnt);
+            atomicAdd((unsigned long long *)&pg[3 * (u64)gcur + 1], (unsigned long long)hsh);
+        }
+        cnt = 0;
+        hsh = 0;
+    }
+};
+
+// All items [0, W) with W = cpre[m] read on the device: every wavefront of a
+// fixed grid takes a contiguous run, 4 chunks of 64 at a time when they lie
+// in one window or in the 64 seeds from the current one.
+template <int ALGO>
+__global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u32 *vbase, u64 *pg) {
+    const int lane = lane_id();
+    const u64 ncap = g.m;
+    const u64 W = L.cpre[ncap];
+    const u64 gw = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
+    const u64 per = (((W + nw - 1) / nw) + WAVE - 1) & ~(u64)(WAVE - 1);
+    const u64 wb = gw * per;
+    const u64 we = (wb + per < W) ? wb + per : W;
+    const u32 *SA = Form<ALGO>::scan_adj(g);
+    const u32 *T = Form<ALGO>::piv_adj(g);
+    GraphAcc ga;
+    auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&pv)[UN], const u32 (&xv)[UN],
+                      const u32 (&gv)[UN]) {
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < UN; j++) any |= h[j];
+        if (!__ballot(any)) return;
+        u32 yi[UN], vb[UN];
+#pragma unroll
+        for (int j = 0; j < UN; j++) {
+            yi[j] = h[j] ? g.inv[y[j]] : 0u;
+            vb[j] = h[j] ? vbase[gv[j]] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < UN; j++) {
+            if (h[j]) {
+                u32 a = pv[j] - vb[j], b = xv[j] - vb[j], c = yi[j] - vb[j];
+                canon3(a, b, c);
+                ga.add(gv[j], tri_digest(a, b, c), pg);
+            }
+        }
+    };
+    if (wb < we) {
+        SeedCursor cur(L.cpre, 0, ncap, wb);
+        u64 kb = wb;
+        while (kb < we) {
+            if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
+                const u64 c = cur.c_lo;
+                const u64 sab = L.cabs[c] + (kb - cur.base) + lane;
+                const u64 t_lo = L.ctlo[c], t_hi = L.cthi[c];
+                u32 y[UN], pv[UN], xv[UN], gv[UN];
+                bool h[UN];
+#pragma unroll
+                for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
+                member_multi(T, t_lo, t_hi, y, h);
+                const u32 pi = L.cpinv[c], xi = L.cxinv[c], gi = L.cgid[c];
+#pragma unroll
+                for (int j = 0; j < UN; j++) { pv[j] = pi; xv[j] = xi; gv[j] = gi; }
+                report(y, h, pv, xv, gv);
+                kb += UN * WAVE;
+                cur.advance(kb, c);
+                continue;
+            }
+            if (kb + UN * WAVE <= we) {
+                const u64 ci = cur.c_lo + lane;
+                const bool inw = ci < ncap;
+                const u64 P = inw ? L.cpre[ci] : ~0ull;
+                const u64 pend = (cur.c_lo + WAVE <= ncap) ? L.cpre[cur.c_lo + WAVE] : ~0ull;
+                if (pend >= kb + UN * WAVE) {
+                    const u64 A = inw ? L.cabs[ci] : 0ull;
+                    const u32 X = inw ? L.cxinv[ci] : 0u, PI = inw ? L.cpinv[ci] : 0u, GI = inw ? L.cgid[ci] : 0u;
+                    const u32 TL = inw ? L.ctlo[ci] : 0u, TH = inw ? L.cthi[ci] : 0u;
+                    const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                    u32 y[UN], pv[UN], xv[UN], gv[UN];
+                    u64 tl[UN], th[UN];
+                    bool h[UN];
+                    int lo_last = 0;
+#pragma unroll
+                    for (int j = 0; j < UN; j++) {
+                        const u32 kr = (u32)(j * WAVE + lane);
+                        int lo = 0;
+#pragma unroll
+                        for (int st = 32; st > 0; st >>= 1) {
+                            const u32 q = __shfl(Q, lo + st, WAVE);
+                            if (q <= kr) lo += st;
+                        }
+                        const u64 rel = (kb + kr) - shfl_u64(P, lo);
+                        y[j] = SA[shfl_u64(A, lo) + rel];
+                        xv[j] = __shfl(X, lo, WAVE);
+                        pv[j] = __shfl(PI, lo, WAVE);
+                        gv[j] = __shfl(GI, lo, WAVE);
+                        tl[j] = __shfl(TL, lo, WAVE);
+                        th[j] = __shfl(TH, lo, WAVE);
+                        if (j == UN - 1) lo_last = __shfl(lo, WAVE - 1, WAVE);
+                    }
+                    member_multi_var(T, tl, th, y, h);
+                    report(y, h, pv, xv, gv);
+                    kb += UN * WAVE;
+                    if (kb < we) {
+                        u64 c = cur.c_lo + (u64)lo_last;
+                        const u64 pn = (lo_last + 1 < WAVE) ? shfl_u64(P, lo_last + 1) : pend;
+                        if (pn <= kb) c++;
+                        cur.reset(c);
+                    }
+                    continue;
+                }
+            }
+            const u64 k = kb + lane;
+            const bool act = k < we;
+            u64 rel;
+            const u64 c = cur.locate(kb, k, rel);
+            if (act) {
+                const u32 y = SA[L.cabs[c] + rel];
+                const u64 t_lo = L.ctlo[c], t_hi = L.cthi[c];
+                const u64 j = lower_bound_dev<u32>(T, t_lo, t_hi, y);
+                if (j < t_hi && T[j] == y) {
+                    const u32 gi = L.cgid[c], vb = vbase[gi];
+                    u32 a = L.cpinv[c] - vb, b = L.cxinv[c] - vb, cc = g.inv[y] - vb;
+                    canon3(a, b, cc);
+                    ga.add(gi, tri_digest(a, b, cc), pg);
+                }
+            }
+            kb += WAVE;
+            cur.advance(kb, c);
+        }
+    }
+    ga.flush(pg);
+}
+
+unsigned grid_b(u64 items) { return grid_for(items, BB, (unsigned)tl_num_cus() * 16); }
+
+}  // namespace
+
+struct tl_batch {
+    u32 k = 0, N = 0;
+    u64 M = 0;
+    tl_csr *g = nullptr;
+    u32 *gid = nullptr, *vbase = nullptr;
+    // listing scratch, owned for the batch's lifetime
+    u32 *flag = nullptr, *cxinv = nullptr, *ctlo = nullptr, *cthi = nullptr, *cpinv = nullptr,
+        *cgid = nullptr, *clen = nullptr;
+    u64 *pos = nullptr, *cabs = nullptr, *cpre = nullptr, *ws = nullptr, *pg = nullptr;
+    hipStream_t cap_stream[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    int device = 0;
+};
+
+namespace {
+
+// Enqueue the whole listing pipeline on s (no host waits, no allocation).
+template <int ALGO>
+void enqueue_batch_list(tl_batch *b, hipStream_t s) {
+    const tl_csr *g = b->g;
+    const GView v{g->off_f, g->off_b, g->adj_f, g->adj_b, g->row_f, g->row_b, g->inv, g->m};
+    const u64 m = g->m;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_b(3ull * b->k)), dim3(BB), 0, s, b->pg, 3ull * b->k, 0ull);
+    hipLaunchKernelGGL((k_bplan<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->flag, b->pg);
+    scan_u32_to_u64(b->flag, b->pos, m, s, b->ws);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_b(m)), dim3(BB), 0, s, b->clen, m, 0u);
+    hipLaunchKernelGGL((k_bcompact<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->pos, b->cabs, b->cxinv,
+                       b->ctlo, b->cthi, b->cpinv, b->cgid, b->clen);
+    scan_u32_to_u64(b->clen, b->cpre, m, s, b->ws);
+    const BSeeds L{b->cpre, b->cabs, b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid};
+    hipLaunchKernelGGL((k_bprobe<ALGO>), dim3((unsigned)tl_num_cus() * 8), dim3(BB), 0, s, v, L, b->vbase, b->pg);
+    TL_HIP(hipGetLastError());
+}
+
+void enqueue_for(tl_batch *b, int algo, hipStream_t s) {
+    if (algo == 0) enqueue_batch_list<0>(b, s);
+    else if (algo == 1) enqueue_batch_list<1>(b, s);
+    else enqueue_batch_list<2>(b, s);
+}
+
+}  // namespace
+
+tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, const u32 *dst, const u32 *rank,
+                            hipStream_t s) {
+    TL_REQUIRE(k > 0, TL_EINVAL, "empty batch");
+    TL_REQUIRE(n && m, TL_EINVAL, "NULL size arrays");
+    std::vector<u32> vb(k + 1);
+    std::vector<u64> eb(k + 1);
+    u64 N = 0, M = 0;
+    for (u32 i = 0; i < k; i++) {
+        vb[i] = (u32)N;
+        eb[i] = M;
+        N += n[i];
+        M += m[i];
+        TL_REQUIRE(N < 0xffffffffull, TL_EINVAL, "batch has 2^32 - 1 vertices or more");
+        TL_REQUIRE(M < (1ull << 32), TL_EINVAL, "batch has 2^32 edges or more");
+    }
+    vb[k] = (u32)N;
+    eb[k] = M;
+    TL_REQUIRE(M == 0 || (src && dst), TL_EINVAL, "src/dst is NULL");
+    TL_REQUIRE(N == 0 || rank, TL_EINVAL, "rank is NULL");
+
+    struct Owner {
+        tl_batch *b;
+        ~Owner() { if (b) tl_batch_free(b); }
+    } own{new tl_batch()};
+    tl_batch *b = own.b;
+    b->k = k;
+    b->N = (u32)N;
+    b->M = M;
+    TL_HIP(hipGetDevice(&b->device));
+    b->vbase = (u32 *)tl_dev_alloc((k + 1) * sizeof(u32), s);
+    b->gid = (u32 *)tl_dev_alloc((N ? N : 1) * sizeof(u32), s);
+    DevBuf ebase((k + 1) * sizeof(u64), s), flag(sizeof(u32), s), urank((N ? N : 1) * sizeof(u32), s);
+    DevBuf usrc((M ? M : 1) * sizeof(u32), s), udst((M ? M : 1) * sizeof(u32), s);
+    h2d_sync(b->vbase, vb.data(), (k + 1) * sizeof(u32), s);
+    h2d_sync(ebase.p, eb.data(), (k + 1) * sizeof(u64), s);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, flag.as<u32>(), 1ull, 0u);
+    if (N)
+        hipLaunchKernelGGL(k_union_vertices, dim3(grid_b(N)), dim3(BB), 0, s, rank, b->vbase, k, (u32)N, b->gid,
+                           urank.as<u32>(), flag.as<u32>());
+    if (M)
+        hipLaunchKernelGGL(k_union_edges, dim3(grid_b(M)), dim3(BB), 0, s, src, dst, ebase.as<u64>(), b->vbase, k, M,
+                           usrc.as<u32>(), udst.as<u32>(), flag.as<u32>());
+    TL_HIP(hipGetLastError());
+    u32 h_flag = 0;
+    d2h_sync(s, {{&h_flag, flag.p, sizeof(u32)}});
+    TL_REQUIRE(!(h_flag & 1u), TL_EINVAL, "a graph's rank is not within [0, n)");
+    TL_REQUIRE(!(h_flag & 2u), TL_EINVAL, "an edge endpoint is >= its graph's n");
+    b->g = orient_impl((u32)N, usrc.as<u32>(), udst.as<u32>(), M, urank.as<u32>(), s);
+
+    // listing scratch for the union's m
+    const u64 mm = b->g->m ? b->g->m : 1;
+    b->cxinv = (u32 *)tl_dev_alloc(mm * 4, s);
+    b->ctlo = (u32 *)tl_dev_alloc(mm * 4, s);
+    b->cthi = (u32 *)tl_dev_alloc(mm * 4, s);
+    b->cpinv = (u32 *)tl_dev_alloc(mm * 4, s);
+    b->cgid = (u32 *)tl_dev_alloc(mm * 4, s);
+    b->clen = (u32 *)tl_dev_alloc(mm * 4, s);
+    b->flag = b->clen;  // the flags are consumed by their scan before clen is cleared
+    b->pos = (u64 *)tl_dev_alloc((mm + 1) * 8, s);
+    b->cabs = (u64 *)tl_dev_alloc(mm * 8, s);
+    b->cpre = (u64 *)tl_dev_alloc((mm + 1) * 8, s);
+    b->ws = (u64 *)tl_dev_alloc((scan_workspace_words(mm) + 1) * 8, s);
+    b->pg = (u64 *)tl_dev_alloc(3ull * k * 8, s);
+    TL_HIP(hipStreamSynchronize(s));
+    tl_batch *r = own.b;
+    own.b = nullptr;
+    return r;
+}
+
+void batch_list_impl(tl_batch *b, int algo, hipStream_t s, int use_graph, u64 *per_graph_host, u64 *per_graph_dev) {
+    PhaseTimer timer(TL_PHASE_BATCH, s);
+    if (b->g->m == 0) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_b(3ull * b->k)), dim3(BB), 0, s, b->pg, 3ull * b->k, 0ull);
+        TL_HIP(hipGetLastError());
+    } else if (!use_graph) {
+        enqueue_for(b, algo, s);
+    } else {
+        if (!b->exec[algo]) {
+            // capture on a private stream, so that the caller's stream state
+            // is untouched, then replay on the caller's stream
+            TL_HIP(hipStreamCreateWithFlags(&b->cap_stream[algo], hipStreamNonBlocking));
+            TL_HIP(hipStreamBeginCapture(b->cap_stream[algo], hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue_for(b, algo, b->cap_stream[algo]);
+            } catch (...) {
+                hipGraph_t dead = nullptr;
+                (void)hipStreamEndCapture(b->cap_stream[algo], &dead);
+                if (dead) (void)hipGraphDestroy(dead);
+                throw;
+            }
+            TL_HIP(hipStreamEndCapture(b->cap_stream[algo], &b->graph[algo]));
+            TL_HIP(hipGraphInstantiate(&b->exec[algo], b->graph[algo], nullptr, nullptr, 0));
+        }
+        TL_HIP(hipGraphLaunch(b->exec[algo], s));
+    }
+    if (per_graph_dev) {
+        TL_HIP(hipMemcpyAsync(per_graph_dev, b->pg, 3ull * b->k * 8, hipMemcpyDeviceToDevice, s));
+    }
+    timer.stop();
+    if (per_graph_host) d2h_sync(s, {{per_graph_host, b->pg, 3ull * b->k * 8}});
+    else TL_HIP(hipStreamSynchronize(s));
+}
+
+void batch_free_impl(tl_batch *b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();  // replays on any stream may still read the buffers
+    for (int a = 0; a < 3; a++) {
+        if (b->exec[a]) (void)hipGraphExecDestroy(b->exec[a]);
+        if (b->graph[a]) (void)hipGraphDestroy(b->graph[a]);
+        if (b->cap_stream[a]) (void)hipStreamDestroy(b->cap_stream[a]);
+    }
+    if (b->g) tl_csr_free(b->g);
+    void *bufs[] = {b->gid, b->vbase, b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid,
+                    b->clen, b->pos, b->cabs, b->cpre, b->ws, b->pg};
+    for (void *p : bufs) tl_dev_free(p);
+    delete b;
+}
+
+void batch_sizes(const tl_batch *b, u32 *k, u32 *n, u64 *m) {
+    if (k) *k = b->k;
+    if (n) *n = b->N;
+    if (m) *m = b->g ? b->g->m : 0;
+}

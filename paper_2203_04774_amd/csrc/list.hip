@@ -32,52 +32,9 @@
 #include "dev_util.h"
 #include "timing.h"
 #include "holes.h"
+#include "probe_common.h"
 
 namespace {
-
-struct GView {
-    const u64 *off_f, *off_b;
-    const u32 *adj_f, *adj_b, *row_f, *row_b, *inv;
-    u64 m;
-};
-
-// Seed-edge geometry for the three forms.
-template <int ALGO>
-struct Seed {
-    u32 p, x;          // pivot and the seed edge's other endpoint
-    const u32 *S;      // scanned list base (S[s_lo .. s_hi))
-    u64 s_lo, s_hi;
-    const u32 *T;      // target array, candidates T[t_lo .. t_hi)
-    u64 t_lo, t_hi;
-    __device__ __forceinline__ Seed(const GView &g, u64 e) {
-        if (ALGO == 0) {
-            p = g.row_b[e]; x = g.adj_b[e];
-            S = g.adj_f; s_lo = g.off_f[x]; s_hi = g.off_f[x + 1];
-            T = g.adj_b; t_lo = e + 1; t_hi = g.off_b[p + 1];
-        } else if (ALGO == 1) {
-            p = g.row_f[e]; x = g.adj_f[e];
-            S = g.adj_f; s_lo = g.off_f[x]; s_hi = g.off_f[x + 1];
-            T = g.adj_f; t_lo = e + 1; t_hi = g.off_f[p + 1];
-        } else {
-            p = g.row_f[e]; x = g.adj_f[e];
-            S = g.adj_b; s_lo = g.off_b[x]; s_hi = g.off_b[x + 1];
-            T = g.adj_b; t_lo = g.off_b[p]; t_hi = g.off_b[p + 1];
-        }
-    }
-};
-
-// Arrays that index seeds, scanned lists and pivot lists for a form.
-template <int ALGO>
-struct Form {
-    // seed edges are the entries of this CSR (pivot-major)
-    static __device__ __forceinline__ const u64 *seed_off(const GView &g) { return ALGO == 0 ? g.off_b : g.off_f; }
-    static __device__ __forceinline__ const u32 *seed_adj(const GView &g) { return ALGO == 0 ? g.adj_b : g.adj_f; }
-    // scanned lists
-    static __device__ __forceinline__ const u32 *scan_adj(const GView &g) { return ALGO == 2 ? g.adj_b : g.adj_f; }
-    // pivot (marked) list
-    static __device__ __forceinline__ const u64 *piv_off(const GView &g) { return ALGO == 1 ? g.off_f : g.off_b; }
-    static __device__ __forceinline__ const u32 *piv_adj(const GView &g) { return ALGO == 1 ? g.adj_f : g.adj_b; }
-};
 
 constexpr int PB = 256;        // threads per block, light kernels
 constexpr int HB = 1024;       // threads per block, heavy-pivot kernel
@@ -340,114 +297,6 @@ __global__ void k_task_splits(Task *tasks, u64 ntasks, const u64 *cpre) {
 }
 
 // ---------------------------------------------------------------- probe
-
-// Walks a run of the flattened work space 64 items at a time and gives each
-// lane the compacted seed c with cpre[c] <= k < cpre[c+1] of its item k, and
-// the item's offset inside that seed's window.  When the whole chunk lies in
-// one seed (long windows) no search is needed; otherwise the chunk spans at
-// most 64 seeds starting at the current one, found by a binary search over
-// a 64-entry window of cpre held one entry per lane.
-struct SeedCursor {
-    const u64 *cpre;
-    u64 ncap;         // cpre[0..ncap] is readable
-    u64 c_lo;         // seed of the chunk's first item
-    u64 base, end;    // cpre[c_lo], cpre[c_lo + 1]
-
-    __device__ __forceinline__ SeedCursor(const u64 *cp, u64 lo, u64 nc, u64 first_item) : cpre(cp), ncap(nc) {
-        c_lo = upper_bound_dev<u64>(cpre, lo, ncap + 1, first_item) - 1;
-        base = cpre[c_lo];
-        end = cpre[c_lo + 1];
-    }
-    // when the seed of the first item is already known
-    __device__ __forceinline__ SeedCursor(const u64 *cp, u64 nc, u64 c) : cpre(cp), ncap(nc), c_lo(c) {
-        base = cpre[c_lo];
-        end = cpre[c_lo + 1];
-    }
-
-    __device__ __forceinline__ u64 locate(u64 kb, u64 k, u64 &rel) const {
-        if (end >= kb + WAVE) {  // wave-uniform
-            rel = k - base;
-            return c_lo;
-        }
-        const int lane = lane_id();
-        const u64 P = (c_lo + lane <= ncap) ? cpre[c_lo + lane] : ~0ull;
-        int lo = 0;
-#pragma unroll
-        for (int st = 32; st > 0; st >>= 1) {
-            u64 pv = shfl_u64(P, lo + st);
-            if (pv <= k) lo += st;
-        }
-        rel = k - shfl_u64(P, lo);
-        return c_lo + lo;
-    }
-
-    // continue from seed c (known to hold the next item)
-    __device__ __forceinline__ void reset(u64 c) {
-        c_lo = c;
-        base = cpre[c_lo];
-        end = cpre[c_lo + 1];
-    }
-
-    // move to the seed of item nk, given c = seed of the last lane's item
-    __device__ __forceinline__ void advance(u64 nk, u64 c) {
-        if (nk < end) return;
-        c_lo = shfl_u64(c, WAVE - 1);
-        if (cpre[c_lo + 1] <= nk) c_lo++;
-        base = cpre[c_lo];
-        end = cpre[c_lo + 1];
-    }
-};
-
-constexpr int UN = 4;  // chunks per iteration when they share one seed window
-
-// UN independent branchless membership tests of y[j] in the sorted list
-// T[lo, hi) (the same list for all j), so their loads overlap.
-__device__ __forceinline__ void member_multi(const u32 *T, u64 lo, u64 hi, const u32 (&y)[UN], bool (&hit)[UN]) {
-    u64 n = hi - lo;
-    if (n == 0) {
-#pragma unroll
-        for (int j = 0; j < UN; j++) hit[j] = false;
-        return;
-    }
-    u64 b[UN];
-#pragma unroll
-    for (int j = 0; j < UN; j++) b[j] = lo;
-    while (n > 1) {
-        const u64 half = n >> 1;
-#pragma unroll
-        for (int j = 0; j < UN; j++) b[j] = (T[b[j] + half] <= y[j]) ? b[j] + half : b[j];
-        n -= half;
-    }
-#pragma unroll
-    for (int j = 0; j < UN; j++) hit[j] = T[b[j]] == y[j];
-}
-
-// As member_multi, with a different list T[lo[j], hi[j]) per element.
-__device__ __forceinline__ void member_multi_var(const u32 *T, const u64 (&lo)[UN], const u64 (&hi)[UN],
-                                                 const u32 (&y)[UN], bool (&hit)[UN]) {
-    u64 b[UN], n[UN];
-    u64 nmax = 0;
-#pragma unroll
-    for (int j = 0; j < UN; j++) {
-        b[j] = lo[j];
-        n[j] = hi[j] > lo[j] ? hi[j] - lo[j] : 0;
-        nmax = n[j] > nmax ? n[j] : nmax;
-    }
-    while (nmax > 1) {
-        nmax = 0;
-#pragma unroll
-        for (int j = 0; j < UN; j++) {
-            if (n[j] > 1) {
-                const u64 half = n[j] >> 1;
-                b[j] = (T[b[j] + half] <= y[j]) ? b[j] + half : b[j];
-                n[j] -= half;
-            }
-            nmax = n[j] > nmax ? n[j] : nmax;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < UN; j++) hit[j] = n[j] == 1 && T[b[j]] == y[j];
-}
 
 // Where listed triangles go.  Positions come from a global cursor in blocks
 // of RESERVE triangles per wavefront (one atomic per block, not per hit).

@@ -51,8 +51,17 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_tile_scan(const T *in, u64 n, co
 
 __global__ void k_set_zero(u64 *p) { *p = 0; }
 
+// Scratch (u64 words) a scan of n elements needs for its tile sums.
+u64 scan_ws_words(u64 n) {
+    u64 tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles <= 1) return 0;
+    return tiles + (tiles + 1) + scan_ws_words(tiles);
+}
+
+// ws: caller scratch of scan_ws_words(n) words, or NULL to take it from the
+// pool (a scan into caller scratch allocates nothing and can be captured).
 template <class T>
-void scan_impl(const T *in, u64 *out, u64 n, hipStream_t s) {
+void scan_impl(const T *in, u64 *out, u64 n, hipStream_t s, u64 *ws) {
     if (n == 0) {
         hipLaunchKernelGGL(k_set_zero, dim3(1), dim3(1), 0, s, out);
         TL_HIP(hipGetLastError());
@@ -65,16 +74,22 @@ void scan_impl(const T *in, u64 *out, u64 n, hipStream_t s) {
         TL_HIP(hipGetLastError());
         return;
     }
-    DevBuf sums(tiles * sizeof(u64), s), offs((tiles + 1) * sizeof(u64), s);
-    hipLaunchKernelGGL((k_tile_sums<T>), dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, in, n, sums.as<u64>());
+    DevBuf own;
+    if (!ws) {
+        own = DevBuf(scan_ws_words(n) * sizeof(u64), s);
+        ws = own.as<u64>();
+    }
+    u64 *sums = ws, *offs = ws + tiles, *rest = ws + tiles + (tiles + 1);
+    hipLaunchKernelGGL((k_tile_sums<T>), dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, in, n, sums);
     TL_HIP(hipGetLastError());
-    scan_impl<u64>(sums.as<u64>(), offs.as<u64>(), tiles, s);
-    hipLaunchKernelGGL((k_tile_scan<T>), dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, in, n,
-                       (const u64 *)offs.as<u64>(), out);
+    scan_impl<u64>(sums, offs, tiles, s, rest);
+    hipLaunchKernelGGL((k_tile_scan<T>), dim3((unsigned)tiles), dim3(SCAN_BLOCK), 0, s, in, n, (const u64 *)offs,
+                       out);
     TL_HIP(hipGetLastError());
 }
 
 }  // namespace
 
-void scan_u32_to_u64(const u32 *in, u64 *out, u64 n, hipStream_t s) { scan_impl<u32>(in, out, n, s); }
-void scan_u64_to_u64(const u64 *in, u64 *out, u64 n, hipStream_t s) { scan_impl<u64>(in, out, n, s); }
+void scan_u32_to_u64(const u32 *in, u64 *out, u64 n, hipStream_t s, u64 *ws) { scan_impl<u32>(in, out, n, s, ws); }
+void scan_u64_to_u64(const u64 *in, u64 *out, u64 n, hipStream_t s, u64 *ws) { scan_impl<u64>(in, out, n, s, ws); }
+u64 scan_workspace_words(u64 n) { return scan_ws_words(n); }

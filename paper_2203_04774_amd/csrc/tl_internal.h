@@ -105,8 +105,10 @@ inline unsigned grid_for(u64 items, unsigned block, unsigned max_blocks = 65535u
 }
 
 // exclusive scan: out[i] = sum_{j<i} in[j] for i in [0, n]; out[n] = total.
-void scan_u32_to_u64(const u32 *in, u64 *out, u64 n, hipStream_t s);
-void scan_u64_to_u64(const u64 *in, u64 *out, u64 n, hipStream_t s);
+// ws: scratch of scan_workspace_words(n) u64, or NULL to use the pool.
+void scan_u32_to_u64(const u32 *in, u64 *out, u64 n, hipStream_t s, u64 *ws = nullptr);
+void scan_u64_to_u64(const u64 *in, u64 *out, u64 n, hipStream_t s, u64 *ws = nullptr);
+u64 scan_workspace_words(u64 n);
 
 // Sort every row of a CSR ascending and drop repeated values inside a row;
 // uniq[r] receives the row's distinct count and the distinct values are
@@ -124,3 +126,10 @@ int set_tuning(const char *key, u64 value);
 tl_list_stats &last_stats();
 int get_tuning(const char *key, u64 *value);
 void set_chunk_triangles(u64 k);
+
+// Batched listing (batch.hip).
+tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, const u32 *dst, const u32 *rank,
+                            hipStream_t s);
+void batch_list_impl(tl_batch *b, int algo, hipStream_t s, int use_graph, u64 *per_graph_host, u64 *per_graph_dev);
+void batch_free_impl(tl_batch *b);
+void batch_sizes(const tl_batch *b, u32 *k, u32 *n, u64 *m);

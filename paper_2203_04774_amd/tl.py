@@ -55,11 +55,19 @@ def _load():
     lib.tl_set_chunk_triangles.argtypes = [u64]
     lib.tl_set_tuning.argtypes = [ctypes.c_char_p, u64]
     lib.tl_get_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(u64)]
+    lib.tl_batch_orient.argtypes = [u32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.tl_batch_list.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.tl_batch_size.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)]
+    lib.tl_batch_free.argtypes = [vp]
+    lib.tl_batch_free.restype = None
+    lib.tl_release_cached_memory.argtypes = []
+    lib.tl_release_cached_memory.restype = i32
     lib.tl_strerror.argtypes = [i32]
     lib.tl_strerror.restype = ctypes.c_char_p
     lib.tl_last_error.restype = ctypes.c_char_p
     for f in ("tl_orient", "tl_cost", "tl_list", "tl_list_range", "tl_csr_size",
-              "tl_csr_copy_to_host", "tl_set_chunk_triangles", "tl_set_tuning", "tl_get_tuning"):
+              "tl_csr_copy_to_host", "tl_set_chunk_triangles", "tl_set_tuning", "tl_get_tuning",
+              "tl_batch_orient", "tl_batch_list", "tl_batch_size"):
         getattr(lib, f).restype = i32
     return lib
 
@@ -180,6 +188,74 @@ def list_triangles(g: Csr, algo: str = "A++", out: torch.Tensor | None = None, o
         return s
     _check(rc, "tl_list")
     return s
+
+
+class Batch:
+    """Handle of a batch of graphs returned by :func:`batch_orient`."""
+
+    def __init__(self, handle):
+        self._h = handle
+        k, n, m = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        _check(_lib.tl_batch_size(handle, ctypes.byref(k), ctypes.byref(n), ctypes.byref(m)), "tl_batch_size")
+        self.k, self.n, self.m = int(k.value), int(n.value), int(m.value)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("handle already freed")
+        return self._h
+
+    def list(self, algo: str = "A++", use_graph: bool = True, out_dev: torch.Tensor | None = None,
+             stream=None):
+        """tl_batch_list: returns a (k, 3) uint64 numpy array of per-graph
+        (count, digest, work); out_dev (device int64 tensor of 3k entries)
+        also receives the table on the stream when given."""
+        import numpy as np
+        table = np.zeros(3 * self.k, np.uint64)
+        dptr = None
+        if out_dev is not None:
+            if not out_dev.is_cuda or out_dev.dtype not in (torch.int64, torch.uint64) \
+                    or out_dev.numel() != 3 * self.k or not out_dev.is_contiguous():
+                raise ValueError("out_dev must be a contiguous device int64 tensor of 3k entries")
+            dptr = ctypes.c_void_p(out_dev.data_ptr())
+        _check(_lib.tl_batch_list(self.handle, ALGOS[algo], 1 if use_graph else 0, table.ctypes.data, dptr,
+                                  _stream_ptr(stream)), "tl_batch_list")
+        return table.reshape(self.k, 3)
+
+    def free(self):
+        if self._h is not None:
+            _lib.tl_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def batch_orient(n, m, src: torch.Tensor, dst: torch.Tensor, rank: torch.Tensor, stream=None) -> Batch:
+    """tl_batch_orient: n, m per-graph sizes (host sequences); src/dst the
+    graphs' edges back to back (local ids), rank their orderings back to
+    back (device int32 tensors)."""
+    import numpy as np
+    n_h = np.ascontiguousarray(n, np.uint32)
+    m_h = np.ascontiguousarray(m, np.uint64)
+    if n_h.shape != m_h.shape or n_h.ndim != 1 or len(n_h) == 0:
+        raise ValueError("n and m must be 1-d of the same non-zero length")
+    if src.numel() != int(m_h.sum()) or dst.numel() != src.numel():
+        raise ValueError("src/dst length differs from sum(m)")
+    if rank.numel() != int(n_h.sum()):
+        raise ValueError("rank length differs from sum(n)")
+    h = ctypes.c_void_p()
+    _check(_lib.tl_batch_orient(len(n_h), n_h.ctypes.data, m_h.ctypes.data, _dptr(src, "src"), _dptr(dst, "dst"),
+                                _dptr(rank, "rank"), _stream_ptr(stream), ctypes.byref(h)), "tl_batch_orient")
+    return Batch(h)
+
+
+def release_cached_memory():
+    """tl_release_cached_memory: hand cached device blocks back to the driver."""
+    _check(_lib.tl_release_cached_memory(), "tl_release_cached_memory")
 
 
 def set_chunk_triangles(k: int):

@@ -211,6 +211,31 @@ def batch_graph(i: int, base_seed: int = 1000) -> Graph:
     return chung_lu(n, gamma, k, seed=seed)
 
 
+def serve_job_params(j: int, base_seed: int = 5000) -> dict:
+    """Job j of the serving workload: RMAT or Chung-Lu (equally likely), a
+    target edge count log-uniform in [10^3, 10^7], degree or core order
+    (equally likely); Chung-Lu exponent uniform in [2.0, 2.8]."""
+    rs = np.random.Generator(np.random.PCG64(base_seed + j))
+    kind = "rmat" if rs.random() < 0.5 else "chunglu"
+    m = int(math.floor(math.exp(rs.uniform(math.log(1e3), math.log(1e7)))))
+    order = "degree" if rs.random() < 0.5 else "core"
+    gamma = float(rs.uniform(2.0, 2.8))
+    return dict(j=j, kind=kind, m_target=m, order=order, gamma=gamma, seed=base_seed + j)
+
+
+def serve_job(j: int, base_seed: int = 5000):
+    """(graph, rank, params) of serving job j: RMAT with scale
+    ceil(log2(m/8)) and edge factor 8, or Chung-Lu with n = m/10 and mean
+    degree 20."""
+    p = serve_job_params(j, base_seed)
+    if p["kind"] == "rmat":
+        scale = max(1, math.ceil(math.log2(p["m_target"] / 8)))
+        g = rmat(scale, 8, seed=p["seed"])
+    else:
+        g = chung_lu(max(p["m_target"] // 10, 2), p["gamma"], 20.0, seed=p["seed"])
+    return g, ordering(g, p["order"]), p
+
+
 class GraphBatch:
     """k graphs stored back to back: graph i has n[i] vertices, its edges
     (local ids) at [ebase[i], ebase[i+1]) of src/dst and its ordering at

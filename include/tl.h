@@ -196,6 +196,71 @@ int tl_batch_size(const tl_batch *b, uint32_t *k, uint32_t *n, uint64_t *m);
 void tl_batch_free(tl_batch *b);
 
 /*
+ * Listing server: continuous batching of listing jobs under a device
+ * memory budget.
+ *
+ * Each job is the problem of tl_orient + tl_list for one graph (Section 1.3,
+ * Algorithms 1 and 2).  Jobs wait in arrival order; a job is admitted when
+ * its modelled device footprint (about 72 bytes per input edge plus 64 per
+ * vertex) fits the budget beside the jobs already admitted.  Admitted jobs
+ * are uploaded, oriented as one disjoint union and listed by the batched
+ * pass, while the next batch is uploaded and oriented on a second stream;
+ * a job with at least solo_edges edges is oriented and listed alone by the
+ * plain listing.  A job whose footprint alone exceeds the budget finishes
+ * with TL_ENOMEM; a malformed job (an endpoint >= n, a rank array that is
+ * not a permutation) finishes with TL_EINVAL without failing the jobs
+ * batched with it.  Results never depend on how jobs were batched.
+ */
+typedef struct tl_server tl_server;
+typedef struct {
+    uint64_t hbm_budget;      /* device bytes the admitted jobs may use (> 0) */
+    uint32_t max_batch_jobs;  /* jobs per batch, at most (0: 4096) */
+    uint64_t max_batch_edges; /* input edges per batch, at most (0: 2^27) */
+    uint64_t solo_edges;      /* jobs with at least this many edges run alone (0: 2^21) */
+    uint32_t pipeline;        /* 1: orient the next batch while one lists */
+} tl_server_config;
+
+typedef struct {
+    uint32_t n;               /* vertices */
+    uint64_t m;               /* input edges */
+    const uint32_t *src, *dst;/* host arrays of m entries */
+    const uint32_t *rank;     /* host array of n entries: the ordering */
+    tl_algo algo;
+} tl_job;                     /* the arrays must stay valid until the job is final */
+
+#define TL_JOB_PENDING (-1)
+typedef struct {
+    int status;               /* TL_JOB_PENDING, TL_OK, TL_EINVAL, TL_ENOMEM, TL_EABORT (cancelled), TL_EHIP */
+    uint64_t count, hash, work; /* as tl_summary, when status is TL_OK */
+    uint64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns; /* steady clock */
+    uint64_t batch_id;        /* the batch that listed the job */
+    uint32_t batch_jobs;      /* jobs in that batch */
+} tl_job_result;
+
+typedef struct {
+    uint64_t submitted, jobs_done, batches, rejected, cancelled, split_batches;
+    uint64_t reserved, peak_reserved, pending, max_batch_jobs_seen;
+} tl_server_stats;
+
+/* Starts the server's two threads on the current device. */
+int tl_server_create(const tl_server_config *cfg, tl_server **out);
+/* Queues a job (never blocks on the device); *id identifies it. */
+int tl_server_submit(tl_server *s, const tl_job *job, uint64_t *id);
+/* Reads a job's result, waiting up to wait_us microseconds (< 0: until it is
+ * final).  A final result is handed out once; the id is then unknown. */
+int tl_server_poll(tl_server *s, uint64_t id, int64_t wait_us, tl_job_result *out);
+/* Cancels a job that is not admitted yet (TL_EINVAL once it is). */
+int tl_server_cancel(tl_server *s, uint64_t id);
+/* paused = 1: admit no further jobs until called again with 0 (admitted
+ * jobs run on).  For callers that queue a burst before letting it in. */
+int tl_server_pause(tl_server *s, int paused);
+int tl_server_get_stats(tl_server *s, tl_server_stats *out);
+/* The modelled device footprint the admission charges for a job. */
+uint64_t tl_server_job_bytes(uint32_t n, uint64_t m);
+/* Cancels waiting jobs, lets admitted ones finish, stops the threads. */
+void tl_server_destroy(tl_server *s);
+
+/*
  * Launch tuning (results never depend on it).  Keys:
  *   heavy_min            items of a pivot before it gets a workgroup (>= 1)
  *   slice_min            items per heavy-pivot task, at least (>= 64)

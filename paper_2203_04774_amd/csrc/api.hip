@@ -140,6 +140,20 @@ void pool_trim() {
     P.free_.clear();
 }
 
+u64 pool_total_bytes() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    Pool &P = pool_of(dev);
+    std::lock_guard<std::mutex> lk(P.mu);
+    u64 t = 0;
+    for (auto &a : P.all_) t += a.second;
+    return t;
+}
+
+void pool_trim_above(u64 limit) {
+    if (pool_total_bytes() > limit) pool_trim();
+}
+
 void *tl_dev_alloc(size_t bytes, hipStream_t s) { return pool_get(bytes, s); }
 void tl_dev_free(void *p) { pool_put(p); }
 
@@ -148,17 +162,25 @@ void tl_dev_free(void *p) { pool_put(p); }
 namespace {
 constexpr size_t STAGE_BYTES = 4u << 20;
 
+// One pinned buffer per thread, released when the thread ends.
+struct Stage {
+    char *buf = nullptr;
+    ~Stage() {
+        if (buf) (void)hipHostFree(buf);
+    }
+};
+
 char *stage_buffer() {
-    thread_local char *buf = nullptr;
-    if (!buf) {
+    thread_local Stage st;
+    if (!st.buf) {
         void *p = nullptr;
         if (hipHostMalloc(&p, STAGE_BYTES, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             throw TlError{TL_ENOMEM, "pinned staging allocation failed"};
         }
-        buf = static_cast<char *>(p);  // kept for the thread's lifetime
+        st.buf = static_cast<char *>(p);
     }
-    return buf;
+    return st.buf;
 }
 }  // namespace
 
@@ -356,7 +378,64 @@ int tl_batch_size(const tl_batch *b, uint32_t *k, uint32_t *n, uint64_t *m) {
 void tl_batch_free(tl_batch *b) {
     if (!b) return;
     (void)guarded([&] {
-        batch_free_impl(b);
+        batch_free_impl(b, true);
+        return TL_OK;
+    });
+}
+
+int tl_server_create(const tl_server_config *cfg, tl_server **out) {
+    return guarded([&] {
+        TL_REQUIRE(out, TL_EINVAL, "out is NULL");
+        *out = nullptr;
+        *out = server_create_impl(cfg);
+        return TL_OK;
+    });
+}
+
+int tl_server_submit(tl_server *s, const tl_job *job, uint64_t *id) {
+    return guarded([&] {
+        TL_REQUIRE(s && id, TL_EINVAL, "NULL argument");
+        *id = server_submit_impl(s, job);
+        return TL_OK;
+    });
+}
+
+int tl_server_poll(tl_server *s, uint64_t id, int64_t wait_us, tl_job_result *out) {
+    return guarded([&] {
+        TL_REQUIRE(s && out, TL_EINVAL, "NULL argument");
+        return server_poll_impl(s, id, wait_us, out);
+    });
+}
+
+int tl_server_cancel(tl_server *s, uint64_t id) {
+    return guarded([&] {
+        TL_REQUIRE(s, TL_EINVAL, "NULL handle");
+        return server_cancel_impl(s, id);
+    });
+}
+
+int tl_server_pause(tl_server *s, int paused) {
+    return guarded([&] {
+        TL_REQUIRE(s, TL_EINVAL, "NULL handle");
+        server_pause_impl(s, paused != 0);
+        return TL_OK;
+    });
+}
+
+int tl_server_get_stats(tl_server *s, tl_server_stats *out) {
+    return guarded([&] {
+        TL_REQUIRE(s && out, TL_EINVAL, "NULL argument");
+        server_stats_impl(s, out);
+        return TL_OK;
+    });
+}
+
+uint64_t tl_server_job_bytes(uint32_t n, uint64_t m) { return job_bytes(n, m); }
+
+void tl_server_destroy(tl_server *s) {
+    if (!s) return;
+    (void)guarded([&] {
+        server_destroy_impl(s);
         return TL_OK;
     });
 }

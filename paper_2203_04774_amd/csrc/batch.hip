@@ -362,7 +362,7 @@ tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, c
 
     struct Owner {
         tl_batch *b;
-        ~Owner() { if (b) tl_batch_free(b); }
+        ~Owner() { if (b) batch_free_impl(b, true); }
     } own{new tl_batch()};
     tl_batch *b = own.b;
     b->k = k;
@@ -443,9 +443,9 @@ void batch_list_impl(tl_batch *b, int algo, hipStream_t s, int use_graph, u64 *p
     else TL_HIP(hipStreamSynchronize(s));
 }
 
-void batch_free_impl(tl_batch *b) {
+void batch_free_impl(tl_batch *b, bool device_sync) {
     if (!b) return;
-    (void)hipDeviceSynchronize();  // replays on any stream may still read the buffers
+    if (device_sync) (void)hipDeviceSynchronize();  // replays on any stream may still read the buffers
     for (int a = 0; a < 3; a++) {
         if (b->exec[a]) (void)hipGraphExecDestroy(b->exec[a]);
         if (b->graph[a]) (void)hipGraphDestroy(b->graph[a]);
@@ -463,3 +463,5 @@ void batch_sizes(const tl_batch *b, u32 *k, u32 *n, u64 *m) {
     if (n) *n = b->N;
     if (m) *m = b->g ? b->g->m : 0;
 }
+
+const tl_csr *batch_csr(const tl_batch *b) { return b->g; }

@@ -1,0 +1,391 @@
+// Listing server: jobs arrive one by one, are admitted against a device
+// memory budget, batched with whatever else is waiting, and listed while
+// the next batch is uploaded and oriented on a second stream.
+//
+// Two threads own the device work.  The ingest thread admits waiting jobs
+// in arrival order while their modelled footprint fits the budget, uploads
+// their edges, and orients them as one disjoint union (batch.hip); a job
+// whose graph is large forms a batch of its own.  The list thread takes
+// oriented batches in order and lists them: a union of small graphs by
+// the batched pass (per-graph rows), a batch of one by the plain listing
+// (light and heavy pivots).  A batch whose union fails validation is
+// split and its jobs are oriented one by one, so a malformed job fails
+// alone.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "tl_internal.h"
+
+namespace {
+
+u64 now_ns() {
+    return (u64)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Job {
+    u64 id = 0;
+    tl_job in{};
+    u64 bytes = 0;  // modelled device footprint
+    tl_job_result res{};
+    bool solo = false;
+};
+
+struct Ready {
+    tl_batch *b = nullptr;
+    std::vector<Job *> jobs;
+    u64 bytes = 0;
+    u64 batch_id = 0;
+};
+
+}  // namespace
+
+struct tl_server {
+    tl_server_config cfg{};
+    int device = 0;
+    hipStream_t s_up = nullptr, s_list = nullptr;
+
+    std::mutex mu;
+    std::condition_variable cv_pending;  // ingest waits: new jobs, freed budget, stop
+    std::condition_variable cv_ready;    // list waits: oriented batches, stop
+    std::condition_variable cv_space;    // ingest waits: room in the ready queue
+    std::condition_variable cv_done;     // pollers wait
+    std::deque<Job *> pending;
+    std::deque<Job *> solo_retry;        // jobs of a union that failed validation
+    std::deque<Ready> ready;
+    std::unordered_map<u64, std::unique_ptr<Job>> jobs;
+    u64 next_id = 1, next_batch = 1;
+    u64 reserved = 0;
+    bool stop = false, paused = false;
+    tl_server_stats st{};
+
+    std::thread ingest, lister;
+};
+
+namespace {
+
+void finish(tl_server *S, Job *j, int status) {
+    j->res.status = status;
+    j->res.t_done_ns = now_ns();
+}
+
+// Called with S->mu held.
+void release_bytes(tl_server *S, u64 bytes) {
+    S->reserved -= bytes;
+    S->cv_pending.notify_all();
+}
+
+// Orients jobs as one union on the upload stream; throws on failure.
+tl_batch *orient_jobs(tl_server *S, const std::vector<Job *> &js) {
+    const u32 k = (u32)js.size();
+    std::vector<u32> n(k);
+    std::vector<u64> m(k);
+    u64 N = 0, M = 0;
+    for (u32 i = 0; i < k; i++) {
+        n[i] = js[i]->in.n;
+        m[i] = js[i]->in.m;
+        N += n[i];
+        M += m[i];
+    }
+    DevBuf src((M ? M : 1) * 4, S->s_up), dst((M ? M : 1) * 4, S->s_up), rank((N ? N : 1) * 4, S->s_up);
+    u64 eo = 0, vo = 0;
+    for (u32 i = 0; i < k; i++) {
+        const tl_job &J = js[i]->in;
+        if (J.m) {
+            TL_HIP(hipMemcpyAsync(src.as<u32>() + eo, J.src, J.m * 4, hipMemcpyHostToDevice, S->s_up));
+            TL_HIP(hipMemcpyAsync(dst.as<u32>() + eo, J.dst, J.m * 4, hipMemcpyHostToDevice, S->s_up));
+        }
+        if (J.n) TL_HIP(hipMemcpyAsync(rank.as<u32>() + vo, J.rank, (u64)J.n * 4, hipMemcpyHostToDevice, S->s_up));
+        eo += J.m;
+        vo += J.n;
+    }
+    return batch_orient_impl(k, n.data(), m.data(), src.as<u32>(), dst.as<u32>(), rank.as<u32>(), S->s_up);
+}
+
+// Picks the next batch (called with S->mu held).  Returns false to wait.
+bool pick(tl_server *S, std::vector<Job *> &out, u64 &bytes) {
+    out.clear();
+    bytes = 0;
+    if (!S->solo_retry.empty()) {
+        Job *j = S->solo_retry.front();
+        S->solo_retry.pop_front();
+        j->solo = true;
+        out.push_back(j);
+        return true;  // its bytes are still reserved
+    }
+    u64 edges = 0;
+    while (!S->paused && !S->pending.empty()) {
+        Job *j = S->pending.front();
+        const bool big = j->in.m >= S->cfg.solo_edges;
+        if (!out.empty() && (big || out.size() >= S->cfg.max_batch_jobs || edges + j->in.m > S->cfg.max_batch_edges))
+            break;
+        if (j->bytes > S->cfg.hbm_budget) {  // can never fit: refuse it
+            S->pending.pop_front();
+            finish(S, j, TL_ENOMEM);
+            S->st.rejected++;
+            S->cv_done.notify_all();
+            continue;
+        }
+        if (S->reserved + bytes + j->bytes > S->cfg.hbm_budget) break;  // wait for memory, keep the order
+        S->pending.pop_front();
+        out.push_back(j);
+        bytes += j->bytes;
+        edges += j->in.m;
+        if (big) {
+            j->solo = true;
+            break;
+        }
+    }
+    if (out.empty()) return false;
+    S->reserved += bytes;
+    S->st.peak_reserved = std::max(S->st.peak_reserved, S->reserved);
+    return true;
+}
+
+void ingest_loop(tl_server *S) {
+    (void)hipSetDevice(S->device);
+    std::vector<Job *> js;
+    for (;;) {
+        u64 bytes = 0;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_pending.wait(lk, [&] { return S->stop || pick(S, js, bytes); });
+            if (S->stop) return;
+            const u64 t = now_ns();
+            for (Job *j : js)
+                if (!j->res.t_admit_ns) j->res.t_admit_ns = t;
+        }
+        const bool retry = js.size() == 1 && js[0]->solo && bytes == 0;
+        if (retry) bytes = js[0]->bytes;
+        tl_batch *b = nullptr;
+        int err = TL_OK;
+        std::string msg;
+        try {
+            b = orient_jobs(S, js);
+        } catch (const TlError &e) {
+            err = e.code;
+            msg = e.msg;
+        } catch (...) {
+            err = TL_EHIP;
+        }
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (err != TL_OK) {
+            if (err == TL_EINVAL && js.size() > 1) {
+                // find the malformed job(s): orient every job of the union alone
+                for (Job *j : js) S->solo_retry.push_back(j);
+                S->st.split_batches++;
+                S->cv_pending.notify_all();
+                continue;  // the bytes stay reserved for the retries
+            }
+            for (Job *j : js) finish(S, j, err);
+            release_bytes(S, bytes);
+            S->cv_done.notify_all();
+            continue;
+        }
+        S->cv_space.wait(lk, [&] { return S->stop || S->ready.size() < (S->cfg.pipeline ? 1u : 0u) + 1u; });
+        Ready r;
+        r.b = b;
+        r.jobs = js;
+        r.bytes = bytes;
+        r.batch_id = S->next_batch++;
+        S->ready.push_back(std::move(r));
+        S->cv_ready.notify_all();
+        if (!S->cfg.pipeline) {
+            // without pipelining, the next upload waits for this batch's listing
+            S->cv_space.wait(lk, [&] { return S->stop || S->ready.empty(); });
+        }
+        if (S->stop) return;
+    }
+}
+
+void list_loop(tl_server *S) {
+    (void)hipSetDevice(S->device);
+    std::vector<u64> table;
+    for (;;) {
+        Ready r;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_ready.wait(lk, [&] { return S->stop || !S->ready.empty(); });
+            if (S->stop) return;
+            r = std::move(S->ready.front());
+        }
+        const u32 k = (u32)r.jobs.size();
+        const u64 t_start = now_ns();
+        int err = TL_OK;
+        std::vector<tl_summary> solo_out;
+        try {
+            if (k == 1 && r.jobs[0]->solo) {
+                // a graph alone: the plain listing with light and heavy pivots
+                tl_summary sm{};
+                list_impl(batch_csr(r.b), (int)r.jobs[0]->in.algo, 0u, 0xffffffffu, nullptr, 0, nullptr, nullptr,
+                          S->s_list, &sm);
+                solo_out.push_back(sm);
+            } else {
+                table.assign(3ull * k, 0);
+                std::vector<u64> t2(3ull * k);
+                bool have[3] = {false, false, false};
+                for (Job *j : r.jobs) have[(int)j->in.algo] = true;
+                for (int a = 0; a < 3; a++) {
+                    if (!have[a]) continue;
+                    batch_list_impl(r.b, a, S->s_list, 0, t2.data(), nullptr);
+                    for (u32 i = 0; i < k; i++)
+                        if ((int)r.jobs[i]->in.algo == a)
+                            for (int c = 0; c < 3; c++) table[3ull * i + c] = t2[3ull * i + c];
+                }
+            }
+        } catch (const TlError &e) {
+            err = e.code;
+        } catch (...) {
+            err = TL_EHIP;
+        }
+        batch_free_impl(r.b, false);  // the list stream has finished with it
+        pool_trim_above(S->cfg.hbm_budget + S->cfg.hbm_budget / 2);
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->ready.pop_front();
+        S->cv_space.notify_all();
+        for (u32 i = 0; i < k; i++) {
+            Job *j = r.jobs[i];
+            j->res.t_start_ns = t_start;
+            j->res.batch_id = r.batch_id;
+            j->res.batch_jobs = k;
+            if (err == TL_OK) {
+                if (!solo_out.empty()) {
+                    j->res.count = solo_out[0].count;
+                    j->res.hash = solo_out[0].hash;
+                    j->res.work = solo_out[0].work;
+                } else {
+                    j->res.count = table[3ull * i];
+                    j->res.hash = table[3ull * i + 1];
+                    j->res.work = table[3ull * i + 2];
+                }
+            }
+            finish(S, j, err);
+        }
+        S->st.batches++;
+        S->st.jobs_done += k;
+        S->st.max_batch_jobs_seen = std::max<u64>(S->st.max_batch_jobs_seen, k);
+        release_bytes(S, r.bytes);
+        S->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+// Modelled device bytes of one job from admission to completion: the
+// uploaded edges and ranks, the union's copies, the orientation's
+// temporaries, the oriented CSR with its inverse, and the listing scratch.
+u64 job_bytes(u64 n, u64 m) { return 72 * m + 64 * n + (2ull << 20); }
+
+tl_server *server_create_impl(const tl_server_config *cfg) {
+    TL_REQUIRE(cfg, TL_EINVAL, "NULL config");
+    TL_REQUIRE(cfg->hbm_budget > 0, TL_EINVAL, "hbm_budget must be > 0");
+    auto S = std::make_unique<tl_server>();
+    S->cfg = *cfg;
+    if (!S->cfg.max_batch_jobs) S->cfg.max_batch_jobs = 4096;
+    if (!S->cfg.max_batch_edges) S->cfg.max_batch_edges = 1ull << 27;
+    if (!S->cfg.solo_edges) S->cfg.solo_edges = 1ull << 21;
+    TL_HIP(hipGetDevice(&S->device));
+    TL_HIP(hipStreamCreateWithFlags(&S->s_up, hipStreamNonBlocking));
+    TL_HIP(hipStreamCreateWithFlags(&S->s_list, hipStreamNonBlocking));
+    tl_server *p = S.release();
+    p->ingest = std::thread(ingest_loop, p);
+    p->lister = std::thread(list_loop, p);
+    return p;
+}
+
+u64 server_submit_impl(tl_server *S, const tl_job *job) {
+    TL_REQUIRE(job, TL_EINVAL, "NULL job");
+    TL_REQUIRE(job->algo == TL_APP || job->algo == TL_APM || job->algo == TL_AMM, TL_EINVAL, "unknown algorithm");
+    TL_REQUIRE(job->m == 0 || (job->src && job->dst), TL_EINVAL, "src/dst is NULL");
+    TL_REQUIRE(job->n == 0 || job->rank, TL_EINVAL, "rank is NULL");
+    TL_REQUIRE(job->m < (1ull << 32) && job->n < 0xffffffffu, TL_EINVAL, "job too large");
+    auto j = std::make_unique<Job>();
+    j->in = *job;
+    j->bytes = job_bytes(job->n, job->m);
+    j->res.status = TL_JOB_PENDING;
+    j->res.t_submit_ns = now_ns();
+    std::lock_guard<std::mutex> lk(S->mu);
+    TL_REQUIRE(!S->stop, TL_EINVAL, "server is stopping");
+    j->id = S->next_id++;
+    const u64 id = j->id;
+    S->pending.push_back(j.get());
+    S->jobs.emplace(id, std::move(j));
+    S->st.submitted++;
+    S->cv_pending.notify_all();
+    return id;
+}
+
+int server_poll_impl(tl_server *S, u64 id, int64_t wait_us, tl_job_result *out) {
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(id);
+    TL_REQUIRE(it != S->jobs.end(), TL_EINVAL, "unknown job id (or its result was already taken)");
+    Job *j = it->second.get();
+    auto done = [&] { return j->res.status != TL_JOB_PENDING; };
+    if (!done() && wait_us != 0) {
+        if (wait_us < 0) S->cv_done.wait(lk, done);
+        else S->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), done);
+    }
+    *out = j->res;
+    if (done()) S->jobs.erase(it);  // a final result is handed out once
+    return TL_OK;
+}
+
+int server_cancel_impl(tl_server *S, u64 id) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(id);
+    TL_REQUIRE(it != S->jobs.end(), TL_EINVAL, "unknown job id");
+    Job *j = it->second.get();
+    auto q = std::find(S->pending.begin(), S->pending.end(), j);
+    if (q == S->pending.end()) return TL_EINVAL;  // admitted already: it runs to completion
+    S->pending.erase(q);
+    finish(S, j, TL_EABORT);
+    S->st.cancelled++;
+    S->cv_done.notify_all();
+    S->cv_pending.notify_all();
+    return TL_OK;
+}
+
+void server_pause_impl(tl_server *S, bool paused) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->paused = paused;
+    S->cv_pending.notify_all();
+}
+
+void server_stats_impl(tl_server *S, tl_server_stats *out) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->st;
+    out->reserved = S->reserved;
+    out->pending = S->pending.size();
+}
+
+void server_destroy_impl(tl_server *S) {
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        // let admitted work finish; jobs still waiting are cancelled
+        for (Job *j : S->pending) finish(S, j, TL_EABORT);
+        S->cv_done.notify_all();
+        S->pending.clear();
+        S->cv_done.wait(lk, [&] { return S->ready.empty() && S->reserved == 0 && S->solo_retry.empty(); });
+        S->stop = true;
+        S->cv_pending.notify_all();
+        S->cv_ready.notify_all();
+        S->cv_space.notify_all();
+    }
+    S->ingest.join();
+    S->lister.join();
+    (void)hipStreamSynchronize(S->s_up);
+    (void)hipStreamSynchronize(S->s_list);
+    (void)hipStreamDestroy(S->s_up);
+    (void)hipStreamDestroy(S->s_list);
+    delete S;
+}

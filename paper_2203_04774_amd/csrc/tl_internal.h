@@ -131,5 +131,23 @@ void set_chunk_triangles(u64 k);
 tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, const u32 *dst, const u32 *rank,
                             hipStream_t s);
 void batch_list_impl(tl_batch *b, int algo, hipStream_t s, int use_graph, u64 *per_graph_host, u64 *per_graph_dev);
-void batch_free_impl(tl_batch *b);
+// device_sync: wait for the whole device first (else the caller has
+// synchronised every stream that used the batch).
+void batch_free_impl(tl_batch *b, bool device_sync);
+const tl_csr *batch_csr(const tl_batch *b);
 void batch_sizes(const tl_batch *b, u32 *k, u32 *n, u64 *m);
+
+// Listing server (serve.hip).
+tl_server *server_create_impl(const tl_server_config *cfg);
+u64 server_submit_impl(tl_server *S, const tl_job *job);
+int server_poll_impl(tl_server *S, u64 id, int64_t wait_us, tl_job_result *out);
+int server_cancel_impl(tl_server *S, u64 id);
+void server_pause_impl(tl_server *S, bool paused);
+void server_stats_impl(tl_server *S, tl_server_stats *out);
+void server_destroy_impl(tl_server *S);
+u64 job_bytes(u64 n, u64 m);
+
+// Cached device bytes (in use and free) of the current device's pool, and a
+// trim of its free blocks when that total exceeds `limit`.
+u64 pool_total_bytes();
+void pool_trim_above(u64 limit);

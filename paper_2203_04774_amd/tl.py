@@ -35,6 +35,33 @@ class Summary(ctypes.Structure):
                 f"scanned={self.scanned})")
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_batch_jobs", ctypes.c_uint32),
+                ("max_batch_edges", ctypes.c_uint64), ("solo_edges", ctypes.c_uint64),
+                ("pipeline", ctypes.c_uint32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint64), ("src", ctypes.c_void_p),
+                ("dst", ctypes.c_void_p), ("rank", ctypes.c_void_p), ("algo", ctypes.c_int)]
+
+
+JOB_PENDING = -1
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("count", ctypes.c_uint64), ("hash", ctypes.c_uint64),
+                ("work", ctypes.c_uint64), ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64), ("batch_id", ctypes.c_uint64),
+                ("batch_jobs", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in (
+        "submitted", "jobs_done", "batches", "rejected", "cancelled", "split_batches", "reserved",
+        "peak_reserved", "pending", "max_batch_jobs_seen")]
+
+
 CHUNK_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)
 
 
@@ -60,6 +87,19 @@ def _load():
     lib.tl_batch_size.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)]
     lib.tl_batch_free.argtypes = [vp]
     lib.tl_batch_free.restype = None
+    lib.tl_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.tl_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(u64)]
+    lib.tl_server_poll.argtypes = [vp, u64, ctypes.c_int64, ctypes.POINTER(JobResult)]
+    lib.tl_server_cancel.argtypes = [vp, u64]
+    lib.tl_server_pause.argtypes = [vp, i32]
+    lib.tl_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.tl_server_job_bytes.argtypes = [u32, u64]
+    lib.tl_server_job_bytes.restype = u64
+    lib.tl_server_destroy.argtypes = [vp]
+    lib.tl_server_destroy.restype = None
+    for f in ("tl_server_create", "tl_server_submit", "tl_server_poll", "tl_server_cancel", "tl_server_pause",
+              "tl_server_get_stats"):
+        getattr(lib, f).restype = i32
     lib.tl_release_cached_memory.argtypes = []
     lib.tl_release_cached_memory.restype = i32
     lib.tl_strerror.argtypes = [i32]
@@ -251,6 +291,71 @@ def batch_orient(n, m, src: torch.Tensor, dst: torch.Tensor, rank: torch.Tensor,
     _check(_lib.tl_batch_orient(len(n_h), n_h.ctypes.data, m_h.ctypes.data, _dptr(src, "src"), _dptr(dst, "dst"),
                                 _dptr(rank, "rank"), _stream_ptr(stream), ctypes.byref(h)), "tl_batch_orient")
     return Batch(h)
+
+
+class Server:
+    """tl_server_*: a listing server on the current device.  Job arrays are
+    host numpy uint32 arrays; they are kept referenced here until the job's
+    final result has been polled."""
+
+    def __init__(self, hbm_budget: int, max_batch_jobs: int = 0, max_batch_edges: int = 0,
+                 solo_edges: int = 0, pipeline: bool = True):
+        cfg = ServerConfig(int(hbm_budget), int(max_batch_jobs), int(max_batch_edges), int(solo_edges),
+                           1 if pipeline else 0)
+        h = ctypes.c_void_p()
+        _check(_lib.tl_server_create(ctypes.byref(cfg), ctypes.byref(h)), "tl_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, n, src, dst, rank, algo: str = "A++") -> int:
+        import numpy as np
+        s = np.ascontiguousarray(src, np.uint32)
+        d = np.ascontiguousarray(dst, np.uint32)
+        r = np.ascontiguousarray(rank, np.uint32)
+        if s.shape != d.shape or len(r) != n:
+            raise ValueError("src/dst lengths differ or rank length != n")
+        job = Job(int(n), len(s), s.ctypes.data if len(s) else None, d.ctypes.data if len(d) else None,
+                  r.ctypes.data if len(r) else None, ALGOS[algo])
+        jid = ctypes.c_uint64()
+        _check(_lib.tl_server_submit(self._h, ctypes.byref(job), ctypes.byref(jid)), "tl_server_submit")
+        self._keep[int(jid.value)] = (s, d, r)
+        return int(jid.value)
+
+    def poll(self, jid: int, wait_us: int = -1) -> JobResult:
+        out = JobResult()
+        _check(_lib.tl_server_poll(self._h, jid, wait_us, ctypes.byref(out)), "tl_server_poll")
+        if out.status != JOB_PENDING:
+            self._keep.pop(jid, None)
+        return out
+
+    def cancel(self, jid: int) -> int:
+        """TL_OK if the job was cancelled, TL_EINVAL if it was admitted already."""
+        return int(_lib.tl_server_cancel(self._h, jid))
+
+    def pause(self, paused: bool = True):
+        _check(_lib.tl_server_pause(self._h, 1 if paused else 0), "tl_server_pause")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib.tl_server_get_stats(self._h, ctypes.byref(st)), "tl_server_get_stats")
+        return {k: int(getattr(st, k)) for k, _ in ServerStats._fields_}
+
+    @staticmethod
+    def job_bytes(n: int, m: int) -> int:
+        """The device footprint admission charges for a job (tl_server_job_bytes)."""
+        return int(_lib.tl_server_job_bytes(int(n), int(m)))
+
+    def close(self):
+        if self._h is not None:
+            _lib.tl_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def release_cached_memory():

@@ -276,6 +276,14 @@ def bench_serve(args):
     P = args.serve_pool
     t0 = time.time()
     pool = [graphgen.serve_job(j) for j in range(P)]
+    if args.serve_pinned:
+        # job arrays in page-locked host memory (uploads by DMA at full link speed)
+        def pinned(a):
+            t = torch.empty(len(a), dtype=torch.int32, pin_memory=True)
+            v = t.numpy().view(np.uint32)
+            v[:] = a
+            return v
+        pool = [(graphgen.Graph(g.n, pinned(g.src), pinned(g.dst), g.name), pinned(r), p) for g, r, p in pool]
     edges = sum(g.m for g, _, _ in pool)
     log(f"[bench] job pool: {P} jobs, {edges} edges, generated in {time.time() - t0:.1f}s")
     gold = None
@@ -341,6 +349,7 @@ def bench_serve(args):
                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                "mean_batch_jobs": njobs / max(st["batches"], 1), "batches": st["batches"],
                "peak_reserved_gb": st["peak_reserved"] / 2 ** 30, "client_max_lag_ms": lag * 1e3,
+               "stage_ms": {k: st[k + "_ns"] / 1e6 for k in ("upload", "orient", "list")},
                "oracle_match": ok}
         sweep.append(row)
         log(f"[bench] rate {lam}/s: {row}")
@@ -362,7 +371,8 @@ def bench_serve(args):
         "config": {"workload": "serve", "pool_jobs": P, "pool_edges": edges,
                    "jobs": "RMAT (scale ceil(log2(m/8)), ef 8) or Chung-Lu (n = m/10, mean degree 20, "
                            "gamma U(2.0, 2.8)); m log-uniform in [1e3, 1e7]; degree or core order; A++",
-                   "budget_gb": args.serve_budget_gb, "rates": args.serve_rates},
+                   "budget_gb": args.serve_budget_gb, "rates": args.serve_rates,
+                   "host_memory": "pinned" if args.serve_pinned else "pageable"},
         "p50_ms": top["p50_ms"],
         "p99_ms": top["p99_ms"],
         "sweep": sweep,
@@ -391,6 +401,7 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=2000, help="jobs per arrival rate, at most")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="arrival window per rate, at most")
     ap.add_argument("--serve-budget-gb", type=int, default=64)
+    ap.add_argument("--serve-pinned", action="store_true", help="job arrays in page-locked host memory")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "

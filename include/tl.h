@@ -240,6 +240,7 @@ typedef struct {
 typedef struct {
     uint64_t submitted, jobs_done, batches, rejected, cancelled, split_batches;
     uint64_t reserved, peak_reserved, pending, max_batch_jobs_seen;
+    uint64_t upload_ns, orient_ns, list_ns; /* thread time in each stage, summed over batches */
 } tl_server_stats;
 
 /* Starts the server's two threads on the current device. */

@@ -97,6 +97,7 @@ tl_batch *orient_jobs(tl_server *S, const std::vector<Job *> &js) {
         N += n[i];
         M += m[i];
     }
+    const u64 t0 = now_ns();
     DevBuf src((M ? M : 1) * 4, S->s_up), dst((M ? M : 1) * 4, S->s_up), rank((N ? N : 1) * 4, S->s_up);
     u64 eo = 0, vo = 0;
     for (u32 i = 0; i < k; i++) {
@@ -109,7 +110,14 @@ tl_batch *orient_jobs(tl_server *S, const std::vector<Job *> &js) {
         eo += J.m;
         vo += J.n;
     }
-    return batch_orient_impl(k, n.data(), m.data(), src.as<u32>(), dst.as<u32>(), rank.as<u32>(), S->s_up);
+    TL_HIP(hipStreamSynchronize(S->s_up));
+    const u64 t1 = now_ns();
+    tl_batch *b = batch_orient_impl(k, n.data(), m.data(), src.as<u32>(), dst.as<u32>(), rank.as<u32>(), S->s_up);
+    const u64 t2 = now_ns();
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st.upload_ns += t1 - t0;
+    S->st.orient_ns += t2 - t1;
+    return b;
 }
 
 // Picks the next batch (called with S->mu held).  Returns false to wait.
@@ -274,6 +282,7 @@ void list_loop(tl_server *S) {
         S->st.batches++;
         S->st.jobs_done += k;
         S->st.max_batch_jobs_seen = std::max<u64>(S->st.max_batch_jobs_seen, k);
+        S->st.list_ns += now_ns() - t_start;
         release_bytes(S, r.bytes);
         S->cv_done.notify_all();
     }

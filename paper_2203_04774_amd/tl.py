@@ -59,7 +59,7 @@ class JobResult(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "submitted", "jobs_done", "batches", "rejected", "cancelled", "split_batches", "reserved",
-        "peak_reserved", "pending", "max_batch_jobs_seen")]
+        "peak_reserved", "pending", "max_batch_jobs_seen", "upload_ns", "orient_ns", "list_ns")]
 
 
 CHUNK_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)

@@ -122,6 +122,9 @@ def bench_batch(args):
     import graphgen
     import paper_2203_04774_amd as tl
 
+    from paper_2203_04774_amd import autotune
+    tuned = autotune.apply()
+    log(f"[bench] batched-pass tuning: {tuned if tuned else 'library defaults'}")
     K = args.batch_graphs
     t0 = time.time()
     B = graphgen.batch(K)
@@ -231,7 +234,8 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": "batch", "graph": WORKLOADS["batch"]["desc"], "graphs": K,
                    "n": int(B.n.sum()), "m": M, "algos": ["A++"],
-                   "step": "tl_batch_orient + tl_batch_list (pass captured as a HIP graph, then launched)"},
+                   "step": "tl_batch_orient + tl_batch_list (pass captured as a HIP graph, then launched)",
+                   "tuning": tuned or "library defaults"},
         "intersect_elems_per_s": W * args.steps / elapsed,
         "plain": {"value": plain_value, "unit": "triangles/s", "graphs": n_plain, "seconds": plain_s,
                   "per_graph_equal_to_batched": same},

@@ -280,6 +280,13 @@ void tl_server_destroy(tl_server *s);
  *   force_mode           testing: 0 bitmap, 1 array, 2 global, 3 reverse,
  *                        4 hash for every heavy pivot where it fits;
  *                        255 = automatic
+ * and for the batched pass (tl_batch_list; a captured pass is captured
+ * again when these change):
+ *   batch_heavy_min      pruned items of a pivot before its list is marked
+ *                        in an LDS bitmap by a workgroup of its own
+ *   batch_heavy_block    threads of such a workgroup: 256, 512 or 1024
+ *   batch_heavy_per_cu   such workgroups per CU (1..2)
+ *   batch_light_per_cu   workgroups of the per-item kernel per CU (1..64)
  * Values apply to later calls in this process; TL_TUNE_<KEY> environment
  * variables (upper case) set the initial values.  Unknown keys or values
  * out of range give TL_EINVAL.

@@ -11,7 +11,14 @@
 // The listing pipeline allocates nothing and never waits for the host: all
 // of its buffers belong to the batch and all sizes are fixed by the union's
 // n and m, so it is captured once per algorithm as a HIP graph and replayed.
+// Its pivots fall in two bins: pivots whose pruned work reaches a threshold
+// (and whose list's rank span fits an LDS bitmap) get a workgroup each, with
+// the list marked in LDS (the paper's B array); all other seed edges form
+// one flattened item space walked by fixed runs of 64-lane wavefronts.
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "tl_internal.h"
@@ -62,8 +69,8 @@ __global__ void k_union_edges(const u32 *src, const u32 *dst, const u64 *ebase, 
     }
 }
 
-// Adds v to dest[key] for runs of equal key across the lanes of a wavefront
-// (keys are non-decreasing along lanes); one atomic per run.
+// Adds v to dest[key * stride] for runs of equal key across the lanes of a
+// wavefront (keys non-decreasing along lanes); one atomic per run.
 __device__ __forceinline__ void wave_segmented_add(bool valid, u32 key, u64 v, u64 *dest, int stride) {
     const int lane = lane_id();
     const u32 kk = valid ? key : 0xffffffffu;
@@ -77,6 +84,41 @@ __device__ __forceinline__ void wave_segmented_add(bool valid, u32 key, u64 v, u
     const bool last = valid && (lane == WAVE - 1 || nk != kk);
     if (last && v) atomicAdd((unsigned long long *)&dest[(u64)kk * stride], (unsigned long long)v);
 }
+
+// ------------------------------------------------------------------ tuning
+
+struct BatchTuning {
+    u64 heavy_min = 4096;   // pruned items of a pivot before it gets a workgroup
+    u64 heavy_block = 512;  // threads of a heavy workgroup: 256, 512 or 1024
+    u64 heavy_per_cu = 2;   // heavy workgroups per CU
+    u64 light_per_cu = 8;   // light workgroups (256 threads) per CU
+};
+
+std::mutex g_btune_mu;
+
+BatchTuning &btune() {
+    static BatchTuning t = [] {
+        BatchTuning d;
+        auto env = [](const char *k, u64 &v) {
+            const char *e = getenv(k);
+            if (e && *e) v = strtoull(e, nullptr, 10);
+        };
+        env("TL_TUNE_BATCH_HEAVY_MIN", d.heavy_min);
+        env("TL_TUNE_BATCH_HEAVY_BLOCK", d.heavy_block);
+        env("TL_TUNE_BATCH_HEAVY_PER_CU", d.heavy_per_cu);
+        env("TL_TUNE_BATCH_LIGHT_PER_CU", d.light_per_cu);
+        if (d.heavy_block != 256 && d.heavy_block != 1024) d.heavy_block = 512;
+        if (d.heavy_per_cu < 1 || d.heavy_per_cu > 2) d.heavy_per_cu = 2;
+        if (d.light_per_cu < 1 || d.light_per_cu > 64) d.light_per_cu = 8;
+        return d;
+    }();
+    return t;
+}
+
+constexpr u32 BH_LDS_BYTES = 64u * 1024u;     // the heavy bin's bitmap
+constexpr u32 BH_BITS = BH_LDS_BYTES * 8u;   // rank span it covers
+
+// -------------------------------------------------------------- the pass
 
 // The window of seed e in its scanned list: the part of S between the
 // smallest and the largest candidate of T (no other element can match).
@@ -93,11 +135,11 @@ __device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u64 &abs) {
     return 0;
 }
 
-// Per seed edge: whether its window is non-empty, and the paper's work
-// (the scanned list's length) added to the pivot's graph.  pg holds
-// (count, digest, work) per graph.
+// Per seed edge: its window length lw[e]; per pivot: the sum of its seeds'
+// lengths wp[p]; per graph: the paper's work (the scanned lists' lengths).
+// pg holds (count, digest, work) per graph.
 template <int ALGO>
-__global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *flag, u64 *pg) {
+__global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *lw, u64 *wp, u64 *pg) {
     const int lane = lane_id();
     const u64 stride = (u64)gridDim.x * blockDim.x;
     const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -105,16 +147,79 @@ __global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *flag
     for (u64 it = 0; it < iters; it++) {
         const u64 e = first + it * stride;
         const bool valid = e < g.m;
-        u32 gr = 0;
+        u32 gr = 0, p = 0, l = 0;
         u64 w = 0;
         if (valid) {
             Seed<ALGO> sd(g, e);
-            gr = gid[sd.p];
+            p = sd.p;
+            gr = gid[p];
             w = sd.s_hi - sd.s_lo;
             u64 abs;
-            flag[e] = seed_window<ALGO>(sd, abs) ? 1u : 0u;
+            l = seed_window<ALGO>(sd, abs);
+            lw[e] = l;
         }
         wave_segmented_add(valid, gr, w, pg + 2, 3);
+        wave_segmented_add(valid, p, l, wp, 1);
+    }
+}
+
+// Pivot bins: 1 when the pivot's items reach heavy_min and its list's rank
+// span fits the bitmap.
+template <int ALGO>
+__global__ void k_bclass(GView g, u32 N, const u64 *wp, u64 heavy_min, u32 *hflag) {
+    const u64 *po = Form<ALGO>::piv_off(g);
+    const u32 *pa = Form<ALGO>::piv_adj(g);
+    GRID_STRIDE(p, N) {
+        u32 h = 0;
+        const u64 w = wp[p];
+        if (w > 0 && w >= heavy_min) {
+            const u64 t0 = po[p], t1 = po[p + 1];
+            if (t1 > t0 && (u64)(pa[t1 - 1] - pa[t0]) < BH_BITS) h = 1u;
+        }
+        hflag[p] = h;
+    }
+}
+
+// Seed flags for a two-part compaction: the low half counts seeds of light
+// pivots, the high half seeds of heavy ones.
+template <int ALGO>
+__global__ void k_bflag(GView g, const u32 *lw, const u32 *hflag, u64 *f64) {
+    GRID_STRIDE(e, g.m) {
+        u64 f = 0;
+        if (lw[e]) {
+            const u32 p = ALGO == 0 ? g.row_b[e] : g.row_f[e];
+            f = hflag[p] ? (1ull << 32) : 1ull;
+        }
+        f64[e] = f;
+    }
+}
+
+// Seeds with a non-empty window, packed in seed order: light pivots' seeds
+// at [0, nlight), heavy pivots' seeds after them.
+template <int ALGO>
+__global__ void k_bcompact(GView g, const u32 *gid, const u32 *lw, const u64 *pos, u64 *cabs, u32 *cxinv, u32 *ctlo,
+                           u32 *cthi, u32 *cpinv, u32 *cgid, u32 *clen) {
+    const u64 nlight = pos[g.m] & 0xffffffffull;
+    GRID_STRIDE(e, g.m) {
+        const u64 pe = pos[e], pn = pos[e + 1];
+        if (pn != pe) {
+            const bool heavy = (pn >> 32) != (pe >> 32);
+            const u64 d = heavy ? nlight + (pe >> 32) : (pe & 0xffffffffull);
+            Seed<ALGO> sd(g, e);
+            cabs[d] = lower_bound_dev<u32>(sd.S, sd.s_lo, sd.s_hi, sd.T[sd.t_lo]);
+            cxinv[d] = g.inv[sd.x];
+            ctlo[d] = (u32)sd.t_lo;
+            cthi[d] = (u32)sd.t_hi;
+            cpinv[d] = g.inv[sd.p];
+            cgid[d] = gid[sd.p];
+            clen[d] = lw[e];
+        }
+    }
+}
+
+__global__ void k_bhlist(u32 N, const u32 *hflag, const u64 *hpre, u32 *hpiv) {
+    GRID_STRIDE(p, N) {
+        if (hflag[p]) hpiv[hpre[p]] = (u32)p;
     }
 }
 
@@ -123,30 +228,8 @@ struct BSeeds {
     const u32 *cxinv, *ctlo, *cthi, *cpinv, *cgid;
 };
 
-// Seeds with a non-empty window, packed in seed order (pos = prefix of the
-// flags); the window is found again rather than stored for every seed.
-template <int ALGO>
-__global__ void k_bcompact(GView g, const u32 *gid, const u64 *pos, u64 *cabs, u32 *cxinv, u32 *ctlo, u32 *cthi,
-                           u32 *cpinv, u32 *cgid, u32 *clen) {
-    GRID_STRIDE(e, g.m) {
-        const u64 d = pos[e];
-        if (pos[e + 1] != d) {
-            Seed<ALGO> sd(g, e);
-            u64 abs;
-            const u32 l = seed_window<ALGO>(sd, abs);
-            cabs[d] = abs;
-            cxinv[d] = g.inv[sd.x];
-            ctlo[d] = (u32)sd.t_lo;
-            cthi[d] = (u32)sd.t_hi;
-            cpinv[d] = g.inv[sd.p];
-            cgid[d] = gid[sd.p];
-            clen[d] = l;
-        }
-    }
-}
-
 // Per-lane accumulator of (count, digest) for the graph of the lane's
-// current items; graphs only grow along a wavefront's run, so each lane
+// current items; a lane's items move through graphs in order, so each lane
 // flushes once per graph it leaves.
 struct GraphAcc {
     u32 gcur = 0xffffffffu;
@@ -169,13 +252,14 @@ struct GraphAcc {
     }
 };
 
-// All items [0, W) with W = cpre[m] read on the device: every wavefront of a
-// fixed grid takes a contiguous run, 4 chunks of 64 at a time when they lie
-// in one window or in the 64 seeds from the current one.
+// Light bin: the items [0, W) of the light seeds, W = cpre[nlight] read on
+// the device; every wavefront of a fixed grid takes a contiguous run, 4
+// chunks of 64 at a time when they lie in one window or in the 64 seeds
+// from the current one.
 template <int ALGO>
-__global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u32 *vbase, u64 *pg) {
+__global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos, const u32 *vbase, u64 *pg) {
     const int lane = lane_id();
-    const u64 ncap = g.m;
+    const u64 ncap = pos[g.m] & 0xffffffffull;
     const u64 W = L.cpre[ncap];
     const u64 gw = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
     const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
@@ -293,7 +377,180 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u32 *vba
     ga.flush(pg);
 }
 
+// Heavy bin: persistent workgroups take heavy pivots from a queue; each
+// marks the pivot's list in an LDS bitmap (bit y - min of the list), then
+// its wavefronts share the items of the pivot's compacted seeds, each item
+// tested by one LDS read, and the marks are cleared for the next pivot.
+// Every workgroup leaves once the queue passes the heavy pivot count.
+template <int ALGO, int HBS>
+__global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *pos, const u32 *hpiv, const u64 *hpre,
+                                                u32 N, const u32 *gid, const u32 *vbase, u64 *queue, u64 *pg) {
+    extern __shared__ u32 bits[];
+    __shared__ u64 next;
+    const int lane = lane_id(), wid = threadIdx.x / WAVE, nwv = HBS / WAVE;
+    const u64 nheavy = hpre[N];
+    const u64 nlight = pos[g.m] & 0xffffffffull;
+    const u64 *so = Form<ALGO>::seed_off(g);
+    const u64 *po = Form<ALGO>::piv_off(g);
+    const u32 *pa = Form<ALGO>::piv_adj(g);
+    const u32 *SA = Form<ALGO>::scan_adj(g);
+    for (u32 i = threadIdx.x; i < BH_BITS / 32; i += HBS) bits[i] = 0u;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd((unsigned long long *)queue, 1ull);
+        __syncthreads();
+        const u64 hi = next;
+        __syncthreads();
+        if (hi >= nheavy) break;  // uniform across the workgroup
+        const u32 p = hpiv[hi];
+        const u64 t0 = po[p], t1 = po[p + 1];
+        const u32 tmin = pa[t0], tmax = pa[t1 - 1];
+        for (u64 i = t0 + threadIdx.x; i < t1; i += HBS) {
+            const u32 v = pa[i] - tmin;
+            atomicOr(&bits[v >> 5], 1u << (v & 31));
+        }
+        __syncthreads();
+        const u64 cb = nlight + (pos[so[p]] >> 32), ce = nlight + (pos[so[p + 1]] >> 32);
+        const u64 a = L.cpre[cb], b = L.cpre[ce];
+        u64 wb, we;
+        {
+            const u64 per = (((b - a + nwv - 1) / nwv) + 63) & ~(u64)63;
+            wb = a + (u64)wid * per;
+            we = (wb + per < b) ? wb + per : b;
+        }
+        const u32 gi = gid[p], vb = vbase[gi];
+        const u32 pl = g.inv[p] - vb;
+        u64 cnt = 0, hsh = 0;
+        auto member = [&](u32 y) -> bool {
+            const u32 v = y - tmin;
+            return y >= tmin && y <= tmax && ((bits[v >> 5] >> (v & 31)) & 1u);
+        };
+        auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < UN; j++) any |= h[j];
+            if (!__ballot(any)) return;
+            u32 yi[UN];
+#pragma unroll
+            for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+#pragma unroll
+            for (int j = 0; j < UN; j++) {
+                if (h[j]) {
+                    u32 x0 = pl, x1 = xv[j] - vb, x2 = yi[j] - vb;
+                    canon3(x0, x1, x2);
+                    cnt += 1;
+                    hsh += tri_digest(x0, x1, x2);
+                }
+            }
+        };
+        if (wb < we) {
+            SeedCursor cur(L.cpre, cb, ce, wb);
+            u64 kb = wb;
+            while (kb < we) {
+                if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
+                    const u64 c = cur.c_lo;
+                    const u64 sab = L.cabs[c] + (kb - cur.base) + lane;
+                    u32 y[UN], xv[UN];
+                    bool h[UN];
+#pragma unroll
+                    for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
+                    const u32 xi = L.cxinv[c];
+#pragma unroll
+                    for (int j = 0; j < UN; j++) {
+                        h[j] = member(y[j]);
+                        xv[j] = xi;
+                    }
+                    report(y, h, xv);
+                    kb += UN * WAVE;
+                    cur.advance(kb, c);
+                    continue;
+                }
+                if (kb + UN * WAVE <= we) {
+                    const u64 ci = cur.c_lo + lane;
+                    const bool inw = ci < ce;
+                    const u64 P = inw ? L.cpre[ci] : ~0ull;
+                    const u64 pend = (cur.c_lo + WAVE <= ce) ? L.cpre[cur.c_lo + WAVE] : ~0ull;
+                    if (pend >= kb + UN * WAVE) {
+                        const u64 A = inw ? L.cabs[ci] : 0ull;
+                        const u32 X = inw ? L.cxinv[ci] : 0u;
+                        const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                        u32 y[UN], xv[UN];
+                        bool h[UN];
+                        int lo_last = 0;
+#pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            const u32 kr = (u32)(j * WAVE + lane);
+                            int lo = 0;
+#pragma unroll
+                            for (int st = 32; st > 0; st >>= 1) {
+                                const u32 q = __shfl(Q, lo + st, WAVE);
+                                if (q <= kr) lo += st;
+                            }
+                            const u64 rel = (kb + kr) - shfl_u64(P, lo);
+                            y[j] = SA[shfl_u64(A, lo) + rel];
+                            xv[j] = __shfl(X, lo, WAVE);
+                            if (j == UN - 1) lo_last = __shfl(lo, WAVE - 1, WAVE);
+                        }
+#pragma unroll
+                        for (int j = 0; j < UN; j++) h[j] = member(y[j]);
+                        report(y, h, xv);
+                        kb += UN * WAVE;
+                        if (kb < we) {
+                            u64 c = cur.c_lo + (u64)lo_last;
+                            const u64 pn = (lo_last + 1 < WAVE) ? shfl_u64(P, lo_last + 1) : pend;
+                            if (pn <= kb) c++;
+                            cur.reset(c);
+                        }
+                        continue;
+                    }
+                }
+                const u64 k = kb + lane;
+                const bool act = k < we;
+                u64 rel;
+                const u64 c = cur.locate(kb, k, rel);
+                if (act) {
+                    const u32 y = SA[L.cabs[c] + rel];
+                    if (member(y)) {
+                        u32 x0 = pl, x1 = L.cxinv[c] - vb, x2 = g.inv[y] - vb;
+                        canon3(x0, x1, x2);
+                        cnt += 1;
+                        hsh += tri_digest(x0, x1, x2);
+                    }
+                }
+                kb += WAVE;
+                cur.advance(kb, c);
+            }
+        }
+        cnt = wave_sum_u64(cnt);
+        hsh = wave_sum_u64(hsh);
+        if (lane == 0 && cnt) {
+            atomicAdd((unsigned long long *)&pg[3 * (u64)gi + 0], (unsigned long long)cnt);
+            atomicAdd((unsigned long long *)&pg[3 * (u64)gi + 1], (unsigned long long)hsh);
+        }
+        __syncthreads();  // every wavefront is done with the marks
+        for (u64 i = t0 + threadIdx.x; i < t1; i += HBS) {
+            const u32 v = pa[i] - tmin;
+            bits[v >> 5] = 0u;
+        }
+        __syncthreads();
+    }
+}
+
 unsigned grid_b(u64 items) { return grid_for(items, BB, (unsigned)tl_num_cus() * 16); }
+
+// Lets the heavy-bin kernels use their whole dynamic LDS (once per process).
+void prepare_batch_kernels() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const void *fns[] = {
+            (const void *)k_bheavy<0, 256>, (const void *)k_bheavy<0, 512>, (const void *)k_bheavy<0, 1024>,
+            (const void *)k_bheavy<1, 256>, (const void *)k_bheavy<1, 512>, (const void *)k_bheavy<1, 1024>,
+            (const void *)k_bheavy<2, 256>, (const void *)k_bheavy<2, 512>, (const void *)k_bheavy<2, 1024>};
+        for (const void *f : fns)
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BH_LDS_BYTES);
+        (void)hipGetLastError();
+    });
+}
 
 }  // namespace
 
@@ -302,43 +559,93 @@ struct tl_batch {
     u64 M = 0;
     tl_csr *g = nullptr;
     u32 *gid = nullptr, *vbase = nullptr;
-    // listing scratch, owned for the batch's lifetime
-    u32 *flag = nullptr, *cxinv = nullptr, *ctlo = nullptr, *cthi = nullptr, *cpinv = nullptr,
-        *cgid = nullptr, *clen = nullptr;
-    u64 *pos = nullptr, *cabs = nullptr, *cpre = nullptr, *ws = nullptr, *pg = nullptr;
+    // listing scratch, owned for the batch's lifetime: per seed edge
+    u32 *lw = nullptr, *cxinv = nullptr, *ctlo = nullptr, *cthi = nullptr, *cpinv = nullptr, *cgid = nullptr,
+        *clen = nullptr;
+    u64 *f64 = nullptr, *pos = nullptr, *cabs = nullptr, *cpre = nullptr;
+    // per pivot
+    u64 *wp = nullptr, *hpre = nullptr;
+    u32 *hflag = nullptr, *hpiv = nullptr;
+    u64 *ws = nullptr, *pg = nullptr, *ctl = nullptr;
     hipStream_t cap_stream[3] = {nullptr, nullptr, nullptr};
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
     hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    BatchTuning cap_tune[3];  // the tuning each captured pass was built with
     int device = 0;
 };
 
 namespace {
 
-// Enqueue the whole listing pipeline on s (no host waits, no allocation).
+bool same_tune(const BatchTuning &a, const BatchTuning &b) {
+    return a.heavy_min == b.heavy_min && a.heavy_block == b.heavy_block && a.heavy_per_cu == b.heavy_per_cu &&
+           a.light_per_cu == b.light_per_cu;
+}
+
+// Enqueue the whole listing pass on s (no host waits, no allocation).
 template <int ALGO>
-void enqueue_batch_list(tl_batch *b, hipStream_t s) {
+void enqueue_batch_list(tl_batch *b, const BatchTuning &tu, hipStream_t s) {
     const tl_csr *g = b->g;
     const GView v{g->off_f, g->off_b, g->adj_f, g->adj_b, g->row_f, g->row_b, g->inv, g->m};
-    const u64 m = g->m;
+    const u64 m = g->m, N = b->N;
+    const unsigned cus = (unsigned)tl_num_cus();
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_b(3ull * b->k)), dim3(BB), 0, s, b->pg, 3ull * b->k, 0ull);
-    hipLaunchKernelGGL((k_bplan<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->flag, b->pg);
-    scan_u32_to_u64(b->flag, b->pos, m, s, b->ws);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_b(N)), dim3(BB), 0, s, b->wp, N, 0ull);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, b->ctl, 1ull, 0ull);
+    hipLaunchKernelGGL((k_bplan<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->lw, b->wp, b->pg);
+    hipLaunchKernelGGL((k_bclass<ALGO>), dim3(grid_b(N)), dim3(BB), 0, s, v, (u32)N, b->wp, tu.heavy_min, b->hflag);
+    hipLaunchKernelGGL((k_bflag<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->lw, b->hflag, b->f64);
+    scan_u64_to_u64(b->f64, b->pos, m, s, b->ws);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_b(m)), dim3(BB), 0, s, b->clen, m, 0u);
-    hipLaunchKernelGGL((k_bcompact<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->pos, b->cabs, b->cxinv,
-                       b->ctlo, b->cthi, b->cpinv, b->cgid, b->clen);
+    hipLaunchKernelGGL((k_bcompact<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->lw, b->pos, b->cabs,
+                       b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid, b->clen);
     scan_u32_to_u64(b->clen, b->cpre, m, s, b->ws);
+    scan_u32_to_u64(b->hflag, b->hpre, N, s, b->ws);
+    hipLaunchKernelGGL(k_bhlist, dim3(grid_b(N)), dim3(BB), 0, s, (u32)N, b->hflag, b->hpre, b->hpiv);
     const BSeeds L{b->cpre, b->cabs, b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid};
-    hipLaunchKernelGGL((k_bprobe<ALGO>), dim3((unsigned)tl_num_cus() * 8), dim3(BB), 0, s, v, L, b->vbase, b->pg);
+    hipLaunchKernelGGL((k_bprobe<ALGO>), dim3(cus * (unsigned)tu.light_per_cu), dim3(BB), 0, s, v, L, b->pos,
+                       b->vbase, b->pg);
+    const dim3 hg(cus * (unsigned)tu.heavy_per_cu);
+    if (tu.heavy_block == 256)
+        hipLaunchKernelGGL((k_bheavy<ALGO, 256>), hg, dim3(256), BH_LDS_BYTES, s, v, L, b->pos, b->hpiv, b->hpre,
+                           (u32)N, b->gid, b->vbase, b->ctl, b->pg);
+    else if (tu.heavy_block == 1024)
+        hipLaunchKernelGGL((k_bheavy<ALGO, 1024>), hg, dim3(1024), BH_LDS_BYTES, s, v, L, b->pos, b->hpiv, b->hpre,
+                           (u32)N, b->gid, b->vbase, b->ctl, b->pg);
+    else
+        hipLaunchKernelGGL((k_bheavy<ALGO, 512>), hg, dim3(512), BH_LDS_BYTES, s, v, L, b->pos, b->hpiv, b->hpre,
+                           (u32)N, b->gid, b->vbase, b->ctl, b->pg);
     TL_HIP(hipGetLastError());
 }
 
-void enqueue_for(tl_batch *b, int algo, hipStream_t s) {
-    if (algo == 0) enqueue_batch_list<0>(b, s);
-    else if (algo == 1) enqueue_batch_list<1>(b, s);
-    else enqueue_batch_list<2>(b, s);
+void enqueue_for(tl_batch *b, int algo, const BatchTuning &tu, hipStream_t s) {
+    if (algo == 0) enqueue_batch_list<0>(b, tu, s);
+    else if (algo == 1) enqueue_batch_list<1>(b, tu, s);
+    else enqueue_batch_list<2>(b, tu, s);
 }
 
 }  // namespace
+
+int batch_set_tuning(const std::string &key, u64 value) {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    BatchTuning &t = btune();
+    if (key == "batch_heavy_min") t.heavy_min = value;
+    else if (key == "batch_heavy_block" && (value == 256 || value == 512 || value == 1024)) t.heavy_block = value;
+    else if (key == "batch_heavy_per_cu" && value >= 1 && value <= 2) t.heavy_per_cu = value;
+    else if (key == "batch_light_per_cu" && value >= 1 && value <= 64) t.light_per_cu = value;
+    else return TL_EINVAL;
+    return TL_OK;
+}
+
+int batch_get_tuning(const std::string &key, u64 *value) {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    const BatchTuning &t = btune();
+    if (key == "batch_heavy_min") *value = t.heavy_min;
+    else if (key == "batch_heavy_block") *value = t.heavy_block;
+    else if (key == "batch_heavy_per_cu") *value = t.heavy_per_cu;
+    else if (key == "batch_light_per_cu") *value = t.light_per_cu;
+    else return TL_EINVAL;
+    return TL_OK;
+}
 
 tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, const u32 *dst, const u32 *rank,
                             hipStream_t s) {
@@ -389,20 +696,27 @@ tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, c
     TL_REQUIRE(!(h_flag & 2u), TL_EINVAL, "an edge endpoint is >= its graph's n");
     b->g = orient_impl((u32)N, usrc.as<u32>(), udst.as<u32>(), M, urank.as<u32>(), s);
 
-    // listing scratch for the union's m
-    const u64 mm = b->g->m ? b->g->m : 1;
+    // listing scratch for the union's m and N
+    const u64 mm = b->g->m ? b->g->m : 1, nn = N ? N : 1;
+    b->lw = (u32 *)tl_dev_alloc(mm * 4, s);
     b->cxinv = (u32 *)tl_dev_alloc(mm * 4, s);
     b->ctlo = (u32 *)tl_dev_alloc(mm * 4, s);
     b->cthi = (u32 *)tl_dev_alloc(mm * 4, s);
     b->cpinv = (u32 *)tl_dev_alloc(mm * 4, s);
     b->cgid = (u32 *)tl_dev_alloc(mm * 4, s);
     b->clen = (u32 *)tl_dev_alloc(mm * 4, s);
-    b->flag = b->clen;  // the flags are consumed by their scan before clen is cleared
+    b->f64 = (u64 *)tl_dev_alloc(mm * 8, s);
+    b->cabs = b->f64;  // the seed flags are consumed by their scan before compaction writes cabs
     b->pos = (u64 *)tl_dev_alloc((mm + 1) * 8, s);
-    b->cabs = (u64 *)tl_dev_alloc(mm * 8, s);
     b->cpre = (u64 *)tl_dev_alloc((mm + 1) * 8, s);
-    b->ws = (u64 *)tl_dev_alloc((scan_workspace_words(mm) + 1) * 8, s);
+    b->wp = (u64 *)tl_dev_alloc(nn * 8, s);
+    b->hpre = (u64 *)tl_dev_alloc((nn + 1) * 8, s);
+    b->hflag = (u32 *)tl_dev_alloc(nn * 4, s);
+    b->hpiv = (u32 *)tl_dev_alloc(nn * 4, s);
+    b->ws = (u64 *)tl_dev_alloc((scan_workspace_words(mm > nn ? mm : nn) + 1) * 8, s);
     b->pg = (u64 *)tl_dev_alloc(3ull * k * 8, s);
+    b->ctl = (u64 *)tl_dev_alloc(8, s);
+    prepare_batch_kernels();
     TL_HIP(hipStreamSynchronize(s));
     tl_batch *r = own.b;
     own.b = nullptr;
@@ -410,20 +724,33 @@ tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, c
 }
 
 void batch_list_impl(tl_batch *b, int algo, hipStream_t s, int use_graph, u64 *per_graph_host, u64 *per_graph_dev) {
+    BatchTuning tu;
+    {
+        std::lock_guard<std::mutex> lk(g_btune_mu);
+        tu = btune();
+    }
     PhaseTimer timer(TL_PHASE_BATCH, s);
     if (b->g->m == 0) {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid_b(3ull * b->k)), dim3(BB), 0, s, b->pg, 3ull * b->k, 0ull);
         TL_HIP(hipGetLastError());
     } else if (!use_graph) {
-        enqueue_for(b, algo, s);
+        enqueue_for(b, algo, tu, s);
     } else {
+        if (b->exec[algo] && !same_tune(b->cap_tune[algo], tu)) {
+            // the tuning changed since the capture: capture again
+            TL_HIP(hipStreamSynchronize(s));
+            (void)hipGraphExecDestroy(b->exec[algo]);
+            (void)hipGraphDestroy(b->graph[algo]);
+            b->exec[algo] = nullptr;
+            b->graph[algo] = nullptr;
+        }
         if (!b->exec[algo]) {
             // capture on a private stream, so that the caller's stream state
             // is untouched, then replay on the caller's stream
-            TL_HIP(hipStreamCreateWithFlags(&b->cap_stream[algo], hipStreamNonBlocking));
+            if (!b->cap_stream[algo]) TL_HIP(hipStreamCreateWithFlags(&b->cap_stream[algo], hipStreamNonBlocking));
             TL_HIP(hipStreamBeginCapture(b->cap_stream[algo], hipStreamCaptureModeThreadLocal));
             try {
-                enqueue_for(b, algo, b->cap_stream[algo]);
+                enqueue_for(b, algo, tu, b->cap_stream[algo]);
             } catch (...) {
                 hipGraph_t dead = nullptr;
                 (void)hipStreamEndCapture(b->cap_stream[algo], &dead);
@@ -432,6 +759,7 @@ void batch_list_impl(tl_batch *b, int algo, hipStream_t s, int use_graph, u64 *p
             }
             TL_HIP(hipStreamEndCapture(b->cap_stream[algo], &b->graph[algo]));
             TL_HIP(hipGraphInstantiate(&b->exec[algo], b->graph[algo], nullptr, nullptr, 0));
+            b->cap_tune[algo] = tu;
         }
         TL_HIP(hipGraphLaunch(b->exec[algo], s));
     }
@@ -452,8 +780,8 @@ void batch_free_impl(tl_batch *b, bool device_sync) {
         if (b->cap_stream[a]) (void)hipStreamDestroy(b->cap_stream[a]);
     }
     if (b->g) tl_csr_free(b->g);
-    void *bufs[] = {b->gid, b->vbase, b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid,
-                    b->clen, b->pos, b->cabs, b->cpre, b->ws, b->pg};
+    void *bufs[] = {b->gid, b->vbase, b->lw, b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid, b->clen, b->f64,
+                    b->pos, b->cpre, b->wp, b->hpre, b->hflag, b->hpiv, b->ws, b->pg, b->ctl};
     for (void *p : bufs) tl_dev_free(p);
     delete b;
 }

@@ -990,6 +990,7 @@ tl_list_stats &last_stats() {
 int set_tuning(const char *key, u64 value) {
     Tuning &t = tuning();
     const std::string k(key ? key : "");
+    if (k.rfind("batch_", 0) == 0) return batch_set_tuning(k, value);
     if (k == "heavy_min" && value >= 1) t.heavy_min = value;
     else if (k == "slice_min" && value >= 64) t.slice_min = value;
     else if (k == "slice_mult" && value >= 1) t.slice_mult = value;
@@ -1007,6 +1008,7 @@ int set_tuning(const char *key, u64 value) {
 int get_tuning(const char *key, u64 *value) {
     const Tuning &t = tuning();
     const std::string k(key ? key : "");
+    if (k.rfind("batch_", 0) == 0) return batch_get_tuning(k, value);
     if (k == "heavy_min") *value = t.heavy_min;
     else if (k == "slice_min") *value = t.slice_min;
     else if (k == "slice_mult") *value = t.slice_mult;

@@ -135,6 +135,9 @@ void batch_list_impl(tl_batch *b, int algo, hipStream_t s, int use_graph, u64 *p
 // synchronised every stream that used the batch).
 void batch_free_impl(tl_batch *b, bool device_sync);
 const tl_csr *batch_csr(const tl_batch *b);
+// Launch parameters of the batched pass (keys batch_*).
+int batch_set_tuning(const std::string &key, u64 value);
+int batch_get_tuning(const std::string &key, u64 *value);
 void batch_sizes(const tl_batch *b, u32 *k, u32 *n, u64 *m);
 
 // Listing server (serve.hip).

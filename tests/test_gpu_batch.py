@@ -163,3 +163,64 @@ def test_batch_rejects_bad_input(tl):
         tl.batch_orient(n, m, dev(np.array([0, 0], np.uint32)), dev(np.array([1, 1], np.uint32)),
                         dev(np.array([0, 1, 2, 1, 1, 0], np.uint32)))
     assert e.value.code == tl.tl.TL_EINVAL
+
+
+BINS = [
+    {"batch_heavy_min": 1},                      # every pivot with work in the LDS bin where it fits
+    {"batch_heavy_min": 1 << 62},                # no LDS bin
+    {"batch_heavy_min": 64, "batch_heavy_block": 256, "batch_heavy_per_cu": 1},
+    {"batch_heavy_min": 512, "batch_heavy_block": 1024, "batch_light_per_cu": 1},
+]
+
+
+@pytest.fixture
+def restore_tuning(tl):
+    keys = ["batch_heavy_min", "batch_heavy_block", "batch_heavy_per_cu", "batch_light_per_cu"]
+    saved = {k: tl.get_tuning(k) for k in keys}
+    yield
+    for k, v in saved.items():
+        tl.set_tuning(k, v)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("bins", BINS, ids=["all-lds", "no-lds", "small-lds", "big-lds"])
+def test_bins_and_shapes_do_not_change_results(tl, algo, bins, restore_tuning):
+    B, graphs = workload_graphs(8, first=40)
+    graphs += fixture_graphs()
+    n, m, s, d, r = pack(graphs[8:])
+    n = np.concatenate([B.n, n])
+    m = np.concatenate([B.m, m])
+    b = tl.batch_orient(n, m, dev(np.concatenate([B.src, s])), dev(np.concatenate([B.dst, d])),
+                        dev(np.concatenate([B.rank, r])))
+    try:
+        want = oracle_table(graphs, algo)
+        for k, v in bins.items():
+            tl.set_tuning(k, v)
+        assert np.array_equal(b.list(algo, use_graph=False), want)
+        assert np.array_equal(b.list(algo, use_graph=True), want)
+    finally:
+        b.free()
+
+
+def test_graph_recaptured_after_tuning_change(tl, restore_tuning):
+    B, graphs = workload_graphs(5, first=200)
+    b = tl.batch_orient(B.n, B.m, dev(B.src), dev(B.dst), dev(B.rank))
+    try:
+        want = oracle_table(graphs, "A++")
+        tl.set_tuning("batch_heavy_min", 1 << 62)
+        assert np.array_equal(b.list("A++"), want)
+        tl.set_tuning("batch_heavy_min", 1)
+        assert np.array_equal(b.list("A++"), want)
+        tl.set_tuning("batch_heavy_block", 1024)
+        assert np.array_equal(b.list("A++"), want)
+    finally:
+        b.free()
+
+
+def test_batch_tuning_keys(tl, restore_tuning):
+    with pytest.raises(tl.TLError):
+        tl.set_tuning("batch_heavy_block", 300)
+    with pytest.raises(tl.TLError):
+        tl.set_tuning("batch_light_per_cu", 0)
+    tl.set_tuning("batch_heavy_per_cu", 1)
+    assert tl.get_tuning("batch_heavy_per_cu") == 1

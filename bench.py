@@ -471,7 +471,8 @@ def main():
     class Stats(ctypes.Structure):
         _fields_ = [(k, ctypes.c_uint64) for k in (
             "light_items", "heavy_items", "light_seeds", "heavy_seeds", "heavy_work", "heavy_pivots",
-            "heavy_staged", "heavy_triangles", "tasks")]
+            "heavy_staged", "heavy_triangles", "tasks", "items_bitmap", "items_array", "items_global",
+            "items_reverse", "items_hash", "items_bucket", "items_split")]
 
     def phase_ms():
         vals = []

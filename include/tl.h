@@ -277,9 +277,18 @@ void tl_server_destroy(tl_server *s);
  *   reverse              1: a heavy pivot whose list fits no LDS form tests
  *                        each edge (y, pivot) by searching y's own sorted
  *                        list instead of the pivot's
+ *   bucket               1: a heavy pivot whose list's rank window is too
+ *                        wide for the LDS bitmap keeps the list in LDS with
+ *                        a table of where each of 8192 equal slices of the
+ *                        window starts (a search then covers one slice)
+ *   split                1: a heavy pivot whose list is too long for LDS
+ *                        marks the entries in the top 2^20 ranks of its
+ *                        window in an LDS bitmap and searches the rest in
+ *                        global memory; 2: also in place of the array and
+ *                        bucket forms
  *   force_mode           testing: 0 bitmap, 1 array, 2 global, 3 reverse,
- *                        4 hash for every heavy pivot where it fits;
- *                        255 = automatic
+ *                        4 hash, 5 bucket, 6 split for every heavy pivot
+ *                        where it fits; 255 = automatic
  * and for the batched pass (tl_batch_list; a captured pass is captured
  * again when these change):
  *   batch_heavy_min      pruned items of a pivot before its list is marked
@@ -322,6 +331,8 @@ typedef struct {
     uint64_t light_seeds, heavy_seeds;
     uint64_t heavy_work, heavy_pivots, heavy_staged, heavy_triangles;
     uint64_t tasks;
+    uint64_t mode_items[7]; /* heavy items by LDS form: bitmap, array, global,
+                               reverse, hash, bucket, split */
 } tl_list_stats;
 int tl_last_list_stats(tl_list_stats *out);
 

@@ -135,11 +135,12 @@ __device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u64 &abs) {
     return 0;
 }
 
-// Per seed edge: its window length lw[e]; per pivot: the sum of its seeds'
-// lengths wp[p]; per graph: the paper's work (the scanned lists' lengths).
+// Per seed edge: its window, start sabs[e] and length lw[e]; per pivot: the
+// sum of its seeds' lengths wp[p]; per graph: the paper's work (the scanned
+// lists' lengths).
 // pg holds (count, digest, work) per graph.
 template <int ALGO>
-__global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *lw, u64 *wp, u64 *pg) {
+__global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *lw, u64 *sabs, u64 *wp, u64 *pg) {
     const int lane = lane_id();
     const u64 stride = (u64)gridDim.x * blockDim.x;
     const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,6 +158,7 @@ __global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *lw, 
             u64 abs;
             l = seed_window<ALGO>(sd, abs);
             lw[e] = l;
+            sabs[e] = abs;
         }
         wave_segmented_add(valid, gr, w, pg + 2, 3);
         wave_segmented_add(valid, p, l, wp, 1);
@@ -197,21 +199,29 @@ __global__ void k_bflag(GView g, const u32 *lw, const u32 *hflag, u64 *f64) {
 // Seeds with a non-empty window, packed in seed order: light pivots' seeds
 // at [0, nlight), heavy pivots' seeds after them.
 template <int ALGO>
-__global__ void k_bcompact(GView g, const u32 *gid, const u32 *lw, const u64 *pos, u64 *cabs, u32 *cxinv, u32 *ctlo,
-                           u32 *cthi, u32 *cpinv, u32 *cgid, u32 *clen) {
+__global__ void k_bcompact(GView g, const u32 *gid, const u32 *lw, const u64 *sabs, const u64 *pos, u64 *cabs,
+                           u32 *cxinv, u32 *ctlo, u32 *cthi, u32 *cpinv, u32 *cgid, u32 *clen) {
     const u64 nlight = pos[g.m] & 0xffffffffull;
     GRID_STRIDE(e, g.m) {
         const u64 pe = pos[e], pn = pos[e + 1];
         if (pn != pe) {
             const bool heavy = (pn >> 32) != (pe >> 32);
             const u64 d = heavy ? nlight + (pe >> 32) : (pe & 0xffffffffull);
-            Seed<ALGO> sd(g, e);
-            cabs[d] = lower_bound_dev<u32>(sd.S, sd.s_lo, sd.s_hi, sd.T[sd.t_lo]);
-            cxinv[d] = g.inv[sd.x];
-            ctlo[d] = (u32)sd.t_lo;
-            cthi[d] = (u32)sd.t_hi;
-            cpinv[d] = g.inv[sd.p];
-            cgid[d] = gid[sd.p];
+            u32 p, x;
+            u64 t_lo, t_hi;
+            if (ALGO == 0) {
+                p = g.row_b[e]; x = g.adj_b[e]; t_lo = e + 1; t_hi = g.off_b[p + 1];
+            } else if (ALGO == 1) {
+                p = g.row_f[e]; x = g.adj_f[e]; t_lo = e + 1; t_hi = g.off_f[p + 1];
+            } else {
+                p = g.row_f[e]; x = g.adj_f[e]; t_lo = g.off_b[p]; t_hi = g.off_b[p + 1];
+            }
+            cabs[d] = sabs[e];
+            cxinv[d] = g.inv[x];
+            ctlo[d] = (u32)t_lo;
+            cthi[d] = (u32)t_hi;
+            cpinv[d] = g.inv[p];
+            cgid[d] = gid[p];
             clen[d] = lw[e];
         }
     }
@@ -591,13 +601,15 @@ void enqueue_batch_list(tl_batch *b, const BatchTuning &tu, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_b(3ull * b->k)), dim3(BB), 0, s, b->pg, 3ull * b->k, 0ull);
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_b(N)), dim3(BB), 0, s, b->wp, N, 0ull);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, b->ctl, 1ull, 0ull);
-    hipLaunchKernelGGL((k_bplan<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->lw, b->wp, b->pg);
+    // the seeds' window starts live in cpre's buffer until the compaction
+    // has read them; the scan of the compacted lengths then overwrites them
+    hipLaunchKernelGGL((k_bplan<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->lw, b->cpre, b->wp, b->pg);
     hipLaunchKernelGGL((k_bclass<ALGO>), dim3(grid_b(N)), dim3(BB), 0, s, v, (u32)N, b->wp, tu.heavy_min, b->hflag);
     hipLaunchKernelGGL((k_bflag<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->lw, b->hflag, b->f64);
     scan_u64_to_u64(b->f64, b->pos, m, s, b->ws);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_b(m)), dim3(BB), 0, s, b->clen, m, 0u);
-    hipLaunchKernelGGL((k_bcompact<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->lw, b->pos, b->cabs,
-                       b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid, b->clen);
+    hipLaunchKernelGGL((k_bcompact<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->lw, b->cpre, b->pos,
+                       b->cabs, b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid, b->clen);
     scan_u32_to_u64(b->clen, b->cpre, m, s, b->ws);
     scan_u32_to_u64(b->hflag, b->hpre, N, s, b->ws);
     hipLaunchKernelGGL(k_bhlist, dim3(grid_b(N)), dim3(BB), 0, s, (u32)N, b->hflag, b->hpre, b->hpiv);

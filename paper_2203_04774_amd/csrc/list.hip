@@ -41,7 +41,8 @@ constexpr int HB = 1024;       // threads per block, heavy-pivot kernel
 constexpr u32 LDS_BYTES = 128 * 1024;
 constexpr u32 LDS_WORDS = LDS_BYTES / 4;
 constexpr u64 LDS_BITS = (u64)LDS_BYTES * 8;
-constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES;
+constexpr u32 LOW_WORDS = 8160;  // SPLIT: list entries below the bitmap's window kept in LDS (160 KB in all)
+constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + LOW_WORDS * 4;
 // Tunable launch parameters (defaults; tl_set_tuning or TL_TUNE_* env vars).
 struct Tuning {
     // defaults from sweeps on the Chung-Lu 2^20 workload (random and degree
@@ -55,6 +56,8 @@ struct Tuning {
     u64 light_blocks_per_cu = 8; // light grid cap
     u64 reverse = 0;             // 1: REVERSE instead of GLOBAL for lists that fit no LDS form
     u64 hash = 0;                // 1: HASH before ARRAY when B's window does not fit LDS
+    u64 bucket = 0;              // 1: BUCKET before ARRAY when B's window does not fit LDS
+    u64 split = 2;               // 1: SPLIT for lists too long for LDS; 2: also before ARRAY/BUCKET
     u64 force_mode = 255;        // testing: use this MODE_* for every heavy pivot where it fits
 };
 Tuning &tuning();
@@ -67,7 +70,26 @@ Tuning &tuning();
 //            iff p in N+_y; for A+-, y in N+_p iff p in N-_y -- a search of
 //            y's own sorted list
 //   HASH     T in an LDS open-addressing table (linear probing, load <= 1/2)
-enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2, MODE_REVERSE = 3, MODE_HASH = 4 };
+//   BUCKET   T in LDS with a table of where each of 8192 equal slices of its
+//            rank window starts: one table read, then a binary search of the
+//            few entries of y's slice
+//   SPLIT    the top LDS_BITS ranks of T's window as an LDS bitmap (B for the
+//            entries that lie there), the entries below binary-searched in
+//            an LDS array when at most LOW_WORDS of them, else in global
+//            memory; under orders that put hubs last most scanned elements
+//            fall in the top part
+enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2, MODE_REVERSE = 3, MODE_HASH = 4, MODE_BUCKET = 5,
+       MODE_SPLIT = 6 };
+constexpr int NMODES = 7;
+constexpr u32 BUCKETS = 8192;                              // slices of the rank window
+constexpr u32 BUCKET_MAX = LDS_WORDS - (BUCKETS + 2) / 2;  // list entries beside a u16 start table
+
+// log2 of the slice width: the smallest s with (range - 1) >> s < BUCKETS
+__host__ __device__ __forceinline__ u32 bucket_shift(u64 range) {
+    u32 sh = 0;
+    while (((range - 1) >> sh) >= BUCKETS) sh++;
+    return sh;
+}
 
 constexpr u32 HASH_MAX = LDS_WORDS / 2;  // list entries a task's hash table holds
 
@@ -157,7 +179,8 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len
 template <int ALGO>
 __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask,
                                                     u64 *slice, u64 heavy_min, u64 slice_min, u64 slice_mult,
-                                                    u64 reverse, u64 use_hash, u64 force_mode, u64 *acc) {
+                                                    u64 reverse, u64 use_hash, u64 use_bucket, u64 use_split,
+                                                    u64 force_mode, u64 *acc) {
     __shared__ u64 lds[PB / WAVE];
     u64 hp = 0, staged = 0;
     GRID_STRIDE(p, n) {
@@ -180,9 +203,14 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             else if (force_mode == MODE_GLOBAL) { md = MODE_GLOBAL; stage = 0; }
             else if (force_mode == MODE_REVERSE) { md = MODE_REVERSE; stage = 0; }
             else if (force_mode == MODE_HASH && tlen <= HASH_MAX) { md = MODE_HASH; stage = 2 * tlen + 2 * tlen; }
+            else if (force_mode == MODE_BUCKET && tlen <= BUCKET_MAX) { md = MODE_BUCKET; stage = 2 * tlen + 16 * BUCKETS; }
+            else if (force_mode == MODE_SPLIT) { md = MODE_SPLIT; stage = 2 * tlen; }
             else if (bm_ok) { md = MODE_BITMAP; stage = 2 * tlen; }
+            else if (use_split >= 2) { md = MODE_SPLIT; stage = 2 * tlen; }
             else if (use_hash && tlen <= HASH_MAX) { md = MODE_HASH; stage = 4 * tlen; }
+            else if (use_bucket && tlen <= BUCKET_MAX) { md = MODE_BUCKET; stage = 2 * tlen + 16 * BUCKETS; }
             else if (arr_ok) { md = MODE_ARRAY; stage = 2 * tlen; }
+            else if (use_split) { md = MODE_SPLIT; stage = 2 * tlen; }
             else if (reverse) { md = MODE_REVERSE; stage = 0; }
             else { md = MODE_GLOBAL; stage = 0; }
             sl = slice_mult * stage;
@@ -190,6 +218,7 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             nt = (u32)((w + sl - 1) / sl);
             hp += 1;
             staged += tlen;
+            atomicAdd((unsigned long long *)&acc[10 + md], (unsigned long long)w);  // items per mode
         }
         mode[p] = md;
         ntask[p] = nt;
@@ -520,7 +549,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
     const u32 *pa = Form<ALGO>::piv_adj(g);
     WaveEmitter<EMIT> em;
     u64 cnt = 0, hsh = 0;
-    __shared__ u64 next_task;
+    __shared__ u64 next_task, split_at;
     for (u32 i = threadIdx.x; i < LDS_WORDS; i += blockDim.x) lds[i] = 0u;  // B starts all false
     __syncthreads();
     for (u64 it = 0;; it++) {
@@ -550,14 +579,37 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         const u64 t0 = po[p], t1 = po[p + 1];
         const u32 tmin = pa[t0], tmax = pa[t1 - 1];
         const u32 tlen = (u32)(t1 - t0);
-        if (tk.mode == MODE_BITMAP) {
-            for (u64 i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
-                const u32 v = pa[i] - tmin;
+        // SPLIT: the bitmap covers ranks [wlo, tmax]; entries [t0, ts) lie below
+        const u32 wlo = (u64)tmax - tmin + 1 > LDS_BITS ? (u32)((u64)tmax + 1 - LDS_BITS) : tmin;
+        if (tk.mode == MODE_SPLIT) {
+            if (threadIdx.x == 0) split_at = lower_bound_dev<u32>(pa, t0, t1, wlo);
+            __syncthreads();
+        }
+        const u64 ts = tk.mode == MODE_SPLIT ? split_at : t0;
+        u32 *low = lds + LDS_WORDS;  // SPLIT: T[t0, ts) when it fits
+        const bool low_lds = tk.mode == MODE_SPLIT && ts - t0 <= LOW_WORDS;
+        if (low_lds) {
+            for (u64 i = t0 + threadIdx.x; i < ts; i += blockDim.x) low[i - t0] = pa[i];
+        }
+        if (tk.mode == MODE_BITMAP || tk.mode == MODE_SPLIT) {
+            for (u64 i = ts + threadIdx.x; i < t1; i += blockDim.x) {
+                const u32 v = pa[i] - wlo;
                 atomicOr(&lds[v >> 5], 1u << (v & 31));
             }
             __syncthreads();
         } else if (tk.mode == MODE_ARRAY) {
             for (u32 i = threadIdx.x; i < tlen; i += blockDim.x) lds[i] = pa[t0 + i];
+            __syncthreads();
+        } else if (tk.mode == MODE_BUCKET) {
+            for (u32 i = threadIdx.x; i < tlen; i += blockDim.x) lds[i] = pa[t0 + i];
+            __syncthreads();
+            // start of slice b: the first entry >= tmin + (b << sh)
+            const u32 sh = bucket_shift((u64)tmax - tmin + 1);
+            unsigned short *bs = reinterpret_cast<unsigned short *>(lds + tlen);
+            for (u32 b = threadIdx.x; b <= BUCKETS; b += blockDim.x) {
+                const u64 key = (u64)tmin + ((u64)b << sh);
+                bs[b] = (unsigned short)(key > tmax ? tlen : lower_bound_dev<u32>(lds, 0, tlen, (u32)key));
+            }
             __syncthreads();
         } else if (tk.mode == MODE_HASH) {
             // keys stored as value + 1 so that the all-zero LDS reads as empty
@@ -577,10 +629,31 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             const u32 pinv = g.inv[p];
             u32 xinv = 0;
             u64 xinv_c = ~0ull;
+            const u32 bsh = tk.mode == MODE_BUCKET ? bucket_shift((u64)tmax - tmin + 1) : 0u;
+            const unsigned short *bst = reinterpret_cast<const unsigned short *>(lds + tlen);
             auto member = [&](u32 y) -> bool {
                 if (tk.mode == MODE_BITMAP) {
                     const u32 v = y - tmin;
                     return y >= tmin && y <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
+                } else if (tk.mode == MODE_SPLIT) {
+                    if (y > tmax) return false;
+                    if (y >= wlo) {
+                        const u32 v = y - wlo;
+                        return (lds[v >> 5] >> (v & 31)) & 1u;
+                    }
+                    if (low_lds) {
+                        const u32 nl = (u32)(ts - t0);
+                        const u64 j = lower_bound_dev<u32>(low, 0, nl, y);
+                        return j < nl && low[j] == y;
+                    }
+                    const u64 j = lower_bound_dev<u32>(pa, t0, ts, y);
+                    return j < ts && pa[j] == y;
+                } else if (tk.mode == MODE_BUCKET) {
+                    if (y < tmin || y > tmax) return false;
+                    const u32 b = (y - tmin) >> bsh;
+                    const u32 lo = bst[b], hi = bst[b + 1];
+                    const u64 j = lower_bound_dev<u32>(lds, lo, hi, y);
+                    return j < hi && lds[j] == y;
                 } else if (tk.mode == MODE_ARRAY) {
                     const u64 j = lower_bound_dev<u32>(lds, 0, tlen, y);
                     return j < tlen && lds[j] == y;
@@ -605,7 +678,34 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             };
             // membership of UN elements at once (interleaved where it is a search)
             auto member_all = [&](const u32 (&y)[UN], bool (&h)[UN]) {
-                if (tk.mode == MODE_ARRAY) {
+                if (tk.mode == MODE_SPLIT) {
+                    // the entries below the bitmap's window: interleaved global searches
+                    u64 lo[UN], hi[UN];
+                    const u64 base = low_lds ? 0 : t0, top = low_lds ? ts - t0 : ts;
+#pragma unroll
+                    for (int j = 0; j < UN; j++) {
+                        lo[j] = base;
+                        hi[j] = y[j] >= wlo ? base : top;
+                    }
+                    member_multi_var(low_lds ? low : pa, lo, hi, y, h);
+#pragma unroll
+                    for (int j = 0; j < UN; j++) {
+                        if (y[j] >= wlo) {
+                            const u32 v = y[j] - wlo;
+                            h[j] = y[j] <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
+                        }
+                    }
+                } else if (tk.mode == MODE_BUCKET) {
+                    u64 lo[UN], hi[UN];
+#pragma unroll
+                    for (int j = 0; j < UN; j++) {
+                        const bool in = y[j] >= tmin && y[j] <= tmax;
+                        const u32 b = in ? (y[j] - tmin) >> bsh : 0u;
+                        lo[j] = in ? bst[b] : 0u;
+                        hi[j] = in ? bst[b + 1] : 0u;
+                    }
+                    member_multi_var(lds, lo, hi, y, h);
+                } else if (tk.mode == MODE_ARRAY) {
                     member_multi(lds, 0, tlen, y, h);
                 } else if (tk.mode == MODE_GLOBAL) {
                     member_multi(pa, t0, t1, y, h);
@@ -722,11 +822,15 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         }
         __syncthreads();  // every wavefront is done with the staged list
         // reset B (or the staged array) so that LDS is all zero again
-        if (tk.mode == MODE_BITMAP) {
-            for (u64 i = t0 + threadIdx.x; i < t1; i += blockDim.x) lds[(pa[i] - tmin) >> 5] = 0u;
+        if (tk.mode == MODE_BITMAP || tk.mode == MODE_SPLIT) {
+            for (u64 i = ts + threadIdx.x; i < t1; i += blockDim.x) lds[(pa[i] - wlo) >> 5] = 0u;
             __syncthreads();
         } else if (tk.mode == MODE_ARRAY) {
             for (u32 i = threadIdx.x; i < tlen; i += blockDim.x) lds[i] = 0u;
+            __syncthreads();
+        } else if (tk.mode == MODE_BUCKET) {
+            const u32 words = tlen + (BUCKETS + 2) / 2;
+            for (u32 i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0u;
             __syncthreads();
         } else if (tk.mode == MODE_HASH) {
             const u32 slots = 1u << hash_bits_for(tlen);
@@ -809,7 +913,7 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
     const Tuning &tu = tuning();
     hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), mode.as<u32>(),
                        ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult,
-                       tu.reverse, tu.hash, tu.force_mode, d_acc);
+                       tu.reverse, tu.hash, tu.bucket, tu.split, tu.force_mode, d_acc);
     TL_HIP(hipGetLastError());
     DevBuf flags(m * sizeof(u64), s), pos((m + 1) * sizeof(u64), s);
     hipLaunchKernelGGL((k_seed_class<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), mode.as<u32>(),
@@ -952,6 +1056,8 @@ Tuning &tuning() {
         env("TL_TUNE_LIGHT_BLOCKS_PER_CU", d.light_blocks_per_cu);
         env("TL_TUNE_REVERSE", d.reverse);
         env("TL_TUNE_HASH", d.hash);
+        env("TL_TUNE_BUCKET", d.bucket);
+        env("TL_TUNE_SPLIT", d.split);
         env("TL_TUNE_FORCE_MODE", d.force_mode);
         return d;
     }();
@@ -1000,7 +1106,9 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "light_blocks_per_cu" && value >= 1 && value <= 64) t.light_blocks_per_cu = value;
     else if (k == "reverse" && value <= 1) t.reverse = value;
     else if (k == "hash" && value <= 1) t.hash = value;
-    else if (k == "force_mode" && (value <= MODE_HASH || value == 255)) t.force_mode = value;
+    else if (k == "bucket" && value <= 1) t.bucket = value;
+    else if (k == "split" && value <= 2) t.split = value;
+    else if (k == "force_mode" && (value < NMODES || value == 255)) t.force_mode = value;
     else return TL_EINVAL;
     return TL_OK;
 }
@@ -1018,6 +1126,8 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "light_blocks_per_cu") *value = t.light_blocks_per_cu;
     else if (k == "reverse") *value = t.reverse;
     else if (k == "hash") *value = t.hash;
+    else if (k == "bucket") *value = t.bucket;
+    else if (k == "split") *value = t.split;
     else if (k == "force_mode") *value = t.force_mode;
     else return TL_EINVAL;
     return TL_OK;
@@ -1048,7 +1158,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     const GView v = view_of(g);
     prepare_kernels();
 
-    constexpr int NACC = 10;
+    constexpr int NACC = 10 + NMODES;
     DevBuf acc(NACC * sizeof(u64), s);
     TL_HIP(hipMemsetAsync(acc.p, 0, NACC * sizeof(u64), s));
     u64 *d_acc = acc.as<u64>();
@@ -1134,6 +1244,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     st.heavy_pivots = h_acc[7];
     st.heavy_triangles = h_acc[8];
     st.heavy_staged = h_acc[9];
+    for (int md = 0; md < NMODES; md++) st.mode_items[md] = h_acc[10 + md];
     st.tasks = P.ntasks;
     return rc;
 }

@@ -30,7 +30,7 @@ def short_name(name: str) -> str:
 
 def list_source_digest() -> str:
     h = hashlib.sha256()
-    for f in ("list.hip", "dev_util.h"):
+    for f in ("list.hip", "dev_util.h", "probe_common.h"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -333,9 +333,30 @@ TUNINGS = {
     "global": {"heavy_min": 1, "force_mode": 2},
     "reverse": {"heavy_min": 1, "force_mode": 3},
     "hash": {"heavy_min": 1, "force_mode": 4},
+    "bucket": {"heavy_min": 1, "force_mode": 5},
+    "split": {"heavy_min": 1, "force_mode": 6},
+    "split-auto": {"heavy_min": 1, "split": 2},
     "tiny-tasks-static": {"heavy_min": 1, "slice_min": 64, "slice_mult": 1, "queue": 0, "splits": 0},
     "tiny-tasks-queue": {"heavy_min": 1, "slice_min": 64, "slice_mult": 1, "queue": 1, "splits": 1},
 }
+
+
+def wide_hub_case(seed):
+    """1.5M vertices; a hub adjacent to 20,000 of them spread over the whole
+    rank range, random edges among those; the hub ranked last."""
+    rs = np.random.default_rng(seed)
+    n = 1_500_000
+    nodes = rs.choice(n, 20_000, replace=False).astype(np.uint32)
+    hub = nodes[0]
+    a = rs.choice(nodes[1:], 80_000)
+    b = rs.choice(nodes[1:], 80_000)
+    src = np.concatenate([np.full(len(nodes) - 1, hub, np.uint32), a]).astype(np.uint32)
+    dst = np.concatenate([nodes[1:], b]).astype(np.uint32)
+    g = graphgen.simplify(n, src, dst)
+    rank = rs.permutation(n).astype(np.uint32)
+    top = int(np.where(rank == n - 1)[0][0])
+    rank[top], rank[hub] = rank[hub], n - 1
+    return n, g.src, g.dst, rank
 
 
 @pytest.fixture
@@ -365,6 +386,12 @@ def test_probe_paths(tl, tuned, algo):
     gr = graphgen.config_rmat12(seed=3)
     for kind in ["degree", "random"]:
         assert_same(tl, gr.n, gr.src, gr.dst, graphgen.ordering(gr, kind, seed=2), algo)
+    # pivot lists spread over rank windows far wider than 8192 slices
+    gc = graphgen.chung_lu(60000, 2.1, 10.0, seed=9)
+    assert_same(tl, gc.n, gc.src, gc.dst, graphgen.random_order(gc.n, seed=4), algo)
+    # a hub whose neighbours span 1.5M ranks: its list's window is wider than an LDS bitmap
+    n, s, d, r = wide_hub_case(11)
+    assert_same(tl, n, s, d, r, algo)
     # chunked: slices of 5000 items cut through heavy tasks
     import torch
     r = graphgen.degree_order(gr)

@@ -179,8 +179,8 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len
 template <int ALGO>
 __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask,
                                                     u64 *slice, u64 heavy_min, u64 slice_min, u64 slice_mult,
-                                                    u64 reverse, u64 use_hash, u64 use_bucket, u64 use_split,
-                                                    u64 force_mode, u64 *acc) {
+                                                    u64 max_task, u64 reverse, u64 use_hash, u64 use_bucket,
+                                                    u64 use_split, u64 force_mode, u64 *acc) {
     __shared__ u64 lds[PB / WAVE];
     u64 hp = 0, staged = 0;
     GRID_STRIDE(p, n) {
@@ -215,6 +215,7 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             else { md = MODE_GLOBAL; stage = 0; }
             sl = slice_mult * stage;
             if (sl < slice_min) sl = slice_min;
+            if (max_task && sl > max_task) sl = max_task;
             nt = (u32)((w + sl - 1) / sl);
             hp += 1;
             staged += tlen;
@@ -900,7 +901,10 @@ struct Plan {
 };
 
 template <int ALGO>
-void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t s, Plan &P) {
+// max_task: items per heavy task at most (0: no limit).  A listing probed in
+// item slices keeps tasks well below a slice, so that every slice has work
+// for all workgroups.
+void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc, hipStream_t s, Plan &P) {
     const u64 m = v.m;
     const unsigned gm = grid_for(m, PB, (unsigned)tl_num_cus() * 16);
     const unsigned gn = grid_for(n, PB, (unsigned)tl_num_cus() * 16);
@@ -912,7 +916,7 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 *d_acc, hipStream_t 
     DevBuf mode((u64)n * sizeof(u32), s), ntask((u64)n * sizeof(u32), s), slice((u64)n * sizeof(u64), s);
     const Tuning &tu = tuning();
     hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), mode.as<u32>(),
-                       ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult,
+                       ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult, max_task,
                        tu.reverse, tu.hash, tu.bucket, tu.split, tu.force_mode, d_acc);
     TL_HIP(hipGetLastError());
     DevBuf flags(m * sizeof(u64), s), pos((m + 1) * sizeof(u64), s);
@@ -1167,9 +1171,14 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     Plan P;
     {
         PhaseTimer plan_timer(TL_PHASE_PLAN, s);
-        if (algo == 0) make_plan<0>(v, g->n, plo, phi, d_acc, s, P);
-        else if (algo == 1) make_plan<1>(v, g->n, plo, phi, d_acc, s, P);
-        else make_plan<2>(v, g->n, plo, phi, d_acc, s, P);
+        u64 max_task = 0;
+        if (cb && !tri) {
+            max_task = g_chunk_triangles / (2 * heavy_max_blocks());
+            if (max_task < 65536) max_task = 65536;
+        }
+        if (algo == 0) make_plan<0>(v, g->n, plo, phi, max_task, d_acc, s, P);
+        else if (algo == 1) make_plan<1>(v, g->n, plo, phi, max_task, d_acc, s, P);
+        else make_plan<2>(v, g->n, plo, phi, max_task, d_acc, s, P);
     }
     out->work = P.work;
     out->scanned = P.w_total;

@@ -102,10 +102,36 @@ def traffic(fetch_csv: str, write_csv: str, calib_mib: float, workload: str, out
     return res
 
 
+def traffic_md(json_path: str, out_md: str) -> None:
+    """Renders a traffic JSON (from traffic()) as a short markdown table."""
+    with open(json_path) as f:
+        d = json.load(f)
+    c = d["calibration"]
+    lines = [f"# HBM traffic per kernel launch, {d['workload']} workload", "",
+             "Commands (two separate counter runs):", "", "```"]
+    lines += [part.strip() for part in d["command"].split(" ; ")]
+    lines += ["```", "",
+              f"Calibration: the run starts with a plain {c['copy_bytes'] / 2**30:.0f} GiB device copy; "
+              f"FETCH_SIZE reported {c['fetch_counter_bytes']:.0f} bytes for it (factor {c['fetch_factor']:.3f}), "
+              f"WRITE_SIZE {c['write_counter_bytes']:.0f} bytes (factor {c['write_factor']:.3f}). Every kernel's "
+              "counter value is scaled by these factors.", "",
+              f"Kernel source digest (list.hip, dev_util.h, probe_common.h): `{d['source_digest']}`; bench.py "
+              "reports these bytes as `roofline.traffic` only while the digest matches the sources.", "",
+              f"Emitting heavy-pivot kernel ({', '.join(d['heavy_kernels'])}): "
+              f"{d['heavy_bytes_per_launch'] / 1e9:.3f} GB per launch over {d['heavy_launches']} launches.", "",
+              "| kernel | launches | fetched GB / launch | written GB / launch |", "|---|---:|---:|---:|"]
+    for k, v in d["per_kernel_bytes_per_launch"].items():
+        lines.append(f"| `{k}` | {v['launches']} | {v['fetch'] / 1e9:.3f} | {v['write'] / 1e9:.3f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6], " ".join(sys.argv[7:]))
+    elif sys.argv[1] == "traffic-md":
+        traffic_md(sys.argv[2], sys.argv[3])
     else:
         raise SystemExit(__doc__)

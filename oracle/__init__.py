@@ -62,6 +62,9 @@ def _load():
     lib.orc_triangle_hash.argtypes = [u32, u32, u32]
     lib.orc_mix64.restype = u64
     lib.orc_mix64.argtypes = [u64]
+    for f in ("orc_degree_order", "orc_split_order"):
+        getattr(lib, f).restype = ctypes.c_int
+        getattr(lib, f).argtypes = [u32, u64, u32p, u32p, u32p]
     _lib = lib
     return lib
 
@@ -215,6 +218,28 @@ def oriented_csr(n, src, dst, rank):
     inv = np.zeros(max(n, 1), np.uint32)
     _check(lib.orc_oriented_csr(n, len(s), s, d, r, fo, fa, bo, ba, inv))
     return fo, fa[:c.m], bo, ba[:c.m], inv[:n]
+
+
+def degree_order(n, src, dst) -> np.ndarray:
+    """Degree ordering of the simple graph (Section 2.2): non-decreasing
+    degree, ties by id; returns rank (rank[u] = position of u)."""
+    lib = _load()
+    s = np.ascontiguousarray(src, np.uint32)
+    d = np.ascontiguousarray(dst, np.uint32)
+    rank = np.zeros(max(n, 1), np.uint32)
+    _check(lib.orc_degree_order(n, len(s), s, d, rank))
+    return rank[:n]
+
+
+def split_order(n, src, dst) -> np.ndarray:
+    """Split ordering (Section 3.3.3) built from the non-increasing degree
+    ordering (the degree ordering read backwards); returns rank."""
+    lib = _load()
+    s = np.ascontiguousarray(src, np.uint32)
+    d = np.ascontiguousarray(dst, np.uint32)
+    rank = np.zeros(max(n, 1), np.uint32)
+    _check(lib.orc_split_order(n, len(s), s, d, rank))
+    return rank[:n]
 
 
 def triangle_hash(a: int, b: int, c: int) -> int:

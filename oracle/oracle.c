@@ -393,3 +393,70 @@ int orc_oriented_csr(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 
     graph_free(&g);
     return 0;
 }
+
+/* ============================================================ orderings */
+
+/*
+ * Degree ordering (Section 2.2): vertices by non-decreasing degree in the
+ * simple graph, ties by increasing id; rank[u] = position of u.
+ */
+typedef struct {
+    u32 deg, id;
+} degkey;
+
+static int cmp_degkey(const void *a, const void *b) {
+    const degkey *x = (const degkey *)a, *y = (const degkey *)b;
+    if (x->deg != y->deg) return (x->deg > y->deg) - (x->deg < y->deg);
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+static int degree_positions(u32 n, u64 m_in, const u32 *src, const u32 *dst, u32 *order) {
+    u32 *ident = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    degkey *k = (degkey *)malloc((size_t)n * sizeof(degkey) + 8);
+    if (!ident || !k) { free(ident); free(k); return -2; }
+    for (u32 u = 0; u < n; u++) ident[u] = u;
+    graph g;
+    int rc = graph_build(&g, n, m_in, src, dst, ident);
+    if (rc) { free(ident); free(k); return rc; }
+    for (u32 u = 0; u < n; u++) {
+        k[u].deg = (u32)(g.off[u + 1] - g.off[u]);
+        k[u].id = u;
+    }
+    qsort(k, n, sizeof(degkey), cmp_degkey);
+    for (u32 i = 0; i < n; i++) order[i] = k[i].id;
+    graph_free(&g);
+    free(ident);
+    free(k);
+    return 0;
+}
+
+int orc_degree_order(u32 n, u64 m_in, const u32 *src, const u32 *dst, u32 *rank) {
+    u32 *order = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    if (!order) return -2;
+    int rc = degree_positions(n, m_in, src, dst, order);
+    if (!rc)
+        for (u32 i = 0; i < n; i++) rank[order[i]] = i;
+    free(order);
+    return rc;
+}
+
+/*
+ * Split (Section 3.3.3): take a non-increasing degree ordering delta
+ * (1-based positions) -- here the degree ordering above read backwards --
+ * and send the vertex at position 2i+1 to index i+1, the vertex at
+ * position 2i to index n+1-i.  rank[u] = index - 1.
+ */
+int orc_split_order(u32 n, u64 m_in, const u32 *src, const u32 *dst, u32 *rank) {
+    u32 *order = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    if (!order) return -2;
+    int rc = degree_positions(n, m_in, src, dst, order);
+    if (!rc) {
+        for (u32 pos = 1; pos <= n; pos++) {    /* delta position, 1-based */
+            u32 u = order[n - pos];             /* non-increasing degree */
+            u32 index = (pos % 2 == 1) ? (pos - 1) / 2 + 1 : n + 1 - pos / 2;
+            rank[u] = index - 1;
+        }
+    }
+    free(order);
+    return rc;
+}

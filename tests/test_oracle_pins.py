@@ -253,3 +253,67 @@ def test_oriented_csr_rows(seed):
         assert fa[fo[x]:fo[x + 1]].tolist() == sorted(want_f[x])
         assert ba[bo[x]:bo[x + 1]].tolist() == sorted(want_b[x])
         assert r[inv[x]] == x
+
+
+# ------------------------------------------------------------ orderings
+
+
+def test_split_worked_example():
+    """Section 3.3.3: the non-increasing degree ordering (e,b,g,a,f,d,c) of
+    the Figure 2 graph has C+- = 7; Split turns it into (e,g,f,c,d,a,b)
+    with C+- = 4 (both printed in the paper, fixture lines 4 and 5)."""
+    n, s, d, orders, names = G.fig2()
+    start, start_cpm = orders[3]
+    split_order, split_cpm = orders[4]
+    deg_rank = oracle.degree_order(n, s, d)
+    assert [int(u) for u in np.argsort(deg_rank)][::-1] == start
+    assert oracle.cost(n, s, d, G.order_to_rank(start)).cpm == start_cpm == 7
+    split = oracle.split_order(n, s, d)
+    assert [int(u) for u in np.argsort(split)] == split_order
+    assert oracle.cost(n, s, d, split).cpm == split_cpm == 4
+
+
+def _with_noise(n, s, d, seed):
+    """The same graph given with loops and repeated (also reversed) edges."""
+    rs = np.random.default_rng(seed)
+    k = len(s) // 3
+    idx = rs.integers(0, max(len(s), 1), k)
+    loops = rs.integers(0, n, 5).astype(np.uint32)
+    return (np.concatenate([s, d[idx], loops]).astype(np.uint32),
+            np.concatenate([d, s[idx], loops]).astype(np.uint32))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_degree_order_definition(seed):
+    n, s, d = rand_graph(900 + seed)
+    s2, d2 = _with_noise(n, s, d, seed)
+    r = oracle.degree_order(n, s2, d2)
+    assert sorted(r.tolist()) == list(range(n))
+    nbr = [set() for _ in range(n)]
+    for a, b in zip(s.tolist(), d.tolist()):
+        if a != b:
+            nbr[a].add(b)
+            nbr[b].add(a)
+    deg = [len(x) for x in nbr]
+    order = np.argsort(r)
+    keys = [(deg[u], int(u)) for u in order]
+    assert all(keys[i] < keys[i + 1] for i in range(n - 1))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_split_reads_degree_order_from_both_ends(seed):
+    """Split's order read from both ends inward, alternately (first, last,
+    second, second to last, ...), is the non-increasing degree ordering."""
+    n, s, d = rand_graph(950 + seed)
+    s2, d2 = _with_noise(n, s, d, seed)
+    split = np.argsort(oracle.split_order(n, s2, d2))
+    delta = np.argsort(oracle.degree_order(n, s2, d2))[::-1]
+    zig = []
+    lo, hi = 0, n - 1
+    while lo <= hi:
+        zig.append(int(split[lo]))
+        if lo != hi:
+            zig.append(int(split[hi]))
+        lo += 1
+        hi -= 1
+    assert zig == [int(u) for u in delta]

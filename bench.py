@@ -36,6 +36,7 @@ WORKLOADS = {
     "rmat26": dict(desc="RMAT scale 26 edge factor 16 a/b/c/d=.57/.19/.19/.05 seed 1",
                    orders=["degree"], algos=["A++"], emit="chunks", chunk=1 << 30),
     "serve": dict(desc="Poisson stream of serving jobs", orders=["degree", "core"], algos=["A++"]),
+    "orders": dict(desc="orderings on the GPU and cost against time", orders=[], algos=[]),
     "batch": dict(desc="independent Chung-Lu graphs i = 0..K-1, n log-uniform in [100, 50000], "
                        "gamma U(2.0, 2.8), mean degree U(8, 40), seed 1000+i, degree order",
                   orders=["degree"], algos=["A++"]),
@@ -387,6 +388,98 @@ def bench_serve(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_orders(args):
+    """Orderings on the GPU and the cost-time relation (Figure 3's
+    experiment): on the Chung-Lu 2^20 graph, (1) the full listing with the
+    ordering computed on the device -- orient by id, tl_order, orient by the
+    ordering, list -- for degree/A++ and Split/A+-, and (2) for each of
+    several orderings and both forms, the paper's cost C against the
+    listing time (count and digest only)."""
+    import ctypes
+
+    import torch
+
+    import graphgen
+    import paper_2203_04774_amd as tl
+
+    g = make_graph("chunglu20")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to("cuda")
+    src, dst = dev(g.src), dev(g.dst)
+    ident = dev(np.arange(g.n, dtype=np.uint32))
+    lib = tl.raw_lib()
+    lib.tl_timing_read.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)) * 1e3, out
+
+    full = {}
+    for kind, algo in (("degree", "A++"), ("split", "A+-")):
+        def run():
+            g0 = tl.orient(g.n, src, dst, ident)
+            t1 = time.perf_counter()
+            rank = tl.order(g0, kind)
+            t2 = time.perf_counter()
+            g0.free()
+            g1 = tl.orient(g.n, src, dst, rank)
+            t3 = time.perf_counter()
+            sm = tl.list_triangles(g1, algo)
+            t4 = time.perf_counter()
+            g1.free()
+            return sm, (t2 - t1) * 1e3, (t3 - t2) * 1e3, (t4 - t3) * 1e3
+        ms, (sm, o_ms, r_ms, l_ms) = timed(run, args.steps)
+        full[f"{kind}-{algo}"] = {"total_ms": ms, "order_ms": o_ms, "orient_ms": r_ms, "list_ms": l_ms,
+                                  "T": int(sm.count), "hash": f"0x{sm.hash:016x}"}
+        log(f"[bench] full listing {kind}-{algo}: {full[f'{kind}-{algo}']}")
+
+    # cost against listing time
+    ranks = {k: graphgen.ordering(g, k, seed=1) for k in ("random", "degree", "core", "identity")}
+    rows = []
+    for kind in ("random", "identity", "degree", "core", "split"):
+        if kind == "split":
+            g0 = tl.orient(g.n, src, dst, ident)
+            r = tl.order(g0, "split")
+            g0.free()
+        else:
+            r = dev(ranks[kind])
+        csr = tl.orient(g.n, src, dst, r)
+        for algo in ("A++", "A+-"):
+            C = tl.cost(csr, algo)
+            ms, sm = timed(lambda: tl.list_triangles(csr, algo), args.steps)
+            rows.append({"order": kind, "algo": algo, "C": C, "list_ms": ms, "T": int(sm.count),
+                         "scanned": int(sm.scanned), "ns_per_C": ms * 1e6 / C})
+            log(f"[bench] cost-time {kind}-{algo}: C={C} list {ms:.2f} ms")
+        csr.free()
+    Cs = np.array([r["C"] for r in rows], float)
+    ts = np.array([r["list_ms"] for r in rows], float)
+    pearson = float(np.corrcoef(Cs, ts)[0, 1])
+    slope, icpt = np.polyfit(Cs, ts, 1)
+    best = min(rows, key=lambda r: r["list_ms"])
+    res = {
+        "metric": "triangles listed/s + intersect elems/s (%HBM peak); batched vs plain; p99 job ms",
+        "value": g_tri / (full["split-A+-"]["total_ms"] / 1e3) if (g_tri := full["split-A+-"]["T"]) else 0.0,
+        "unit": "triangles/s (full listing, Split/A+-)",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": full["split-A+-"]["total_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "orders", "graph": WORKLOADS["chunglu20"]["desc"], "n": g.n, "m": g.m},
+        "full_listing": full,
+        "split_A+-_vs_degree_A++_full": full["degree-A++"]["total_ms"] / full["split-A+-"]["total_ms"],
+        "cost_time": rows,
+        "cost_time_pearson_r": pearson,
+        "cost_time_fit_ms": {"per_G_of_C": slope * 1e9, "intercept_ms": icpt},
+        "fastest_listing": f"{best['order']}-{best['algo']}",
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,6 +509,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "orders":
+        bench_orders(args)
         return
 
     import ctypes

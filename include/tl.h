@@ -147,6 +147,27 @@ int tl_csr_copy_to_host(const tl_csr *g, uint64_t *off_fwd, uint32_t *adj_fwd,
 void tl_csr_free(tl_csr *g);
 
 /*
+ * Orderings computed on the device, for the full listing (ordering time
+ * included) on the GPU.
+ *
+ * From an oriented graph g (any orientation: a vertex's degree in the
+ * simple graph is its successors plus its predecessors), writes a new
+ * ordering as rank_dev[u] (device uint32 array of g's n entries, the same
+ * layout as tl_orient's rank argument):
+ *   TL_ORDER_DEGREE  non-decreasing degree, ties by increasing vertex id
+ *                    (the degree ordering of Section 2.2)
+ *   TL_ORDER_SPLIT   Split (Section 3.3.3): the non-increasing degree
+ *                    ordering (the degree ordering read backwards) dealt
+ *                    alternately to the front and the back: the vertex at
+ *                    position 2i+1 gets index i+1, the one at 2i index n+1-i
+ *                    (1-based; rank = index - 1)
+ * Orient again with the result (tl_orient) to list under it.  Returns after
+ * the stream has finished; TL_EINVAL for an unknown kind or a NULL pointer.
+ */
+typedef enum { TL_ORDER_DEGREE = 0, TL_ORDER_SPLIT = 1 } tl_order_kind;
+int tl_order(const tl_csr *g, tl_order_kind kind, uint32_t *rank_dev, void *stream);
+
+/*
  * Batched listing: many independent graphs listed by one pass.
  *
  * The problem solved for each graph is the one of tl_orient + tl_list
@@ -286,6 +307,9 @@ void tl_server_destroy(tl_server *s);
  *                        window in an LDS bitmap and searches the rest in
  *                        global memory; 2: also in place of the array and
  *                        bucket forms
+ *   orient_sort          1: tl_orient builds both CSRs by device radix sorts
+ *                        of packed (row, column) keys; 0: by per-vertex
+ *                        counters, scatter and row sorts
  *   force_mode           testing: 0 bitmap, 1 array, 2 global, 3 reverse,
  *                        4 hash, 5 bucket, 6 split for every heavy pivot
  *                        where it fits; 255 = automatic
@@ -344,7 +368,8 @@ enum {
     TL_PHASE_PROBE_LIGHT = 4, /* the light-pivot probe kernel alone */
     TL_PHASE_PROBE_HEAVY = 5, /* the heavy-pivot probe kernel alone */
     TL_PHASE_BATCH = 6,       /* one tl_batch_list pass (all of its kernels) */
-    TL_NUM_PHASES = 7
+    TL_PHASE_ORDER = 7,       /* tl_order */
+    TL_NUM_PHASES = 8
 };
 int tl_timing_enable(int on);
 int tl_timing_reset(void);

@@ -347,6 +347,14 @@ const char *tl_strerror(int code) {
 
 const char *tl_last_error(void) { return g_last_error.c_str(); }
 
+int tl_order(const tl_csr *g, tl_order_kind kind, uint32_t *rank_dev, void *stream) {
+    return guarded([&] {
+        TL_REQUIRE(g, TL_EINVAL, "NULL handle");
+        order_impl(g, (int)kind, rank_dev, (hipStream_t)stream);
+        return TL_OK;
+    });
+}
+
 int tl_batch_orient(uint32_t k, const uint32_t *n, const uint64_t *m, const uint32_t *src, const uint32_t *dst,
                     const uint32_t *rank, void *stream, tl_batch **out) {
     return guarded([&] {

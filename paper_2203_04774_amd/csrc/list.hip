@@ -58,6 +58,7 @@ struct Tuning {
     u64 hash = 0;                // 1: HASH before ARRAY when B's window does not fit LDS
     u64 bucket = 0;              // 1: BUCKET before ARRAY when B's window does not fit LDS
     u64 split = 2;               // 1: SPLIT for lists too long for LDS; 2: also before ARRAY/BUCKET
+    u64 orient_sort = 1;         // 1: orientation by radix sort; 0: by per-vertex counters and scatter
     u64 force_mode = 255;        // testing: use this MODE_* for every heavy pivot where it fits
 };
 Tuning &tuning();
@@ -1062,6 +1063,7 @@ Tuning &tuning() {
         env("TL_TUNE_HASH", d.hash);
         env("TL_TUNE_BUCKET", d.bucket);
         env("TL_TUNE_SPLIT", d.split);
+        env("TL_TUNE_ORIENT_SORT", d.orient_sort);
         env("TL_TUNE_FORCE_MODE", d.force_mode);
         return d;
     }();
@@ -1091,6 +1093,7 @@ void prepare_kernels() {
 }  // namespace
 
 u64 chunk_triangles() { return g_chunk_triangles; }
+bool orient_by_sort() { return tuning().orient_sort != 0; }
 
 tl_list_stats &last_stats() {
     thread_local tl_list_stats st{};
@@ -1112,6 +1115,7 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "hash" && value <= 1) t.hash = value;
     else if (k == "bucket" && value <= 1) t.bucket = value;
     else if (k == "split" && value <= 2) t.split = value;
+    else if (k == "orient_sort" && value <= 1) t.orient_sort = value;
     else if (k == "force_mode" && (value < NMODES || value == 255)) t.force_mode = value;
     else return TL_EINVAL;
     return TL_OK;
@@ -1132,6 +1136,7 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "hash") *value = t.hash;
     else if (k == "bucket") *value = t.bucket;
     else if (k == "split") *value = t.split;
+    else if (k == "orient_sort") *value = t.orient_sort;
     else if (k == "force_mode") *value = t.force_mode;
     else return TL_EINVAL;
     return TL_OK;

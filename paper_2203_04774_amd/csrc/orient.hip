@@ -5,11 +5,19 @@
 // Pipeline, all on the caller's stream:
 //   1. validate: rank is a permutation of [0,n) and every endpoint id < n
 //   2. relabel + orient: edge {a,b} -> (lo,hi) = (min, max)(rank[a], rank[b]);
-//      self-loops dropped; per-row counts of lo
-//   3. scan -> raw row offsets; scatter hi into row lo
-//   4. sort each row, drop repeated pairs; compact only if some were repeated
-//   5. backward CSR: count by target, scan, scatter, sort rows
+//      self-loops dropped
+//   3-4. forward CSR with sorted rows and repeated pairs dropped, built one
+//      of two ways:
+//      sort:    keys lo * 2^b + hi (2^b > n) sorted by a device radix sort;
+//               equal neighbours dropped; row sizes from runs of equal lo
+//      scatter: per-row counts of lo (atomics), scan, scatter hi into row
+//               lo, sort each row, compact if some pairs repeated
+//   5. backward CSR: keys hi * 2^b + lo sorted (sort), or count by target,
+//      scan, scatter, sort rows (scatter)
 //   6. inverse permutation inv[rank[u]] = u
+// The sort way does no atomics on per-vertex counters, so hubs whose rows
+// or columns are long cost no serialisation; its work is independent of
+// the ordering.
 #include "tl_internal.h"
 #include "dev_util.h"
 #include "timing.h"
@@ -83,6 +91,70 @@ __global__ void k_transpose_scatter(const u32 *adj_f, const u32 *row_f, u64 m, c
     }
 }
 
+// ---- the sort way
+
+__global__ void k_fwd_keys(const u32 *src, const u32 *dst, u64 m_in, const u32 *rank, int b, u64 sent, u64 *keys) {
+    GRID_STRIDE(i, m_in) {
+        const u32 ra = rank[src[i]], rb = rank[dst[i]];
+        keys[i] = ra == rb ? sent : (ra < rb ? ((u64)ra << b) | rb : ((u64)rb << b) | ra);
+    }
+}
+
+// 1 for the first of each run of equal keys, sentinel (loops) excluded
+__global__ void k_unique_flags(const u64 *keys, u64 n, u64 sent, u32 *flag) {
+    GRID_STRIDE(i, n) {
+        const u64 k = keys[i];
+        flag[i] = (k != sent && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+    }
+}
+
+__global__ void k_fwd_emit(const u64 *keys, const u32 *flag, const u64 *pos, u64 n, int b, u32 *adj, u32 *row) {
+    const u64 mask = (1ull << b) - 1;
+    GRID_STRIDE(i, n) {
+        if (flag[i]) {
+            const u64 k = keys[i], j = pos[i];
+            adj[j] = (u32)(k & mask);
+            row[j] = (u32)(k >> b);
+        }
+    }
+}
+
+// cnt[r] += length of each run of r in the sorted array row[0..m): one
+// atomic per run per wavefront
+__global__ void k_run_count(const u32 *row, u64 m, u32 *cnt) {
+    const int lane = lane_id();
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 iters = m > first - lane ? (m - (first - lane) + stride - 1) / stride : 0;  // wave-uniform
+    for (u64 it = 0; it < iters; it++) {
+        const u64 j = first + it * stride;
+        const bool valid = j < m;
+        const u32 key = valid ? row[j] : 0xffffffffu;
+        u32 v = valid ? 1u : 0u;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const u32 t = __shfl_up(v, d, WAVE);
+            const u32 q = __shfl_up(key, d, WAVE);
+            if (lane >= d && q == key) v += t;
+        }
+        const u32 nk = __shfl_down(key, 1, WAVE);
+        if (valid && (lane == WAVE - 1 || nk != key)) atomicAdd(&cnt[key], v);
+    }
+}
+
+__global__ void k_bwd_keys(const u32 *adj_f, const u32 *row_f, u64 m, int b, u64 *keys) {
+    GRID_STRIDE(j, m) { keys[j] = ((u64)adj_f[j] << b) | row_f[j]; }
+}
+
+__global__ void k_bwd_emit(const u64 *keys, u64 m, int b, u32 *adj_b, u32 *row_b) {
+    const u64 mask = (1ull << b) - 1;
+    GRID_STRIDE(j, m) {
+        const u64 k = keys[j];
+        adj_b[j] = (u32)(k & mask);
+        row_b[j] = (u32)(k >> b);
+    }
+}
+
 __global__ void k_inverse(const u32 *rank, u32 n, u32 *inv) {
     GRID_STRIDE(i, n) { inv[rank[i]] = (u32)i; }
 }
@@ -95,6 +167,64 @@ struct CsrOwner {
     ~CsrOwner() { if (g) tl_csr_free(g); }
     tl_csr *release() { tl_csr *p = g; g = nullptr; return p; }
 };
+
+}  // namespace
+
+namespace {
+
+// Steps 2-5 by sorting (see the file comment); cnt: n + 1 scratch counters.
+void orient_sorted(tl_csr *g, u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *rank, u32 *cnt,
+                   hipStream_t s) {
+    int b = 1;
+    while ((1ull << b) <= (u64)n) b++;  // ids < n <= 2^b - 1: the all-ones key is free
+    const u64 sent = 2 * b >= 64 ? ~0ull : (1ull << (2 * b)) - 1;
+    const u64 mi = m_in ? m_in : 1;
+    DevBuf keys(mi * sizeof(u64), s), tmp(mi * sizeof(u64), s);
+    u64 m = 0;
+    DevBuf pos((mi + 1) * sizeof(u64), s);
+    if (m_in) {
+        hipLaunchKernelGGL(k_fwd_keys, dim3(grid_n(m_in)), dim3(256), 0, s, src, dst, m_in, rank, b, sent,
+                           keys.as<u64>());
+        TL_HIP(hipGetLastError());
+        const u64 *sorted = radix_sort_u64(keys.as<u64>(), tmp.as<u64>(), m_in, 2 * b, s);
+        u64 *other = sorted == keys.as<u64>() ? tmp.as<u64>() : keys.as<u64>();
+        u32 *flag = reinterpret_cast<u32 *>(other);  // the other buffer is free now
+        hipLaunchKernelGGL(k_unique_flags, dim3(grid_n(m_in)), dim3(256), 0, s, sorted, m_in, sent, flag);
+        TL_HIP(hipGetLastError());
+        scan_u32_to_u64(flag, pos.as<u64>(), m_in, s);
+        d2h_sync(s, {{&m, pos.as<u64>() + m_in, sizeof(u64)}});
+        g->m = m;
+        g->adj_f = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
+        g->row_f = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
+        hipLaunchKernelGGL(k_fwd_emit, dim3(grid_n(m_in)), dim3(256), 0, s, sorted, flag, pos.as<u64>(), m_in, b,
+                           g->adj_f, g->row_f);
+        TL_HIP(hipGetLastError());
+    } else {
+        g->m = 0;
+        g->adj_f = (u32 *)tl_dev_alloc(sizeof(u32), s);
+        g->row_f = (u32 *)tl_dev_alloc(sizeof(u32), s);
+    }
+    if (n) TL_HIP(hipMemsetAsync(cnt, 0, (u64)n * sizeof(u32), s));
+    if (m) {
+        hipLaunchKernelGGL(k_run_count, dim3(grid_n(m)), dim3(256), 0, s, g->row_f, m, cnt);
+        TL_HIP(hipGetLastError());
+    }
+    scan_u32_to_u64(cnt, g->off_f, n, s);
+    // backward CSR: the same entries sorted by (hi, lo)
+    g->adj_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
+    g->row_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
+    if (n) TL_HIP(hipMemsetAsync(cnt, 0, (u64)n * sizeof(u32), s));
+    if (m) {
+        hipLaunchKernelGGL(k_bwd_keys, dim3(grid_n(m)), dim3(256), 0, s, g->adj_f, g->row_f, m, b, keys.as<u64>());
+        TL_HIP(hipGetLastError());
+        const u64 *sorted = radix_sort_u64(keys.as<u64>(), tmp.as<u64>(), m, 2 * b, s);
+        hipLaunchKernelGGL(k_bwd_emit, dim3(grid_n(m)), dim3(256), 0, s, sorted, m, b, g->adj_b, g->row_b);
+        TL_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_run_count, dim3(grid_n(m)), dim3(256), 0, s, g->row_b, m, cnt);
+        TL_HIP(hipGetLastError());
+    }
+    scan_u32_to_u64(cnt, g->off_b, n, s);
+}
 
 }  // namespace
 
@@ -133,6 +263,17 @@ tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *
     g->off_f = (u64 *)tl_dev_alloc((u64)(n + 1) * sizeof(u64), s);
     g->off_b = (u64 *)tl_dev_alloc((u64)(n + 1) * sizeof(u64), s);
     g->inv = (u32 *)tl_dev_alloc((u64)(n ? n : 1) * sizeof(u32), s);
+
+    if (orient_by_sort()) {
+        orient_sorted(g, n, src, dst, m_in, rank, cnt.as<u32>(), s);
+        if (n) {
+            hipLaunchKernelGGL(k_inverse, dim3(grid_n(n)), dim3(256), 0, s, rank, n, g->inv);
+            TL_HIP(hipGetLastError());
+        }
+        timer.stop();
+        TL_HIP(hipStreamSynchronize(s));
+        return own.release();
+    }
 
     // ---- 2-3. count rows, scan, scatter
     u32 *rowcnt = cnt.as<u32>();

@@ -1,0 +1,111 @@
+// Device-wide stable LSD radix sort of 64-bit keys, 8-bit digits.
+//
+// Each pass: every tile of RT keys counts its digits in LDS (k_rs_hist,
+// counts stored digit-major so that one exclusive scan gives every tile's
+// global offset per digit); then each tile ranks its keys by digit with
+// wavefront ballots (stable: tile order is kept within a digit), stages
+// them sorted in LDS and writes each digit's run to its global segment, so
+// that consecutive lanes write consecutive addresses.
+#include "tl_internal.h"
+#include "dev_util.h"
+
+namespace {
+
+constexpr int RB = 256;            // threads per tile
+constexpr int RI = 16;             // keys per thread
+constexpr u32 RT = RB * RI;        // keys per tile
+constexpr int RD = 256;            // digit values
+constexpr int RNW = RB / WAVE;
+
+__global__ __launch_bounds__(RB) void k_rs_hist(const u64 *keys, u64 n, int sh, u32 *counts, u64 ntiles) {
+    __shared__ u32 h[RD];
+    const int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    const u64 base = (u64)blockIdx.x * RT;
+#pragma unroll
+    for (int j = 0; j < RI; j++) {
+        const u64 i = base + (u64)j * RB + t;
+        if (i < n) atomicAdd(&h[(keys[i] >> sh) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(u64)t * ntiles + blockIdx.x] = h[t];
+}
+
+__global__ __launch_bounds__(RB) void k_rs_scatter(const u64 *in, u64 *out, u64 n, int sh, const u32 *counts,
+                                                   const u64 *offs, u64 ntiles) {
+    __shared__ u64 stage[RT];
+    __shared__ u32 tbase[RD], run[RD];
+    __shared__ u32 wcnt[RNW][RD];
+    __shared__ u64 gbase[RD];
+    __shared__ u64 lds64[RNW];
+    const int t = threadIdx.x, lane = lane_id(), wid = t / WAVE;
+    const u64 tile = blockIdx.x;
+    const u64 base = tile * RT;
+    const u32 cnt = (u32)(n - base < RT ? n - base : RT);
+    {
+        const u32 c = counts[(u64)t * ntiles + tile];
+        u64 tot;
+        tbase[t] = (u32)block_excl_scan_u64<RB>(c, lds64, tot);
+        gbase[t] = offs[(u64)t * ntiles + tile];
+        run[t] = 0;
+    }
+    __syncthreads();
+    for (int r = 0; r < RI; r++) {
+        const u64 i = base + (u64)r * RB + t;
+        const bool valid = i < n;
+        const u64 k = valid ? in[i] : 0ull;
+        const u32 d = (u32)(k >> sh) & 255u;
+        u64 mask = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const u64 bb = __ballot((d >> b) & 1u);
+            mask &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const u32 rk = __popcll(mask & lanemask_lt());
+#pragma unroll
+        for (int w = 0; w < RNW; w++) wcnt[w][t] = 0;
+        __syncthreads();
+        if (valid && rk == 0) wcnt[wid][d] = __popcll(mask);
+        __syncthreads();
+        if (valid) {
+            u32 p = tbase[d] + run[d] + rk;
+            for (int w = 0; w < wid; w++) p += wcnt[w][d];
+            stage[p] = k;
+        }
+        __syncthreads();
+        u32 add = 0;
+#pragma unroll
+        for (int w = 0; w < RNW; w++) add += wcnt[w][t];
+        run[t] += add;
+        __syncthreads();
+    }
+    for (u32 j = t; j < cnt; j += RB) {
+        const u64 k = stage[j];
+        const u32 d = (u32)(k >> sh) & 255u;
+        out[gbase[d] + (j - tbase[d])] = k;
+    }
+}
+
+}  // namespace
+
+u64 *radix_sort_u64(u64 *keys, u64 *tmp, u64 n, int bits, hipStream_t s) {
+    if (n <= 1 || bits <= 0) return keys;
+    const u64 ntiles = (n + RT - 1) / RT;
+    TL_REQUIRE(ntiles < (1ull << 31), TL_EINVAL, "radix sort: too many keys");
+    DevBuf counts((u64)RD * ntiles * sizeof(u32), s), offs(((u64)RD * ntiles + 1) * sizeof(u64), s);
+    DevBuf ws((scan_workspace_words((u64)RD * ntiles) + 1) * sizeof(u64), s);
+    u64 *src = keys, *dst = tmp;
+    for (int sh = 0; sh < bits; sh += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(RB), 0, s, src, n, sh, counts.as<u32>(), ntiles);
+        TL_HIP(hipGetLastError());
+        scan_u32_to_u64(counts.as<u32>(), offs.as<u64>(), (u64)RD * ntiles, s, ws.as<u64>());
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(RB), 0, s, src, dst, n, sh, counts.as<u32>(),
+                           offs.as<u64>(), ntiles);
+        TL_HIP(hipGetLastError());
+        u64 *sw = src;
+        src = dst;
+        dst = sw;
+    }
+    return src;
+}

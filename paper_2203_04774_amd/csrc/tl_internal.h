@@ -110,6 +110,10 @@ void scan_u32_to_u64(const u32 *in, u64 *out, u64 n, hipStream_t s, u64 *ws = nu
 void scan_u64_to_u64(const u64 *in, u64 *out, u64 n, hipStream_t s, u64 *ws = nullptr);
 u64 scan_workspace_words(u64 n);
 
+// Stable ascending sort of n 64-bit keys by their low `bits` bits (radix.hip);
+// tmp holds n keys of scratch; returns whichever of keys/tmp holds the result.
+u64 *radix_sort_u64(u64 *keys, u64 *tmp, u64 n, int bits, hipStream_t s);
+
 // Sort every row of a CSR ascending and drop repeated values inside a row;
 // uniq[r] receives the row's distinct count and the distinct values are
 // packed at the start of the row.  Values must be < n_values.
@@ -117,6 +121,7 @@ void segmented_sort_unique(const u64 *off, u32 nrows, u32 *adj, u64 nnz, u32 n_v
                            hipStream_t s);
 
 // Orientation and listing drivers (orient.hip, list.hip).
+bool orient_by_sort();  // tuning key orient_sort
 tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *rank, hipStream_t s);
 u64 cost_impl(const tl_csr *g, int algo, hipStream_t s);
 int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl_chunk_fn cb, void *user,
@@ -154,3 +159,6 @@ u64 job_bytes(u64 n, u64 m);
 // trim of its free blocks when that total exceeds `limit`.
 u64 pool_total_bytes();
 void pool_trim_above(u64 limit);
+
+// Orderings from an oriented graph (order.hip): kind 0 degree, 1 Split.
+void order_impl(const tl_csr *g, int kind, u32 *rank, hipStream_t s);

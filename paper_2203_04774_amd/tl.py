@@ -82,6 +82,8 @@ def _load():
     lib.tl_set_chunk_triangles.argtypes = [u64]
     lib.tl_set_tuning.argtypes = [ctypes.c_char_p, u64]
     lib.tl_get_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(u64)]
+    lib.tl_order.argtypes = [vp, i32, vp, vp]
+    lib.tl_order.restype = i32
     lib.tl_batch_orient.argtypes = [u32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
     lib.tl_batch_list.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.tl_batch_size.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)]
@@ -186,6 +188,21 @@ def orient(n: int, src: torch.Tensor, dst: torch.Tensor, rank: torch.Tensor, str
     _check(_lib.tl_orient(n, _dptr(src, "src"), _dptr(dst, "dst"), src.numel(), _dptr(rank, "rank"),
                           _stream_ptr(stream), ctypes.byref(h)), "tl_orient")
     return Csr(h)
+
+
+ORDERS = {"degree": 0, "split": 1}
+
+
+def order(g: Csr, kind: str = "degree", out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """tl_order: a new ordering (device int32 rank tensor of g.n entries)
+    computed on the device from the oriented graph g."""
+    if out is None:
+        out = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")[: g.n]
+    elif out.numel() != g.n:
+        raise ValueError("out must have g.n entries")
+    ptr = _dptr(out, "out") if g.n else None
+    _check(_lib.tl_order(g.handle, ORDERS[kind], ptr, _stream_ptr(stream)), "tl_order")
+    return out
 
 
 def cost(g: Csr, algo: str = "A++", stream=None) -> int:

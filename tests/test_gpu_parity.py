@@ -416,3 +416,47 @@ def test_probe_paths(tl, tuned, algo):
     finally:
         tl.set_chunk_triangles(1 << 24)
         g.free()
+
+
+@pytest.mark.parametrize("case", ["rmat12", "pow2-dups", "tiny", "empty-edges", "chunglu-random"])
+def test_orient_sort_and_scatter_agree(tl, case):
+    """The two ways of building the CSRs (radix sort of packed keys, or
+    per-vertex counters and scatter) give identical arrays, and both equal
+    the oracle's oriented graph."""
+    rs = np.random.default_rng(17)
+    if case == "rmat12":
+        g = graphgen.config_rmat12(seed=4)
+        n, s, d = g.n, g.src, g.dst
+        r = graphgen.degree_order(g)
+    elif case == "pow2-dups":  # n a power of two; loops and repeated pairs in the input
+        n = 1024
+        s = rs.integers(0, n, 9000).astype(np.uint32)
+        d = rs.integers(0, n, 9000).astype(np.uint32)
+        r = rs.permutation(n).astype(np.uint32)
+    elif case == "tiny":
+        n, s, d = 1, np.zeros(1, np.uint32), np.zeros(1, np.uint32)
+        r = np.zeros(1, np.uint32)
+    elif case == "empty-edges":
+        n, s, d = 5, np.zeros(0, np.uint32), np.zeros(0, np.uint32)
+        r = rs.permutation(n).astype(np.uint32)
+    else:
+        g = graphgen.chung_lu(200000, 2.1, 10.0, seed=3)
+        n, s, d = g.n, g.src, g.dst
+        r = graphgen.random_order(n, seed=5)
+    saved = tl.get_tuning("orient_sort")
+    arrays = []
+    try:
+        for way in (1, 0):
+            tl.set_tuning("orient_sort", way)
+            c = tl.orient(n, dev(s), dev(d), dev(r))
+            arrays.append(c.to_host())
+            c.free()
+    finally:
+        tl.set_tuning("orient_sort", saved)
+    for a, b in zip(arrays[0], arrays[1]):
+        assert np.array_equal(a, b)
+    fo, fa, bo, ba, inv = oracle.oriented_csr(n, s, d, r)
+    got = arrays[0]
+    assert np.array_equal(got[0], fo) and np.array_equal(got[1], fa)
+    assert np.array_equal(got[2], bo) and np.array_equal(got[3], ba)
+    assert np.array_equal(got[4], inv)

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
     const int lane = lane_id();
     const u64 ncap = pos[g.m] & 0xffffffffull;
     const u64 W = L.cpre[ncap];
-    const u64 gw = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const u64 gw = (u64)blockIdx.x * (blockDim.x / WAVE) + wave_id();
     const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
     const u64 per = (((W + nw - 1) / nw) + WAVE - 1) & ~(u64)(WAVE - 1);
     const u64 wb = gw * per;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
                         gv[j] = __shfl(GI, lo, WAVE);
                         tl[j] = __shfl(TL, lo, WAVE);
                         th[j] = __shfl(TH, lo, WAVE);
-                        if (j == UN - 1) lo_last = __shfl(lo, WAVE - 1, WAVE);
+                        if (j == UN - 1) lo_last = (int)uni32((u32)__shfl(lo, WAVE - 1, WAVE));
                     }
                     member_multi_var(T, tl, th, y, h);
                     report(y, h, pv, xv, gv);
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
                                                 u32 N, const u32 *gid, const u32 *vbase, u64 *queue, u64 *pg) {
     extern __shared__ u32 bits[];
     __shared__ u64 next;
-    const int lane = lane_id(), wid = threadIdx.x / WAVE, nwv = HBS / WAVE;
+    const int lane = lane_id(), wid = (int)wave_id(), nwv = HBS / WAVE;
     const u64 nheavy = hpre[N];
     const u64 nlight = pos[g.m] & 0xffffffffull;
     const u64 *so = Form<ALGO>::seed_off(g);
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd((unsigned long long *)queue, 1ull);
         __syncthreads();
-        const u64 hi = next;
+        const u64 hi = uni64(next);
         __syncthreads();
         if (hi >= nheavy) break;  // uniform across the workgroup
         const u32 p = hpiv[hi];
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
                             const u64 rel = (kb + kr) - shfl_u64(P, lo);
                             y[j] = SA[shfl_u64(A, lo) + rel];
                             xv[j] = __shfl(X, lo, WAVE);
-                            if (j == UN - 1) lo_last = __shfl(lo, WAVE - 1, WAVE);
+                            if (j == UN - 1) lo_last = (int)uni32((u32)__shfl(lo, WAVE - 1, WAVE));
                         }
 #pragma unroll
                         for (int j = 0; j < UN; j++) h[j] = member(y[j]);

@@ -8,6 +8,16 @@
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// For values that are equal in every active lane: moved to scalar registers,
+// so that the loops and branches they steer compile as wave-uniform (scalar
+// branches, scalar loads) instead of per-lane masks.
+__device__ __forceinline__ uint32_t uni32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    return ((uint64_t)uni32((uint32_t)(v >> 32)) << 32) | uni32((uint32_t)v);
+}
+// this lane's wavefront within its workgroup
+__device__ __forceinline__ uint32_t wave_id() { return uni32(threadIdx.x / WAVE); }
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     int l = lane_id();
     return l ? (~0ull >> (64 - l)) : 0ull;

@@ -28,6 +28,8 @@
 #include <cstdlib>
 #include <mutex>
 
+#include <type_traits>
+
 #include "tl_internal.h"
 #include "dev_util.h"
 #include "timing.h"
@@ -415,7 +417,7 @@ struct LightSeeds {
 template <int ALGO, bool EMIT>
 __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 ncap, u64 k0, u64 k1, Out o) {
     const int lane = lane_id();
-    const u64 gw = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const u64 gw = (u64)blockIdx.x * (blockDim.x / WAVE) + wave_id();
     const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
     const u64 span = k1 - k0;
     const u64 per = (((span + nw - 1) / nw) + WAVE - 1) & ~(u64)(WAVE - 1);
@@ -497,7 +499,7 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
                         pv[j] = __shfl(PI, lo, WAVE);
                         tl[j] = __shfl(TL, lo, WAVE);
                         th[j] = __shfl(TH, lo, WAVE);
-                        if (j == UN - 1) lo_last = __shfl(lo, WAVE - 1, WAVE);
+                        if (j == UN - 1) lo_last = (int)uni32((u32)__shfl(lo, WAVE - 1, WAVE));
                     }
                     member_multi_var(T, tl, th, y, h);
                     report(y, h, pv, xv);
@@ -545,7 +547,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                                                     const u64 *cabs, const u32 *cxinv, const u64 *cpre, u64 k0,
                                                     u64 k1, Out o, int use_queue, int use_splits) {
     extern __shared__ u32 lds[];  // the pivot list: B as a bitmap, or a sorted array
-    const int lane = lane_id(), wid = threadIdx.x / WAVE, nwv = blockDim.x / WAVE;
+    const int lane = lane_id(), wid = (int)wave_id(), nwv = blockDim.x / WAVE;
     const u32 *SA = Form<ALGO>::scan_adj(g);
     const u64 *po = Form<ALGO>::piv_off(g);
     const u32 *pa = Form<ALGO>::piv_adj(g);
@@ -560,7 +562,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             // tasks handed out dynamically: one atomic per task per workgroup
             if (threadIdx.x == 0) next_task = atomicAdd((unsigned long long *)&o.acc[5], 1ull);
             __syncthreads();
-            ti = next_task;
+            ti = uni64(next_task);
             __syncthreads();
         } else {
             ti = blockIdx.x + it * gridDim.x;
@@ -573,7 +575,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         struct {
             u64 a, b, cb, ce;
             u32 p, mode;
-        } tk{tg.a, tg.b, tg.cb, tg.ce, tg.p, tg.mode};
+        } tk{uni64(tg.a), uni64(tg.b), uni64(tg.cb), uni64(tg.ce), uni32(tg.p), uni32(tg.mode)};
         const u64 a = tk.a > k0 ? tk.a : k0;
         const u64 b = tk.b < k1 ? tk.b : k1;
         if (a >= b) continue;  // uniform across the block
@@ -587,7 +589,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
             if (threadIdx.x == 0) split_at = lower_bound_dev<u32>(pa, t0, t1, wlo);
             __syncthreads();
         }
-        const u64 ts = tk.mode == MODE_SPLIT ? split_at : t0;
+        const u64 ts = tk.mode == MODE_SPLIT ? uni64(split_at) : t0;
         u32 *low = lds + LDS_WORDS;  // SPLIT: T[t0, ts) when it fits
         const bool low_lds = tk.mode == MODE_SPLIT && ts - t0 <= LOW_WORDS;
         if (low_lds) {
@@ -625,202 +627,240 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         }
         u64 wb, we;
         wave_share(a, b, (u32)nwv, (u32)wid, wb, we);
-        if (wb < we) {
-            const bool exact = use_splits && a == tk.a && b == tk.b;  // not clipped by a chunk slice
-            SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tg.ws[wid]) : SeedCursor(cpre, tk.cb, tk.ce, wb);
-            const u32 pinv = g.inv[p];
-            u32 xinv = 0;
-            u64 xinv_c = ~0ull;
-            const u32 bsh = tk.mode == MODE_BUCKET ? bucket_shift((u64)tmax - tmin + 1) : 0u;
-            const unsigned short *bst = reinterpret_cast<const unsigned short *>(lds + tlen);
-            auto member = [&](u32 y) -> bool {
-                if (tk.mode == MODE_BITMAP) {
-                    const u32 v = y - tmin;
-                    return y >= tmin && y <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
-                } else if (tk.mode == MODE_SPLIT) {
-                    if (y > tmax) return false;
-                    if (y >= wlo) {
-                        const u32 v = y - wlo;
-                        return (lds[v >> 5] >> (v & 31)) & 1u;
-                    }
-                    if (low_lds) {
-                        const u32 nl = (u32)(ts - t0);
-                        const u64 j = lower_bound_dev<u32>(low, 0, nl, y);
-                        return j < nl && low[j] == y;
-                    }
-                    const u64 j = lower_bound_dev<u32>(pa, t0, ts, y);
-                    return j < ts && pa[j] == y;
-                } else if (tk.mode == MODE_BUCKET) {
-                    if (y < tmin || y > tmax) return false;
-                    const u32 b = (y - tmin) >> bsh;
-                    const u32 lo = bst[b], hi = bst[b + 1];
-                    const u64 j = lower_bound_dev<u32>(lds, lo, hi, y);
-                    return j < hi && lds[j] == y;
-                } else if (tk.mode == MODE_ARRAY) {
-                    const u64 j = lower_bound_dev<u32>(lds, 0, tlen, y);
-                    return j < tlen && lds[j] == y;
-                } else if (tk.mode == MODE_HASH) {
-                    const u32 hk = hash_bits_for(tlen), hmask = (1u << hk) - 1;
-                    u32 h = hash_slot(y, hk);
-                    for (;;) {  // ends: the table is at most half full
-                        const u32 v = lds[h];
-                        if (v == y + 1) return true;
-                        if (v == 0u) return false;
-                        h = (h + 1) & hmask;
-                    }
-                } else if (tk.mode == MODE_REVERSE) {
-                    const u64 *ro = Reverse<ALGO>::off(g);
-                    const u32 *ra = Reverse<ALGO>::adj(g);
-                    const u64 r0 = ro[y], r1 = ro[y + 1];
-                    const u64 j = lower_bound_dev<u32>(ra, r0, r1, p);
-                    return j < r1 && ra[j] == p;
-                }
-                const u64 j = lower_bound_dev<u32>(pa, t0, t1, y);
-                return j < t1 && pa[j] == y;
-            };
-            // membership of UN elements at once (interleaved where it is a search)
-            auto member_all = [&](const u32 (&y)[UN], bool (&h)[UN]) {
-                if (tk.mode == MODE_SPLIT) {
-                    // the entries below the bitmap's window: interleaved global searches
-                    u64 lo[UN], hi[UN];
-                    const u64 base = low_lds ? 0 : t0, top = low_lds ? ts - t0 : ts;
-#pragma unroll
-                    for (int j = 0; j < UN; j++) {
-                        lo[j] = base;
-                        hi[j] = y[j] >= wlo ? base : top;
-                    }
-                    member_multi_var(low_lds ? low : pa, lo, hi, y, h);
-#pragma unroll
-                    for (int j = 0; j < UN; j++) {
-                        if (y[j] >= wlo) {
-                            const u32 v = y[j] - wlo;
-                            h[j] = y[j] <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
+        // the walk, compiled once per LDS form so that each has its own tight loop
+        auto walk = [&](auto mode_tag) {
+            constexpr int MD = decltype(mode_tag)::value;
+            if (wb < we) {
+                const bool exact = use_splits && a == tk.a && b == tk.b;  // not clipped by a chunk slice
+                SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tg.ws[wid]) : SeedCursor(cpre, tk.cb, tk.ce, wb);
+                const u32 pinv = g.inv[p];
+                u32 xinv = 0;
+                u64 xinv_c = ~0ull;
+                const u32 bsh = MD == MODE_BUCKET ? bucket_shift((u64)tmax - tmin + 1) : 0u;
+                const unsigned short *bst = reinterpret_cast<const unsigned short *>(lds + tlen);
+                auto member = [&](u32 y) -> bool {
+                    if (MD == MODE_BITMAP) {
+                        const u32 v = y - tmin;
+                        return y >= tmin && y <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
+                    } else if (MD == MODE_SPLIT) {
+                        if (y > tmax) return false;
+                        if (y >= wlo) {
+                            const u32 v = y - wlo;
+                            return (lds[v >> 5] >> (v & 31)) & 1u;
                         }
+                        if (low_lds) {
+                            const u32 nl = (u32)(ts - t0);
+                            const u64 j = lower_bound_dev<u32>(low, 0, nl, y);
+                            return j < nl && low[j] == y;
+                        }
+                        const u64 j = lower_bound_dev<u32>(pa, t0, ts, y);
+                        return j < ts && pa[j] == y;
+                    } else if (MD == MODE_BUCKET) {
+                        if (y < tmin || y > tmax) return false;
+                        const u32 b = (y - tmin) >> bsh;
+                        const u32 lo = bst[b], hi = bst[b + 1];
+                        const u64 j = lower_bound_dev<u32>(lds, lo, hi, y);
+                        return j < hi && lds[j] == y;
+                    } else if (MD == MODE_ARRAY) {
+                        const u64 j = lower_bound_dev<u32>(lds, 0, tlen, y);
+                        return j < tlen && lds[j] == y;
+                    } else if (MD == MODE_HASH) {
+                        const u32 hk = hash_bits_for(tlen), hmask = (1u << hk) - 1;
+                        u32 h = hash_slot(y, hk);
+                        for (;;) {  // ends: the table is at most half full
+                            const u32 v = lds[h];
+                            if (v == y + 1) return true;
+                            if (v == 0u) return false;
+                            h = (h + 1) & hmask;
+                        }
+                    } else if (MD == MODE_REVERSE) {
+                        const u64 *ro = Reverse<ALGO>::off(g);
+                        const u32 *ra = Reverse<ALGO>::adj(g);
+                        const u64 r0 = ro[y], r1 = ro[y + 1];
+                        const u64 j = lower_bound_dev<u32>(ra, r0, r1, p);
+                        return j < r1 && ra[j] == p;
                     }
-                } else if (tk.mode == MODE_BUCKET) {
-                    u64 lo[UN], hi[UN];
-#pragma unroll
+                    const u64 j = lower_bound_dev<u32>(pa, t0, t1, y);
+                    return j < t1 && pa[j] == y;
+                };
+                // membership of UN elements at once (interleaved where it is a search)
+                auto member_all = [&](const u32 (&y)[UN], bool (&h)[UN]) {
+                    if (MD == MODE_SPLIT) {
+                        // the entries below the bitmap's window: interleaved global searches
+                        u64 lo[UN], hi[UN];
+                        const u64 base = low_lds ? 0 : t0, top = low_lds ? ts - t0 : ts;
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            lo[j] = base;
+                            hi[j] = y[j] >= wlo ? base : top;
+                        }
+                        member_multi_var(low_lds ? low : pa, lo, hi, y, h);
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            if (y[j] >= wlo) {
+                                const u32 v = y[j] - wlo;
+                                h[j] = y[j] <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
+                            }
+                        }
+                    } else if (MD == MODE_BUCKET) {
+                        u64 lo[UN], hi[UN];
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            const bool in = y[j] >= tmin && y[j] <= tmax;
+                            const u32 b = in ? (y[j] - tmin) >> bsh : 0u;
+                            lo[j] = in ? bst[b] : 0u;
+                            hi[j] = in ? bst[b + 1] : 0u;
+                        }
+                        member_multi_var(lds, lo, hi, y, h);
+                    } else if (MD == MODE_ARRAY) {
+                        member_multi(lds, 0, tlen, y, h);
+                    } else if (MD == MODE_GLOBAL) {
+                        member_multi(pa, t0, t1, y, h);
+                    } else {
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) h[j] = member(y[j]);
+                    }
+                };
+                // listed triangles of a group: yi gathers issued together
+                auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
+                    bool any = false;
+    #pragma unroll
+                    for (int j = 0; j < UN; j++) any |= h[j];
+                    if (!__ballot(any)) return;
+                    u32 yi[UN];
+    #pragma unroll
+                    for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+    #pragma unroll
                     for (int j = 0; j < UN; j++) {
-                        const bool in = y[j] >= tmin && y[j] <= tmax;
-                        const u32 b = in ? (y[j] - tmin) >> bsh : 0u;
-                        lo[j] = in ? bst[b] : 0u;
-                        hi[j] = in ? bst[b + 1] : 0u;
+                        u32 xa = 0, xb = 0, xc = 0;
+                        if (h[j]) {
+                            xa = pinv; xb = xv[j]; xc = yi[j];
+                            canon3(xa, xb, xc);
+                            cnt += 1;
+                            hsh += tri_digest(xa, xb, xc);
+                        }
+                        em.push(h[j], xa, xb, xc, o);
                     }
-                    member_multi_var(lds, lo, hi, y, h);
-                } else if (tk.mode == MODE_ARRAY) {
-                    member_multi(lds, 0, tlen, y, h);
-                } else if (tk.mode == MODE_GLOBAL) {
-                    member_multi(pa, t0, t1, y, h);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < UN; j++) h[j] = member(y[j]);
-                }
-            };
-            // listed triangles of a group: yi gathers issued together
-            auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
-                bool any = false;
-#pragma unroll
-                for (int j = 0; j < UN; j++) any |= h[j];
-                if (!__ballot(any)) return;
-                u32 yi[UN];
-#pragma unroll
-                for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
-#pragma unroll
-                for (int j = 0; j < UN; j++) {
-                    u32 xa = 0, xb = 0, xc = 0;
-                    if (h[j]) {
-                        xa = pinv; xb = xv[j]; xc = yi[j];
-                        canon3(xa, xb, xc);
-                        cnt += 1;
-                        hsh += tri_digest(xa, xb, xc);
+                };
+                u64 kb = wb;
+                while (kb < we) {
+                    if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && cur.end >= kb + 2 * UN * WAVE &&
+                        kb + 2 * UN * WAVE <= we) {
+                        // 2 UN full chunks inside one seed window: all loads in
+                        // flight before the first test (one LDS read per test)
+                        const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
+                        u32 y[UN], y2[UN], xv[UN];
+                        bool h[UN];
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) y2[j] = SA[sab + (u64)(UN + j) * WAVE];
+                        if (xinv_c != cur.c_lo) {  // once per seed
+                            xinv = cxinv[cur.c_lo];
+                            xinv_c = cur.c_lo;
+                        }
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) xv[j] = xinv;
+                        member_all(y, h);
+                        report(y, h, xv);
+                        member_all(y2, h);
+                        report(y2, h, xv);
+                        kb += 2 * UN * WAVE;
+                        cur.advance(kb, cur.c_lo);
+                        continue;
                     }
-                    em.push(h[j], xa, xb, xc, o);
-                }
-            };
-            u64 kb = wb;
-            while (kb < we) {
-                if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
-                    // UN full chunks inside one seed window
-                    const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
-                    u32 y[UN], xv[UN];
-                    bool h[UN];
-#pragma unroll
-                    for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
-                    if (xinv_c != cur.c_lo) {  // once per seed
-                        xinv = cxinv[cur.c_lo];
-                        xinv_c = cur.c_lo;
-                    }
-#pragma unroll
-                    for (int j = 0; j < UN; j++) xv[j] = xinv;
-                    member_all(y, h);
-                    report(y, h, xv);
-                    kb += UN * WAVE;
-                    cur.advance(kb, cur.c_lo);
-                    continue;
-                }
-                if (kb + UN * WAVE <= we) {
-                    // short windows: if the next UN chunks lie in the 64 seeds
-                    // starting at the current one, one load of their prefix,
-                    // scan start and endpoint id serves all UN chunks
-                    const u64 ci = cur.c_lo + lane;
-                    const bool inw = ci < tk.ce;
-                    const u64 P = inw ? cpre[ci] : ~0ull;
-                    const u64 pend = (cur.c_lo + WAVE <= tk.ce) ? cpre[cur.c_lo + WAVE] : ~0ull;
-                    if (pend >= kb + UN * WAVE) {
-                        const u64 A = inw ? cabs[ci] : 0ull;
-                        const u32 X = inw ? cxinv[ci] : 0u;
-                        // prefixes relative to kb (those at or below kb read as 0)
-                        const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                    if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
+                        // UN full chunks inside one seed window
+                        const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
                         u32 y[UN], xv[UN];
                         bool h[UN];
-                        int lo_last = 0;
-#pragma unroll
-                        for (int j = 0; j < UN; j++) {
-                            const u32 kr = (u32)(j * WAVE + lane);
-                            int lo = 0;
-#pragma unroll
-                            for (int st = 32; st > 0; st >>= 1) {
-                                const u32 q = __shfl(Q, lo + st, WAVE);
-                                if (q <= kr) lo += st;
-                            }
-                            const u64 rel = (kb + kr) - shfl_u64(P, lo);
-                            y[j] = SA[shfl_u64(A, lo) + rel];
-                            xv[j] = __shfl(X, lo, WAVE);
-                            if (j == UN - 1) lo_last = __shfl(lo, WAVE - 1, WAVE);
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
+                        if (xinv_c != cur.c_lo) {  // once per seed
+                            xinv = cxinv[cur.c_lo];
+                            xinv_c = cur.c_lo;
                         }
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) xv[j] = xinv;
                         member_all(y, h);
                         report(y, h, xv);
                         kb += UN * WAVE;
-                        if (kb < we) {
-                            // seed of item kb: the last lane's seed, or the next one
-                            u64 c = cur.c_lo + (u64)lo_last;
-                            const u64 pn = (lo_last + 1 < WAVE) ? shfl_u64(P, lo_last + 1) : pend;
-                            if (pn <= kb) c++;
-                            cur.reset(c);
-                        }
+                        cur.advance(kb, cur.c_lo);
                         continue;
                     }
-                }
-                const u64 k = kb + lane;
-                const bool act = k < we;
-                u64 rel;
-                const u64 c = cur.locate(kb, k, rel);
-                bool hit = false;
-                u32 xa = 0, xb = 0, xc = 0;
-                if (act) {
-                    const u32 y = SA[cabs[c] + rel];
-                    hit = member(y);
-                    if (hit) {
-                        xa = pinv; xb = cxinv[c]; xc = g.inv[y];
-                        canon3(xa, xb, xc);
-                        cnt += 1;
-                        hsh += tri_digest(xa, xb, xc);
+                    if (kb + UN * WAVE <= we) {
+                        // short windows: if the next UN chunks lie in the 64 seeds
+                        // starting at the current one, one load of their prefix,
+                        // scan start and endpoint id serves all UN chunks
+                        const u64 ci = cur.c_lo + lane;
+                        const bool inw = ci < tk.ce;
+                        const u64 P = inw ? cpre[ci] : ~0ull;
+                        const u64 pend = (cur.c_lo + WAVE <= tk.ce) ? cpre[cur.c_lo + WAVE] : ~0ull;
+                        if (pend >= kb + UN * WAVE) {
+                            const u64 A = inw ? cabs[ci] : 0ull;
+                            const u32 X = inw ? cxinv[ci] : 0u;
+                            // prefixes relative to kb (those at or below kb read as 0)
+                            const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                            u32 y[UN], xv[UN];
+                            bool h[UN];
+                            int lo_last = 0;
+    #pragma unroll
+                            for (int j = 0; j < UN; j++) {
+                                const u32 kr = (u32)(j * WAVE + lane);
+                                int lo = 0;
+    #pragma unroll
+                                for (int st = 32; st > 0; st >>= 1) {
+                                    const u32 q = __shfl(Q, lo + st, WAVE);
+                                    if (q <= kr) lo += st;
+                                }
+                                const u64 rel = (kb + kr) - shfl_u64(P, lo);
+                                y[j] = SA[shfl_u64(A, lo) + rel];
+                                xv[j] = __shfl(X, lo, WAVE);
+                                if (j == UN - 1) lo_last = (int)uni32((u32)__shfl(lo, WAVE - 1, WAVE));
+                            }
+                            member_all(y, h);
+                            report(y, h, xv);
+                            kb += UN * WAVE;
+                            if (kb < we) {
+                                // seed of item kb: the last lane's seed, or the next one
+                                u64 c = cur.c_lo + (u64)lo_last;
+                                const u64 pn = (lo_last + 1 < WAVE) ? shfl_u64(P, lo_last + 1) : pend;
+                                if (pn <= kb) c++;
+                                cur.reset(c);
+                            }
+                            continue;
+                        }
                     }
+                    const u64 k = kb + lane;
+                    const bool act = k < we;
+                    u64 rel;
+                    const u64 c = cur.locate(kb, k, rel);
+                    bool hit = false;
+                    u32 xa = 0, xb = 0, xc = 0;
+                    if (act) {
+                        const u32 y = SA[cabs[c] + rel];
+                        hit = member(y);
+                        if (hit) {
+                            xa = pinv; xb = cxinv[c]; xc = g.inv[y];
+                            canon3(xa, xb, xc);
+                            cnt += 1;
+                            hsh += tri_digest(xa, xb, xc);
+                        }
+                    }
+                    em.push(hit, xa, xb, xc, o);
+                    kb += WAVE;
+                    cur.advance(kb, c);
                 }
-                em.push(hit, xa, xb, xc, o);
-                kb += WAVE;
-                cur.advance(kb, c);
             }
+        };
+        switch (tk.mode) {
+            case MODE_BITMAP: walk(std::integral_constant<int, MODE_BITMAP>{}); break;
+            case MODE_ARRAY: walk(std::integral_constant<int, MODE_ARRAY>{}); break;
+            case MODE_GLOBAL: walk(std::integral_constant<int, MODE_GLOBAL>{}); break;
+            case MODE_REVERSE: walk(std::integral_constant<int, MODE_REVERSE>{}); break;
+            case MODE_HASH: walk(std::integral_constant<int, MODE_HASH>{}); break;
+            case MODE_BUCKET: walk(std::integral_constant<int, MODE_BUCKET>{}); break;
+            default: walk(std::integral_constant<int, MODE_SPLIT>{}); break;
         }
         __syncthreads();  // every wavefront is done with the staged list
         // reset B (or the staged array) so that LDS is all zero again

@@ -65,15 +65,16 @@ struct SeedCursor {
     u64 c_lo;         // seed of the chunk's first item
     u64 base, end;    // cpre[c_lo], cpre[c_lo + 1]
 
+    // (all arguments wave-uniform; the cursor's fields stay wave-uniform)
     __device__ __forceinline__ SeedCursor(const u64 *cp, u64 lo, u64 nc, u64 first_item) : cpre(cp), ncap(nc) {
-        c_lo = upper_bound_dev<u64>(cpre, lo, ncap + 1, first_item) - 1;
-        base = cpre[c_lo];
-        end = cpre[c_lo + 1];
+        c_lo = uni64(upper_bound_dev<u64>(cpre, lo, ncap + 1, first_item) - 1);
+        base = uni64(cpre[c_lo]);
+        end = uni64(cpre[c_lo + 1]);
     }
     // when the seed of the first item is already known
-    __device__ __forceinline__ SeedCursor(const u64 *cp, u64 nc, u64 c) : cpre(cp), ncap(nc), c_lo(c) {
-        base = cpre[c_lo];
-        end = cpre[c_lo + 1];
+    __device__ __forceinline__ SeedCursor(const u64 *cp, u64 nc, u64 c) : cpre(cp), ncap(nc), c_lo(uni64(c)) {
+        base = uni64(cpre[c_lo]);
+        end = uni64(cpre[c_lo + 1]);
     }
 
     __device__ __forceinline__ u64 locate(u64 kb, u64 k, u64 &rel) const {
@@ -95,9 +96,9 @@ struct SeedCursor {
 
     // continue from seed c (known to hold the next item)
     __device__ __forceinline__ void reset(u64 c) {
-        c_lo = c;
-        base = cpre[c_lo];
-        end = cpre[c_lo + 1];
+        c_lo = uni64(c);
+        base = uni64(cpre[c_lo]);
+        end = uni64(cpre[c_lo + 1]);
     }
 
     // move to the seed of item nk, given c = seed of the last lane's item
@@ -105,10 +106,10 @@ struct SeedCursor {
     // then c = ncap and the cursor parks there without reading past cpre[ncap])
     __device__ __forceinline__ void advance(u64 nk, u64 c) {
         if (nk < end) return;
-        c_lo = shfl_u64(c, WAVE - 1);
-        if (c_lo < ncap && cpre[c_lo + 1] <= nk) c_lo++;
-        base = cpre[c_lo];
-        end = c_lo < ncap ? cpre[c_lo + 1] : base;
+        c_lo = uni64(shfl_u64(c, WAVE - 1));
+        if (c_lo < ncap && uni64(cpre[c_lo + 1]) <= nk) c_lo++;
+        base = uni64(cpre[c_lo]);
+        end = c_lo < ncap ? uni64(cpre[c_lo + 1]) : base;
     }
 };
 

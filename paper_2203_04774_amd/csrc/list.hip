@@ -112,6 +112,7 @@ struct Reverse {
 };
 
 constexpr int HW = HB / 64;    // wavefronts per heavy workgroup
+constexpr int HG = 2;          // groups of UN chunks loaded together in the bitmap forms' long windows
 
 struct Task {
     u64 a, b;      // item range
@@ -744,28 +745,29 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                 };
                 u64 kb = wb;
                 while (kb < we) {
-                    if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && cur.end >= kb + 2 * UN * WAVE &&
-                        kb + 2 * UN * WAVE <= we) {
-                        // 2 UN full chunks inside one seed window: all loads in
-                        // flight before the first test (one LDS read per test)
+                    if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && cur.end >= kb + HG * UN * WAVE &&
+                        kb + HG * UN * WAVE <= we) {
+                        // HG groups of UN full chunks inside one seed window: all
+                        // loads in flight before the first test (one LDS read each)
                         const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
-                        u32 y[UN], y2[UN], xv[UN];
+                        u32 y[HG][UN], xv[UN];
                         bool h[UN];
-    #pragma unroll
-                        for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
-    #pragma unroll
-                        for (int j = 0; j < UN; j++) y2[j] = SA[sab + (u64)(UN + j) * WAVE];
+#pragma unroll
+                        for (int q = 0; q < HG; q++)
+#pragma unroll
+                            for (int j = 0; j < UN; j++) y[q][j] = SA[sab + (u64)(q * UN + j) * WAVE];
                         if (xinv_c != cur.c_lo) {  // once per seed
                             xinv = cxinv[cur.c_lo];
                             xinv_c = cur.c_lo;
                         }
-    #pragma unroll
+#pragma unroll
                         for (int j = 0; j < UN; j++) xv[j] = xinv;
-                        member_all(y, h);
-                        report(y, h, xv);
-                        member_all(y2, h);
-                        report(y2, h, xv);
-                        kb += 2 * UN * WAVE;
+#pragma unroll
+                        for (int q = 0; q < HG; q++) {
+                            member_all(y[q], h);
+                            report(y[q], h, xv);
+                        }
+                        kb += HG * UN * WAVE;
                         cur.advance(kb, cur.c_lo);
                         continue;
                     }

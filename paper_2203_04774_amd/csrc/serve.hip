@@ -2,15 +2,17 @@
 // memory budget, batched with whatever else is waiting, and listed while
 // the next batch is uploaded and oriented on a second stream.
 //
-// Two threads own the device work.  The ingest thread admits waiting jobs
-// in arrival order while their modelled footprint fits the budget, uploads
-// their edges, and orients them as one disjoint union (batch.hip); a job
-// whose graph is large forms a batch of its own.  The list thread takes
-// oriented batches in order and lists them: a union of small graphs by
-// the batched pass (per-graph rows), a batch of one by the plain listing
-// (light and heavy pivots).  A batch whose union fails validation is
-// split and its jobs are oriented one by one, so a malformed job fails
-// alone.
+// Three threads own the device work, each on its own stream.  The upload
+// thread admits waiting jobs in arrival order while their modelled
+// footprint fits the budget and copies their edges and orderings to the
+// device; a job whose graph is large forms a batch of its own.  The orient
+// thread orients each uploaded batch as one disjoint union (batch.hip).
+// The list thread lists oriented batches in order: a union of small graphs
+// by the batched pass (per-graph rows), a batch of one by the plain
+// listing (light and heavy pivots).  So the copy of one batch, the
+// orientation of the next and the listing of a third overlap.  A batch
+// whose union fails validation is split and its jobs are oriented one by
+// one, so a malformed job fails alone.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -48,28 +50,39 @@ struct Ready {
     u64 batch_id = 0;
 };
 
+// A batch whose edges and orderings are on the device, waiting to be oriented.
+struct Uploaded {
+    std::vector<Job *> jobs;
+    u64 bytes = 0;
+    DevBuf src, dst, rank;
+};
+
 }  // namespace
 
 struct tl_server {
     tl_server_config cfg{};
     int device = 0;
-    hipStream_t s_up = nullptr, s_list = nullptr;
+    hipStream_t s_copy = nullptr, s_up = nullptr, s_list = nullptr;
 
     std::mutex mu;
-    std::condition_variable cv_pending;  // ingest waits: new jobs, freed budget, stop
+    std::condition_variable cv_pending;  // upload waits: new jobs, freed budget, stop
     std::condition_variable cv_ready;    // list waits: oriented batches, stop
-    std::condition_variable cv_space;    // ingest waits: room in the ready queue
+    std::condition_variable cv_space;    // orient waits: room in the ready queue
+    std::condition_variable cv_uploaded; // orient waits: uploaded batches, stop
+    std::condition_variable cv_upspace;  // upload waits: room in the uploaded queue
     std::condition_variable cv_done;     // pollers wait
     std::deque<Job *> pending;
     std::deque<Job *> solo_retry;        // jobs of a union that failed validation
     std::deque<Ready> ready;
+    std::deque<std::unique_ptr<Uploaded>> uploaded;
+    u32 in_flight = 0;                   // batches between admission and the end of their listing
     std::unordered_map<u64, std::unique_ptr<Job>> jobs;
     u64 next_id = 1, next_batch = 1;
     u64 reserved = 0;
     bool stop = false, paused = false;
     tl_server_stats st{};
 
-    std::thread ingest, lister;
+    std::thread uploader, orienter, lister;
 };
 
 namespace {
@@ -85,38 +98,50 @@ void release_bytes(tl_server *S, u64 bytes) {
     S->cv_pending.notify_all();
 }
 
-// Orients jobs as one union on the upload stream; throws on failure.
-tl_batch *orient_jobs(tl_server *S, const std::vector<Job *> &js) {
-    const u32 k = (u32)js.size();
-    std::vector<u32> n(k);
-    std::vector<u64> m(k);
+// Copies the jobs' arrays to the device on the copy stream; throws on failure.
+std::unique_ptr<Uploaded> upload_jobs(tl_server *S, const std::vector<Job *> &js) {
     u64 N = 0, M = 0;
-    for (u32 i = 0; i < k; i++) {
-        n[i] = js[i]->in.n;
-        m[i] = js[i]->in.m;
-        N += n[i];
-        M += m[i];
+    for (Job *j : js) {
+        N += j->in.n;
+        M += j->in.m;
     }
     const u64 t0 = now_ns();
-    DevBuf src((M ? M : 1) * 4, S->s_up), dst((M ? M : 1) * 4, S->s_up), rank((N ? N : 1) * 4, S->s_up);
+    auto U = std::make_unique<Uploaded>();
+    U->jobs = js;
+    U->src = DevBuf((M ? M : 1) * 4, S->s_copy);
+    U->dst = DevBuf((M ? M : 1) * 4, S->s_copy);
+    U->rank = DevBuf((N ? N : 1) * 4, S->s_copy);
     u64 eo = 0, vo = 0;
-    for (u32 i = 0; i < k; i++) {
-        const tl_job &J = js[i]->in;
+    for (Job *j : js) {
+        const tl_job &J = j->in;
         if (J.m) {
-            TL_HIP(hipMemcpyAsync(src.as<u32>() + eo, J.src, J.m * 4, hipMemcpyHostToDevice, S->s_up));
-            TL_HIP(hipMemcpyAsync(dst.as<u32>() + eo, J.dst, J.m * 4, hipMemcpyHostToDevice, S->s_up));
+            TL_HIP(hipMemcpyAsync(U->src.as<u32>() + eo, J.src, J.m * 4, hipMemcpyHostToDevice, S->s_copy));
+            TL_HIP(hipMemcpyAsync(U->dst.as<u32>() + eo, J.dst, J.m * 4, hipMemcpyHostToDevice, S->s_copy));
         }
-        if (J.n) TL_HIP(hipMemcpyAsync(rank.as<u32>() + vo, J.rank, (u64)J.n * 4, hipMemcpyHostToDevice, S->s_up));
+        if (J.n) TL_HIP(hipMemcpyAsync(U->rank.as<u32>() + vo, J.rank, (u64)J.n * 4, hipMemcpyHostToDevice, S->s_copy));
         eo += J.m;
         vo += J.n;
     }
-    TL_HIP(hipStreamSynchronize(S->s_up));
-    const u64 t1 = now_ns();
-    tl_batch *b = batch_orient_impl(k, n.data(), m.data(), src.as<u32>(), dst.as<u32>(), rank.as<u32>(), S->s_up);
-    const u64 t2 = now_ns();
+    TL_HIP(hipStreamSynchronize(S->s_copy));
     std::lock_guard<std::mutex> lk(S->mu);
-    S->st.upload_ns += t1 - t0;
-    S->st.orient_ns += t2 - t1;
+    S->st.upload_ns += now_ns() - t0;
+    return U;
+}
+
+// Orients an uploaded batch as one union on the orient stream; throws on failure.
+tl_batch *orient_uploaded(tl_server *S, Uploaded &U) {
+    const u32 k = (u32)U.jobs.size();
+    std::vector<u32> n(k);
+    std::vector<u64> m(k);
+    for (u32 i = 0; i < k; i++) {
+        n[i] = U.jobs[i]->in.n;
+        m[i] = U.jobs[i]->in.m;
+    }
+    const u64 t0 = now_ns();
+    tl_batch *b = batch_orient_impl(k, n.data(), m.data(), U.src.as<u32>(), U.dst.as<u32>(), U.rank.as<u32>(),
+                                    S->s_up);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st.orient_ns += now_ns() - t0;
     return b;
 }
 
@@ -160,47 +185,96 @@ bool pick(tl_server *S, std::vector<Job *> &out, u64 &bytes) {
     return true;
 }
 
-void ingest_loop(tl_server *S) {
+// Called with S->mu held: a failed batch either splits (a malformed job
+// among several: each is retried alone) or fails its jobs.
+void fail_batch(tl_server *S, const std::vector<Job *> &js, u64 bytes, int err) {
+    S->in_flight--;
+    if (err == TL_EINVAL && js.size() > 1) {
+        for (Job *j : js) S->solo_retry.push_back(j);
+        S->st.split_batches++;
+        S->cv_pending.notify_all();
+        return;  // the bytes stay reserved for the retries
+    }
+    for (Job *j : js) finish(S, j, err);
+    release_bytes(S, bytes);
+    S->cv_done.notify_all();
+}
+
+void upload_loop(tl_server *S) {
     (void)hipSetDevice(S->device);
     std::vector<Job *> js;
     for (;;) {
         u64 bytes = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_pending.wait(lk, [&] { return S->stop || pick(S, js, bytes); });
+            // without pipelining a batch is admitted only when the previous one is listed
+            S->cv_pending.wait(lk, [&] {
+                return S->stop || ((S->cfg.pipeline || S->in_flight == 0) && pick(S, js, bytes));
+            });
             if (S->stop) return;
+            S->in_flight++;
             const u64 t = now_ns();
             for (Job *j : js)
                 if (!j->res.t_admit_ns) j->res.t_admit_ns = t;
         }
-        const bool retry = js.size() == 1 && js[0]->solo && bytes == 0;
-        if (retry) bytes = js[0]->bytes;
-        tl_batch *b = nullptr;
+        if (js.size() == 1 && js[0]->solo && bytes == 0) bytes = js[0]->bytes;  // a retry: reserved already
+        std::unique_ptr<Uploaded> U;
         int err = TL_OK;
-        std::string msg;
         try {
-            b = orient_jobs(S, js);
+            U = upload_jobs(S, js);
         } catch (const TlError &e) {
             err = e.code;
-            msg = e.msg;
         } catch (...) {
             err = TL_EHIP;
         }
         std::unique_lock<std::mutex> lk(S->mu);
         if (err != TL_OK) {
-            if (err == TL_EINVAL && js.size() > 1) {
-                // find the malformed job(s): orient every job of the union alone
-                for (Job *j : js) S->solo_retry.push_back(j);
-                S->st.split_batches++;
-                S->cv_pending.notify_all();
-                continue;  // the bytes stay reserved for the retries
-            }
-            for (Job *j : js) finish(S, j, err);
-            release_bytes(S, bytes);
-            S->cv_done.notify_all();
+            fail_batch(S, js, bytes, err);
             continue;
         }
-        S->cv_space.wait(lk, [&] { return S->stop || S->ready.size() < (S->cfg.pipeline ? 1u : 0u) + 1u; });
+        U->bytes = bytes;
+        S->cv_upspace.wait(lk, [&] { return S->stop || S->uploaded.size() < 1; });
+        if (S->stop) return;
+        S->uploaded.push_back(std::move(U));
+        S->cv_uploaded.notify_all();
+    }
+}
+
+void orient_loop(tl_server *S) {
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        std::unique_ptr<Uploaded> U;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_uploaded.wait(lk, [&] { return S->stop || !S->uploaded.empty(); });
+            if (S->stop) return;
+            U = std::move(S->uploaded.front());
+            S->uploaded.pop_front();
+            S->cv_upspace.notify_all();
+        }
+        tl_batch *b = nullptr;
+        int err = TL_OK;
+        try {
+            b = orient_uploaded(S, *U);
+        } catch (const TlError &e) {
+            err = e.code;
+        } catch (...) {
+            err = TL_EHIP;
+        }
+        const std::vector<Job *> js = U->jobs;
+        const u64 bytes = U->bytes;
+        U.reset();  // the copies are no longer needed (the orient stream has finished with them)
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (err != TL_OK) {
+            fail_batch(S, js, bytes, err);
+            continue;
+        }
+        S->cv_space.wait(lk, [&] { return S->stop || S->ready.size() < 2u; });
+        if (S->stop) {
+            lk.unlock();
+            batch_free_impl(b, true);
+            return;
+        }
         Ready r;
         r.b = b;
         r.jobs = js;
@@ -208,11 +282,6 @@ void ingest_loop(tl_server *S) {
         r.batch_id = S->next_batch++;
         S->ready.push_back(std::move(r));
         S->cv_ready.notify_all();
-        if (!S->cfg.pipeline) {
-            // without pipelining, the next upload waits for this batch's listing
-            S->cv_space.wait(lk, [&] { return S->stop || S->ready.empty(); });
-        }
-        if (S->stop) return;
     }
 }
 
@@ -260,7 +329,9 @@ void list_loop(tl_server *S) {
         pool_trim_above(S->cfg.hbm_budget + S->cfg.hbm_budget / 2);
         std::unique_lock<std::mutex> lk(S->mu);
         S->ready.pop_front();
+        S->in_flight--;
         S->cv_space.notify_all();
+        S->cv_pending.notify_all();
         for (u32 i = 0; i < k; i++) {
             Job *j = r.jobs[i];
             j->res.t_start_ns = t_start;
@@ -304,10 +375,12 @@ tl_server *server_create_impl(const tl_server_config *cfg) {
     if (!S->cfg.max_batch_edges) S->cfg.max_batch_edges = 1ull << 27;
     if (!S->cfg.solo_edges) S->cfg.solo_edges = 1ull << 21;
     TL_HIP(hipGetDevice(&S->device));
+    TL_HIP(hipStreamCreateWithFlags(&S->s_copy, hipStreamNonBlocking));
     TL_HIP(hipStreamCreateWithFlags(&S->s_up, hipStreamNonBlocking));
     TL_HIP(hipStreamCreateWithFlags(&S->s_list, hipStreamNonBlocking));
     tl_server *p = S.release();
-    p->ingest = std::thread(ingest_loop, p);
+    p->uploader = std::thread(upload_loop, p);
+    p->orienter = std::thread(orient_loop, p);
     p->lister = std::thread(list_loop, p);
     return p;
 }
@@ -384,17 +457,23 @@ void server_destroy_impl(tl_server *S) {
         for (Job *j : S->pending) finish(S, j, TL_EABORT);
         S->cv_done.notify_all();
         S->pending.clear();
-        S->cv_done.wait(lk, [&] { return S->ready.empty() && S->reserved == 0 && S->solo_retry.empty(); });
+        S->cv_done.wait(lk, [&] {
+            return S->in_flight == 0 && S->ready.empty() && S->uploaded.empty() && S->reserved == 0 &&
+                   S->solo_retry.empty();
+        });
         S->stop = true;
         S->cv_pending.notify_all();
+        S->cv_uploaded.notify_all();
+        S->cv_upspace.notify_all();
         S->cv_ready.notify_all();
         S->cv_space.notify_all();
     }
-    S->ingest.join();
+    S->uploader.join();
+    S->orienter.join();
     S->lister.join();
-    (void)hipStreamSynchronize(S->s_up);
-    (void)hipStreamSynchronize(S->s_list);
-    (void)hipStreamDestroy(S->s_up);
-    (void)hipStreamDestroy(S->s_list);
+    for (hipStream_t st : {S->s_copy, S->s_up, S->s_list}) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
     delete S;
 }

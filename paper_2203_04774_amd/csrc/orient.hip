@@ -186,7 +186,7 @@ void orient_sorted(tl_csr *g, u32 n, const u32 *src, const u32 *dst, u64 m_in, c
         hipLaunchKernelGGL(k_fwd_keys, dim3(grid_n(m_in)), dim3(256), 0, s, src, dst, m_in, rank, b, sent,
                            keys.as<u64>());
         TL_HIP(hipGetLastError());
-        const u64 *sorted = radix_sort_u64(keys.as<u64>(), tmp.as<u64>(), m_in, 2 * b, s);
+        const u64 *sorted = radix_sort_u64(keys.as<u64>(), tmp.as<u64>(), m_in, 0, 2 * b, s);
         u64 *other = sorted == keys.as<u64>() ? tmp.as<u64>() : keys.as<u64>();
         u32 *flag = reinterpret_cast<u32 *>(other);  // the other buffer is free now
         hipLaunchKernelGGL(k_unique_flags, dim3(grid_n(m_in)), dim3(256), 0, s, sorted, m_in, sent, flag);
@@ -210,14 +210,15 @@ void orient_sorted(tl_csr *g, u32 n, const u32 *src, const u32 *dst, u64 m_in, c
         TL_HIP(hipGetLastError());
     }
     scan_u32_to_u64(cnt, g->off_f, n, s);
-    // backward CSR: the same entries sorted by (hi, lo)
+    // backward CSR: the same entries sorted by (hi, lo).  They are sorted by
+    // (lo, hi) already, so a stable sort on the hi field alone suffices.
     g->adj_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
     g->row_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
     if (n) TL_HIP(hipMemsetAsync(cnt, 0, (u64)n * sizeof(u32), s));
     if (m) {
         hipLaunchKernelGGL(k_bwd_keys, dim3(grid_n(m)), dim3(256), 0, s, g->adj_f, g->row_f, m, b, keys.as<u64>());
         TL_HIP(hipGetLastError());
-        const u64 *sorted = radix_sort_u64(keys.as<u64>(), tmp.as<u64>(), m, 2 * b, s);
+        const u64 *sorted = radix_sort_u64(keys.as<u64>(), tmp.as<u64>(), m, b, b, s);
         hipLaunchKernelGGL(k_bwd_emit, dim3(grid_n(m)), dim3(256), 0, s, sorted, m, b, g->adj_b, g->row_b);
         TL_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_run_count, dim3(grid_n(m)), dim3(256), 0, s, g->row_b, m, cnt);

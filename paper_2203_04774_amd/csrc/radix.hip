@@ -89,14 +89,14 @@ __global__ __launch_bounds__(RB) void k_rs_scatter(const u64 *in, u64 *out, u64 
 
 }  // namespace
 
-u64 *radix_sort_u64(u64 *keys, u64 *tmp, u64 n, int bits, hipStream_t s) {
+u64 *radix_sort_u64(u64 *keys, u64 *tmp, u64 n, int lo_bit, int bits, hipStream_t s) {
     if (n <= 1 || bits <= 0) return keys;
     const u64 ntiles = (n + RT - 1) / RT;
     TL_REQUIRE(ntiles < (1ull << 31), TL_EINVAL, "radix sort: too many keys");
     DevBuf counts((u64)RD * ntiles * sizeof(u32), s), offs(((u64)RD * ntiles + 1) * sizeof(u64), s);
     DevBuf ws((scan_workspace_words((u64)RD * ntiles) + 1) * sizeof(u64), s);
     u64 *src = keys, *dst = tmp;
-    for (int sh = 0; sh < bits; sh += 8) {
+    for (int sh = lo_bit; sh < lo_bit + bits; sh += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(RB), 0, s, src, n, sh, counts.as<u32>(), ntiles);
         TL_HIP(hipGetLastError());
         scan_u32_to_u64(counts.as<u32>(), offs.as<u64>(), (u64)RD * ntiles, s, ws.as<u64>());

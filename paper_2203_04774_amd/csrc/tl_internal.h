@@ -110,9 +110,10 @@ void scan_u32_to_u64(const u32 *in, u64 *out, u64 n, hipStream_t s, u64 *ws = nu
 void scan_u64_to_u64(const u64 *in, u64 *out, u64 n, hipStream_t s, u64 *ws = nullptr);
 u64 scan_workspace_words(u64 n);
 
-// Stable ascending sort of n 64-bit keys by their low `bits` bits (radix.hip);
-// tmp holds n keys of scratch; returns whichever of keys/tmp holds the result.
-u64 *radix_sort_u64(u64 *keys, u64 *tmp, u64 n, int bits, hipStream_t s);
+// Stable ascending sort of n 64-bit keys by bits [lo_bit, lo_bit + bits)
+// (radix.hip); tmp holds n keys of scratch; returns whichever of keys/tmp
+// holds the result.
+u64 *radix_sort_u64(u64 *keys, u64 *tmp, u64 n, int lo_bit, int bits, hipStream_t s);
 
 // Sort every row of a CSR ascending and drop repeated values inside a row;
 // uniq[r] receives the row's distinct count and the distinct values are

@@ -141,13 +141,11 @@ __device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u64 &abs) {
 // pg holds (count, digest, work) per graph.
 template <int ALGO>
 __global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *lw, u64 *sabs, u64 *wp, u64 *pg) {
-    const int lane = lane_id();
-    const u64 stride = (u64)gridDim.x * blockDim.x;
-    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    const u64 iters = g.m > first - lane ? (g.m - (first - lane) + stride - 1) / stride : 0;  // wave-uniform
+    const XcdRange rg(g.m);  // the grid is a multiple of 8 workgroups
+    const u64 iters = uni64(rg.wave_iters());
     for (u64 it = 0; it < iters; it++) {
-        const u64 e = first + it * stride;
-        const bool valid = e < g.m;
+        const u64 e = rg.first + it * rg.stride;
+        const bool valid = e < rg.end;
         u32 gr = 0, p = 0, l = 0;
         u64 w = 0;
         if (valid) {
@@ -547,6 +545,8 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
 }
 
 unsigned grid_b(u64 items) { return grid_for(items, BB, (unsigned)tl_num_cus() * 16); }
+// a grid of whole groups of 8 workgroups (for XcdRange walks)
+unsigned grid_x8(u64 items) { return (grid_b(items) + 7u) & ~7u; }
 
 // Lets the heavy-bin kernels use their whole dynamic LDS (once per process).
 void prepare_batch_kernels() {
@@ -603,7 +603,7 @@ void enqueue_batch_list(tl_batch *b, const BatchTuning &tu, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, b->ctl, 1ull, 0ull);
     // the seeds' window starts live in cpre's buffer until the compaction
     // has read them; the scan of the compacted lengths then overwrites them
-    hipLaunchKernelGGL((k_bplan<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->gid, b->lw, b->cpre, b->wp, b->pg);
+    hipLaunchKernelGGL((k_bplan<ALGO>), dim3(grid_x8(m)), dim3(BB), 0, s, v, b->gid, b->lw, b->cpre, b->wp, b->pg);
     hipLaunchKernelGGL((k_bclass<ALGO>), dim3(grid_b(N)), dim3(BB), 0, s, v, (u32)N, b->wp, tu.heavy_min, b->hflag);
     hipLaunchKernelGGL((k_bflag<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->lw, b->hflag, b->f64);
     scan_u64_to_u64(b->f64, b->pos, m, s, b->ws);

@@ -129,6 +129,31 @@ __device__ __forceinline__ uint64_t tri_digest(uint32_t a, uint32_t b, uint32_t 
     return sm64_mix(sm64_mix(((uint64_t)a << 32) | b) + c);
 }
 
+// XCD-aware split of [0, n) for a grid whose size is a multiple of 8:
+// workgroups are dispatched to the 8 XCDs in turn (workgroup b on XCD
+// b % 8), so each XCD takes one contiguous eighth of the range and its
+// workgroups stride through that eighth together; what they touch at a
+// time then stays in that XCD's own L2.  first/stride/end describe this
+// thread's walk; `base` is where its wavefront starts (for wave-uniform
+// trip counts).
+struct XcdRange {
+    uint64_t first, stride, end, base;
+    __device__ __forceinline__ explicit XcdRange(uint64_t n) {
+        const uint32_t nx = 8u, xcd = blockIdx.x % nx, per_xcd = gridDim.x / nx, lb = blockIdx.x / nx;
+        const uint64_t chunk = (n + nx - 1) / nx;
+        const uint64_t lo = (uint64_t)xcd * chunk;
+        end = lo + chunk < n ? lo + chunk : n;
+        if (lo > end) end = lo;
+        stride = (uint64_t)per_xcd * blockDim.x;
+        base = lo + (uint64_t)lb * blockDim.x + (threadIdx.x & ~(uint64_t)(WAVE - 1));
+        first = base + (threadIdx.x & (WAVE - 1));
+    }
+    // iterations of this wavefront (the same for all its lanes)
+    __device__ __forceinline__ uint64_t wave_iters() const {
+        return end > base ? (end - base + stride - 1) / stride : 0;
+    }
+};
+
 #define GRID_STRIDE(i, n)                                                                \
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)(n); \
          i += (uint64_t)gridDim.x * blockDim.x)

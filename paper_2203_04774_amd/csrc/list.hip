@@ -186,6 +186,9 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
                                                     u64 max_task, u64 reverse, u64 use_hash, u64 use_bucket,
                                                     u64 use_split, u64 force_mode, u64 *acc) {
     __shared__ u64 lds[PB / WAVE];
+    __shared__ u64 mode_items[NMODES];  // heavy items per form, summed in LDS (one global atomic per form)
+    if (threadIdx.x < NMODES) mode_items[threadIdx.x] = 0;
+    __syncthreads();
     u64 hp = 0, staged = 0;
     GRID_STRIDE(p, n) {
         const u64 w = wp[p];
@@ -223,18 +226,20 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             nt = (u32)((w + sl - 1) / sl);
             hp += 1;
             staged += tlen;
-            atomicAdd((unsigned long long *)&acc[10 + md], (unsigned long long)w);  // items per mode
+            atomicAdd((unsigned long long *)&mode_items[md], (unsigned long long)w);
         }
         mode[p] = md;
         ntask[p] = nt;
         slice[p] = sl;
     }
-    hp = block_sum_u64<PB>(hp, lds);
+    hp = block_sum_u64<PB>(hp, lds);  // synchronises: mode_items is complete
     staged = block_sum_u64<PB>(staged, lds);
     if (threadIdx.x == 0 && hp) {
         atomicAdd((unsigned long long *)&acc[7], (unsigned long long)hp);
         atomicAdd((unsigned long long *)&acc[9], (unsigned long long)staged);
     }
+    if (threadIdx.x < NMODES && mode_items[threadIdx.x])
+        atomicAdd((unsigned long long *)&acc[10 + threadIdx.x], (unsigned long long)mode_items[threadIdx.x]);
 }
 
 // Class flag per seed, packed for one scan: low half light, high half heavy.

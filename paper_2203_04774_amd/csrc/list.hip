@@ -360,9 +360,7 @@ struct Out {
         if (pos < cap) d = tri + 3 * pos;
         else if (pos - cap < spill_cap) d = spill + 3 * (pos - cap);
         else return;
-        d[0] = a;
-        d[1] = b;
-        d[2] = c;
+        *reinterpret_cast<uint3 *>(d) = make_uint3(a, b, c);  // one 12-byte store
     }
 };
 
@@ -390,6 +388,41 @@ struct WaveEmitter {
             re = nb + RESERVE;
         }
         if (hit) o.put(pos, a, b, c);
+    }
+
+    // UN pushes at once: one reservation covers the whole group's hits
+    // (at most UN * 64 <= RESERVE, so at most one new block is needed)
+    __device__ __forceinline__ void push_group(const bool (&hit)[UN], const u32 (&a)[UN], const u32 (&b)[UN],
+                                               const u32 (&c)[UN], const Out &o) {
+        if (!EMIT) return;
+        u64 bal[UN];
+        u32 off[UN];
+        u32 tot = 0;
+#pragma unroll
+        for (int j = 0; j < UN; j++) {
+            bal[j] = __ballot(hit[j]);
+            off[j] = tot;
+            tot += (u32)__popcll(bal[j]);
+        }
+        if (!tot) return;
+        const u64 avail = re - rb, old_rb = rb;
+        u64 nb = 0;
+        if (avail >= tot) {
+            rb += tot;
+        } else {
+            if (lane_id() == 0) nb = atomicAdd((unsigned long long *)&o.acc[3], (unsigned long long)RESERVE);
+            nb = uni64(shfl_u64(nb, 0));
+            rb = nb + (tot - avail);
+            re = nb + RESERVE;
+        }
+        const u64 lt = lanemask_lt();
+#pragma unroll
+        for (int j = 0; j < UN; j++) {
+            if (hit[j]) {
+                const u64 q = off[j] + (u64)__popcll(bal[j] & lt);
+                o.put(q < avail ? old_rb + q : nb + (q - avail), a[j], b[j], c[j]);
+            }
+        }
     }
 
     __device__ __forceinline__ void finish(const Out &o) {
@@ -441,17 +474,18 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
         u32 yi[UN];
 #pragma unroll
         for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+        u32 ta[UN], tb[UN], tc[UN];
 #pragma unroll
         for (int j = 0; j < UN; j++) {
-            u32 a = 0, b = 0, c = 0;
+            ta[j] = 0; tb[j] = 0; tc[j] = 0;
             if (h[j]) {
-                a = pv[j]; b = xv[j]; c = yi[j];
-                canon3(a, b, c);
+                ta[j] = pv[j]; tb[j] = xv[j]; tc[j] = yi[j];
+                canon3(ta[j], tb[j], tc[j]);
                 cnt += 1;
-                hsh += tri_digest(a, b, c);
+                hsh += tri_digest(ta[j], tb[j], tc[j]);
             }
-            em.push(h[j], a, b, c, o);
         }
+        em.push_group(h, ta, tb, tc, o);
     };
     if (wb < we) {
         SeedCursor cur(L.cpre, 0, ncap, wb);
@@ -736,17 +770,18 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                     u32 yi[UN];
     #pragma unroll
                     for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+                    u32 ta[UN], tb[UN], tc[UN];
     #pragma unroll
                     for (int j = 0; j < UN; j++) {
-                        u32 xa = 0, xb = 0, xc = 0;
+                        ta[j] = 0; tb[j] = 0; tc[j] = 0;
                         if (h[j]) {
-                            xa = pinv; xb = xv[j]; xc = yi[j];
-                            canon3(xa, xb, xc);
+                            ta[j] = pinv; tb[j] = xv[j]; tc[j] = yi[j];
+                            canon3(ta[j], tb[j], tc[j]);
                             cnt += 1;
-                            hsh += tri_digest(xa, xb, xc);
+                            hsh += tri_digest(ta[j], tb[j], tc[j]);
                         }
-                        em.push(h[j], xa, xb, xc, o);
                     }
+                    em.push_group(h, ta, tb, tc, o);
                 };
                 u64 kb = wb;
                 while (kb < we) {

@@ -127,8 +127,8 @@ __device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u64 &abs) {
     abs = 0;
     if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
         const u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
-        const u64 a = lower_bound_dev<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
-        const u64 b = upper_bound_dev<u32>(sd.S, a, sd.s_hi, tmax);
+        const u64 a = lower_bound_front<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
+        const u64 b = upper_bound_back<u32>(sd.S, a, sd.s_hi, tmax);
         abs = a;
         return (u32)(b - a);
     }

@@ -111,6 +111,32 @@ __device__ __forceinline__ uint64_t upper_bound_dev(const T *a, uint64_t lo, uin
 }
 
 // splitmix64 output function (Steele, Lea, Flood, OOPSLA 2014)
+// The same searches, probing first the few entries next to one end of the
+// range (they share its cache lines) before halving the rest.  A window
+// bound that lies near that end then costs one or two lines instead of a
+// line per halving step; elsewhere it costs the plain search plus those
+// probes.  Results are those of lower_bound_dev / upper_bound_dev.
+template <class T>
+__device__ __forceinline__ uint64_t lower_bound_front(const T *a, uint64_t lo, uint64_t hi, T x) {
+    uint64_t step = 1, prev = lo;
+    while (step <= 8 && lo + step - 1 < hi) {  // a[lo], a[lo+1], a[lo+3], a[lo+7]
+        if (!(a[lo + step - 1] < x)) return lower_bound_dev<T>(a, prev, lo + step - 1, x);
+        prev = lo + step;
+        step <<= 1;
+    }
+    return lower_bound_dev<T>(a, prev, hi, x);
+}
+template <class T>
+__device__ __forceinline__ uint64_t upper_bound_back(const T *a, uint64_t lo, uint64_t hi, T x) {
+    uint64_t step = 1, prev = hi;
+    while (step <= 8 && hi >= lo + step) {  // a[hi-1], a[hi-2], a[hi-4], a[hi-8]
+        if (a[hi - step] <= x) return upper_bound_dev<T>(a, hi - step + 1, prev, x);
+        prev = hi - step;
+        step <<= 1;
+    }
+    return upper_bound_dev<T>(a, lo, prev, x);
+}
+
 __device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;

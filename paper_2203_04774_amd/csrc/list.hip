@@ -154,8 +154,8 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len
                 work += sd.s_hi - sd.s_lo;
                 if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
                     u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
-                    u64 a = lower_bound_dev<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
-                    u64 b = upper_bound_dev<u32>(sd.S, a, sd.s_hi, tmax);
+                    u64 a = lower_bound_front<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
+                    u64 b = upper_bound_back<u32>(sd.S, a, sd.s_hi, tmax);
                     l = (u32)(b - a);
                     abs = a;
                 }

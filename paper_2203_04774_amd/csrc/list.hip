@@ -783,6 +783,17 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                     }
                     em.push_group(h, ta, tb, tc, o);
                 };
+                // the 64-seed window starting at c0: prefixes, scan starts, endpoint ids
+                auto fetch_window = [&](u64 c0, u64 &P, u64 &A, u32 &X, u64 &pend) {
+                    const u64 ci = c0 + lane;
+                    const bool inw = ci < tk.ce;
+                    P = inw ? cpre[ci] : ~0ull;
+                    A = inw ? cabs[ci] : 0ull;
+                    X = inw ? cxinv[ci] : 0u;
+                    pend = uni64((c0 + WAVE <= tk.ce) ? cpre[c0 + WAVE] : ~0ull);
+                };
+                u64 pf_c = ~0ull, pf_P = 0, pf_A = 0, pf_pend = 0;  // prefetched window (pf_c: its first seed)
+                u32 pf_X = 0;
                 u64 kb = wb;
                 while (kb < we) {
                     if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && cur.end >= kb + HG * UN * WAVE &&
@@ -833,24 +844,27 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                     if (kb + UN * WAVE <= we) {
                         // short windows: if the next UN chunks lie in the 64 seeds
                         // starting at the current one, one load of their prefix,
-                        // scan start and endpoint id serves all UN chunks
-                        const u64 ci = cur.c_lo + lane;
-                        const bool inw = ci < tk.ce;
-                        const u64 P = inw ? cpre[ci] : ~0ull;
-                        const u64 pend = (cur.c_lo + WAVE <= tk.ce) ? cpre[cur.c_lo + WAVE] : ~0ull;
+                        // scan start and endpoint id serves all UN chunks.  The
+                        // next window's loads are issued before this group's
+                        // tests, so they overlap (software pipelining).
+                        u64 P, A, pend;
+                        u32 X;
+                        if (pf_c == cur.c_lo) {
+                            P = pf_P; A = pf_A; X = pf_X; pend = pf_pend;
+                        } else {
+                            fetch_window(cur.c_lo, P, A, X, pend);
+                        }
                         if (pend >= kb + UN * WAVE) {
-                            const u64 A = inw ? cabs[ci] : 0ull;
-                            const u32 X = inw ? cxinv[ci] : 0u;
                             // prefixes relative to kb (those at or below kb read as 0)
                             const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
                             u32 y[UN], xv[UN];
                             bool h[UN];
                             int lo_last = 0;
-    #pragma unroll
+#pragma unroll
                             for (int j = 0; j < UN; j++) {
                                 const u32 kr = (u32)(j * WAVE + lane);
                                 int lo = 0;
-    #pragma unroll
+#pragma unroll
                                 for (int st = 32; st > 0; st >>= 1) {
                                     const u32 q = __shfl(Q, lo + st, WAVE);
                                     if (q <= kr) lo += st;
@@ -860,16 +874,19 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                                 xv[j] = __shfl(X, lo, WAVE);
                                 if (j == UN - 1) lo_last = (int)uni32((u32)__shfl(lo, WAVE - 1, WAVE));
                             }
-                            member_all(y, h);
-                            report(y, h, xv);
-                            kb += UN * WAVE;
-                            if (kb < we) {
-                                // seed of item kb: the last lane's seed, or the next one
+                            const u64 kn = kb + UN * WAVE;
+                            if (kn < we) {
+                                // seed of item kn: the last lane's seed, or the next one
                                 u64 c = cur.c_lo + (u64)lo_last;
                                 const u64 pn = (lo_last + 1 < WAVE) ? shfl_u64(P, lo_last + 1) : pend;
-                                if (pn <= kb) c++;
+                                if (pn <= kn) c++;
                                 cur.reset(c);
+                                fetch_window(cur.c_lo, pf_P, pf_A, pf_X, pf_pend);
+                                pf_c = cur.c_lo;
                             }
+                            member_all(y, h);
+                            report(y, h, xv);
+                            kb = kn;
                             continue;
                         }
                     }

@@ -62,7 +62,7 @@ def _load():
     lib.orc_triangle_hash.argtypes = [u32, u32, u32]
     lib.orc_mix64.restype = u64
     lib.orc_mix64.argtypes = [u64]
-    for f in ("orc_degree_order", "orc_split_order"):
+    for f in ("orc_degree_order", "orc_split_order", "orc_coreness", "orc_core_order"):
         getattr(lib, f).restype = ctypes.c_int
         getattr(lib, f).argtypes = [u32, u64, u32p, u32p, u32p]
     _lib = lib
@@ -239,6 +239,26 @@ def split_order(n, src, dst) -> np.ndarray:
     d = np.ascontiguousarray(dst, np.uint32)
     rank = np.zeros(max(n, 1), np.uint32)
     _check(lib.orc_split_order(n, len(s), s, d, rank))
+    return rank[:n]
+
+
+def coreness(n, src, dst) -> np.ndarray:
+    """Coreness of every vertex of the simple graph (Section 1.3)."""
+    lib = _load()
+    s = np.ascontiguousarray(src, np.uint32)
+    d = np.ascontiguousarray(dst, np.uint32)
+    core = np.zeros(max(n, 1), np.uint32)
+    _check(lib.orc_coreness(n, len(s), s, d, core))
+    return core[:n]
+
+
+def core_order(n, src, dst) -> np.ndarray:
+    """Core ordering: non-decreasing coreness, ties by id; returns rank."""
+    lib = _load()
+    s = np.ascontiguousarray(src, np.uint32)
+    d = np.ascontiguousarray(dst, np.uint32)
+    rank = np.zeros(max(n, 1), np.uint32)
+    _check(lib.orc_core_order(n, len(s), s, d, rank))
     return rank[:n]
 
 

@@ -460,3 +460,83 @@ int orc_split_order(u32 n, u64 m_in, const u32 *src, const u32 *dst, u32 *rank) 
     free(order);
     return rc;
 }
+
+/*
+ * Coreness (Section 1.3): c_u is the largest k such that u belongs to a
+ * subgraph in which every vertex has degree at least k.  Computed by
+ * bucket peeling in order of current degree (linear time, as Section 1.3
+ * notes): repeatedly remove a vertex of minimum current degree; its
+ * coreness is the largest minimum degree seen so far.
+ * Core ordering: non-decreasing coreness, ties by id (Section 1.3 fixes
+ * only the coreness order); rank[u] = position.
+ */
+int orc_coreness(u32 n, u64 m_in, const u32 *src, const u32 *dst, u32 *core) {
+    u32 *ident = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    if (!ident) return -2;
+    for (u32 u = 0; u < n; u++) ident[u] = u;
+    graph g;
+    int rc = graph_build(&g, n, m_in, src, dst, ident);
+    free(ident);
+    if (rc) return rc;
+    u32 maxd = 0;
+    u32 *deg = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    unsigned char *gone = (unsigned char *)calloc((size_t)n + 1, 1);
+    for (u32 u = 0; u < n; u++) {
+        deg[u] = (u32)(g.off[u + 1] - g.off[u]);
+        if (deg[u] > maxd) maxd = deg[u];
+    }
+    /* buckets of vertices by current degree, as doubly linked lists */
+    u32 *head = (u32 *)malloc(((size_t)maxd + 1) * sizeof(u32));
+    u32 *next = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    u32 *prev = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    const u32 NIL = 0xffffffffu;
+    for (u32 d = 0; d <= maxd; d++) head[d] = NIL;
+    for (u32 u = n; u-- > 0;) {  /* so that each list starts with its smallest id */
+        prev[u] = NIL;
+        next[u] = head[deg[u]];
+        if (head[deg[u]] != NIL) prev[head[deg[u]]] = u;
+        head[deg[u]] = u;
+    }
+    u32 level = 0, d = 0;
+    for (u32 removed = 0; removed < n; removed++) {
+        while (head[d] == NIL) d++;
+        u32 u = head[d];
+        head[d] = next[u];
+        if (next[u] != NIL) prev[next[u]] = NIL;
+        gone[u] = 1;
+        if (d > level) level = d;
+        core[u] = level;
+        for (u64 j = g.off[u]; j < g.off[u + 1]; j++) {
+            u32 w = g.adj[j];
+            if (gone[w]) continue;
+            /* move w from bucket deg[w] to deg[w] - 1 */
+            u32 dw = deg[w];
+            if (prev[w] != NIL) next[prev[w]] = next[w]; else head[dw] = next[w];
+            if (next[w] != NIL) prev[next[w]] = prev[w];
+            deg[w] = dw - 1;
+            prev[w] = NIL;
+            next[w] = head[dw - 1];
+            if (head[dw - 1] != NIL) prev[head[dw - 1]] = w;
+            head[dw - 1] = w;
+            if (dw - 1 < d) d = dw - 1;
+        }
+    }
+    free(head); free(next); free(prev); free(deg); free(gone);
+    graph_free(&g);
+    return 0;
+}
+
+int orc_core_order(u32 n, u64 m_in, const u32 *src, const u32 *dst, u32 *rank) {
+    u32 *core = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    degkey *k = (degkey *)malloc((size_t)n * sizeof(degkey) + 8);
+    if (!core || !k) { free(core); free(k); return -2; }
+    int rc = orc_coreness(n, m_in, src, dst, core);
+    if (!rc) {
+        for (u32 u = 0; u < n; u++) { k[u].deg = core[u]; k[u].id = u; }
+        qsort(k, n, sizeof(degkey), cmp_degkey);
+        for (u32 i = 0; i < n; i++) rank[k[i].id] = i;
+    }
+    free(core);
+    free(k);
+    return rc;
+}

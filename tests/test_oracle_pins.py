@@ -317,3 +317,66 @@ def test_split_reads_degree_order_from_both_ends(seed):
         lo += 1
         hi -= 1
     assert zig == [int(u) for u in delta]
+
+
+def _coreness_by_definition(n, s, d):
+    """c_u = the largest k such that u lies in the k-core, each k-core found
+    by deleting vertices of degree < k until none is left (Section 1.3)."""
+    nbr = [set() for _ in range(n)]
+    for a, b in zip(s.tolist(), d.tolist()):
+        if a != b:
+            nbr[a].add(b)
+            nbr[b].add(a)
+    core = [0] * n
+    k = 1
+    while True:
+        alive = set(range(n))
+        changed = True
+        while changed:
+            changed = False
+            for u in list(alive):
+                if len(nbr[u] & alive) < k:
+                    alive.discard(u)
+                    changed = True
+        if not alive:
+            return core
+        for u in alive:
+            core[u] = k
+        k += 1
+
+
+def test_coreness_closed_forms():
+    assert oracle.coreness(*G.complete(7)).tolist() == [6] * 7
+    assert oracle.coreness(*G.wheel(10)).tolist() == [3] * 10
+    assert oracle.coreness(*G.grid(4, 6)).tolist() == [2] * 24
+    assert oracle.coreness(*G.star(9)).tolist() == [1] * 9
+    assert oracle.coreness(*G.cycle(11)).tolist() == [2] * 11
+    path = (6, np.arange(5, dtype=np.uint32), np.arange(1, 6, dtype=np.uint32))
+    assert oracle.coreness(*path).tolist() == [1] * 6
+    one = (3, np.array([0], np.uint32), np.array([1], np.uint32))  # vertex 2 isolated
+    assert oracle.coreness(*one).tolist() == [1, 1, 0]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_coreness_matches_definition(seed):
+    n, s, d = rand_graph(1100 + seed)
+    s2, d2 = _with_noise(n, s, d, seed)
+    assert oracle.coreness(n, s2, d2).tolist() == _coreness_by_definition(n, s, d)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_core_order_sorts_by_coreness_then_id(seed):
+    n, s, d = rand_graph(1200 + seed)
+    core = oracle.coreness(n, s, d)
+    order = np.argsort(oracle.core_order(n, s, d))
+    keys = [(int(core[u]), int(u)) for u in order]
+    assert all(keys[i] < keys[i + 1] for i in range(n - 1))
+
+
+def test_coreness_agrees_with_the_generators_peeling():
+    """Two independent peelings (the oracle's buckets, the input generators'
+    heap) give the same coreness on a 20,000-vertex heavy-tailed graph."""
+    import graphgen
+    g = graphgen.chung_lu(20000, 2.1, 12.0, seed=5)
+    _, core = graphgen.core_order(g, return_core=True)
+    assert np.array_equal(oracle.coreness(g.n, g.src, g.dst), core)

@@ -161,10 +161,13 @@ void tl_csr_free(tl_csr *g);
  *                    alternately to the front and the back: the vertex at
  *                    position 2i+1 gets index i+1, the one at 2i index n+1-i
  *                    (1-based; rank = index - 1)
+ *   TL_ORDER_CORE    non-decreasing coreness, ties by increasing vertex id
+ *                    (a core ordering of Section 1.3; coreness computed by
+ *                    level-synchronous peeling on the device)
  * Orient again with the result (tl_orient) to list under it.  Returns after
  * the stream has finished; TL_EINVAL for an unknown kind or a NULL pointer.
  */
-typedef enum { TL_ORDER_DEGREE = 0, TL_ORDER_SPLIT = 1 } tl_order_kind;
+typedef enum { TL_ORDER_DEGREE = 0, TL_ORDER_SPLIT = 1, TL_ORDER_CORE = 2 } tl_order_kind;
 int tl_order(const tl_csr *g, tl_order_kind kind, uint32_t *rank_dev, void *stream);
 
 /*

@@ -47,6 +47,7 @@ def test_orders_match_oracle_with_noisy_input(tl, seed):
     start = rs.permutation(n).astype(np.uint32)      # any orientation gives the same degrees
     assert np.array_equal(gpu_order(tl, n, s, d, "degree", start), oracle.degree_order(n, s, d))
     assert np.array_equal(gpu_order(tl, n, s, d, "split", start), oracle.split_order(n, s, d))
+    assert np.array_equal(gpu_order(tl, n, s, d, "core", start), oracle.core_order(n, s, d))
 
 
 @pytest.mark.parametrize("which", ["rmat12", "chunglu20"])
@@ -54,6 +55,12 @@ def test_orders_match_oracle_on_workloads(tl, which):
     g = graphgen.config_rmat12() if which == "rmat12" else graphgen.config_chunglu20()
     assert np.array_equal(gpu_order(tl, g.n, g.src, g.dst, "degree"), oracle.degree_order(g.n, g.src, g.dst))
     assert np.array_equal(gpu_order(tl, g.n, g.src, g.dst, "split"), oracle.split_order(g.n, g.src, g.dst))
+    assert np.array_equal(gpu_order(tl, g.n, g.src, g.dst, "core"), oracle.core_order(g.n, g.src, g.dst))
+
+
+def test_core_closed_forms(tl):
+    for (n, s, d) in [G.complete(9), G.wheel(12), G.grid(5, 7), G.star(10), G.cycle(13)]:
+        assert np.array_equal(gpu_order(tl, n, s, d, "core"), oracle.core_order(n, s, d))
 
 
 def test_small_and_empty(tl):
@@ -61,9 +68,10 @@ def test_small_and_empty(tl):
         s = np.zeros(0, np.uint32)
         assert np.array_equal(gpu_order(tl, n, s, s, "degree"), np.arange(n, dtype=np.uint32))
         assert np.array_equal(gpu_order(tl, n, s, s, "split"), oracle.split_order(n, s, s))
+        assert np.array_equal(gpu_order(tl, n, s, s, "core"), np.arange(n, dtype=np.uint32))
 
 
-@pytest.mark.parametrize("kind,algo", [("split", "A+-"), ("degree", "A++")])
+@pytest.mark.parametrize("kind,algo", [("split", "A+-"), ("degree", "A++"), ("core", "A+-")])
 def test_full_listing_on_device(tl, kind, algo):
     """Edges -> orientation by id -> ordering on the device -> orientation
     by that ordering -> listing; equal to the oracle under the oracle's
@@ -78,7 +86,8 @@ def test_full_listing_on_device(tl, kind, algo):
         c = tl.cost(g1, algo)
     finally:
         g1.free()
-    r = oracle.split_order(g.n, g.src, g.dst) if kind == "split" else oracle.degree_order(g.n, g.src, g.dst)
+    r = {"split": oracle.split_order, "degree": oracle.degree_order, "core": oracle.core_order}[kind](
+        g.n, g.src, g.dst)
     L = oracle.list_triangles(g.n, g.src, g.dst, r, algo, want_triangles=False)
     assert (got.count, got.hash, got.work) == (L.count, L.hash, L.work)
     assert c == oracle.cost(g.n, g.src, g.dst, r).for_algo(algo)
@@ -90,7 +99,7 @@ def test_bad_kind(tl):
     g = tl.orient(n, dev(s), dev(d), dev(np.arange(n, dtype=np.uint32)))
     try:
         out = dev(np.zeros(n, np.uint32))
-        rc = tl.raw_lib().tl_order(g.handle, 7, ctypes.c_void_p(out.data_ptr()), None)
+        rc = tl.raw_lib().tl_order(g.handle, 9, ctypes.c_void_p(out.data_ptr()), None)
         assert rc == tl.tl.TL_EINVAL
     finally:
         g.free()

@@ -392,9 +392,10 @@ def bench_orders(args):
     """Orderings on the GPU and the cost-time relation (Figure 3's
     experiment): on the Chung-Lu 2^20 graph, (1) the full listing with the
     ordering computed on the device -- orient by id, tl_order, orient by the
-    ordering, list -- for degree/A++ and Split/A+-, and (2) for each of
+    ordering, list -- and (2) for each of
     several orderings and both forms, the paper's cost C against the
-    listing time (count and digest only)."""
+    listing time (count and digest only).  Full listings: degree/A++,
+    Split/A+- and core/A+-."""
     import ctypes
 
     import torch
@@ -421,7 +422,7 @@ def bench_orders(args):
         return float(np.median(ts)) * 1e3, out
 
     full = {}
-    for kind, algo in (("degree", "A++"), ("split", "A+-")):
+    for kind, algo in (("degree", "A++"), ("split", "A+-"), ("core", "A+-")):
         def run():
             g0 = tl.orient(g.n, src, dst, ident)
             t1 = time.perf_counter()

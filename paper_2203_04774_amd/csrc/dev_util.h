@@ -18,6 +18,10 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
 // this lane's wavefront within its workgroup
 __device__ __forceinline__ uint32_t wave_id() { return uni32(threadIdx.x / WAVE); }
 
+// Orders a wavefront's own LDS accesses in the compiler (the hardware
+// already runs one wavefront's LDS operations in issue order).
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     int l = lane_id();
     return l ? (~0ull >> (64 - l)) : 0ull;

@@ -43,8 +43,11 @@ constexpr int HB = 1024;       // threads per block, heavy-pivot kernel
 constexpr u32 LDS_BYTES = 128 * 1024;
 constexpr u32 LDS_WORDS = LDS_BYTES / 4;
 constexpr u64 LDS_BITS = (u64)LDS_BYTES * 8;
-constexpr u32 LOW_WORDS = 8160;  // SPLIT: list entries below the bitmap's window kept in LDS (160 KB in all)
-constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + LOW_WORDS * 4;
+constexpr u32 LOW_WORDS = 6112;  // SPLIT: list entries below the bitmap's window kept in LDS
+constexpr u32 STAGE_WORDS = 2 * WAVE;  // per wavefront: 64 staged (endpoint, third vertex) pairs
+// bitmap + low entries + staging for every wavefront: 160 KB in all
+constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + LOW_WORDS * 4 + (HB / WAVE) * STAGE_WORDS * 4;
+static_assert(HEAVY_LDS_BYTES + 64 <= 160 * 1024, "heavy kernel LDS");
 // Tunable launch parameters (defaults; tl_set_tuning or TL_TUNE_* env vars).
 struct Tuning {
     // defaults from sweeps on the Chung-Lu 2^20 workload (random and degree
@@ -631,6 +634,10 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         }
         const u64 ts = tk.mode == MODE_SPLIT ? uni64(split_at) : t0;
         u32 *low = lds + LDS_WORDS;  // SPLIT: T[t0, ts) when it fits
+        uint2 *stage = reinterpret_cast<uint2 *>(lds + LDS_WORDS + LOW_WORDS + (u32)wid * STAGE_WORDS);
+        // seed-start flags of the short-window walk, in the staging area's
+        // first 256 bytes (the two are used one after the other)
+        unsigned char *flag = reinterpret_cast<unsigned char *>(stage);
         const bool low_lds = tk.mode == MODE_SPLIT && ts - t0 <= LOW_WORDS;
         if (low_lds) {
             for (u64 i = t0 + threadIdx.x; i < ts; i += blockDim.x) low[i - t0] = pa[i];
@@ -726,15 +733,24 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                 // membership of UN elements at once (interleaved where it is a search)
                 auto member_all = [&](const u32 (&y)[UN], bool (&h)[UN]) {
                     if (MD == MODE_SPLIT) {
-                        // the entries below the bitmap's window: interleaved global searches
-                        u64 lo[UN], hi[UN];
-                        const u64 base = low_lds ? 0 : t0, top = low_lds ? ts - t0 : ts;
+                        // the entries below the bitmap's window: interleaved searches,
+                        // skipped when no lane has such an element (the usual case)
+                        bool below = false;
     #pragma unroll
-                        for (int j = 0; j < UN; j++) {
-                            lo[j] = base;
-                            hi[j] = y[j] >= wlo ? base : top;
+                        for (int j = 0; j < UN; j++) below |= y[j] < wlo;
+                        if (__ballot(below)) {
+                            u64 lo[UN], hi[UN];
+                            const u64 base = low_lds ? 0 : t0, top = low_lds ? ts - t0 : ts;
+    #pragma unroll
+                            for (int j = 0; j < UN; j++) {
+                                lo[j] = base;
+                                hi[j] = y[j] >= wlo ? base : top;
+                            }
+                            member_multi_var(low_lds ? low : pa, lo, hi, y, h);
+                        } else {
+    #pragma unroll
+                            for (int j = 0; j < UN; j++) h[j] = false;
                         }
-                        member_multi_var(low_lds ? low : pa, lo, hi, y, h);
     #pragma unroll
                         for (int j = 0; j < UN; j++) {
                             if (y[j] >= wlo) {
@@ -761,27 +777,39 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                         for (int j = 0; j < UN; j++) h[j] = member(y[j]);
                     }
                 };
-                // listed triangles of a group: yi gathers issued together
+                // listed triangles of a group: the hits of all UN chunks are
+                // first packed into consecutive lanes (through this
+                // wavefront's LDS staging area, 64 at a time), so that the id
+                // lookup, canonical order, digest and store run once per 64
+                // triangles rather than once per chunk that holds any
                 auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
-                    bool any = false;
-    #pragma unroll
-                    for (int j = 0; j < UN; j++) any |= h[j];
-                    if (!__ballot(any)) return;
-                    u32 yi[UN];
-    #pragma unroll
-                    for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
-                    u32 ta[UN], tb[UN], tc[UN];
+                    u64 bal[UN];
+                    u32 q[UN], tot = 0;
+                    const u64 lt = lanemask_lt();
     #pragma unroll
                     for (int j = 0; j < UN; j++) {
-                        ta[j] = 0; tb[j] = 0; tc[j] = 0;
-                        if (h[j]) {
-                            ta[j] = pinv; tb[j] = xv[j]; tc[j] = yi[j];
-                            canon3(ta[j], tb[j], tc[j]);
-                            cnt += 1;
-                            hsh += tri_digest(ta[j], tb[j], tc[j]);
-                        }
+                        bal[j] = __ballot(h[j]);
+                        q[j] = tot + (u32)__popcll(bal[j] & lt);  // position among the group's hits
+                        tot += (u32)__popcll(bal[j]);
                     }
-                    em.push_group(h, ta, tb, tc, o);
+                    for (u32 r0 = 0; r0 < tot; r0 += WAVE) {
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            if (h[j] && q[j] - r0 < (u32)WAVE) stage[q[j] - r0] = make_uint2(xv[j], y[j]);
+                        }
+                        wave_lds_fence();
+                        const bool v = (u32)lane < tot - r0;
+                        u32 ta = 0, tb = 0, tc = 0;
+                        if (v) {
+                            const uint2 e = stage[lane];
+                            ta = pinv; tb = e.x; tc = g.inv[e.y];
+                            canon3(ta, tb, tc);
+                            cnt += 1;
+                            hsh += tri_digest(ta, tb, tc);
+                        }
+                        wave_lds_fence();
+                        em.push(v, ta, tb, tc, o);
+                    }
                 };
                 // the 64-seed window starting at c0: prefixes, scan starts, endpoint ids
                 auto fetch_window = [&](u64 c0, u64 &P, u64 &A, u32 &X, u64 &pend) {
@@ -855,25 +883,32 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                             fetch_window(cur.c_lo, P, A, X, pend);
                         }
                         if (pend >= kb + UN * WAVE) {
-                            // prefixes relative to kb (those at or below kb read as 0)
+                            // Seed of each item: every seed marks the item it
+                            // starts at (relative to kb) in this wavefront's
+                            // LDS flags; a ballot of the flags of each chunk
+                            // and a count of the set flags up to a lane give
+                            // that lane's seed within the window.  Item k of
+                            // seed c sits at scan index (A - P)[c] + k.
                             const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                            const u64 D = A - P;
+                            reinterpret_cast<u32 *>(flag)[lane] = 0u;
+                            wave_lds_fence();
+                            if (Q < (u32)(UN * WAVE)) flag[Q] = 1;  // the first seed marks 0
+                            wave_lds_fence();
                             u32 y[UN], xv[UN];
                             bool h[UN];
-                            int lo_last = 0;
+                            u32 started = 0;  // seeds started in the chunks before j
 #pragma unroll
                             for (int j = 0; j < UN; j++) {
-                                const u32 kr = (u32)(j * WAVE + lane);
-                                int lo = 0;
-#pragma unroll
-                                for (int st = 32; st > 0; st >>= 1) {
-                                    const u32 q = __shfl(Q, lo + st, WAVE);
-                                    if (q <= kr) lo += st;
-                                }
-                                const u64 rel = (kb + kr) - shfl_u64(P, lo);
-                                y[j] = SA[shfl_u64(A, lo) + rel];
+                                const u32 f = flag[j * WAVE + lane];
+                                const u64 S = __ballot(f != 0u);
+                                const int lo = (int)(started + f + (u32)__popcll(S & lanemask_lt())) - 1;
+                                started += (u32)__popcll(S);
+                                y[j] = SA[shfl_u64(D, lo) + (kb + (u64)(j * WAVE + lane))];
                                 xv[j] = __shfl(X, lo, WAVE);
-                                if (j == UN - 1) lo_last = (int)uni32((u32)__shfl(lo, WAVE - 1, WAVE));
                             }
+                            wave_lds_fence();
+                            const int lo_last = (int)started - 1;
                             const u64 kn = kb + UN * WAVE;
                             if (kn < we) {
                                 // seed of item kn: the last lane's seed, or the next one

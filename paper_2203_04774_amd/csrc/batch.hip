@@ -277,25 +277,37 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
     const u32 *SA = Form<ALGO>::scan_adj(g);
     const u32 *T = Form<ALGO>::piv_adj(g);
     GraphAcc ga;
+    // per wavefront: 64 staged hits (pivot, endpoint, third vertex, graph);
+    // its first 256 bytes also hold the short-window walk's seed-start flags
+    __shared__ uint4 stage_all[(BB / WAVE) * WAVE];
+    uint4 *stage = stage_all + wave_id() * WAVE;
+    unsigned char *flag = reinterpret_cast<unsigned char *>(stage);
+    // the hits of a group packed into consecutive lanes, 64 at a time
     auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&pv)[UN], const u32 (&xv)[UN],
                       const u32 (&gv)[UN]) {
-        bool any = false;
-#pragma unroll
-        for (int j = 0; j < UN; j++) any |= h[j];
-        if (!__ballot(any)) return;
-        u32 yi[UN], vb[UN];
+        u64 bal[UN];
+        u32 q[UN], tot = 0;
+        const u64 lt = lanemask_lt();
 #pragma unroll
         for (int j = 0; j < UN; j++) {
-            yi[j] = h[j] ? g.inv[y[j]] : 0u;
-            vb[j] = h[j] ? vbase[gv[j]] : 0u;
+            bal[j] = __ballot(h[j]);
+            q[j] = tot + (u32)__popcll(bal[j] & lt);
+            tot += (u32)__popcll(bal[j]);
         }
+        for (u32 r0 = 0; r0 < tot; r0 += WAVE) {
 #pragma unroll
-        for (int j = 0; j < UN; j++) {
-            if (h[j]) {
-                u32 a = pv[j] - vb[j], b = xv[j] - vb[j], c = yi[j] - vb[j];
-                canon3(a, b, c);
-                ga.add(gv[j], tri_digest(a, b, c), pg);
+            for (int j = 0; j < UN; j++) {
+                if (h[j] && q[j] - r0 < (u32)WAVE) stage[q[j] - r0] = make_uint4(pv[j], xv[j], y[j], gv[j]);
             }
+            wave_lds_fence();
+            if ((u32)lane < tot - r0) {
+                const uint4 e = stage[lane];
+                const u32 vb = vbase[e.w];
+                u32 a = e.x - vb, b = e.y - vb, c = g.inv[e.z] - vb;
+                canon3(a, b, c);
+                ga.add(e.w, tri_digest(a, b, c), pg);
+            }
+            wave_lds_fence();
         }
     };
     if (wb < we) {
@@ -328,28 +340,20 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
                     const u64 A = inw ? L.cabs[ci] : 0ull;
                     const u32 X = inw ? L.cxinv[ci] : 0u, PI = inw ? L.cpinv[ci] : 0u, GI = inw ? L.cgid[ci] : 0u;
                     const u32 TL = inw ? L.ctlo[ci] : 0u, TH = inw ? L.cthi[ci] : 0u;
-                    const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                    const u64 D = A - P;  // item k of seed c is at scan index D[c] + k
+                    int lo[UN];
+                    const int lo_last = locate_short(P, kb, flag, lo);
                     u32 y[UN], pv[UN], xv[UN], gv[UN];
                     u64 tl[UN], th[UN];
                     bool h[UN];
-                    int lo_last = 0;
 #pragma unroll
                     for (int j = 0; j < UN; j++) {
-                        const u32 kr = (u32)(j * WAVE + lane);
-                        int lo = 0;
-#pragma unroll
-                        for (int st = 32; st > 0; st >>= 1) {
-                            const u32 q = __shfl(Q, lo + st, WAVE);
-                            if (q <= kr) lo += st;
-                        }
-                        const u64 rel = (kb + kr) - shfl_u64(P, lo);
-                        y[j] = SA[shfl_u64(A, lo) + rel];
-                        xv[j] = __shfl(X, lo, WAVE);
-                        pv[j] = __shfl(PI, lo, WAVE);
-                        gv[j] = __shfl(GI, lo, WAVE);
-                        tl[j] = __shfl(TL, lo, WAVE);
-                        th[j] = __shfl(TH, lo, WAVE);
-                        if (j == UN - 1) lo_last = (int)uni32((u32)__shfl(lo, WAVE - 1, WAVE));
+                        y[j] = SA[shfl_u64(D, lo[j]) + (kb + (u64)(j * WAVE + lane))];
+                        xv[j] = __shfl(X, lo[j], WAVE);
+                        pv[j] = __shfl(PI, lo[j], WAVE);
+                        gv[j] = __shfl(GI, lo[j], WAVE);
+                        tl[j] = __shfl(TL, lo[j], WAVE);
+                        th[j] = __shfl(TH, lo[j], WAVE);
                     }
                     member_multi_var(T, tl, th, y, h);
                     report(y, h, pv, xv, gv);
@@ -395,7 +399,12 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
                                                 u32 N, const u32 *gid, const u32 *vbase, u64 *queue, u64 *pg) {
     extern __shared__ u32 bits[];
     __shared__ u64 next;
+    // per wavefront: 64 staged hits (endpoint, third vertex); its first 256
+    // bytes also hold the short-window walk's seed-start flags
+    __shared__ uint2 stage_all[(HBS / WAVE) * WAVE];
     const int lane = lane_id(), wid = (int)wave_id(), nwv = HBS / WAVE;
+    uint2 *stage = stage_all + wid * WAVE;
+    unsigned char *flag = reinterpret_cast<unsigned char *>(stage);
     const u64 nheavy = hpre[N];
     const u64 nlight = pos[g.m] & 0xffffffffull;
     const u64 *so = Form<ALGO>::seed_off(g);
@@ -433,22 +442,31 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
             const u32 v = y - tmin;
             return y >= tmin && y <= tmax && ((bits[v >> 5] >> (v & 31)) & 1u);
         };
+        // the hits of a group packed into consecutive lanes, 64 at a time
         auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
-            bool any = false;
-#pragma unroll
-            for (int j = 0; j < UN; j++) any |= h[j];
-            if (!__ballot(any)) return;
-            u32 yi[UN];
-#pragma unroll
-            for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
+            u64 bal[UN];
+            u32 q[UN], tot = 0;
+            const u64 lt = lanemask_lt();
 #pragma unroll
             for (int j = 0; j < UN; j++) {
-                if (h[j]) {
-                    u32 x0 = pl, x1 = xv[j] - vb, x2 = yi[j] - vb;
+                bal[j] = __ballot(h[j]);
+                q[j] = tot + (u32)__popcll(bal[j] & lt);
+                tot += (u32)__popcll(bal[j]);
+            }
+            for (u32 r0 = 0; r0 < tot; r0 += WAVE) {
+#pragma unroll
+                for (int j = 0; j < UN; j++) {
+                    if (h[j] && q[j] - r0 < (u32)WAVE) stage[q[j] - r0] = make_uint2(xv[j], y[j]);
+                }
+                wave_lds_fence();
+                if ((u32)lane < tot - r0) {
+                    const uint2 e = stage[lane];
+                    u32 x0 = pl, x1 = e.x - vb, x2 = g.inv[e.y] - vb;
                     canon3(x0, x1, x2);
                     cnt += 1;
                     hsh += tri_digest(x0, x1, x2);
                 }
+                wave_lds_fence();
             }
         };
         if (wb < we) {
@@ -481,23 +499,15 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
                     if (pend >= kb + UN * WAVE) {
                         const u64 A = inw ? L.cabs[ci] : 0ull;
                         const u32 X = inw ? L.cxinv[ci] : 0u;
-                        const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                        const u64 D = A - P;  // item k of seed c is at scan index D[c] + k
+                        int lo[UN];
+                        const int lo_last = locate_short(P, kb, flag, lo);
                         u32 y[UN], xv[UN];
                         bool h[UN];
-                        int lo_last = 0;
 #pragma unroll
                         for (int j = 0; j < UN; j++) {
-                            const u32 kr = (u32)(j * WAVE + lane);
-                            int lo = 0;
-#pragma unroll
-                            for (int st = 32; st > 0; st >>= 1) {
-                                const u32 q = __shfl(Q, lo + st, WAVE);
-                                if (q <= kr) lo += st;
-                            }
-                            const u64 rel = (kb + kr) - shfl_u64(P, lo);
-                            y[j] = SA[shfl_u64(A, lo) + rel];
-                            xv[j] = __shfl(X, lo, WAVE);
-                            if (j == UN - 1) lo_last = (int)uni32((u32)__shfl(lo, WAVE - 1, WAVE));
+                            y[j] = SA[shfl_u64(D, lo[j]) + (kb + (u64)(j * WAVE + lane))];
+                            xv[j] = __shfl(X, lo[j], WAVE);
                         }
 #pragma unroll
                         for (int j = 0; j < UN; j++) h[j] = member(y[j]);

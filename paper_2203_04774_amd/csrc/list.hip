@@ -393,41 +393,6 @@ struct WaveEmitter {
         if (hit) o.put(pos, a, b, c);
     }
 
-    // UN pushes at once: one reservation covers the whole group's hits
-    // (at most UN * 64 <= RESERVE, so at most one new block is needed)
-    __device__ __forceinline__ void push_group(const bool (&hit)[UN], const u32 (&a)[UN], const u32 (&b)[UN],
-                                               const u32 (&c)[UN], const Out &o) {
-        if (!EMIT) return;
-        u64 bal[UN];
-        u32 off[UN];
-        u32 tot = 0;
-#pragma unroll
-        for (int j = 0; j < UN; j++) {
-            bal[j] = __ballot(hit[j]);
-            off[j] = tot;
-            tot += (u32)__popcll(bal[j]);
-        }
-        if (!tot) return;
-        const u64 avail = re - rb, old_rb = rb;
-        u64 nb = 0;
-        if (avail >= tot) {
-            rb += tot;
-        } else {
-            if (lane_id() == 0) nb = atomicAdd((unsigned long long *)&o.acc[3], (unsigned long long)RESERVE);
-            nb = uni64(shfl_u64(nb, 0));
-            rb = nb + (tot - avail);
-            re = nb + RESERVE;
-        }
-        const u64 lt = lanemask_lt();
-#pragma unroll
-        for (int j = 0; j < UN; j++) {
-            if (hit[j]) {
-                const u64 q = off[j] + (u64)__popcll(bal[j] & lt);
-                o.put(q < avail ? old_rb + q : nb + (q - avail), a[j], b[j], c[j]);
-            }
-        }
-    }
-
     __device__ __forceinline__ void finish(const Out &o) {
         if (!EMIT || re == rb) return;
         if (lane_id() == 0) {
@@ -469,26 +434,41 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
     const u32 *T = Form<ALGO>::piv_adj(g);
     WaveEmitter<EMIT> em;
     u64 cnt = 0, hsh = 0;
+    // per wavefront: 64 staged hits (pivot, endpoint, third vertex); its
+    // first 256 bytes also hold the seed-start flags of the short-window walk
+    __shared__ uint4 stage_all[(PB / WAVE) * WAVE];
+    uint4 *stage = stage_all + wave_id() * WAVE;
+    unsigned char *flag = reinterpret_cast<unsigned char *>(stage);
+    // the hits of a group packed into consecutive lanes, 64 at a time, before
+    // the id lookup, canonical order, digest and store
     auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&pv)[UN], const u32 (&xv)[UN]) {
-        bool any = false;
-#pragma unroll
-        for (int j = 0; j < UN; j++) any |= h[j];
-        if (!__ballot(any)) return;
-        u32 yi[UN];
-#pragma unroll
-        for (int j = 0; j < UN; j++) yi[j] = h[j] ? g.inv[y[j]] : 0u;
-        u32 ta[UN], tb[UN], tc[UN];
+        u64 bal[UN];
+        u32 q[UN], tot = 0;
+        const u64 lt = lanemask_lt();
 #pragma unroll
         for (int j = 0; j < UN; j++) {
-            ta[j] = 0; tb[j] = 0; tc[j] = 0;
-            if (h[j]) {
-                ta[j] = pv[j]; tb[j] = xv[j]; tc[j] = yi[j];
-                canon3(ta[j], tb[j], tc[j]);
-                cnt += 1;
-                hsh += tri_digest(ta[j], tb[j], tc[j]);
-            }
+            bal[j] = __ballot(h[j]);
+            q[j] = tot + (u32)__popcll(bal[j] & lt);
+            tot += (u32)__popcll(bal[j]);
         }
-        em.push_group(h, ta, tb, tc, o);
+        for (u32 r0 = 0; r0 < tot; r0 += WAVE) {
+#pragma unroll
+            for (int j = 0; j < UN; j++) {
+                if (h[j] && q[j] - r0 < (u32)WAVE) stage[q[j] - r0] = make_uint4(pv[j], xv[j], y[j], 0u);
+            }
+            wave_lds_fence();
+            const bool v = (u32)lane < tot - r0;
+            u32 ta = 0, tb = 0, tc = 0;
+            if (v) {
+                const uint4 e = stage[lane];
+                ta = e.x; tb = e.y; tc = g.inv[e.z];
+                canon3(ta, tb, tc);
+                cnt += 1;
+                hsh += tri_digest(ta, tb, tc);
+            }
+            wave_lds_fence();
+            em.push(v, ta, tb, tc, o);
+        }
     };
     if (wb < we) {
         SeedCursor cur(L.cpre, 0, ncap, wb);
@@ -522,27 +502,20 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
                     const u64 A = inw ? L.cabs[ci] : 0ull;
                     const u32 X = inw ? L.cxinv[ci] : 0u, PI = inw ? L.cpinv[ci] : 0u;
                     const u32 TL = inw ? L.ctlo[ci] : 0u, TH = inw ? L.cthi[ci] : 0u;
-                    const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                    // item k of seed c is at scan index (A - P)[c] + k
+                    const u64 D = A - P;
+                    int lo[UN];
+                    const int lo_last = locate_short(P, kb, flag, lo);
                     u32 y[UN], pv[UN], xv[UN];
                     u64 tl[UN], th[UN];
                     bool h[UN];
-                    int lo_last = 0;
 #pragma unroll
                     for (int j = 0; j < UN; j++) {
-                        const u32 kr = (u32)(j * WAVE + lane);
-                        int lo = 0;
-#pragma unroll
-                        for (int st = 32; st > 0; st >>= 1) {
-                            const u32 q = __shfl(Q, lo + st, WAVE);
-                            if (q <= kr) lo += st;
-                        }
-                        const u64 rel = (kb + kr) - shfl_u64(P, lo);
-                        y[j] = SA[shfl_u64(A, lo) + rel];
-                        xv[j] = __shfl(X, lo, WAVE);
-                        pv[j] = __shfl(PI, lo, WAVE);
-                        tl[j] = __shfl(TL, lo, WAVE);
-                        th[j] = __shfl(TH, lo, WAVE);
-                        if (j == UN - 1) lo_last = (int)uni32((u32)__shfl(lo, WAVE - 1, WAVE));
+                        y[j] = SA[shfl_u64(D, lo[j]) + (kb + (u64)(j * WAVE + lane))];
+                        xv[j] = __shfl(X, lo[j], WAVE);
+                        pv[j] = __shfl(PI, lo[j], WAVE);
+                        tl[j] = __shfl(TL, lo[j], WAVE);
+                        th[j] = __shfl(TH, lo[j], WAVE);
                     }
                     member_multi_var(T, tl, th, y, h);
                     report(y, h, pv, xv);
@@ -883,32 +856,17 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                             fetch_window(cur.c_lo, P, A, X, pend);
                         }
                         if (pend >= kb + UN * WAVE) {
-                            // Seed of each item: every seed marks the item it
-                            // starts at (relative to kb) in this wavefront's
-                            // LDS flags; a ballot of the flags of each chunk
-                            // and a count of the set flags up to a lane give
-                            // that lane's seed within the window.  Item k of
-                            // seed c sits at scan index (A - P)[c] + k.
-                            const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+                            // item k of seed c is at scan index (A - P)[c] + k
                             const u64 D = A - P;
-                            reinterpret_cast<u32 *>(flag)[lane] = 0u;
-                            wave_lds_fence();
-                            if (Q < (u32)(UN * WAVE)) flag[Q] = 1;  // the first seed marks 0
-                            wave_lds_fence();
+                            int lo[UN];
+                            const int lo_last = locate_short(P, kb, flag, lo);
                             u32 y[UN], xv[UN];
                             bool h[UN];
-                            u32 started = 0;  // seeds started in the chunks before j
 #pragma unroll
                             for (int j = 0; j < UN; j++) {
-                                const u32 f = flag[j * WAVE + lane];
-                                const u64 S = __ballot(f != 0u);
-                                const int lo = (int)(started + f + (u32)__popcll(S & lanemask_lt())) - 1;
-                                started += (u32)__popcll(S);
-                                y[j] = SA[shfl_u64(D, lo) + (kb + (u64)(j * WAVE + lane))];
-                                xv[j] = __shfl(X, lo, WAVE);
+                                y[j] = SA[shfl_u64(D, lo[j]) + (kb + (u64)(j * WAVE + lane))];
+                                xv[j] = __shfl(X, lo[j], WAVE);
                             }
-                            wave_lds_fence();
-                            const int lo_last = (int)started - 1;
                             const u64 kn = kb + UN * WAVE;
                             if (kn < we) {
                                 // seed of item kn: the last lane's seed, or the next one

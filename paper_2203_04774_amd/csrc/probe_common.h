@@ -115,6 +115,32 @@ struct SeedCursor {
 
 constexpr int UN = 4;  // chunks per iteration when they share one seed window
 
+// Seeds of the UN chunks of 64 items from kb on, when they all lie in the 64
+// consecutive seeds whose work prefixes P the lanes hold (lane 0's seed
+// holds item kb).  Every seed marks the item it starts at, relative to kb,
+// in the wavefront's 256 bytes of LDS flags; for chunk j, a ballot of the
+// flags and a count of the set ones up to a lane give lo[j], the lane
+// (seed) that holds item kb + 64 j + lane.  Returns the seed of the last
+// item.  Compacted seeds have non-empty windows, so starts are distinct.
+__device__ __forceinline__ int locate_short(u64 P, u64 kb, unsigned char *flag, int (&lo)[UN]) {
+    const int lane = lane_id();
+    const u32 Q = P <= kb ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+    reinterpret_cast<u32 *>(flag)[lane] = 0u;
+    wave_lds_fence();
+    if (Q < (u32)(UN * WAVE)) flag[Q] = 1;  // the first seed marks item 0
+    wave_lds_fence();
+    u32 started = 0;  // seeds started in the chunks before j
+#pragma unroll
+    for (int j = 0; j < UN; j++) {
+        const u32 f = flag[j * WAVE + lane];
+        const u64 S = __ballot(f != 0u);
+        lo[j] = (int)(started + f + (u32)__popcll(S & lanemask_lt())) - 1;
+        started += (u32)__popcll(S);
+    }
+    wave_lds_fence();
+    return (int)started - 1;
+}
+
 // UN independent branchless membership tests of y[j] in the sorted list
 // T[lo, hi) (the same list for all j), so their loads overlap.
 __device__ __forceinline__ void member_multi(const u32 *T, u64 lo, u64 hi, const u32 (&y)[UN], bool (&hit)[UN]) {

@@ -65,6 +65,8 @@ def _load():
     for f in ("orc_degree_order", "orc_split_order", "orc_coreness", "orc_core_order"):
         getattr(lib, f).restype = ctypes.c_int
         getattr(lib, f).argtypes = [u32, u64, u32p, u32p, u32p]
+    lib.orc_check_order.restype = ctypes.c_int
+    lib.orc_check_order.argtypes = [u32, u64, u32p, u32p, u32p, ctypes.POINTER(ctypes.c_uint8)]
     _lib = lib
     return lib
 
@@ -260,6 +262,21 @@ def core_order(n, src, dst) -> np.ndarray:
     rank = np.zeros(max(n, 1), np.uint32)
     _check(lib.orc_core_order(n, len(s), s, d, rank))
     return rank[:n]
+
+
+def check_order(n, src, dst, with_side=False):
+    """Check ordering (Section 3.3.2): vertices by non-increasing degree
+    (the degree ordering read backwards), each put right after the
+    beginning block or right before the end block, whichever gives it the
+    smaller C+- share (ties: beginning).  Returns rank, or (rank, side)
+    with side[u] = 0 for beginning, 1 for end."""
+    lib = _load()
+    s = np.ascontiguousarray(src, np.uint32)
+    d = np.ascontiguousarray(dst, np.uint32)
+    rank = np.zeros(max(n, 1), np.uint32)
+    side = np.zeros(max(n, 1), np.uint8)
+    _check(lib.orc_check_order(n, len(s), s, d, rank, side.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+    return (rank[:n], side[:n]) if with_side else rank[:n]
 
 
 def triangle_hash(a: int, b: int, c: int) -> int:

@@ -35,6 +35,9 @@
  * splitmix64's published output sequence and the sum against hashing the
  * brute-force triangle set.
  *
+ * Orderings (degree, Split, coreness and core ordering, Check) are stated
+ * beside their functions below, each with the passage it follows.
+ *
  * Restricting the outer loop to pivots whose rank lies in [lo, hi) lists
  * exactly the triangles whose pivot (w for A++, u for A+-, v for A--) has
  * such a rank;
@@ -538,5 +541,57 @@ int orc_core_order(u32 n, u64 m_in, const u32 *src, const u32 *dst, u32 *rank) {
     }
     free(core);
     free(k);
+    return rc;
+}
+
+/*
+ * Check (Section 3.3.2): vertices are taken by non-increasing degree (the
+ * degree ordering read backwards, as for Split).  Before u is placed, its
+ * neighbours split into N_b (placed at the beginning), N_e (placed at the
+ * end) and N_? (not placed yet).  Placed right after the beginning block,
+ * u costs C_b = |N_b| (|N_e| + |N_?|); placed right before the end block,
+ * C_e = (|N_b| + |N_?|) |N_e|.  The cheaper side is taken; on equal costs
+ * the beginning (a reading: the paper does not say).  Beginning positions
+ * are handed out 1, 2, ... and end positions n, n-1, ...; rank[u] =
+ * position - 1.  side[u] (optional) = 0 for beginning, 1 for end.
+ */
+int orc_check_order(u32 n, u64 m_in, const u32 *src, const u32 *dst, u32 *rank, unsigned char *side) {
+    u32 *order = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    u32 *ident = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    unsigned char *where = (unsigned char *)malloc((size_t)n + 1);  /* 0 unplaced, 1 beginning, 2 end */
+    if (!order || !ident || !where) { free(order); free(ident); free(where); return -2; }
+    int rc = degree_positions(n, m_in, src, dst, order);
+    graph g;
+    if (!rc) {
+        for (u32 u = 0; u < n; u++) ident[u] = u;
+        rc = graph_build(&g, n, m_in, src, dst, ident);
+    }
+    if (!rc) {
+        memset(where, 0, (size_t)n + 1);
+        u32 n_begin = 0, n_end = 0;
+        for (u32 i = 0; i < n; i++) {
+            u32 u = order[n - 1 - i];  /* non-increasing degree */
+            u64 nb = 0, ne = 0, nq = 0;
+            for (u64 j = g.off[u]; j < g.off[u + 1]; j++) {
+                unsigned char w = where[g.adj[j]];
+                if (w == 1) nb++;
+                else if (w == 2) ne++;
+                else nq++;
+            }
+            u64 cb = nb * (ne + nq), ce = (nb + nq) * ne;
+            if (cb <= ce) {
+                where[u] = 1;
+                n_begin++;
+                rank[u] = n_begin - 1;        /* position |V_b| + 1 */
+            } else {
+                where[u] = 2;
+                rank[u] = n - n_end - 1;      /* position n - |V_e| */
+                n_end++;
+            }
+            if (side) side[u] = where[u] - 1;
+        }
+        graph_free(&g);
+    }
+    free(order); free(ident); free(where);
     return rc;
 }

@@ -2,7 +2,9 @@
 
 Each check is independent of the oracle's own code: brute-force enumeration,
 trace(A^3)/6, closed forms, the printed values of the Figure 2 example and
-the Split example (Section 3.3.3), the costs stated for the gadget graphs of
+the Split example (Section 3.3.3), the Check result worked by hand on the
+Figure 2 graph together with the optimum its caption states (re-found by
+trying every ordering), the costs stated for the gadget graphs of
 Appendices A and B, the linear-cost property of Appendix B, and splitmix64's
 published output sequence for the digest's mixing function.
 """
@@ -380,3 +382,96 @@ def test_coreness_agrees_with_the_generators_peeling():
     g = graphgen.chung_lu(20000, 2.1, 12.0, seed=5)
     _, core = graphgen.core_order(g, return_core=True)
     assert np.array_equal(oracle.coreness(g.n, g.src, g.dst), core)
+
+
+# ------------------------------------------------------------ Check
+
+
+def _cpm_python(n, s, d, rank):
+    """C+- of an ordering by direct counting (Definition 1)."""
+    nbr = [set() for _ in range(n)]
+    for a, b in zip(s.tolist(), d.tolist()):
+        if a != b:
+            nbr[a].add(b)
+            nbr[b].add(a)
+    tot = 0
+    for u in range(n):
+        plus = sum(1 for v in nbr[u] if rank[v] > rank[u])
+        tot += plus * (len(nbr[u]) - plus)
+    return tot
+
+
+def test_check_worked_example():
+    """Check (Section 3.3.2) on the Figure 2 graph, worked by hand.  The
+    vertices come by non-increasing degree, (e,b,g,a,f,d,c) (the order
+    printed with C+- = 7).  e: nothing placed, C_b = C_e = 0, beginning.
+    b: N_b = {e}, N_? = {a,c,g}: C_b = 3 > C_e = 0, end.  g: N_e = {b},
+    N_? = {c,f}: C_b = 0 < C_e = 2, beginning.  a: N_b = {e}, N_e = {b},
+    N_? = {d}: C_b = C_e = 2, beginning.  f and d: every neighbour at the
+    beginning, C_b = C_e = 0, beginning.  c: N_b = {g}, N_e = {b}: C_b =
+    C_e = 1, beginning.  Result (e,g,a,f,d,c,b); its C+- = 3 is the optimum
+    the Figure 2 caption states, found again here by trying all 5,040
+    orderings."""
+    n, s, d, orders, names = G.fig2()
+    rank, side = oracle.check_order(n, s, d, with_side=True)
+    assert [names[int(u)] for u in np.argsort(rank)] == list("egafdcb")
+    assert [int(x) for x in side] == [0, 1, 0, 0, 0, 0, 0]  # a..g: only b at the end
+    opt_order, opt_cpm = orders[2]
+    assert oracle.cost(n, s, d, rank).cpm == opt_cpm == 3
+    best = min(_cpm_python(n, s, d, np.array(p)) for p in itertools.permutations(range(n)))
+    assert best == 3
+
+
+def test_check_small_closed_forms():
+    # path 0-1-2-3: by non-increasing degree 2, 1, 3, 0; 1 finds 2 at the
+    # beginning and one unplaced neighbour (C_b = 1 > C_e = 0): end
+    path = (4, np.array([0, 1, 2], np.uint32), np.array([1, 2, 3], np.uint32))
+    rank = oracle.check_order(*path)
+    assert rank.tolist() == [2, 3, 0, 1]
+    assert oracle.cost(*path, rank).cpm == 0
+    # star: the centre first, then every leaf (one neighbour, at the
+    # beginning: C_b = C_e = 0) after it, by decreasing id
+    n, s, d = G.star(9)
+    order = np.argsort(oracle.check_order(n, s, d))
+    centre = int(np.bincount(np.concatenate([s, d])).argmax())
+    assert order[0] == centre
+    assert order[1:].tolist() == sorted([u for u in range(n) if u != centre], reverse=True)
+    # edgeless: every vertex at the beginning, in the order taken
+    rank = oracle.check_order(5, np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    assert rank.tolist() == [4, 3, 2, 1, 0]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_check_structure_and_greedy_choice(seed):
+    """On random graphs (given with loops and repeated edges): the result is
+    a permutation; the beginning block holds its vertices in the order they
+    were taken and the end block in reverse; and every vertex's own C+-
+    share in the final ordering is the smaller of its two options, with the
+    options recounted from the final sides and the order of placement."""
+    n, s, d = rand_graph(1300 + seed)
+    s2, d2 = _with_noise(n, s, d, seed)
+    rank, side = oracle.check_order(n, s2, d2, with_side=True)
+    assert sorted(rank.tolist()) == list(range(n))
+    taken = np.argsort(oracle.degree_order(n, s, d))[::-1]  # non-increasing degree
+    when = np.empty(n, np.int64)
+    when[taken] = np.arange(n)
+    begin = [int(u) for u in taken if side[u] == 0]
+    end = [int(u) for u in taken if side[u] == 1]
+    assert [int(u) for u in np.argsort(rank)] == begin + end[::-1]
+    nbr = [set() for _ in range(n)]
+    for a, b in zip(s.tolist(), d.tolist()):
+        if a != b:
+            nbr[a].add(b)
+            nbr[b].add(a)
+    total = 0
+    for u in range(n):
+        nb = sum(1 for v in nbr[u] if when[v] < when[u] and side[v] == 0)
+        ne = sum(1 for v in nbr[u] if when[v] < when[u] and side[v] == 1)
+        nq = len(nbr[u]) - nb - ne
+        cb, ce = nb * (ne + nq), (nb + nq) * ne
+        plus = sum(1 for v in nbr[u] if rank[v] > rank[u])
+        share = plus * (len(nbr[u]) - plus)
+        assert share == min(cb, ce)
+        assert side[u] == (0 if cb <= ce else 1)
+        total += share
+    assert oracle.cost(n, s, d, rank).cpm == total == _cpm_python(n, s, d, rank)

@@ -395,7 +395,7 @@ def bench_orders(args):
     ordering, list -- and (2) for each of
     several orderings and both forms, the paper's cost C against the
     listing time (count and digest only).  Full listings: degree/A++,
-    Split/A+- and core/A+-."""
+    Split/A+-, core/A+- and Check/A+-."""
     import ctypes
 
     import torch
@@ -422,7 +422,7 @@ def bench_orders(args):
         return float(np.median(ts)) * 1e3, out
 
     full = {}
-    for kind, algo in (("degree", "A++"), ("split", "A+-"), ("core", "A+-")):
+    for kind, algo in (("degree", "A++"), ("split", "A+-"), ("core", "A+-"), ("check", "A+-")):
         def run():
             g0 = tl.orient(g.n, src, dst, ident)
             t1 = time.perf_counter()
@@ -443,10 +443,10 @@ def bench_orders(args):
     # cost against listing time
     ranks = {k: graphgen.ordering(g, k, seed=1) for k in ("random", "degree", "core", "identity")}
     rows = []
-    for kind in ("random", "identity", "degree", "core", "split"):
-        if kind == "split":
+    for kind in ("random", "identity", "degree", "core", "split", "check"):
+        if kind in ("split", "check"):
             g0 = tl.orient(g.n, src, dst, ident)
-            r = tl.order(g0, "split")
+            r = tl.order(g0, kind)
             g0.free()
         else:
             r = dev(ranks[kind])

@@ -164,10 +164,14 @@ void tl_csr_free(tl_csr *g);
  *   TL_ORDER_CORE    non-decreasing coreness, ties by increasing vertex id
  *                    (a core ordering of Section 1.3; coreness computed by
  *                    level-synchronous peeling on the device)
+ *   TL_ORDER_CHECK   Check (Section 3.3.2): vertices taken by non-increasing
+ *                    degree (TL_ORDER_DEGREE read backwards); each goes right
+ *                    after the beginning block if |N_b| (|N_e| + |N_?|) <=
+ *                    (|N_b| + |N_?|) |N_e|, else right before the end block
  * Orient again with the result (tl_orient) to list under it.  Returns after
  * the stream has finished; TL_EINVAL for an unknown kind or a NULL pointer.
  */
-typedef enum { TL_ORDER_DEGREE = 0, TL_ORDER_SPLIT = 1, TL_ORDER_CORE = 2 } tl_order_kind;
+typedef enum { TL_ORDER_DEGREE = 0, TL_ORDER_SPLIT = 1, TL_ORDER_CORE = 2, TL_ORDER_CHECK = 3 } tl_order_kind;
 int tl_order(const tl_csr *g, tl_order_kind kind, uint32_t *rank_dev, void *stream);
 
 /*

@@ -1,9 +1,12 @@
 // Orderings computed on the device from an oriented graph: the degree
 // ordering (Section 2.2: non-decreasing degree, ties by id), Split
 // (Section 3.3.3: the non-increasing degree ordering dealt alternately to
-// the front and the back) and the core ordering (Section 1.3: non-decreasing
-// coreness, ties by id; coreness by level-synchronous peeling).  Together with tl_orient and tl_list they make
-// the full listing (ordering included) run on the GPU.
+// the front and the back), the core ordering (Section 1.3: non-decreasing
+// coreness, ties by id; coreness by level-synchronous peeling) and Check
+// (Section 3.3.2: by non-increasing degree, each vertex after the beginning
+// block or before the end block, whichever gives it the smaller C+- share;
+// decided level by level, see below).  Together with tl_orient and tl_list
+// they make the full listing (ordering included) run on the GPU.
 #include <hipcub/hipcub.hpp>
 
 #include "tl_internal.h"
@@ -123,6 +126,111 @@ __global__ void k_core_keys(const u32 *core, const u32 *inv, u32 n, u32 *key, u3
     }
 }
 
+// ------------------------------------------------------------------ Check
+//
+// A vertex's choice depends only on the sides of its neighbours taken
+// before it, so the sequential greedy is replayed exactly by levels: a
+// vertex is decided once every earlier neighbour is (pending = 0), and the
+// vertices of one level share no edge.  Positions follow from the sides:
+// beginning vertices in the order taken, end vertices in reverse.
+
+constexpr unsigned char SIDE_BEGIN = 0, SIDE_END = 1;
+
+// dpos[r]: when rank r is taken (0 = first, the largest degree)
+__global__ void k_check_dpos(const u32 *sorted, const u32 *inv, u32 n, u32 *posid, u32 *dpos, int phase) {
+    GRID_STRIDE(i, n) {
+        if (phase == 0) posid[sorted[i]] = (u32)i;
+        else dpos[i] = n - 1 - posid[inv[i]];
+    }
+}
+
+// pending[r] = neighbours taken before r; ranks with none start the first level
+__global__ void k_check_init(const u64 *off_f, const u32 *adj_f, const u64 *off_b, const u32 *adj_b, const u32 *dpos,
+                             u32 n, u32 *pending, u32 *frontier, u32 *fcount) {
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 iters = (u64)n > first - lane_id() ? ((u64)n - (first - lane_id()) + stride - 1) / stride : 0;
+    for (u64 it = 0; it < iters; it++) {
+        const u64 r = first + it * stride;
+        u32 p = 0;
+        if (r < n) {
+            const u32 d = dpos[r];
+            for (u64 j = off_f[r]; j < off_f[r + 1]; j++) p += dpos[adj_f[j]] < d;
+            for (u64 j = off_b[r]; j < off_b[r + 1]; j++) p += dpos[adj_b[j]] < d;
+            pending[r] = p;
+        }
+        const bool ready = r < n && p == 0;
+        const u64 bal = __ballot(ready);
+        if (!bal) continue;
+        u32 base = 0;
+        if (lane_id() == 0) base = atomicAdd(fcount, (u32)__popcll(bal));
+        base = __shfl(base, 0, WAVE);
+        if (ready) frontier[base + __popcll(bal & lanemask_lt())] = (u32)r;
+    }
+}
+
+// One level: a wavefront per vertex counts its earlier neighbours on each
+// side, takes the cheaper side, then releases its later neighbours (those
+// whose last earlier neighbour this was join the next level).
+__global__ void k_check_level(const u64 *off_f, const u32 *adj_f, const u64 *off_b, const u32 *adj_b,
+                              const u32 *dpos, const u32 *frontier, u32 nf, unsigned char *side, u32 *pending,
+                              u32 *next, u32 *ncount) {
+    const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
+    const int lane = lane_id();
+    for (u64 f = w0; f < nf; f += nw) {
+        const u32 r = uni32(frontier[f]);
+        const u32 d = dpos[r];
+        const u64 f0 = off_f[r], f1 = off_f[r + 1], b0 = off_b[r], b1 = off_b[r + 1];
+        const u64 deg = (f1 - f0) + (b1 - b0);
+        u64 nb = 0, ne = 0;
+        for (u64 j = lane; j < deg; j += WAVE) {
+            const u32 w = j < f1 - f0 ? adj_f[f0 + j] : adj_b[b0 + (j - (f1 - f0))];
+            if (dpos[w] < d) {
+                if (side[w] == SIDE_BEGIN) nb++;
+                else ne++;
+            }
+        }
+        nb = wave_sum_u64(nb);
+        ne = wave_sum_u64(ne);
+        const u64 nq = deg - nb - ne;
+        const u64 cb = nb * (ne + nq), ce = (nb + nq) * ne;
+        if (lane == 0) side[r] = cb <= ce ? SIDE_BEGIN : SIDE_END;
+        const u64 trips = (deg + WAVE - 1) / WAVE;
+        for (u64 t = 0; t < trips; t++) {
+            const u64 j = t * WAVE + lane;
+            bool ready = false;
+            u32 w = 0;
+            if (j < deg) {
+                w = j < f1 - f0 ? adj_f[f0 + j] : adj_b[b0 + (j - (f1 - f0))];
+                if (dpos[w] > d) ready = atomicSub(&pending[w], 1u) == 1u;
+            }
+            const u64 bal = __ballot(ready);
+            if (!bal) continue;
+            u32 base = 0;
+            if (lane == 0) base = atomicAdd(ncount, (u32)__popcll(bal));
+            base = __shfl(base, 0, WAVE);
+            if (ready) next[base + __popcll(bal & lanemask_lt())] = w;
+        }
+    }
+}
+
+// begin[i] = 1 when the vertex taken i-th went to the beginning
+__global__ void k_check_flags(const u32 *dpos, const unsigned char *side, u32 n, u32 *begin) {
+    GRID_STRIDE(r, n) { begin[dpos[r]] = side[r] == SIDE_BEGIN ? 1u : 0u; }
+}
+
+// beginning: position = beginning vertices taken before; end: n - 1 minus
+// the end vertices taken before
+__global__ void k_check_rank(const u32 *dpos, const unsigned char *side, const u64 *bpre, const u32 *inv, u32 n,
+                             u32 *rank) {
+    GRID_STRIDE(r, n) {
+        const u32 i = dpos[r];
+        const u64 b = bpre[i];
+        rank[inv[r]] = side[r] == SIDE_BEGIN ? (u32)b : (u32)(n - 1 - (i - b));
+    }
+}
+
 }  // namespace
 
 // Coreness of every rank by level-synchronous peeling, then keys (coreness
@@ -163,8 +271,47 @@ void coreness_keys(const tl_csr *g, u32 *key, u32 *ids, hipStream_t s) {
     TL_HIP(hipGetLastError());
 }
 
+// Check's ranks from the degree ordering's `sorted` (ids by non-decreasing
+// degree, ties by id), read backwards as the order in which vertices are taken.
+void check_ranks(const tl_csr *g, const u32 *sorted, u32 *rank, hipStream_t s) {
+    const u32 n = g->n;
+    DevBuf posid((u64)n * 4, s), dpos((u64)n * 4, s), pending((u64)n * 4, s), fa((u64)n * 4, s),
+        fb((u64)n * 4, s), side((u64)n, s), cnt(8, s), bpre(((u64)n + 1) * 8, s);
+    for (int phase = 0; phase < 2; phase++) {
+        hipLaunchKernelGGL(k_check_dpos, dim3(grid_o(n)), dim3(256), 0, s, sorted, g->inv, n, posid.as<u32>(),
+                           dpos.as<u32>(), phase);
+        TL_HIP(hipGetLastError());
+    }
+    TL_HIP(hipMemsetAsync(cnt.p, 0, 8, s));
+    hipLaunchKernelGGL(k_check_init, dim3(grid_o(n)), dim3(256), 0, s, g->off_f, g->adj_f, g->off_b, g->adj_b,
+                       dpos.as<u32>(), n, pending.as<u32>(), fa.as<u32>(), cnt.as<u32>());
+    TL_HIP(hipGetLastError());
+    u32 nf = 0;
+    d2h_sync(s, {{&nf, cnt.p, 4}});
+    u32 *cur = fa.as<u32>(), *nxt = fb.as<u32>();
+    u64 done = 0;
+    while (nf) {
+        done += nf;
+        TL_HIP(hipMemsetAsync(cnt.p, 0, 4, s));
+        hipLaunchKernelGGL(k_check_level, dim3(grid_o((u64)nf * WAVE)), dim3(256), 0, s, g->off_f, g->adj_f,
+                           g->off_b, g->adj_b, dpos.as<u32>(), cur, nf, side.as<unsigned char>(), pending.as<u32>(),
+                           nxt, cnt.as<u32>());
+        TL_HIP(hipGetLastError());
+        d2h_sync(s, {{&nf, cnt.p, 4}});
+        std::swap(cur, nxt);
+    }
+    TL_REQUIRE(done == n, TL_EHIP, "Check levels did not reach every vertex");
+    hipLaunchKernelGGL(k_check_flags, dim3(grid_o(n)), dim3(256), 0, s, dpos.as<u32>(), side.as<unsigned char>(), n,
+                       posid.as<u32>());
+    TL_HIP(hipGetLastError());
+    scan_u32_to_u64(posid.as<u32>(), bpre.as<u64>(), n, s);
+    hipLaunchKernelGGL(k_check_rank, dim3(grid_o(n)), dim3(256), 0, s, dpos.as<u32>(), side.as<unsigned char>(),
+                       bpre.as<u64>(), g->inv, n, rank);
+    TL_HIP(hipGetLastError());
+}
+
 void order_impl(const tl_csr *g, int kind, u32 *rank, hipStream_t s) {
-    TL_REQUIRE(kind >= 0 && kind <= 2, TL_EINVAL, "unknown ordering");
+    TL_REQUIRE(kind >= 0 && kind <= 3, TL_EINVAL, "unknown ordering");
     const u32 n = g->n;
     if (n == 0) return;
     TL_REQUIRE(rank, TL_EINVAL, "rank is NULL");
@@ -189,8 +336,13 @@ void order_impl(const tl_csr *g, int kind, u32 *rank, hipStream_t s) {
     DevBuf tmp(tmp_bytes ? tmp_bytes : 1, s);
     TL_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, deg.as<u32>(), deg2.as<u32>(), ids.as<u32>(),
                                               sorted.as<u32>(), (int)n, 0, bits, s));
-    hipLaunchKernelGGL(k_rank_of, dim3(grid_o(n)), dim3(256), 0, s, sorted.as<u32>(), n, kind == 1 ? 1 : 0, rank);
-    TL_HIP(hipGetLastError());
+    if (kind == 3) {
+        check_ranks(g, sorted.as<u32>(), rank, s);
+    } else {
+        hipLaunchKernelGGL(k_rank_of, dim3(grid_o(n)), dim3(256), 0, s, sorted.as<u32>(), n, kind == 1 ? 1 : 0,
+                           rank);
+        TL_HIP(hipGetLastError());
+    }
     timer.stop();
     TL_HIP(hipStreamSynchronize(s));
 }

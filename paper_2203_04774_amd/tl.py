@@ -190,7 +190,7 @@ def orient(n: int, src: torch.Tensor, dst: torch.Tensor, rank: torch.Tensor, str
     return Csr(h)
 
 
-ORDERS = {"degree": 0, "split": 1, "core": 2}
+ORDERS = {"degree": 0, "split": 1, "core": 2, "check": 3}
 
 
 def order(g: Csr, kind: str = "degree", out: torch.Tensor | None = None, stream=None) -> torch.Tensor:

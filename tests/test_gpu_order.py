@@ -1,6 +1,6 @@
-"""GPU orderings (tl_order) against the oracle's: the degree ordering and
-Split (Section 3.3.3), and the full listing with the ordering computed on
-the device."""
+"""GPU orderings (tl_order) against the oracle's: the degree ordering,
+Split (Section 3.3.3), the core ordering (Section 1.3) and Check (Section
+3.3.2), and the full listing with the ordering computed on the device."""
 import numpy as np
 import pytest
 
@@ -48,6 +48,7 @@ def test_orders_match_oracle_with_noisy_input(tl, seed):
     assert np.array_equal(gpu_order(tl, n, s, d, "degree", start), oracle.degree_order(n, s, d))
     assert np.array_equal(gpu_order(tl, n, s, d, "split", start), oracle.split_order(n, s, d))
     assert np.array_equal(gpu_order(tl, n, s, d, "core", start), oracle.core_order(n, s, d))
+    assert np.array_equal(gpu_order(tl, n, s, d, "check", start), oracle.check_order(n, s, d))
 
 
 @pytest.mark.parametrize("which", ["rmat12", "chunglu20"])
@@ -56,6 +57,20 @@ def test_orders_match_oracle_on_workloads(tl, which):
     assert np.array_equal(gpu_order(tl, g.n, g.src, g.dst, "degree"), oracle.degree_order(g.n, g.src, g.dst))
     assert np.array_equal(gpu_order(tl, g.n, g.src, g.dst, "split"), oracle.split_order(g.n, g.src, g.dst))
     assert np.array_equal(gpu_order(tl, g.n, g.src, g.dst, "core"), oracle.core_order(g.n, g.src, g.dst))
+    assert np.array_equal(gpu_order(tl, g.n, g.src, g.dst, "check"), oracle.check_order(g.n, g.src, g.dst))
+
+
+def test_check_worked_example(tl):
+    """Check on the Figure 2 graph: (e,g,a,f,d,c,b), worked by hand."""
+    n, s, d, orders, names = G.fig2()
+    r = gpu_order(tl, n, s, d, "check")
+    assert [names[int(u)] for u in np.argsort(r)] == list("egafdcb")
+
+
+def test_check_shapes(tl):
+    for (n, s, d) in [G.complete(9), G.wheel(12), G.grid(5, 7), G.star(10), G.cycle(13),
+                      G.complete_bipartite(5, 8), (6, np.arange(5, dtype=np.uint32), np.arange(1, 6, dtype=np.uint32))]:
+        assert np.array_equal(gpu_order(tl, n, s, d, "check"), oracle.check_order(n, s, d))
 
 
 def test_core_closed_forms(tl):
@@ -69,9 +84,10 @@ def test_small_and_empty(tl):
         assert np.array_equal(gpu_order(tl, n, s, s, "degree"), np.arange(n, dtype=np.uint32))
         assert np.array_equal(gpu_order(tl, n, s, s, "split"), oracle.split_order(n, s, s))
         assert np.array_equal(gpu_order(tl, n, s, s, "core"), np.arange(n, dtype=np.uint32))
+        assert np.array_equal(gpu_order(tl, n, s, s, "check"), oracle.check_order(n, s, s))
 
 
-@pytest.mark.parametrize("kind,algo", [("split", "A+-"), ("degree", "A++"), ("core", "A+-")])
+@pytest.mark.parametrize("kind,algo", [("split", "A+-"), ("degree", "A++"), ("core", "A+-"), ("check", "A+-")])
 def test_full_listing_on_device(tl, kind, algo):
     """Edges -> orientation by id -> ordering on the device -> orientation
     by that ordering -> listing; equal to the oracle under the oracle's
@@ -86,7 +102,8 @@ def test_full_listing_on_device(tl, kind, algo):
         c = tl.cost(g1, algo)
     finally:
         g1.free()
-    r = {"split": oracle.split_order, "degree": oracle.degree_order, "core": oracle.core_order}[kind](
+    r = {"split": oracle.split_order, "degree": oracle.degree_order, "core": oracle.core_order,
+         "check": oracle.check_order}[kind](
         g.n, g.src, g.dst)
     L = oracle.list_triangles(g.n, g.src, g.dst, r, algo, want_triangles=False)
     assert (got.count, got.hash, got.work) == (L.count, L.hash, L.work)

@@ -65,6 +65,9 @@ def _load():
     for f in ("orc_degree_order", "orc_split_order", "orc_coreness", "orc_core_order"):
         getattr(lib, f).restype = ctypes.c_int
         getattr(lib, f).argtypes = [u32, u64, u32p, u32p, u32p]
+    lib.orc_neigh_order.restype = ctypes.c_int
+    lib.orc_neigh_order.argtypes = [u32, u64, u32p, u32p, u32p, ctypes.c_double, u32, u32, u32p,
+                                    ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32)]
     lib.orc_check_order.restype = ctypes.c_int
     lib.orc_check_order.argtypes = [u32, u64, u32p, u32p, u32p, ctypes.POINTER(ctypes.c_uint8)]
     _lib = lib
@@ -277,6 +280,22 @@ def check_order(n, src, dst, with_side=False):
     side = np.zeros(max(n, 1), np.uint8)
     _check(lib.orc_check_order(n, len(s), s, d, rank, side.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
     return (rank[:n], side[:n]) if with_side else rank[:n]
+
+
+def neigh_order(n, src, dst, rank_in, eps=0.01, max_passes=100, max_visits=0):
+    """Neigh (Algorithm 3) from the ordering rank_in; returns (rank, C+-,
+    passes).  Every candidate place is priced from scratch: small graphs
+    only.  max_visits > 0 stops after that many vertex visits."""
+    lib = _load()
+    s = np.ascontiguousarray(src, np.uint32)
+    d = np.ascontiguousarray(dst, np.uint32)
+    r0 = np.ascontiguousarray(rank_in, np.uint32)
+    rank = np.zeros(max(n, 1), np.uint32)
+    c = ctypes.c_uint64(0)
+    p = ctypes.c_uint32(0)
+    _check(lib.orc_neigh_order(n, len(s), s, d, r0, float(eps), max_passes, max_visits, rank, ctypes.byref(c),
+                               ctypes.byref(p)))
+    return rank[:n], int(c.value), int(p.value)
 
 
 def triangle_hash(a: int, b: int, c: int) -> int:

@@ -35,7 +35,7 @@
  * splitmix64's published output sequence and the sum against hashing the
  * brute-force triangle set.
  *
- * Orderings (degree, Split, coreness and core ordering, Check) are stated
+ * Orderings (degree, Split, coreness and core ordering, Check, Neigh) are stated
  * beside their functions below, each with the passage it follows.
  *
  * Restricting the outer loop to pivots whose rank lies in [lo, hi) lists
@@ -593,5 +593,139 @@ int orc_check_order(u32 n, u64 m_in, const u32 *src, const u32 *dst, u32 *rank, 
         graph_free(&g);
     }
     free(order); free(ident); free(where);
+    return rc;
+}
+
+/*
+ * Neigh (Algorithm 3, Section 3.3.1): a pass visits every vertex u and
+ * moves it to the place among its neighbours that gives the lowest C+-:
+ * with N_u sorted by the current order as v_1 .. v_d, candidate p = 1..d
+ * puts u right after v_p, candidate 0 right before v_1.  Passes repeat
+ * while a pass brings C+- below (1 - eps) times its value at the pass's
+ * start (the algorithm's loop condition), at most max_passes times.
+ * Readings (the paper leaves them open): a pass visits vertices by
+ * increasing id; when u's current place is among the cheapest it stays
+ * put, otherwise the smallest cheapest p is taken.
+ * Every candidate's C+- is computed from scratch on the candidate order
+ * (Definition 1), and the order is a plain array: slow, for small graphs.
+ * max_visits > 0 stops after that many vertex visits (for checking single
+ * moves).  rank_in: the starting order; rank_out: the result.
+ */
+static u64 cpm_of_positions(const graph *g, const u32 *pos) {
+    u64 c = 0;
+    for (u32 u = 0; u < g->n; u++) {
+        u64 plus = 0, d = g->off[u + 1] - g->off[u];
+        for (u64 j = g->off[u]; j < g->off[u + 1]; j++) plus += pos[g->adj[j]] > pos[u];
+        c += plus * (d - plus);
+    }
+    return c;
+}
+
+/* order without u, then u inserted at index `at` of that shorter order */
+static void place(const u32 *order, u32 n, u32 u, u32 at, u32 *out) {
+    u32 k = 0;
+    for (u32 i = 0; i < n; i++) {
+        if (order[i] == u) continue;
+        if (k == at) out[k++] = u;
+        out[k++] = order[i];
+    }
+    if (k == at) out[k++] = u;
+}
+
+static int cmp_u64(const void *a, const void *b) {
+    u64 x = *(const u64 *)a, y = *(const u64 *)b;
+    return (x > y) - (x < y);
+}
+
+int orc_neigh_order(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank_in, double eps,
+                    u32 max_passes, u32 max_visits, u32 *rank_out, u64 *cpm_out, u32 *passes_out) {
+    u32 *ident = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    if (!ident) return -2;
+    for (u32 u = 0; u < n; u++) ident[u] = u;
+    graph g;
+    int rc = graph_build(&g, n, m_in, src, dst, ident);
+    free(ident);
+    if (rc) return rc;
+    /* rank_in must be a permutation */
+    unsigned char *seen = (unsigned char *)calloc((size_t)n + 1, 1);
+    u32 *order = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    u32 *cand = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    u32 *pos = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    u32 *cpos = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    u64 maxd = 0;
+    for (u32 u = 0; u < n; u++)
+        if (g.off[u + 1] - g.off[u] > maxd) maxd = g.off[u + 1] - g.off[u];
+    u64 *nb = (u64 *)malloc((size_t)(maxd + 1) * sizeof(u64));
+    u64 *cost = (u64 *)malloc((size_t)(maxd + 1) * sizeof(u64));
+    if (!seen || !order || !cand || !pos || !cpos || !nb || !cost) rc = -2;
+    for (u32 u = 0; !rc && u < n; u++) {
+        if (rank_in[u] >= n || seen[rank_in[u]]) rc = -1;
+        else { seen[rank_in[u]] = 1; pos[u] = rank_in[u]; order[rank_in[u]] = u; }
+    }
+    u64 c = 0;
+    u32 passes = 0, visits = 0;
+    int stop = 0;
+    if (!rc) {
+        c = cpm_of_positions(&g, pos);
+        while (!stop && passes < max_passes) {
+            const u64 c0 = c;
+            for (u32 u = 0; u < n && !stop; u++) {
+                if (max_visits && visits == max_visits) { stop = 1; break; }
+                visits++;
+                const u64 d = g.off[u + 1] - g.off[u];
+                if (d == 0) continue;
+                /* neighbours by current position */
+                for (u64 j = 0; j < d; j++) {
+                    u32 v = g.adj[g.off[u] + j];
+                    nb[j] = ((u64)pos[v] << 32) | v;
+                }
+                qsort(nb, d, sizeof(u64), cmp_u64);
+                u64 pcur = 0;
+                for (u64 j = 0; j < d; j++) pcur += (u32)(nb[j] >> 32) < pos[u];
+                /* C+- of every candidate, from scratch */
+                u64 best = ~0ull;
+                for (u64 p = 0; p <= d; p++) {
+                    u32 at;
+                    if (p == 0) {
+                        u32 v1 = (u32)nb[0];
+                        at = pos[v1] - (pos[u] < pos[v1] ? 1 : 0);  /* index of v_1 once u is out */
+                    } else {
+                        u32 vp = (u32)nb[p - 1];
+                        at = pos[vp] - (pos[u] < pos[vp] ? 1 : 0) + 1;
+                    }
+                    place(order, n, u, at, cand);
+                    for (u32 i = 0; i < n; i++) cpos[cand[i]] = i;
+                    cost[p] = cpm_of_positions(&g, cpos);
+                    if (cost[p] < best) best = cost[p];
+                }
+                u64 pstar = pcur;
+                if (cost[pcur] != best) {
+                    for (pstar = 0; cost[pstar] != best; pstar++) {}
+                }
+                if (pstar != pcur) {
+                    u32 at;
+                    if (pstar == 0) {
+                        u32 v1 = (u32)nb[0];
+                        at = pos[v1] - (pos[u] < pos[v1] ? 1 : 0);
+                    } else {
+                        u32 vp = (u32)nb[pstar - 1];
+                        at = pos[vp] - (pos[u] < pos[vp] ? 1 : 0) + 1;
+                    }
+                    place(order, n, u, at, cand);
+                    memcpy(order, cand, (size_t)n * sizeof(u32));
+                    for (u32 i = 0; i < n; i++) pos[order[i]] = i;
+                    c = best;
+                }
+            }
+            if (stop) break;
+            passes++;
+            if (!((double)c < (1.0 - eps) * (double)c0)) break;
+        }
+        for (u32 u = 0; u < n; u++) rank_out[u] = pos[u];
+        if (cpm_out) *cpm_out = c;
+        if (passes_out) *passes_out = passes;
+    }
+    free(seen); free(order); free(cand); free(pos); free(cpos); free(nb); free(cost);
+    graph_free(&g);
     return rc;
 }

@@ -4,7 +4,8 @@ Each check is independent of the oracle's own code: brute-force enumeration,
 trace(A^3)/6, closed forms, the printed values of the Figure 2 example and
 the Split example (Section 3.3.3), the Check result worked by hand on the
 Figure 2 graph together with the optimum its caption states (re-found by
-trying every ordering), the costs stated for the gadget graphs of
+trying every ordering), Neigh's first move in the Figure 2 caption and the
+local optimality of its result, the costs stated for the gadget graphs of
 Appendices A and B, the linear-cost property of Appendix B, and splitmix64's
 published output sequence for the digest's mixing function.
 """
@@ -475,3 +476,73 @@ def test_check_structure_and_greedy_choice(seed):
         assert side[u] == (0 if cb <= ce else 1)
         total += share
     assert oracle.cost(n, s, d, rank).cpm == total == _cpm_python(n, s, d, rank)
+
+
+# ------------------------------------------------------------ Neigh
+
+
+def _candidates(order, u, nbrs):
+    """Neigh's candidate orders for u (Algorithm 3): u right before its first
+    neighbour, or right after its p-th, neighbours taken in the order."""
+    rest = [x for x in order if x != u]
+    ns = sorted(nbrs, key=rest.index)
+    out = [rest[:rest.index(ns[0])] + [u] + rest[rest.index(ns[0]):]]
+    for v in ns:
+        i = rest.index(v) + 1
+        out.append(rest[:i] + [u] + rest[i:])
+    return out
+
+
+def test_neigh_first_move_is_figure2s():
+    """Figure 2: from (a,b,...,g), C+- = 9, vertex a moves right after e,
+    giving (b,c,d,e,a,f,g) with C+- = 6 (both orders and costs printed in
+    the caption).  The four places among a's neighbours are priced here
+    independently; after e is the only cheapest."""
+    n, s, d, orders, names = G.fig2()
+    start, start_cpm = orders[0]
+    moved, moved_cpm = orders[1]
+    a = names.index("a")
+    nbrs = {int(y) for x, y in zip(s, d) if x == a} | {int(x) for x, y in zip(s, d) if y == a}
+    costs = [oracle.cost(n, s, d, G.order_to_rank(c)).cpm for c in _candidates(start, a, nbrs)]
+    assert costs[0] == start_cpm == 9 and costs[-1] == moved_cpm == 6
+    assert costs.index(min(costs)) == len(costs) - 1 and costs.count(6) == 1
+    rank, cpm, _ = oracle.neigh_order(n, s, d, G.order_to_rank(start), max_visits=1)
+    assert [int(u) for u in np.argsort(rank)] == moved and cpm == 6
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_neigh_ends_in_a_local_optimum(seed):
+    """Run to a standstill (eps = 0), no vertex has a cheaper place among its
+    neighbours (every candidate priced by Definition 1 via the pinned
+    cost), and C+- never rose from the start."""
+    rs = np.random.default_rng(1400 + seed)
+    n = int(rs.integers(20, 60))
+    s, d = G.erdos_renyi(n, float(rs.uniform(0.05, 0.2)), 1400 + seed)[1:]
+    r0 = rs.permutation(n).astype(np.uint32)
+    rank, cpm, passes = oracle.neigh_order(n, s, d, r0, eps=0.0, max_passes=1000)
+    assert passes < 1000
+    assert sorted(rank.tolist()) == list(range(n))
+    assert cpm == oracle.cost(n, s, d, rank).cpm <= oracle.cost(n, s, d, r0).cpm
+    order = [int(u) for u in np.argsort(rank)]
+    nbr = [set() for _ in range(n)]
+    for a, b in zip(s.tolist(), d.tolist()):
+        if a != b:
+            nbr[a].add(b)
+            nbr[b].add(a)
+    for u in range(n):
+        if nbr[u]:
+            for c in _candidates(order, u, nbr[u]):
+                assert oracle.cost(n, s, d, G.order_to_rank(c)).cpm >= cpm
+
+
+def test_neigh_keeps_an_optimal_order():
+    """From an order of minimum C+- (found by trying all orders of a 7-vertex
+    graph), every vertex is already at a cheapest place: nothing moves."""
+    rs = np.random.default_rng(1500)
+    n = 7
+    s, d = G.erdos_renyi(n, 0.5, 1500)[1:]
+    best = min(itertools.permutations(range(n)), key=lambda p: _cpm_python(n, s, d, np.array(p)))
+    r0 = np.array(best, np.uint32)
+    rank, cpm, passes = oracle.neigh_order(n, s, d, r0, eps=0.0)
+    assert np.array_equal(rank, r0) and passes == 1
+    assert cpm == _cpm_python(n, s, d, r0)

@@ -395,7 +395,8 @@ def bench_orders(args):
     ordering, list -- and (2) for each of
     several orderings and both forms, the paper's cost C against the
     listing time (count and digest only).  Full listings: degree/A++,
-    Split/A+-, core/A+- and Check/A+-."""
+    Split/A+-, core/A+- and Check/A+-; Neigh (on the host, from the degree
+    ordering) is in the cost-time rows with its own running time."""
     import ctypes
 
     import torch
@@ -443,11 +444,20 @@ def bench_orders(args):
     # cost against listing time
     ranks = {k: graphgen.ordering(g, k, seed=1) for k in ("random", "degree", "core", "identity")}
     rows = []
-    for kind in ("random", "identity", "degree", "core", "split", "check"):
+    neigh_info = None
+    for kind in ("random", "identity", "degree", "core", "split", "check", "neigh"):
         if kind in ("split", "check"):
             g0 = tl.orient(g.n, src, dst, ident)
             r = tl.order(g0, kind)
             g0.free()
+        elif kind == "neigh":
+            # Neigh (Algorithm 3, on the host) from the degree ordering, eps = 0.01
+            g0 = tl.orient(g.n, src, dst, dev(ranks["degree"]))
+            r, nres = tl.order_neigh(g0, eps=0.01)
+            g0.free()
+            neigh_info = {"start": "degree", "eps": 0.01, "seconds": nres.seconds, "passes": nres.passes,
+                          "moves": int(nres.moves), "cpm_start": int(nres.cpm_start), "cpm": int(nres.cpm)}
+            log(f"[bench] neigh from degree: {neigh_info}")
         else:
             r = dev(ranks[kind])
         csr = tl.orient(g.n, src, dst, r)
@@ -477,6 +487,7 @@ def bench_orders(args):
         "cost_time_pearson_r": pearson,
         "cost_time_fit_ms": {"per_G_of_C": slope * 1e9, "intercept_ms": icpt},
         "fastest_listing": f"{best['order']}-{best['algo']}",
+        "neigh": neigh_info,
     }
     print(json.dumps(res), flush=True)
 

@@ -175,6 +175,31 @@ typedef enum { TL_ORDER_DEGREE = 0, TL_ORDER_SPLIT = 1, TL_ORDER_CORE = 2, TL_OR
 int tl_order(const tl_csr *g, tl_order_kind kind, uint32_t *rank_dev, void *stream);
 
 /*
+ * Neigh (Algorithm 3, Section 3.3.1): a local search that starts from the
+ * ordering g is oriented by and, pass after pass, visits every vertex (by
+ * increasing id) and moves it to the cheapest place among its neighbours
+ * for C+-: with N_u sorted by the current order as v_1 .. v_d, place 0 is
+ * right before v_1 and place p right after v_p.  A vertex whose current
+ * place is among the cheapest stays; otherwise it takes the smallest
+ * cheapest p.  Passes repeat while a pass brings C+- below (1 - eps) times
+ * its value at the pass's start, at most max_passes times; max_visits > 0
+ * stops after that many vertex visits.  The search is sequential, so it
+ * runs on the host (a copy of g's CSR is read back first).
+ * rank_dev: device uint32 array of g's n entries, the result as rank[u].
+ * out (host, optional): C+- at the start and at the end, passes completed,
+ * vertex visits, moves, wall-clock seconds.  Returns after the stream has
+ * finished; TL_EINVAL for a NULL handle or eps outside [0, 1).
+ */
+typedef struct {
+    uint64_t cpm_start, cpm;
+    uint32_t passes, visits;
+    uint64_t moves;
+    double seconds;
+} tl_neigh_result;
+int tl_order_neigh(const tl_csr *g, double eps, uint32_t max_passes, uint32_t max_visits, uint32_t *rank_dev,
+                   tl_neigh_result *out, void *stream);
+
+/*
  * Batched listing: many independent graphs listed by one pass.
  *
  * The problem solved for each graph is the one of tl_orient + tl_list

@@ -355,6 +355,16 @@ int tl_order(const tl_csr *g, tl_order_kind kind, uint32_t *rank_dev, void *stre
     });
 }
 
+int tl_order_neigh(const tl_csr *g, double eps, uint32_t max_passes, uint32_t max_visits, uint32_t *rank_dev,
+                   tl_neigh_result *out, void *stream) {
+    return guarded([&] {
+        TL_REQUIRE(g, TL_EINVAL, "NULL handle");
+        TL_REQUIRE(rank_dev || g->n == 0, TL_EINVAL, "rank is NULL");
+        neigh_impl(g, eps, max_passes, max_visits, rank_dev, out, (hipStream_t)stream);
+        return TL_OK;
+    });
+}
+
 int tl_batch_orient(uint32_t k, const uint32_t *n, const uint64_t *m, const uint32_t *src, const uint32_t *dst,
                     const uint32_t *rank, void *stream, tl_batch **out) {
     return guarded([&] {

@@ -163,3 +163,5 @@ void pool_trim_above(u64 limit);
 
 // Orderings from an oriented graph (order.hip): kind 0 degree, 1 Split.
 void order_impl(const tl_csr *g, int kind, u32 *rank, hipStream_t s);
+void neigh_impl(const tl_csr *g, double eps, u32 max_passes, u32 max_visits, u32 *rank_dev, tl_neigh_result *res,
+                hipStream_t s);

@@ -65,6 +65,11 @@ class ServerStats(ctypes.Structure):
 CHUNK_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)
 
 
+class NeighResult(ctypes.Structure):
+    _fields_ = [("cpm_start", ctypes.c_uint64), ("cpm", ctypes.c_uint64), ("passes", ctypes.c_uint32),
+                ("visits", ctypes.c_uint32), ("moves", ctypes.c_uint64), ("seconds", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -84,6 +89,9 @@ def _load():
     lib.tl_get_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(u64)]
     lib.tl_order.argtypes = [vp, i32, vp, vp]
     lib.tl_order.restype = i32
+    lib.tl_order_neigh.argtypes = [vp, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32, vp,
+                                   ctypes.POINTER(NeighResult), vp]
+    lib.tl_order_neigh.restype = i32
     lib.tl_batch_orient.argtypes = [u32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
     lib.tl_batch_list.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.tl_batch_size.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)]
@@ -203,6 +211,21 @@ def order(g: Csr, kind: str = "degree", out: torch.Tensor | None = None, stream=
     ptr = _dptr(out, "out") if g.n else None
     _check(_lib.tl_order(g.handle, ORDERS[kind], ptr, _stream_ptr(stream)), "tl_order")
     return out
+
+
+def order_neigh(g: Csr, eps: float = 0.01, max_passes: int = 100, max_visits: int = 0,
+                out: torch.Tensor | None = None, stream=None):
+    """tl_order_neigh: Neigh (Algorithm 3) from the ordering g is oriented
+    by; returns (device int32 rank tensor, NeighResult)."""
+    if out is None:
+        out = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")[: g.n]
+    elif out.numel() != g.n:
+        raise ValueError("out must have g.n entries")
+    ptr = _dptr(out, "out") if g.n else None
+    res = NeighResult()
+    _check(_lib.tl_order_neigh(g.handle, float(eps), int(max_passes), int(max_visits), ptr, ctypes.byref(res),
+                               _stream_ptr(stream)), "tl_order_neigh")
+    return out, res
 
 
 def cost(g: Csr, algo: str = "A++", stream=None) -> int:

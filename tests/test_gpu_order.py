@@ -1,6 +1,7 @@
 """GPU orderings (tl_order) against the oracle's: the degree ordering,
 Split (Section 3.3.3), the core ordering (Section 1.3) and Check (Section
-3.3.2), and the full listing with the ordering computed on the device."""
+3.3.2), and the full listing with the ordering computed on the device; the
+library's Neigh (Algorithm 3, run on the host) against the oracle's."""
 import numpy as np
 import pytest
 
@@ -120,3 +121,70 @@ def test_bad_kind(tl):
         assert rc == tl.tl.TL_EINVAL
     finally:
         g.free()
+
+
+def neigh(tl, n, s, d, start_rank, **kw):
+    g = tl.orient(n, dev(s), dev(d), dev(start_rank))
+    try:
+        r, res = tl.order_neigh(g, **kw)
+        return r.cpu().numpy().view(np.uint32), res
+    finally:
+        g.free()
+
+
+def test_neigh_figure2_first_move(tl):
+    """Figure 2: from (a,...,g), C+- = 9, a moves right after e, C+- = 6."""
+    n, s, d, orders, names = G.fig2()
+    r, res = neigh(tl, n, s, d, G.order_to_rank(orders[0][0]), max_visits=1)
+    assert [int(u) for u in np.argsort(r)] == orders[1][0]
+    assert (res.cpm_start, res.cpm, res.visits, res.moves) == (9, 6, 1, 1)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_neigh_matches_oracle(tl, seed):
+    """The library's Neigh (linked list with labels, costs from degrees)
+    against the oracle's (every candidate priced from scratch), from random
+    starting orders, on graphs given with loops and repeated edges."""
+    rs = np.random.default_rng(1600 + seed)
+    n = int(rs.integers(30, 400))
+    k = int(rs.integers(2, 8)) * n
+    s = rs.integers(0, n, k).astype(np.uint32)
+    d = (s + rs.integers(0, max(n // 8, 2), k)).astype(np.uint32) % n  # some locality, loops included
+    r0 = rs.permutation(n).astype(np.uint32)
+    eps, passes = [(0.0, 1000), (0.01, 1000), (0.3, 1000), (0.0, 1)][seed % 4]
+    got, res = neigh(tl, n, s, d, r0, eps=eps, max_passes=passes)
+    want, cpm, npass = oracle.neigh_order(n, s, d, r0, eps=eps, max_passes=passes)
+    assert np.array_equal(got, want)
+    assert (res.cpm, res.passes) == (cpm, npass)
+    assert res.cpm_start == oracle.cost(n, s, d, r0).cpm
+
+
+def test_neigh_matches_oracle_on_a_heavy_tailed_graph(tl):
+    g = graphgen.chung_lu(600, 2.1, 10.0, seed=9)
+    r0 = oracle.degree_order(g.n, g.src, g.dst)
+    got, res = neigh(tl, g.n, g.src, g.dst, r0, eps=0.01)
+    want, cpm, npass = oracle.neigh_order(g.n, g.src, g.dst, r0, eps=0.01)
+    assert np.array_equal(got, want) and (res.cpm, res.passes) == (cpm, npass)
+    assert cpm < oracle.cost(g.n, g.src, g.dst, r0).cpm
+
+
+def test_neigh_full_listing_and_errors(tl):
+    import ctypes
+    g = graphgen.chung_lu(500, 2.3, 12.0, seed=4)
+    r0 = np.arange(g.n, dtype=np.uint32)
+    g0 = tl.orient(g.n, dev(g.src), dev(g.dst), dev(r0))
+    try:
+        rank, res = tl.order_neigh(g0, eps=0.01)
+        rc = tl.raw_lib().tl_order_neigh(g0.handle, ctypes.c_double(1.5), 10, 0, ctypes.c_void_p(rank.data_ptr()),
+                                         None, None)
+        assert rc != 0  # eps outside [0, 1)
+    finally:
+        g0.free()
+    g1 = tl.orient(g.n, dev(g.src), dev(g.dst), rank)
+    try:
+        got = tl.list_triangles(g1, "A+-")
+    finally:
+        g1.free()
+    want_rank, cpm, _ = oracle.neigh_order(g.n, g.src, g.dst, r0, eps=0.01)
+    L = oracle.list_triangles(g.n, g.src, g.dst, want_rank, "A+-", want_triangles=False)
+    assert (got.count, got.hash, got.work) == (L.count, L.hash, L.work) and L.work == cpm == res.cpm

@@ -43,10 +43,11 @@ constexpr int HB = 1024;       // threads per block, heavy-pivot kernel
 constexpr u32 LDS_BYTES = 128 * 1024;
 constexpr u32 LDS_WORDS = LDS_BYTES / 4;
 constexpr u64 LDS_BITS = (u64)LDS_BYTES * 8;
-constexpr u32 LOW_WORDS = 6112;  // SPLIT: list entries below the bitmap's window kept in LDS
+constexpr u32 LOW_WORDS = 5088;  // SPLIT: list entries below the bitmap's window kept in LDS
 constexpr u32 STAGE_WORDS = 2 * WAVE;  // per wavefront: 64 staged (endpoint, third vertex) pairs
-// bitmap + low entries + staging for every wavefront: 160 KB in all
-constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + LOW_WORDS * 4 + (HB / WAVE) * STAGE_WORDS * 4;
+constexpr u32 FLAG_WORDS = UN * WAVE / 4;  // per wavefront: seed-start flags of the short-window walk
+// bitmap + low entries + staging and flags for every wavefront: 160 KB in all
+constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + LOW_WORDS * 4 + (HB / WAVE) * (STAGE_WORDS + FLAG_WORDS) * 4;
 static_assert(HEAVY_LDS_BYTES + 64 <= 160 * 1024, "heavy kernel LDS");
 // Tunable launch parameters (defaults; tl_set_tuning or TL_TUNE_* env vars).
 struct Tuning {
@@ -434,13 +435,30 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
     const u32 *T = Form<ALGO>::piv_adj(g);
     WaveEmitter<EMIT> em;
     u64 cnt = 0, hsh = 0;
-    // per wavefront: 64 staged hits (pivot, endpoint, third vertex); its
-    // first 256 bytes also hold the seed-start flags of the short-window walk
+    // per wavefront: 64 staged hits (pivot, endpoint, third vertex) and the
+    // seed-start flags of the short-window walk
     __shared__ uint4 stage_all[(PB / WAVE) * WAVE];
+    __shared__ unsigned char flag_all[(PB / WAVE) * UN * WAVE];
     uint4 *stage = stage_all + wave_id() * WAVE;
-    unsigned char *flag = reinterpret_cast<unsigned char *>(stage);
-    // the hits of a group packed into consecutive lanes, 64 at a time, before
-    // the id lookup, canonical order, digest and store
+    unsigned char *flag = flag_all + wave_id() * (UN * WAVE);
+    // hits are packed into the staging area across groups and finished 64
+    // at a time: id lookup, canonical order, digest and store on full
+    // wavefronts whatever the hit rate
+    u32 staged = 0;  // wave-uniform
+    auto flush = [&](u32 k) {
+        wave_lds_fence();
+        const bool v = (u32)lane < k;
+        u32 ta = 0, tb = 0, tc = 0;
+        if (v) {
+            const uint4 e = stage[lane];
+            ta = e.x; tb = e.y; tc = g.inv[e.z];
+            canon3(ta, tb, tc);
+            cnt += 1;
+            hsh += tri_digest(ta, tb, tc);
+        }
+        wave_lds_fence();
+        em.push(v, ta, tb, tc, o);
+    };
     auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&pv)[UN], const u32 (&xv)[UN]) {
         u64 bal[UN];
         u32 q[UN], tot = 0;
@@ -451,23 +469,19 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
             q[j] = tot + (u32)__popcll(bal[j] & lt);
             tot += (u32)__popcll(bal[j]);
         }
-        for (u32 r0 = 0; r0 < tot; r0 += WAVE) {
+        for (u32 r0 = 0; r0 < tot;) {
+            const u32 room = (u32)WAVE - staged;
 #pragma unroll
             for (int j = 0; j < UN; j++) {
-                if (h[j] && q[j] - r0 < (u32)WAVE) stage[q[j] - r0] = make_uint4(pv[j], xv[j], y[j], 0u);
+                if (h[j] && q[j] - r0 < room) stage[staged + (q[j] - r0)] = make_uint4(pv[j], xv[j], y[j], 0u);
             }
-            wave_lds_fence();
-            const bool v = (u32)lane < tot - r0;
-            u32 ta = 0, tb = 0, tc = 0;
-            if (v) {
-                const uint4 e = stage[lane];
-                ta = e.x; tb = e.y; tc = g.inv[e.z];
-                canon3(ta, tb, tc);
-                cnt += 1;
-                hsh += tri_digest(ta, tb, tc);
+            const u32 take = tot - r0 < room ? tot - r0 : room;
+            staged += take;
+            r0 += take;
+            if (staged == (u32)WAVE) {
+                flush(WAVE);
+                staged = 0;
             }
-            wave_lds_fence();
-            em.push(v, ta, tb, tc, o);
         }
     };
     if (wb < we) {
@@ -552,6 +566,7 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
             cur.advance(kb, c);
         }
     }
+    if (staged) flush(staged);
     em.finish(o);
     flush_counts(cnt, hsh, o.acc);
 }
@@ -608,9 +623,8 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
         const u64 ts = tk.mode == MODE_SPLIT ? uni64(split_at) : t0;
         u32 *low = lds + LDS_WORDS;  // SPLIT: T[t0, ts) when it fits
         uint2 *stage = reinterpret_cast<uint2 *>(lds + LDS_WORDS + LOW_WORDS + (u32)wid * STAGE_WORDS);
-        // seed-start flags of the short-window walk, in the staging area's
-        // first 256 bytes (the two are used one after the other)
-        unsigned char *flag = reinterpret_cast<unsigned char *>(stage);
+        unsigned char *flag =
+            reinterpret_cast<unsigned char *>(lds + LDS_WORDS + LOW_WORDS + HW * STAGE_WORDS + (u32)wid * FLAG_WORDS);
         const bool low_lds = tk.mode == MODE_SPLIT && ts - t0 <= LOW_WORDS;
         if (low_lds) {
             for (u64 i = t0 + threadIdx.x; i < ts; i += blockDim.x) low[i - t0] = pa[i];
@@ -750,11 +764,26 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                         for (int j = 0; j < UN; j++) h[j] = member(y[j]);
                     }
                 };
-                // listed triangles of a group: the hits of all UN chunks are
-                // first packed into consecutive lanes (through this
-                // wavefront's LDS staging area, 64 at a time), so that the id
-                // lookup, canonical order, digest and store run once per 64
-                // triangles rather than once per chunk that holds any
+                // Listed triangles: the hits of every group are packed into
+                // this wavefront's LDS staging area (consecutive slots, kept
+                // across groups), and each time 64 are waiting they are
+                // finished together: the id lookup, canonical order, digest
+                // and store then run on full wavefronts whatever the hit rate.
+                u32 staged = 0;  // hits waiting in the staging area (wave-uniform)
+                auto flush = [&](u32 k) {
+                    wave_lds_fence();
+                    const bool v = (u32)lane < k;
+                    u32 ta = 0, tb = 0, tc = 0;
+                    if (v) {
+                        const uint2 e = stage[lane];
+                        ta = pinv; tb = e.x; tc = g.inv[e.y];
+                        canon3(ta, tb, tc);
+                        cnt += 1;
+                        hsh += tri_digest(ta, tb, tc);
+                    }
+                    wave_lds_fence();
+                    em.push(v, ta, tb, tc, o);
+                };
                 auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
                     u64 bal[UN];
                     u32 q[UN], tot = 0;
@@ -765,23 +794,19 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                         q[j] = tot + (u32)__popcll(bal[j] & lt);  // position among the group's hits
                         tot += (u32)__popcll(bal[j]);
                     }
-                    for (u32 r0 = 0; r0 < tot; r0 += WAVE) {
+                    for (u32 r0 = 0; r0 < tot;) {
+                        const u32 room = (u32)WAVE - staged;
     #pragma unroll
                         for (int j = 0; j < UN; j++) {
-                            if (h[j] && q[j] - r0 < (u32)WAVE) stage[q[j] - r0] = make_uint2(xv[j], y[j]);
+                            if (h[j] && q[j] - r0 < room) stage[staged + (q[j] - r0)] = make_uint2(xv[j], y[j]);
                         }
-                        wave_lds_fence();
-                        const bool v = (u32)lane < tot - r0;
-                        u32 ta = 0, tb = 0, tc = 0;
-                        if (v) {
-                            const uint2 e = stage[lane];
-                            ta = pinv; tb = e.x; tc = g.inv[e.y];
-                            canon3(ta, tb, tc);
-                            cnt += 1;
-                            hsh += tri_digest(ta, tb, tc);
+                        const u32 take = tot - r0 < room ? tot - r0 : room;
+                        staged += take;
+                        r0 += take;
+                        if (staged == (u32)WAVE) {
+                            flush(WAVE);
+                            staged = 0;
                         }
-                        wave_lds_fence();
-                        em.push(v, ta, tb, tc, o);
                     }
                 };
                 // the 64-seed window starting at c0: prefixes, scan starts, endpoint ids
@@ -903,6 +928,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                     kb += WAVE;
                     cur.advance(kb, c);
                 }
+                if (staged) flush(staged);
             }
         };
         switch (tk.mode) {

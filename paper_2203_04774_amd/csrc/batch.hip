@@ -277,12 +277,25 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
     const u32 *SA = Form<ALGO>::scan_adj(g);
     const u32 *T = Form<ALGO>::piv_adj(g);
     GraphAcc ga;
-    // per wavefront: 64 staged hits (pivot, endpoint, third vertex, graph);
-    // its first 256 bytes also hold the short-window walk's seed-start flags
+    // per wavefront: 64 staged hits (pivot, endpoint, third vertex, graph)
+    // and the short-window walk's seed-start flags
     __shared__ uint4 stage_all[(BB / WAVE) * WAVE];
+    __shared__ unsigned char flag_all[(BB / WAVE) * UN * WAVE];
     uint4 *stage = stage_all + wave_id() * WAVE;
-    unsigned char *flag = reinterpret_cast<unsigned char *>(stage);
-    // the hits of a group packed into consecutive lanes, 64 at a time
+    unsigned char *flag = flag_all + wave_id() * (UN * WAVE);
+    // hits are packed into the staging area across groups and finished 64 at a time
+    u32 staged = 0;  // wave-uniform
+    auto flush = [&](u32 k) {
+        wave_lds_fence();
+        if ((u32)lane < k) {
+            const uint4 e = stage[lane];
+            const u32 vb = vbase[e.w];
+            u32 a = e.x - vb, b = e.y - vb, c = g.inv[e.z] - vb;
+            canon3(a, b, c);
+            ga.add(e.w, tri_digest(a, b, c), pg);
+        }
+        wave_lds_fence();
+    };
     auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&pv)[UN], const u32 (&xv)[UN],
                       const u32 (&gv)[UN]) {
         u64 bal[UN];
@@ -294,20 +307,19 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
             q[j] = tot + (u32)__popcll(bal[j] & lt);
             tot += (u32)__popcll(bal[j]);
         }
-        for (u32 r0 = 0; r0 < tot; r0 += WAVE) {
+        for (u32 r0 = 0; r0 < tot;) {
+            const u32 room = (u32)WAVE - staged;
 #pragma unroll
             for (int j = 0; j < UN; j++) {
-                if (h[j] && q[j] - r0 < (u32)WAVE) stage[q[j] - r0] = make_uint4(pv[j], xv[j], y[j], gv[j]);
+                if (h[j] && q[j] - r0 < room) stage[staged + (q[j] - r0)] = make_uint4(pv[j], xv[j], y[j], gv[j]);
             }
-            wave_lds_fence();
-            if ((u32)lane < tot - r0) {
-                const uint4 e = stage[lane];
-                const u32 vb = vbase[e.w];
-                u32 a = e.x - vb, b = e.y - vb, c = g.inv[e.z] - vb;
-                canon3(a, b, c);
-                ga.add(e.w, tri_digest(a, b, c), pg);
+            const u32 take = tot - r0 < room ? tot - r0 : room;
+            staged += take;
+            r0 += take;
+            if (staged == (u32)WAVE) {
+                flush(WAVE);
+                staged = 0;
             }
-            wave_lds_fence();
         }
     };
     if (wb < we) {
@@ -386,6 +398,7 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
             cur.advance(kb, c);
         }
     }
+    if (staged) flush(staged);
     ga.flush(pg);
 }
 
@@ -399,12 +412,13 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
                                                 u32 N, const u32 *gid, const u32 *vbase, u64 *queue, u64 *pg) {
     extern __shared__ u32 bits[];
     __shared__ u64 next;
-    // per wavefront: 64 staged hits (endpoint, third vertex); its first 256
-    // bytes also hold the short-window walk's seed-start flags
+    // per wavefront: 64 staged hits (endpoint, third vertex) and the
+    // short-window walk's seed-start flags
     __shared__ uint2 stage_all[(HBS / WAVE) * WAVE];
+    __shared__ unsigned char flag_all[(HBS / WAVE) * UN * WAVE];
     const int lane = lane_id(), wid = (int)wave_id(), nwv = HBS / WAVE;
     uint2 *stage = stage_all + wid * WAVE;
-    unsigned char *flag = reinterpret_cast<unsigned char *>(stage);
+    unsigned char *flag = flag_all + wid * (UN * WAVE);
     const u64 nheavy = hpre[N];
     const u64 nlight = pos[g.m] & 0xffffffffull;
     const u64 *so = Form<ALGO>::seed_off(g);
@@ -442,7 +456,20 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
             const u32 v = y - tmin;
             return y >= tmin && y <= tmax && ((bits[v >> 5] >> (v & 31)) & 1u);
         };
-        // the hits of a group packed into consecutive lanes, 64 at a time
+        // hits packed into the staging area across groups, finished 64 at a
+        // time (and at the end of the pivot)
+        u32 staged = 0;  // wave-uniform
+        auto flush = [&](u32 k) {
+            wave_lds_fence();
+            if ((u32)lane < k) {
+                const uint2 e = stage[lane];
+                u32 x0 = pl, x1 = e.x - vb, x2 = g.inv[e.y] - vb;
+                canon3(x0, x1, x2);
+                cnt += 1;
+                hsh += tri_digest(x0, x1, x2);
+            }
+            wave_lds_fence();
+        };
         auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
             u64 bal[UN];
             u32 q[UN], tot = 0;
@@ -453,20 +480,19 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
                 q[j] = tot + (u32)__popcll(bal[j] & lt);
                 tot += (u32)__popcll(bal[j]);
             }
-            for (u32 r0 = 0; r0 < tot; r0 += WAVE) {
+            for (u32 r0 = 0; r0 < tot;) {
+                const u32 room = (u32)WAVE - staged;
 #pragma unroll
                 for (int j = 0; j < UN; j++) {
-                    if (h[j] && q[j] - r0 < (u32)WAVE) stage[q[j] - r0] = make_uint2(xv[j], y[j]);
+                    if (h[j] && q[j] - r0 < room) stage[staged + (q[j] - r0)] = make_uint2(xv[j], y[j]);
                 }
-                wave_lds_fence();
-                if ((u32)lane < tot - r0) {
-                    const uint2 e = stage[lane];
-                    u32 x0 = pl, x1 = e.x - vb, x2 = g.inv[e.y] - vb;
-                    canon3(x0, x1, x2);
-                    cnt += 1;
-                    hsh += tri_digest(x0, x1, x2);
+                const u32 take = tot - r0 < room ? tot - r0 : room;
+                staged += take;
+                r0 += take;
+                if (staged == (u32)WAVE) {
+                    flush(WAVE);
+                    staged = 0;
                 }
-                wave_lds_fence();
             }
         };
         if (wb < we) {
@@ -539,6 +565,7 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
                 cur.advance(kb, c);
             }
         }
+        if (staged) flush(staged);
         cnt = wave_sum_u64(cnt);
         hsh = wave_sum_u64(hsh);
         if (lane == 0 && cnt) {

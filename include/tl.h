@@ -345,6 +345,10 @@ void tl_server_destroy(tl_server *s);
  *   force_mode           testing: 0 bitmap, 1 array, 2 global, 3 reverse,
  *                        4 hash, 5 bucket, 6 split for every heavy pivot
  *                        where it fits; 255 = automatic
+ *   plan_full            a seed edge whose scanned list has at most this
+ *                        many entries scans all of it instead of the window
+ *                        found by two binary searches (0..2^20; results are
+ *                        the same, only the work split changes)
  * and for the batched pass (tl_batch_list; a captured pass is captured
  * again when these change):
  *   batch_heavy_min      pruned items of a pivot before its list is marked
@@ -352,6 +356,7 @@ void tl_server_destroy(tl_server *s);
  *   batch_heavy_block    threads of such a workgroup: 256, 512 or 1024
  *   batch_heavy_per_cu   such workgroups per CU (1..2)
  *   batch_light_per_cu   workgroups of the per-item kernel per CU (1..64)
+ *   batch_plan_full      as plan_full, for the batched pass
  * Values apply to later calls in this process; TL_TUNE_<KEY> environment
  * variables (upper case) set the initial values.  Unknown keys or values
  * out of range give TL_EINVAL.

@@ -92,6 +92,7 @@ struct BatchTuning {
     u64 heavy_block = 512;  // threads of a heavy workgroup: 256, 512 or 1024
     u64 heavy_per_cu = 2;   // heavy workgroups per CU
     u64 light_per_cu = 8;   // light workgroups (256 threads) per CU
+    u64 plan_full = 8;      // scanned lists this short are taken whole (no window searches)
 };
 
 std::mutex g_btune_mu;
@@ -107,6 +108,7 @@ BatchTuning &btune() {
         env("TL_TUNE_BATCH_HEAVY_BLOCK", d.heavy_block);
         env("TL_TUNE_BATCH_HEAVY_PER_CU", d.heavy_per_cu);
         env("TL_TUNE_BATCH_LIGHT_PER_CU", d.light_per_cu);
+        env("TL_TUNE_BATCH_PLAN_FULL", d.plan_full);
         if (d.heavy_block != 256 && d.heavy_block != 1024) d.heavy_block = 512;
         if (d.heavy_per_cu < 1 || d.heavy_per_cu > 2) d.heavy_per_cu = 2;
         if (d.light_per_cu < 1 || d.light_per_cu > 64) d.light_per_cu = 8;
@@ -123,8 +125,14 @@ constexpr u32 BH_BITS = BH_LDS_BYTES * 8u;   // rank span it covers
 // The window of seed e in its scanned list: the part of S between the
 // smallest and the largest candidate of T (no other element can match).
 template <int ALGO>
-__device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u64 &abs) {
+__device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u32 full_max, u64 &abs) {
     abs = 0;
+    if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi && sd.s_hi - sd.s_lo <= full_max) {
+        // short list: scanned whole; elements outside the window fail the
+        // membership test like any non-member
+        abs = sd.s_lo;
+        return (u32)(sd.s_hi - sd.s_lo);
+    }
     if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
         const u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
         const u64 a = lower_bound_front<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
@@ -140,7 +148,8 @@ __device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u64 &abs) {
 // lists' lengths).
 // pg holds (count, digest, work) per graph.
 template <int ALGO>
-__global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *lw, u64 *sabs, u64 *wp, u64 *pg) {
+__global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 full_max, u32 *lw, u64 *sabs, u64 *wp,
+                                              u64 *pg) {
     const XcdRange rg(g.m);  // the grid is a multiple of 8 workgroups
     const u64 iters = uni64(rg.wave_iters());
     for (u64 it = 0; it < iters; it++) {
@@ -154,7 +163,7 @@ __global__ __launch_bounds__(BB) void k_bplan(GView g, const u32 *gid, u32 *lw, 
             gr = gid[p];
             w = sd.s_hi - sd.s_lo;
             u64 abs;
-            l = seed_window<ALGO>(sd, abs);
+            l = seed_window<ALGO>(sd, full_max, abs);
             lw[e] = l;
             sabs[e] = abs;
         }
@@ -625,7 +634,7 @@ namespace {
 
 bool same_tune(const BatchTuning &a, const BatchTuning &b) {
     return a.heavy_min == b.heavy_min && a.heavy_block == b.heavy_block && a.heavy_per_cu == b.heavy_per_cu &&
-           a.light_per_cu == b.light_per_cu;
+           a.light_per_cu == b.light_per_cu && a.plan_full == b.plan_full;
 }
 
 // Enqueue the whole listing pass on s (no host waits, no allocation).
@@ -640,7 +649,8 @@ void enqueue_batch_list(tl_batch *b, const BatchTuning &tu, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, b->ctl, 1ull, 0ull);
     // the seeds' window starts live in cpre's buffer until the compaction
     // has read them; the scan of the compacted lengths then overwrites them
-    hipLaunchKernelGGL((k_bplan<ALGO>), dim3(grid_x8(m)), dim3(BB), 0, s, v, b->gid, b->lw, b->cpre, b->wp, b->pg);
+    hipLaunchKernelGGL((k_bplan<ALGO>), dim3(grid_x8(m)), dim3(BB), 0, s, v, b->gid, (u32)tu.plan_full, b->lw, b->cpre,
+                       b->wp, b->pg);
     hipLaunchKernelGGL((k_bclass<ALGO>), dim3(grid_b(N)), dim3(BB), 0, s, v, (u32)N, b->wp, tu.heavy_min, b->hflag);
     hipLaunchKernelGGL((k_bflag<ALGO>), dim3(grid_b(m)), dim3(BB), 0, s, v, b->lw, b->hflag, b->f64);
     scan_u64_to_u64(b->f64, b->pos, m, s, b->ws);
@@ -681,6 +691,7 @@ int batch_set_tuning(const std::string &key, u64 value) {
     else if (key == "batch_heavy_block" && (value == 256 || value == 512 || value == 1024)) t.heavy_block = value;
     else if (key == "batch_heavy_per_cu" && value >= 1 && value <= 2) t.heavy_per_cu = value;
     else if (key == "batch_light_per_cu" && value >= 1 && value <= 64) t.light_per_cu = value;
+    else if (key == "batch_plan_full" && value <= (1u << 20)) t.plan_full = value;
     else return TL_EINVAL;
     return TL_OK;
 }
@@ -692,6 +703,7 @@ int batch_get_tuning(const std::string &key, u64 *value) {
     else if (key == "batch_heavy_block") *value = t.heavy_block;
     else if (key == "batch_heavy_per_cu") *value = t.heavy_per_cu;
     else if (key == "batch_light_per_cu") *value = t.light_per_cu;
+    else if (key == "batch_plan_full") *value = t.plan_full;
     else return TL_EINVAL;
     return TL_OK;
 }

@@ -66,6 +66,7 @@ struct Tuning {
     u64 split = 2;               // 1: SPLIT for lists too long for LDS; 2: also before ARRAY/BUCKET
     u64 orient_sort = 1;         // 1: orientation by radix sort; 0: by per-vertex counters and scatter
     u64 force_mode = 255;        // testing: use this MODE_* for every heavy pivot where it fits
+    u64 plan_full = 16;          // scanned lists this short are taken whole (no window searches)
 };
 Tuning &tuning();
 
@@ -139,7 +140,8 @@ __host__ __device__ __forceinline__ void wave_share(u64 a, u64 b, u32 nwv, u32 w
 // Window of every seed edge; per-pivot work W_p (segmented by pivot, since
 // seeds are pivot-major); the paper's work for the listed pivots.
 template <int ALGO>
-__global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len, u64 *sabs, u64 *wp, u64 *acc) {
+__global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 full_max, u32 *len, u64 *sabs, u64 *wp,
+                                             u64 *acc) {
     __shared__ u64 lds[PB / WAVE];
     u64 work = 0;
     const int lane = lane_id();
@@ -157,11 +159,18 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 *len
             if (sd.p >= plo && sd.p < phi) {
                 work += sd.s_hi - sd.s_lo;
                 if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
-                    u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
-                    u64 a = lower_bound_front<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
-                    u64 b = upper_bound_back<u32>(sd.S, a, sd.s_hi, tmax);
-                    l = (u32)(b - a);
-                    abs = a;
+                    if (sd.s_hi - sd.s_lo <= full_max) {
+                        // short list: scanned whole; the elements outside the
+                        // window fail the membership test like any non-member
+                        l = (u32)(sd.s_hi - sd.s_lo);
+                        abs = sd.s_lo;
+                    } else {
+                        u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
+                        u64 a = lower_bound_front<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
+                        u64 b = upper_bound_back<u32>(sd.S, a, sd.s_hi, tmax);
+                        l = (u32)(b - a);
+                        abs = a;
+                    }
                 }
             }
             len[e] = l;
@@ -724,14 +733,14 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                         // skipped when no lane has such an element (the usual case)
                         bool below = false;
     #pragma unroll
-                        for (int j = 0; j < UN; j++) below |= y[j] < wlo;
+                        for (int j = 0; j < UN; j++) below |= y[j] < wlo && y[j] >= tmin;
                         if (__ballot(below)) {
                             u64 lo[UN], hi[UN];
                             const u64 base = low_lds ? 0 : t0, top = low_lds ? ts - t0 : ts;
     #pragma unroll
                             for (int j = 0; j < UN; j++) {
                                 lo[j] = base;
-                                hi[j] = y[j] >= wlo ? base : top;
+                                hi[j] = (y[j] >= wlo || y[j] < tmin) ? base : top;
                             }
                             member_multi_var(low_lds ? low : pa, lo, hi, y, h);
                         } else {
@@ -1029,7 +1038,8 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
     const unsigned gn = grid_for(n, PB, (unsigned)tl_num_cus() * 16);
     DevBuf len(m * sizeof(u32), s), sabs(m * sizeof(u64), s), wp((u64)n * sizeof(u64), s);
     TL_HIP(hipMemsetAsync(wp.p, 0, (u64)n * sizeof(u64), s));
-    hipLaunchKernelGGL((k_plan<ALGO>), dim3(gm), dim3(PB), 0, s, v, plo, phi, len.as<u32>(), sabs.as<u64>(),
+    hipLaunchKernelGGL((k_plan<ALGO>), dim3(gm), dim3(PB), 0, s, v, plo, phi, (u32)tuning().plan_full, len.as<u32>(),
+                       sabs.as<u64>(),
                        wp.as<u64>(), d_acc);
     TL_HIP(hipGetLastError());
     DevBuf mode((u64)n * sizeof(u32), s), ntask((u64)n * sizeof(u32), s), slice((u64)n * sizeof(u64), s);
@@ -1183,6 +1193,7 @@ Tuning &tuning() {
         env("TL_TUNE_SPLIT", d.split);
         env("TL_TUNE_ORIENT_SORT", d.orient_sort);
         env("TL_TUNE_FORCE_MODE", d.force_mode);
+        env("TL_TUNE_PLAN_FULL", d.plan_full);
         return d;
     }();
     return t;
@@ -1235,6 +1246,7 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "split" && value <= 2) t.split = value;
     else if (k == "orient_sort" && value <= 1) t.orient_sort = value;
     else if (k == "force_mode" && (value < NMODES || value == 255)) t.force_mode = value;
+    else if (k == "plan_full" && value <= (1u << 20)) t.plan_full = value;
     else return TL_EINVAL;
     return TL_OK;
 }
@@ -1256,6 +1268,7 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "split") *value = t.split;
     else if (k == "orient_sort") *value = t.orient_sort;
     else if (k == "force_mode") *value = t.force_mode;
+    else if (k == "plan_full") *value = t.plan_full;
     else return TL_EINVAL;
     return TL_OK;
 }

@@ -583,9 +583,10 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
 // Heavy tasks: one workgroup stages the pivot's list in LDS, then its
 // wavefronts share the task's items.  Items are clipped to [k0, k1).
 template <int ALGO, bool EMIT>
-__global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, u64 ntasks, const u32 *cseed,
-                                                    const u64 *cabs, const u32 *cxinv, const u64 *cpre, u64 k0,
-                                                    u64 k1, Out o, int use_queue, int use_splits) {
+__global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restrict__ tasks, u64 ntasks,
+                                                    const u32 *__restrict__ cseed, const u64 *__restrict__ cabs,
+                                                    const u32 *__restrict__ cxinv, const u64 *__restrict__ cpre,
+                                                    u64 k0, u64 k1, Out o, int use_queue, int use_splits) {
     extern __shared__ u32 lds[];  // the pivot list: B as a bitmap, or a sorted array
     const int lane = lane_id(), wid = (int)wave_id(), nwv = blockDim.x / WAVE;
     const u32 *SA = Form<ALGO>::scan_adj(g);
@@ -747,13 +748,35 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
     #pragma unroll
                             for (int j = 0; j < UN; j++) h[j] = false;
                         }
+                        // the bitmap part, branch-free: every word is read (index
+                        // clamped into the bitmap) so that the UN reads overlap
+                        u32 w[UN], v[UN];
     #pragma unroll
                         for (int j = 0; j < UN; j++) {
-                            if (y[j] >= wlo) {
-                                const u32 v = y[j] - wlo;
-                                h[j] = y[j] <= tmax && ((lds[v >> 5] >> (v & 31)) & 1u);
-                            }
+                            const u32 d = y[j] - wlo;
+                            v[j] = d < (u32)(LDS_BITS - 1) ? d : (u32)(LDS_BITS - 1);
+                            w[j] = lds[v[j] >> 5];
                         }
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            const bool in = (y[j] >= wlo) & (y[j] <= tmax);
+                            const bool bit = (w[j] >> (v[j] & 31)) & 1u;
+                            h[j] = in ? bit : h[j];
+                        }
+                    } else if (MD == MODE_BITMAP) {
+                        // branch-free: the index is clamped into the bitmap and the
+                        // word always read, so that the UN reads overlap; an
+                        // element outside [tmin, tmax] is rejected by the range test
+                        const u32 span = tmax - tmin;
+                        u32 w[UN], v[UN];
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            const u32 d = y[j] - tmin;
+                            v[j] = d < (u32)(LDS_BITS - 1) ? d : (u32)(LDS_BITS - 1);
+                            w[j] = lds[v[j] >> 5];
+                        }
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) h[j] = ((y[j] - tmin) <= span) & ((w[j] >> (v[j] & 31)) & 1u);
                     } else if (MD == MODE_BUCKET) {
                         u64 lo[UN], hi[UN];
     #pragma unroll
@@ -835,6 +858,10 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                         kb + HG * UN * WAVE <= we) {
                         // HG groups of UN full chunks inside one seed window: all
                         // loads in flight before the first test (one LDS read each)
+                        if (xinv_c != cur.c_lo) {  // once per seed, before the element loads
+                            xinv = cxinv[cur.c_lo];
+                            xinv_c = cur.c_lo;
+                        }
                         const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
                         u32 y[HG][UN], xv[UN];
                         bool h[UN];
@@ -842,10 +869,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                         for (int q = 0; q < HG; q++)
 #pragma unroll
                             for (int j = 0; j < UN; j++) y[q][j] = SA[sab + (u64)(q * UN + j) * WAVE];
-                        if (xinv_c != cur.c_lo) {  // once per seed
-                            xinv = cxinv[cur.c_lo];
-                            xinv_c = cur.c_lo;
-                        }
 #pragma unroll
                         for (int j = 0; j < UN; j++) xv[j] = xinv;
 #pragma unroll
@@ -859,15 +882,15 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *tasks, 
                     }
                     if (cur.end >= kb + UN * WAVE && kb + UN * WAVE <= we) {
                         // UN full chunks inside one seed window
+                        if (xinv_c != cur.c_lo) {  // once per seed, before the element loads
+                            xinv = cxinv[cur.c_lo];
+                            xinv_c = cur.c_lo;
+                        }
                         const u64 sab = cabs[cur.c_lo] + (kb - cur.base) + lane;
                         u32 y[UN], xv[UN];
                         bool h[UN];
     #pragma unroll
                         for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
-                        if (xinv_c != cur.c_lo) {  // once per seed
-                            xinv = cxinv[cur.c_lo];
-                            xinv_c = cur.c_lo;
-                        }
     #pragma unroll
                         for (int j = 0; j < UN; j++) xv[j] = xinv;
                         member_all(y, h);

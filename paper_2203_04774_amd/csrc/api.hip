@@ -289,6 +289,7 @@ void tl_csr_free(tl_csr *g) {
     tl_dev_free(g->off_b);
     tl_dev_free(g->adj_b);
     tl_dev_free(g->row_b);
+    tl_dev_free(g->twin_b);
     tl_dev_free(g->inv);
     delete g;
 }

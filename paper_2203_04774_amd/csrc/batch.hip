@@ -136,7 +136,9 @@ __device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u32 full_max, u
     if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
         const u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
         const u64 a = lower_bound_front<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
-        const u64 b = upper_bound_back<u32>(sd.S, a, sd.s_hi, tmax);
+        // A++: the pivot p itself sits in S = N+_x at twin_b[e], above every
+        // candidate, so the window ends at or before it
+        const u64 b = upper_bound_back<u32>(sd.S, a, ALGO == 0 ? (u64)sd.twin : sd.s_hi, tmax);
         abs = a;
         return (u32)(b - a);
     }
@@ -641,7 +643,7 @@ bool same_tune(const BatchTuning &a, const BatchTuning &b) {
 template <int ALGO>
 void enqueue_batch_list(tl_batch *b, const BatchTuning &tu, hipStream_t s) {
     const tl_csr *g = b->g;
-    const GView v{g->off_f, g->off_b, g->adj_f, g->adj_b, g->row_f, g->row_b, g->inv, g->m};
+    const GView v{g->off_f, g->off_b, g->adj_f, g->adj_b, g->row_f, g->row_b, g->inv, g->m, g->twin_b};
     const u64 m = g->m, N = b->N;
     const unsigned cus = (unsigned)tl_num_cus();
     hipLaunchKernelGGL(k_fill_u64, dim3(grid_b(3ull * b->k)), dim3(BB), 0, s, b->pg, 3ull * b->k, 0ull);

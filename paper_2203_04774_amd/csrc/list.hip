@@ -167,7 +167,9 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 full
                     } else {
                         u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
                         u64 a = lower_bound_front<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
-                        u64 b = upper_bound_back<u32>(sd.S, a, sd.s_hi, tmax);
+                        // A++: the pivot p itself sits in S = N+_x at twin_b[e],
+                        // above every candidate, so the window ends at or before it
+                        u64 b = upper_bound_back<u32>(sd.S, a, ALGO == 0 ? (u64)sd.twin : sd.s_hi, tmax);
                         l = (u32)(b - a);
                         abs = a;
                     }
@@ -1036,7 +1038,7 @@ __global__ __launch_bounds__(PB) void k_cost(const u64 *off_f, const u64 *off_b,
 u64 g_chunk_triangles = 1ull << 24;
 
 GView view_of(const tl_csr *g) {
-    return GView{g->off_f, g->off_b, g->adj_f, g->adj_b, g->row_f, g->row_b, g->inv, g->m};
+    return GView{g->off_f, g->off_b, g->adj_f, g->adj_b, g->row_f, g->row_b, g->inv, g->m, g->twin_b};
 }
 
 // Everything a listing's probe phase needs, produced by the plan.

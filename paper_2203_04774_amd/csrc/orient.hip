@@ -142,16 +142,30 @@ __global__ void k_run_count(const u32 *row, u64 m, u32 *cnt) {
     }
 }
 
-__global__ void k_bwd_keys(const u32 *adj_f, const u32 *row_f, u64 m, int b, u64 *keys) {
-    GRID_STRIDE(j, m) { keys[j] = ((u64)adj_f[j] << b) | row_f[j]; }
+// backward keys: column above, the forward entry's index below (m < 2^32);
+// a stable sort on the column field keeps each column's entries in forward
+// order, i.e. by row
+__global__ void k_bwd_keys(const u32 *adj_f, u64 m, u64 *keys) {
+    GRID_STRIDE(j, m) { keys[j] = ((u64)adj_f[j] << 32) | (u32)j; }
 }
 
-__global__ void k_bwd_emit(const u64 *keys, u64 m, int b, u32 *adj_b, u32 *row_b) {
-    const u64 mask = (1ull << b) - 1;
+__global__ void k_bwd_emit(const u64 *keys, u64 m, const u32 *row_f, u32 *adj_b, u32 *row_b, u32 *twin_b) {
     GRID_STRIDE(j, m) {
         const u64 k = keys[j];
-        adj_b[j] = (u32)(k & mask);
-        row_b[j] = (u32)(k >> b);
+        const u32 i = (u32)k;
+        adj_b[j] = row_f[i];
+        row_b[j] = (u32)(k >> 32);
+        twin_b[j] = i;
+    }
+}
+
+// twin_b[j] for a backward CSR built without the index: the position of the
+// entry's row in its column vertex's successor list
+__global__ void k_twin_search(const u64 *off_f, const u32 *adj_f, const u32 *adj_b, const u32 *row_b, u64 m,
+                              u32 *twin_b) {
+    GRID_STRIDE(j, m) {
+        const u32 u = adj_b[j], v = row_b[j];
+        twin_b[j] = (u32)lower_bound_dev<u32>(adj_f, off_f[u], off_f[u + 1], v);
     }
 }
 
@@ -214,12 +228,14 @@ void orient_sorted(tl_csr *g, u32 n, const u32 *src, const u32 *dst, u64 m_in, c
     // (lo, hi) already, so a stable sort on the hi field alone suffices.
     g->adj_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
     g->row_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
+    g->twin_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
     if (n) TL_HIP(hipMemsetAsync(cnt, 0, (u64)n * sizeof(u32), s));
     if (m) {
-        hipLaunchKernelGGL(k_bwd_keys, dim3(grid_n(m)), dim3(256), 0, s, g->adj_f, g->row_f, m, b, keys.as<u64>());
+        hipLaunchKernelGGL(k_bwd_keys, dim3(grid_n(m)), dim3(256), 0, s, g->adj_f, m, keys.as<u64>());
         TL_HIP(hipGetLastError());
-        const u64 *sorted = radix_sort_u64(keys.as<u64>(), tmp.as<u64>(), m, b, b, s);
-        hipLaunchKernelGGL(k_bwd_emit, dim3(grid_n(m)), dim3(256), 0, s, sorted, m, b, g->adj_b, g->row_b);
+        const u64 *sorted = radix_sort_u64(keys.as<u64>(), tmp.as<u64>(), m, 32, b, s);
+        hipLaunchKernelGGL(k_bwd_emit, dim3(grid_n(m)), dim3(256), 0, s, sorted, m, g->row_f, g->adj_b, g->row_b,
+                           g->twin_b);
         TL_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_run_count, dim3(grid_n(m)), dim3(256), 0, s, g->row_b, m, cnt);
         TL_HIP(hipGetLastError());
@@ -321,6 +337,7 @@ tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *
     // ---- 5. backward CSR (predecessor lists)
     g->adj_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
     g->row_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
+    g->twin_b = (u32 *)tl_dev_alloc((m ? m : 1) * sizeof(u32), s);
     if (n) TL_HIP(hipMemsetAsync(rowcnt, 0, (u64)n * sizeof(u32), s));
     if (m) {
         hipLaunchKernelGGL(k_count_targets, dim3(grid_n(m)), dim3(256), 0, s, g->adj_f, m, rowcnt);
@@ -333,6 +350,9 @@ tl_csr *orient_impl(u32 n, const u32 *src, const u32 *dst, u64 m_in, const u32 *
                            rowcnt, g->adj_b, g->row_b);
         TL_HIP(hipGetLastError());
         segmented_sort_unique(g->off_b, n, g->adj_b, m, n, uniq.as<u32>(), s);
+        hipLaunchKernelGGL(k_twin_search, dim3(grid_n(m)), dim3(256), 0, s, g->off_f, g->adj_f, g->adj_b, g->row_b,
+                           m, g->twin_b);
+        TL_HIP(hipGetLastError());
     }
 
     // ---- 6. inverse permutation

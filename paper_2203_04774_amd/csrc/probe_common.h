@@ -12,6 +12,7 @@ struct GView {
     const u64 *off_f, *off_b;
     const u32 *adj_f, *adj_b, *row_f, *row_b, *inv;
     u64 m;
+    const u32 *twin_b;  // twin_b[e]: where backward entry e's edge sits in adj_f
 };
 
 // Seed-edge geometry for the three forms.
@@ -22,11 +23,14 @@ struct Seed {
     u64 s_lo, s_hi;
     const u32 *T;      // target array, candidates T[t_lo .. t_hi)
     u64 t_lo, t_hi;
+    u32 twin;          // A++: index of p in S (S[twin] = p)
     __device__ __forceinline__ Seed(const GView &g, u64 e) {
+        twin = 0;
         if (ALGO == 0) {
             p = g.row_b[e]; x = g.adj_b[e];
             S = g.adj_f; s_lo = g.off_f[x]; s_hi = g.off_f[x + 1];
             T = g.adj_b; t_lo = e + 1; t_hi = g.off_b[p + 1];
+            twin = g.twin_b[e];
         } else if (ALGO == 1) {
             p = g.row_f[e]; x = g.adj_f[e];
             S = g.adj_f; s_lo = g.off_f[x]; s_hi = g.off_f[x + 1];

@@ -90,6 +90,7 @@ struct tl_csr {
     u64 *off_b = nullptr;  // n+1: backward CSR offsets
     u32 *adj_b = nullptr;  // m:   predecessor ranks, rows ascending
     u32 *row_b = nullptr;  // m:   row (target rank) of each backward entry
+    u32 *twin_b = nullptr; // m:   index in adj_f of each backward entry's edge
     u32 *inv = nullptr;    // n:   inv[r] = vertex of rank r
 };
 

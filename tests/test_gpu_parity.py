@@ -449,17 +449,23 @@ def test_orient_sort_and_scatter_agree(tl, case):
         n, s, d = g.n, g.src, g.dst
         r = graphgen.random_order(n, seed=5)
     saved = tl.get_tuning("orient_sort")
-    arrays = []
+    arrays, listed = [], []
     try:
         for way in (1, 0):
             tl.set_tuning("orient_sort", way)
             c = tl.orient(n, dev(s), dev(d), dev(r))
             arrays.append(c.to_host())
+            # the A++ plan ends each window at the pivot's own place in the
+            # scanned list, which each way records while orienting
+            sm = tl.list_triangles(c, "A++")
+            listed.append((sm.count, sm.hash, sm.work))
             c.free()
     finally:
         tl.set_tuning("orient_sort", saved)
     for a, b in zip(arrays[0], arrays[1]):
         assert np.array_equal(a, b)
+    ref = oracle.list_triangles(n, s, d, r, "A++", want_triangles=False)
+    assert listed[0] == listed[1] == (ref.count, ref.hash, ref.work)
     fo, fa, bo, ba, inv = oracle.oriented_csr(n, s, d, r)
     got = arrays[0]
     assert np.array_equal(got[0], fo) and np.array_equal(got[1], fa)

@@ -363,7 +363,7 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
                     const u64 A = inw ? L.cabs[ci] : 0ull;
                     const u32 X = inw ? L.cxinv[ci] : 0u, PI = inw ? L.cpinv[ci] : 0u, GI = inw ? L.cgid[ci] : 0u;
                     const u32 TL = inw ? L.ctlo[ci] : 0u, TH = inw ? L.cthi[ci] : 0u;
-                    const u64 D = A - P;  // item k of seed c is at scan index D[c] + k
+                    const u32 E = (u32)(A - P + kb);  // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
                     int lo[UN];
                     const int lo_last = locate_short(P, kb, flag, lo);
                     u32 y[UN], pv[UN], xv[UN], gv[UN];
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
                     bool h[UN];
 #pragma unroll
                     for (int j = 0; j < UN; j++) {
-                        y[j] = SA[shfl_u64(D, lo[j]) + (kb + (u64)(j * WAVE + lane))];
+                        y[j] = SA[(u32)(__shfl(E, lo[j], WAVE) + (u32)(j * WAVE + lane))];
                         xv[j] = __shfl(X, lo[j], WAVE);
                         pv[j] = __shfl(PI, lo[j], WAVE);
                         gv[j] = __shfl(GI, lo[j], WAVE);
@@ -536,14 +536,14 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *po
                     if (pend >= kb + UN * WAVE) {
                         const u64 A = inw ? L.cabs[ci] : 0ull;
                         const u32 X = inw ? L.cxinv[ci] : 0u;
-                        const u64 D = A - P;  // item k of seed c is at scan index D[c] + k
+                        const u32 E = (u32)(A - P + kb);  // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
                         int lo[UN];
                         const int lo_last = locate_short(P, kb, flag, lo);
                         u32 y[UN], xv[UN];
                         bool h[UN];
 #pragma unroll
                         for (int j = 0; j < UN; j++) {
-                            y[j] = SA[shfl_u64(D, lo[j]) + (kb + (u64)(j * WAVE + lane))];
+                            y[j] = SA[(u32)(__shfl(E, lo[j], WAVE) + (u32)(j * WAVE + lane))];
                             xv[j] = __shfl(X, lo[j], WAVE);
                         }
 #pragma unroll

@@ -53,7 +53,7 @@ static_assert(HEAVY_LDS_BYTES + 64 <= 160 * 1024, "heavy kernel LDS");
 struct Tuning {
     // defaults from sweeps on the Chung-Lu 2^20 workload (random and degree
     // orders, A++ and A+-) on MI355X
-    u64 heavy_min = 16384;       // items of a pivot before it gets a workgroup
+    u64 heavy_min = 8192;        // items of a pivot before it gets a workgroup
     u64 slice_min = 262144;      // items per heavy task, at least
     u64 slice_mult = 16;         // ... and at least this many times its staging cost
     u64 heavy_blocks_per_cu = 1; // heavy grid = this many workgroups per CU
@@ -527,8 +527,7 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
                     const u64 A = inw ? L.cabs[ci] : 0ull;
                     const u32 X = inw ? L.cxinv[ci] : 0u, PI = inw ? L.cpinv[ci] : 0u;
                     const u32 TL = inw ? L.ctlo[ci] : 0u, TH = inw ? L.cthi[ci] : 0u;
-                    // item k of seed c is at scan index (A - P)[c] + k
-                    const u64 D = A - P;
+                    const u32 E = (u32)(A - P + kb);  // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
                     int lo[UN];
                     const int lo_last = locate_short(P, kb, flag, lo);
                     u32 y[UN], pv[UN], xv[UN];
@@ -536,7 +535,7 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 n
                     bool h[UN];
 #pragma unroll
                     for (int j = 0; j < UN; j++) {
-                        y[j] = SA[shfl_u64(D, lo[j]) + (kb + (u64)(j * WAVE + lane))];
+                        y[j] = SA[(u32)(__shfl(E, lo[j], WAVE) + (u32)(j * WAVE + lane))];
                         xv[j] = __shfl(X, lo[j], WAVE);
                         pv[j] = __shfl(PI, lo[j], WAVE);
                         tl[j] = __shfl(TL, lo[j], WAVE);
@@ -915,15 +914,14 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                             fetch_window(cur.c_lo, P, A, X, pend);
                         }
                         if (pend >= kb + UN * WAVE) {
-                            // item k of seed c is at scan index (A - P)[c] + k
-                            const u64 D = A - P;
+                            const u32 E = (u32)(A - P + kb);  // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
                             int lo[UN];
                             const int lo_last = locate_short(P, kb, flag, lo);
                             u32 y[UN], xv[UN];
                             bool h[UN];
 #pragma unroll
                             for (int j = 0; j < UN; j++) {
-                                y[j] = SA[shfl_u64(D, lo[j]) + (kb + (u64)(j * WAVE + lane))];
+                                y[j] = SA[(u32)(__shfl(E, lo[j], WAVE) + (u32)(j * WAVE + lane))];
                                 xv[j] = __shfl(X, lo[j], WAVE);
                             }
                             const u64 kn = kb + UN * WAVE;

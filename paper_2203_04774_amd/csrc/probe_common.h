@@ -146,19 +146,21 @@ __device__ __forceinline__ int locate_short(u64 P, u64 kb, unsigned char *flag, 
 }
 
 // UN independent branchless membership tests of y[j] in the sorted list
-// T[lo, hi) (the same list for all j), so their loads overlap.
-__device__ __forceinline__ void member_multi(const u32 *T, u64 lo, u64 hi, const u32 (&y)[UN], bool (&hit)[UN]) {
-    u64 n = hi - lo;
+// T[lo, hi) (the same list for all j), so their loads overlap.  Indices are
+// 32-bit: adjacency arrays hold fewer than 2^32 entries.
+__device__ __forceinline__ void member_multi(const u32 *T, u64 lo64, u64 hi64, const u32 (&y)[UN], bool (&hit)[UN]) {
+    const u32 lo = (u32)lo64;
+    u32 n = (u32)(hi64 - lo64);
     if (n == 0) {
 #pragma unroll
         for (int j = 0; j < UN; j++) hit[j] = false;
         return;
     }
-    u64 b[UN];
+    u32 b[UN];
 #pragma unroll
     for (int j = 0; j < UN; j++) b[j] = lo;
     while (n > 1) {
-        const u64 half = n >> 1;
+        const u32 half = n >> 1;
 #pragma unroll
         for (int j = 0; j < UN; j++) b[j] = (T[b[j] + half] <= y[j]) ? b[j] + half : b[j];
         n -= half;
@@ -170,12 +172,12 @@ __device__ __forceinline__ void member_multi(const u32 *T, u64 lo, u64 hi, const
 // As member_multi, with a different list T[lo[j], hi[j]) per element.
 __device__ __forceinline__ void member_multi_var(const u32 *T, const u64 (&lo)[UN], const u64 (&hi)[UN],
                                                  const u32 (&y)[UN], bool (&hit)[UN]) {
-    u64 b[UN], n[UN];
-    u64 nmax = 0;
+    u32 b[UN], n[UN];
+    u32 nmax = 0;
 #pragma unroll
     for (int j = 0; j < UN; j++) {
-        b[j] = lo[j];
-        n[j] = hi[j] > lo[j] ? hi[j] - lo[j] : 0;
+        b[j] = (u32)lo[j];
+        n[j] = hi[j] > lo[j] ? (u32)(hi[j] - lo[j]) : 0u;
         nmax = n[j] > nmax ? n[j] : nmax;
     }
     while (nmax > 1) {
@@ -183,7 +185,7 @@ __device__ __forceinline__ void member_multi_var(const u32 *T, const u64 (&lo)[U
 #pragma unroll
         for (int j = 0; j < UN; j++) {
             if (n[j] > 1) {
-                const u64 half = n[j] >> 1;
+                const u32 half = n[j] >> 1;
                 b[j] = (T[b[j] + half] <= y[j]) ? b[j] + half : b[j];
                 n[j] -= half;
             }

@@ -2,10 +2,12 @@
 //
 // Each pass: every tile of RT keys counts its digits in LDS (k_rs_hist,
 // counts stored digit-major so that one exclusive scan gives every tile's
-// global offset per digit); then each tile ranks its keys by digit with
-// wavefront ballots (stable: tile order is kept within a digit), stages
-// them sorted in LDS and writes each digit's run to its global segment, so
-// that consecutive lanes write consecutive addresses.
+// global offset per digit); then each wavefront of the tile ranks its own
+// contiguous run of keys by digit with ballots against per-wavefront digit
+// counters (stable: key order is kept within a digit), the counters become
+// offsets, the tile's keys are staged sorted in LDS and each digit's run is
+// written to its global segment, so that consecutive lanes write
+// consecutive addresses.
 #include "tl_internal.h"
 #include "dev_util.h"
 
@@ -35,8 +37,8 @@ __global__ __launch_bounds__(RB) void k_rs_hist(const u64 *keys, u64 n, int sh, 
 __global__ __launch_bounds__(RB) void k_rs_scatter(const u64 *in, u64 *out, u64 n, int sh, const u32 *counts,
                                                    const u64 *offs, u64 ntiles) {
     __shared__ u64 stage[RT];
-    __shared__ u32 tbase[RD], run[RD];
-    __shared__ u32 wcnt[RNW][RD];
+    __shared__ u32 tbase[RD];
+    __shared__ u32 wcnt[RNW][RD];  // per wavefront: keys of each digit seen so far, then its offset
     __shared__ u64 gbase[RD];
     __shared__ u64 lds64[RNW];
     const int t = threadIdx.x, lane = lane_id(), wid = t / WAVE;
@@ -48,42 +50,61 @@ __global__ __launch_bounds__(RB) void k_rs_scatter(const u64 *in, u64 *out, u64 
         u64 tot;
         tbase[t] = (u32)block_excl_scan_u64<RB>(c, lds64, tot);
         gbase[t] = offs[(u64)t * ntiles + tile];
-        run[t] = 0;
+#pragma unroll
+        for (int w = 0; w < RNW; w++) wcnt[w][t] = 0;
     }
     __syncthreads();
+    // Each wavefront takes a contiguous run of RI * 64 keys (coalesced
+    // loads) and ranks them round by round against its own digit counters;
+    // one wavefront's LDS operations run in order, so no barrier is needed.
+    const u64 wbase = base + (u64)wid * (RI * WAVE);
+    u64 k[RI];
+    u32 rk[RI];
+#pragma unroll
     for (int r = 0; r < RI; r++) {
-        const u64 i = base + (u64)r * RB + t;
+        const u64 i = wbase + (u64)r * WAVE + lane;
         const bool valid = i < n;
-        const u64 k = valid ? in[i] : 0ull;
-        const u32 d = (u32)(k >> sh) & 255u;
+        k[r] = valid ? in[i] : 0ull;
+        const u32 d = (u32)(k[r] >> sh) & 255u;
         u64 mask = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
             const u64 bb = __ballot((d >> b) & 1u);
             mask &= ((d >> b) & 1u) ? bb : ~bb;
         }
-        const u32 rk = __popcll(mask & lanemask_lt());
-#pragma unroll
-        for (int w = 0; w < RNW; w++) wcnt[w][t] = 0;
-        __syncthreads();
-        if (valid && rk == 0) wcnt[wid][d] = __popcll(mask);
-        __syncthreads();
-        if (valid) {
-            u32 p = tbase[d] + run[d] + rk;
-            for (int w = 0; w < wid; w++) p += wcnt[w][d];
-            stage[p] = k;
-        }
-        __syncthreads();
-        u32 add = 0;
-#pragma unroll
-        for (int w = 0; w < RNW; w++) add += wcnt[w][t];
-        run[t] += add;
-        __syncthreads();
+        const u32 below = __popcll(mask & lanemask_lt());
+        wave_lds_fence();
+        const u32 seen = wcnt[wid][d];
+        rk[r] = seen + below;
+        wave_lds_fence();
+        if (valid && below == 0) wcnt[wid][d] = seen + (u32)__popcll(mask);
+        wave_lds_fence();
     }
+    __syncthreads();
+    // offset of each wavefront's block of digit d inside the tile's run of d
+    {
+        u32 acc = tbase[t];
+#pragma unroll
+        for (int w = 0; w < RNW; w++) {
+            const u32 c = wcnt[w][t];
+            wcnt[w][t] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RI; r++) {
+        const u64 i = wbase + (u64)r * WAVE + lane;
+        if (i < n) {
+            const u32 d = (u32)(k[r] >> sh) & 255u;
+            stage[wcnt[wid][d] + rk[r]] = k[r];
+        }
+    }
+    __syncthreads();
     for (u32 j = t; j < cnt; j += RB) {
-        const u64 k = stage[j];
-        const u32 d = (u32)(k >> sh) & 255u;
-        out[gbase[d] + (j - tbase[d])] = k;
+        const u64 key = stage[j];
+        const u32 d = (u32)(key >> sh) & 255u;
+        out[gbase[d] + (j - tbase[d])] = key;
     }
 }
 

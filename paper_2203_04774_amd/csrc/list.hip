@@ -434,7 +434,12 @@ struct LightSeeds {
 // chunks of 64 items at a time whenever they fall in one seed window or in
 // the 64 seeds starting at the current one.
 template <int ALGO, bool EMIT>
-__global__ __launch_bounds__(PB) void k_probe_light(GView g, LightSeeds L, u64 ncap, u64 k0, u64 k1, Out o) {
+__global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restrict__ cpre, const u64 *__restrict__ cabs,
+                                                    const u32 *__restrict__ cxinv, const u32 *__restrict__ ctlo,
+                                                    const u32 *__restrict__ cthi, const u32 *__restrict__ cpinv,
+                                                    u64 ncap, u64 k0, u64 k1, Out o) {
+    // restrict-qualified arguments: reads at wave-uniform indices become scalar loads
+    const LightSeeds L{cpre, cabs, cxinv, ctlo, cthi, cpinv};
     const int lane = lane_id();
     const u64 gw = (u64)blockIdx.x * (blockDim.x / WAVE) + wave_id();
     const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
@@ -1140,12 +1145,13 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
         u64 blocks = (waves_needed + (PB / WAVE) - 1) / (PB / WAVE);
         if (blocks > light_max_blocks()) blocks = light_max_blocks();
         if (blocks < 1) blocks = 1;
+        const LightSeeds L = light_seeds(P);
         if (emit)
-            hipLaunchKernelGGL((k_probe_light<ALGO, true>), dim3((unsigned)blocks), dim3(PB), 0, s, v, light_seeds(P),
-                               P.nlight, l0, l1, o);
+            hipLaunchKernelGGL((k_probe_light<ALGO, true>), dim3((unsigned)blocks), dim3(PB), 0, s, v, L.cpre, L.cabs,
+                               L.cxinv, L.ctlo, L.cthi, L.cpinv, P.nlight, l0, l1, o);
         else
-            hipLaunchKernelGGL((k_probe_light<ALGO, false>), dim3((unsigned)blocks), dim3(PB), 0, s, v, light_seeds(P),
-                               P.nlight, l0, l1, o);
+            hipLaunchKernelGGL((k_probe_light<ALGO, false>), dim3((unsigned)blocks), dim3(PB), 0, s, v, L.cpre, L.cabs,
+                               L.cxinv, L.ctlo, L.cthi, L.cpinv, P.nlight, l0, l1, o);
         TL_HIP(hipGetLastError());
     }
     // heavy part

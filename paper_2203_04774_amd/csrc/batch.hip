@@ -276,7 +276,12 @@ struct GraphAcc {
 // chunks of 64 at a time when they lie in one window or in the 64 seeds
 // from the current one.
 template <int ALGO>
-__global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos, const u32 *vbase, u64 *pg) {
+__global__ __launch_bounds__(BB) void k_bprobe(GView g, const u64 *__restrict__ cpre, const u64 *__restrict__ cabs, const u32 *__restrict__ cxinv,
+                         const u32 *__restrict__ ctlo, const u32 *__restrict__ cthi, const u32 *__restrict__ cpinv,
+                         const u32 *__restrict__ cgid, const u64 *__restrict__ pos,
+                                               const u32 *__restrict__ vbase, u64 *pg) {
+    // restrict-qualified arguments: reads at wave-uniform indices become scalar loads
+    const BSeeds L{cpre, cabs, cxinv, ctlo, cthi, cpinv, cgid};
     const int lane = lane_id();
     const u64 ncap = pos[g.m] & 0xffffffffull;
     const u64 W = L.cpre[ncap];
@@ -419,8 +424,13 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, BSeeds L, const u64 *pos
 // tested by one LDS read, and the marks are cleared for the next pivot.
 // Every workgroup leaves once the queue passes the heavy pivot count.
 template <int ALGO, int HBS>
-__global__ __launch_bounds__(HBS) void k_bheavy(GView g, BSeeds L, const u64 *pos, const u32 *hpiv, const u64 *hpre,
-                                                u32 N, const u32 *gid, const u32 *vbase, u64 *queue, u64 *pg) {
+__global__ __launch_bounds__(HBS) void k_bheavy(GView g, const u64 *__restrict__ cpre, const u64 *__restrict__ cabs, const u32 *__restrict__ cxinv,
+                         const u32 *__restrict__ ctlo, const u32 *__restrict__ cthi, const u32 *__restrict__ cpinv,
+                         const u32 *__restrict__ cgid, const u64 *__restrict__ pos,
+                                                const u32 *__restrict__ hpiv, const u64 *__restrict__ hpre, u32 N,
+                                                const u32 *__restrict__ gid, const u32 *__restrict__ vbase,
+                                                u64 *queue, u64 *pg) {
+    const BSeeds L{cpre, cabs, cxinv, ctlo, cthi, cpinv, cgid};
     extern __shared__ u32 bits[];
     __shared__ u64 next;
     // per wavefront: 64 staged hits (endpoint, third vertex) and the
@@ -662,19 +672,21 @@ void enqueue_batch_list(tl_batch *b, const BatchTuning &tu, hipStream_t s) {
     scan_u32_to_u64(b->clen, b->cpre, m, s, b->ws);
     scan_u32_to_u64(b->hflag, b->hpre, N, s, b->ws);
     hipLaunchKernelGGL(k_bhlist, dim3(grid_b(N)), dim3(BB), 0, s, (u32)N, b->hflag, b->hpre, b->hpiv);
-    const BSeeds L{b->cpre, b->cabs, b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid};
-    hipLaunchKernelGGL((k_bprobe<ALGO>), dim3(cus * (unsigned)tu.light_per_cu), dim3(BB), 0, s, v, L, b->pos,
-                       b->vbase, b->pg);
+// the compacted seed arrays, as the walks' restrict-qualified arguments
+#define TL_BSEEDS b->cpre, b->cabs, b->cxinv, b->ctlo, b->cthi, b->cpinv, b->cgid
+    hipLaunchKernelGGL((k_bprobe<ALGO>), dim3(cus * (unsigned)tu.light_per_cu), dim3(BB), 0, s, v, TL_BSEEDS,
+                       b->pos, b->vbase, b->pg);
     const dim3 hg(cus * (unsigned)tu.heavy_per_cu);
     if (tu.heavy_block == 256)
-        hipLaunchKernelGGL((k_bheavy<ALGO, 256>), hg, dim3(256), BH_LDS_BYTES, s, v, L, b->pos, b->hpiv, b->hpre,
-                           (u32)N, b->gid, b->vbase, b->ctl, b->pg);
+        hipLaunchKernelGGL((k_bheavy<ALGO, 256>), hg, dim3(256), BH_LDS_BYTES, s, v, TL_BSEEDS, b->pos, b->hpiv,
+                           b->hpre, (u32)N, b->gid, b->vbase, b->ctl, b->pg);
     else if (tu.heavy_block == 1024)
-        hipLaunchKernelGGL((k_bheavy<ALGO, 1024>), hg, dim3(1024), BH_LDS_BYTES, s, v, L, b->pos, b->hpiv, b->hpre,
-                           (u32)N, b->gid, b->vbase, b->ctl, b->pg);
+        hipLaunchKernelGGL((k_bheavy<ALGO, 1024>), hg, dim3(1024), BH_LDS_BYTES, s, v, TL_BSEEDS, b->pos, b->hpiv,
+                           b->hpre, (u32)N, b->gid, b->vbase, b->ctl, b->pg);
     else
-        hipLaunchKernelGGL((k_bheavy<ALGO, 512>), hg, dim3(512), BH_LDS_BYTES, s, v, L, b->pos, b->hpiv, b->hpre,
-                           (u32)N, b->gid, b->vbase, b->ctl, b->pg);
+        hipLaunchKernelGGL((k_bheavy<ALGO, 512>), hg, dim3(512), BH_LDS_BYTES, s, v, TL_BSEEDS, b->pos, b->hpiv,
+                           b->hpre, (u32)N, b->gid, b->vbase, b->ctl, b->pg);
+#undef TL_BSEEDS
     TL_HIP(hipGetLastError());
 }
 

@@ -276,7 +276,8 @@ struct GraphAcc {
 // chunks of 64 at a time when they lie in one window or in the 64 seeds
 // from the current one.
 template <int ALGO>
-__global__ __launch_bounds__(BB) void k_bprobe(GView g, const u64 *__restrict__ cpre, const u64 *__restrict__ cabs, const u32 *__restrict__ cxinv,
+__global__ __launch_bounds__(BB) void k_bprobe(GView g, const u64 *__restrict__ cpre, const u64 *__restrict__ cabs,
+                         const u32 *__restrict__ cxinv,
                          const u32 *__restrict__ ctlo, const u32 *__restrict__ cthi, const u32 *__restrict__ cpinv,
                          const u32 *__restrict__ cgid, const u64 *__restrict__ pos,
                                                const u32 *__restrict__ vbase, u64 *pg) {
@@ -368,7 +369,8 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, const u64 *__restrict__ 
                     const u64 A = inw ? L.cabs[ci] : 0ull;
                     const u32 X = inw ? L.cxinv[ci] : 0u, PI = inw ? L.cpinv[ci] : 0u, GI = inw ? L.cgid[ci] : 0u;
                     const u32 TL = inw ? L.ctlo[ci] : 0u, TH = inw ? L.cthi[ci] : 0u;
-                    const u32 E = (u32)(A - P + kb);  // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
+                    // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
+                    const u32 E = (u32)(A - P + kb);
                     int lo[UN];
                     const int lo_last = locate_short(P, kb, flag, lo);
                     u32 y[UN], pv[UN], xv[UN], gv[UN];
@@ -424,7 +426,8 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, const u64 *__restrict__ 
 // tested by one LDS read, and the marks are cleared for the next pivot.
 // Every workgroup leaves once the queue passes the heavy pivot count.
 template <int ALGO, int HBS>
-__global__ __launch_bounds__(HBS) void k_bheavy(GView g, const u64 *__restrict__ cpre, const u64 *__restrict__ cabs, const u32 *__restrict__ cxinv,
+__global__ __launch_bounds__(HBS) void k_bheavy(GView g, const u64 *__restrict__ cpre, const u64 *__restrict__ cabs,
+                         const u32 *__restrict__ cxinv,
                          const u32 *__restrict__ ctlo, const u32 *__restrict__ cthi, const u32 *__restrict__ cpinv,
                          const u32 *__restrict__ cgid, const u64 *__restrict__ pos,
                                                 const u32 *__restrict__ hpiv, const u64 *__restrict__ hpre, u32 N,
@@ -546,7 +549,8 @@ __global__ __launch_bounds__(HBS) void k_bheavy(GView g, const u64 *__restrict__
                     if (pend >= kb + UN * WAVE) {
                         const u64 A = inw ? L.cabs[ci] : 0ull;
                         const u32 X = inw ? L.cxinv[ci] : 0u;
-                        const u32 E = (u32)(A - P + kb);  // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
+                        // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
+                        const u32 E = (u32)(A - P + kb);
                         int lo[UN];
                         const int lo_last = locate_short(P, kb, flag, lo);
                         u32 y[UN], xv[UN];

@@ -225,7 +225,10 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             else if (force_mode == MODE_GLOBAL) { md = MODE_GLOBAL; stage = 0; }
             else if (force_mode == MODE_REVERSE) { md = MODE_REVERSE; stage = 0; }
             else if (force_mode == MODE_HASH && tlen <= HASH_MAX) { md = MODE_HASH; stage = 2 * tlen + 2 * tlen; }
-            else if (force_mode == MODE_BUCKET && tlen <= BUCKET_MAX) { md = MODE_BUCKET; stage = 2 * tlen + 16 * BUCKETS; }
+            else if (force_mode == MODE_BUCKET && tlen <= BUCKET_MAX) {
+                md = MODE_BUCKET;
+                stage = 2 * tlen + 16 * BUCKETS;
+            }
             else if (force_mode == MODE_SPLIT) { md = MODE_SPLIT; stage = 2 * tlen; }
             else if (bm_ok) { md = MODE_BITMAP; stage = 2 * tlen; }
             else if (use_split >= 2) { md = MODE_SPLIT; stage = 2 * tlen; }
@@ -532,7 +535,8 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
                     const u64 A = inw ? L.cabs[ci] : 0ull;
                     const u32 X = inw ? L.cxinv[ci] : 0u, PI = inw ? L.cpinv[ci] : 0u;
                     const u32 TL = inw ? L.ctlo[ci] : 0u, TH = inw ? L.cthi[ci] : 0u;
-                    const u32 E = (u32)(A - P + kb);  // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
+                    // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
+                    const u32 E = (u32)(A - P + kb);
                     int lo[UN];
                     const int lo_last = locate_short(P, kb, flag, lo);
                     u32 y[UN], pv[UN], xv[UN];
@@ -682,7 +686,8 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
             constexpr int MD = decltype(mode_tag)::value;
             if (wb < we) {
                 const bool exact = use_splits && a == tk.a && b == tk.b;  // not clipped by a chunk slice
-                SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tg.ws[wid]) : SeedCursor(cpre, tk.cb, tk.ce, wb);
+                SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tg.ws[wid])
+                                       : SeedCursor(cpre, tk.cb, tk.ce, wb);
                 const u32 pinv = g.inv[p];
                 u32 xinv = 0;
                 u64 xinv_c = ~0ull;
@@ -919,7 +924,8 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                             fetch_window(cur.c_lo, P, A, X, pend);
                         }
                         if (pend >= kb + UN * WAVE) {
-                            const u32 E = (u32)(A - P + kb);  // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
+                            // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
+                            const u32 E = (u32)(A - P + kb);
                             int lo[UN];
                             const int lo_last = locate_short(P, kb, flag, lo);
                             u32 y[UN], xv[UN];
@@ -1243,7 +1249,8 @@ void prepare_kernels() {
         const void *fns[] = {(const void *)k_probe_heavy<0, true>, (const void *)k_probe_heavy<0, false>,
                              (const void *)k_probe_heavy<1, true>, (const void *)k_probe_heavy<1, false>,
                              (const void *)k_probe_heavy<2, true>, (const void *)k_probe_heavy<2, false>};
-        for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, HEAVY_LDS_BYTES);
+        for (const void *f : fns)
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, HEAVY_LDS_BYTES);
         (void)hipGetLastError();
     });
 }

@@ -56,7 +56,8 @@ __global__ __launch_bounds__(256) void k_bin_fill(const u64 *off, u32 nrows, con
             if (b) local = atomicAdd(&cnt[b], 1u);
         }
         __syncthreads();
-        if (threadIdx.x < NBINS && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+        if (threadIdx.x < NBINS && cnt[threadIdx.x])
+            base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
         __syncthreads();
         if (r < nrows && b) rows[bin_start[b] + base[b] + local] = (u32)r;
         __syncthreads();

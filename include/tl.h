@@ -347,7 +347,7 @@ void tl_server_destroy(tl_server *s);
  *                        where it fits; 255 = automatic
  *   plan_full            a seed edge whose scanned list has at most this
  *                        many entries scans all of it instead of the window
- *                        found by two binary searches (0..2^20; results are
+ *                        found by two binary searches (0..255; results are
  *                        the same, only the work split changes)
  * and for the batched pass (tl_batch_list; a captured pass is captured
  * again when these change):

@@ -66,7 +66,8 @@ struct Tuning {
     u64 split = 2;               // 1: SPLIT for lists too long for LDS; 2: also before ARRAY/BUCKET
     u64 orient_sort = 1;         // 1: orientation by radix sort; 0: by per-vertex counters and scatter
     u64 force_mode = 255;        // testing: use this MODE_* for every heavy pivot where it fits
-    u64 plan_full = 16;          // scanned lists this short are taken whole (no window searches)
+    u64 plan_full = 16;          // scanned lists this short are taken whole (no window searches);
+                                 // below UN * WAVE, so that whole lists never fill a long window
 };
 Tuning &tuning();
 
@@ -807,6 +808,22 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                         for (int j = 0; j < UN; j++) h[j] = member(y[j]);
                     }
                 };
+                // Long windows (at least UN chunks inside one seed) come from
+                // the plan's window searches, never from a list taken whole
+                // (plan_full < UN * WAVE), so every element lies in the seed's
+                // candidate range and hence in [tmin, tmax]: the bitmap form
+                // needs no range test.
+                auto member_long = [&](const u32 (&y)[UN], bool (&h)[UN]) {
+                    if (MD == MODE_BITMAP) {
+                        u32 w[UN];
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) w[j] = lds[(y[j] - tmin) >> 5];
+    #pragma unroll
+                        for (int j = 0; j < UN; j++) h[j] = (w[j] >> ((y[j] - tmin) & 31)) & 1u;
+                    } else {
+                        member_all(y, h);
+                    }
+                };
                 // Listed triangles: the hits of every group are packed into
                 // this wavefront's LDS staging area (consecutive slots, kept
                 // across groups), and each time 64 are waiting they are
@@ -884,7 +901,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                         for (int j = 0; j < UN; j++) xv[j] = xinv;
 #pragma unroll
                         for (int q = 0; q < HG; q++) {
-                            member_all(y[q], h);
+                            member_long(y[q], h);
                             report(y[q], h, xv);
                         }
                         kb += HG * UN * WAVE;
@@ -904,7 +921,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                         for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
     #pragma unroll
                         for (int j = 0; j < UN; j++) xv[j] = xinv;
-                        member_all(y, h);
+                        member_long(y, h);
                         report(y, h, xv);
                         kb += UN * WAVE;
                         cur.advance(kb, cur.c_lo);
@@ -1072,9 +1089,9 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
     const unsigned gn = grid_for(n, PB, (unsigned)tl_num_cus() * 16);
     DevBuf len(m * sizeof(u32), s), sabs(m * sizeof(u64), s), wp((u64)n * sizeof(u64), s);
     TL_HIP(hipMemsetAsync(wp.p, 0, (u64)n * sizeof(u64), s));
-    hipLaunchKernelGGL((k_plan<ALGO>), dim3(gm), dim3(PB), 0, s, v, plo, phi, (u32)tuning().plan_full, len.as<u32>(),
-                       sabs.as<u64>(),
-                       wp.as<u64>(), d_acc);
+    const u32 full_max = (u32)std::min<u64>(tuning().plan_full, UN * WAVE - 1);  // see member_long
+    hipLaunchKernelGGL((k_plan<ALGO>), dim3(gm), dim3(PB), 0, s, v, plo, phi, full_max, len.as<u32>(),
+                       sabs.as<u64>(), wp.as<u64>(), d_acc);
     TL_HIP(hipGetLastError());
     DevBuf mode((u64)n * sizeof(u32), s), ntask((u64)n * sizeof(u32), s), slice((u64)n * sizeof(u64), s);
     const Tuning &tu = tuning();
@@ -1229,6 +1246,7 @@ Tuning &tuning() {
         env("TL_TUNE_ORIENT_SORT", d.orient_sort);
         env("TL_TUNE_FORCE_MODE", d.force_mode);
         env("TL_TUNE_PLAN_FULL", d.plan_full);
+        if (d.plan_full >= (u64)(UN * WAVE)) d.plan_full = UN * WAVE - 1;
         return d;
     }();
     return t;
@@ -1282,7 +1300,7 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "split" && value <= 2) t.split = value;
     else if (k == "orient_sort" && value <= 1) t.orient_sort = value;
     else if (k == "force_mode" && (value < NMODES || value == 255)) t.force_mode = value;
-    else if (k == "plan_full" && value <= (1u << 20)) t.plan_full = value;
+    else if (k == "plan_full" && value < (u64)(UN * WAVE)) t.plan_full = value;
     else return TL_EINVAL;
     return TL_OK;
 }

@@ -60,3 +60,20 @@ def test_null_arguments_rejected_without_device_work(lib):
 def test_python_binding_imports():
     import paper_2203_04774_amd as tl
     assert set(tl.ALGOS) == {"A++", "A+-", "A--"}
+
+
+def test_tuning_keys_and_ranges(lib):
+    """Tuning is host state: known keys take values in range, others are
+    refused (plan_full stays below one long window of 256 items, which the
+    heavy walk's unchecked bitmap reads rely on)."""
+    lib.tl_set_tuning.argtypes = [ctypes.c_char_p, ctypes.c_uint64]
+    lib.tl_get_tuning.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint64)]
+    v = ctypes.c_uint64()
+    assert lib.tl_get_tuning(b"plan_full", ctypes.byref(v)) == 0
+    old = v.value
+    assert lib.tl_set_tuning(b"plan_full", 255) == 0
+    assert lib.tl_set_tuning(b"plan_full", 256) != 0
+    assert lib.tl_get_tuning(b"plan_full", ctypes.byref(v)) == 0 and v.value == 255
+    assert lib.tl_set_tuning(b"plan_full", old) == 0
+    assert lib.tl_set_tuning(b"no_such_key", 1) != 0
+    assert lib.tl_set_tuning(b"batch_plan_full", 8) == 0

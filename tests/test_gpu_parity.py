@@ -339,10 +339,11 @@ TUNINGS = {
     "tiny-tasks-static": {"heavy_min": 1, "slice_min": 64, "slice_mult": 1, "queue": 0, "splits": 0},
     "tiny-tasks-queue": {"heavy_min": 1, "slice_min": 64, "slice_mult": 1, "queue": 1, "splits": 1},
 }
-# every scanned list taken whole by the plan (no window searches): elements
-# outside the window must fail each membership test like any non-member
+# every scanned list of up to 255 entries (the largest setting) taken whole
+# by the plan: elements outside the window must fail each membership test
+# like any non-member
 for _name in ["all-light", "bitmap", "array", "global", "reverse", "hash", "bucket", "split", "split-auto"]:
-    TUNINGS[_name + "+whole-lists"] = {**TUNINGS[_name], "plan_full": 1 << 20}
+    TUNINGS[_name + "+whole-lists"] = {**TUNINGS[_name], "plan_full": 255}
 TUNINGS["no-whole-lists"] = {"plan_full": 0}
 
 

@@ -513,8 +513,8 @@ def main():
     ap.add_argument("--serve-pinned", action="store_true", help="job arrays in page-locked host memory")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the listing runs on one GPU; --gpus {args.gpus} is not supported "
+              "(pivot ranges of equal work per GPU via tl_list_range would be the multi-GPU form)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         bench_batch(args)

@@ -62,10 +62,11 @@ __global__ void k_rank_degree(const u64 *off_f, const u64 *off_b, u32 n, u32 *de
     }
 }
 
-// Peeling round at `level`: every vertex still present whose current degree
-// is at most `level` leaves now with coreness `level` (one atomic per
-// wavefront for the frontier's size).
-__global__ void k_core_frontier(u32 n, const u32 *deg, u32 *core, u32 level, u32 *frontier, u32 *fcount) {
+// Start of a level: the level is the smallest degree left (*plevel, from
+// k_core_min); every vertex still present with that degree leaves now with
+// coreness `level` (one atomic per wavefront for the frontier's size).
+__global__ void k_core_frontier(u32 n, const u32 *deg, u32 *core, const u32 *plevel, u32 *frontier, u32 *fcount) {
+    const u32 level = *plevel;
     const u64 stride = (u64)gridDim.x * blockDim.x;
     const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     const u64 iters = (u64)n > first - lane_id() ? ((u64)n - (first - lane_id()) + stride - 1) / stride : 0;
@@ -84,21 +85,42 @@ __global__ void k_core_frontier(u32 n, const u32 *deg, u32 *core, u32 level, u32
     }
 }
 
-// The frontier's vertices leave: one wavefront per vertex lowers the
-// degree of each neighbour still present.
-__global__ void k_core_peel(const u64 *off_f, const u32 *adj_f, const u64 *off_b, const u32 *adj_b,
-                            const u32 *frontier, u32 nf, const u32 *core, u32 *deg) {
-    const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
-    for (u64 f = w0; f < nf; f += nw) {
+constexpr int VB = 256;  // threads per frontier vertex (one workgroup each)
+
+// appends the lanes' ready vertices to out (one atomic per wavefront)
+__device__ __forceinline__ void wave_push(bool ready, u32 w, u32 *out, u32 *count) {
+    const u64 bal = __ballot(ready);
+    if (!bal) return;
+    u32 base = 0;
+    if (lane_id() == 0) base = atomicAdd(count, (u32)__popcll(bal));
+    base = __shfl(base, 0, WAVE);
+    if (ready) out[base + __popcll(bal & lanemask_lt())] = w;
+}
+
+// The frontier's vertices leave, a workgroup per vertex (hubs' lists are
+// shared by its 256 threads): every neighbour still present loses one
+// degree, and the one whose degree drops to `level` leaves next, with
+// coreness `level` (exactly one decrement sees the drop).
+__global__ __launch_bounds__(VB) void k_core_peel(const u64 *off_f, const u32 *adj_f, const u64 *off_b,
+                                                  const u32 *adj_b, const u32 *frontier, u32 nf, u32 level,
+                                                  u32 *core, u32 *deg, u32 *next, u32 *ncount) {
+    for (u32 f = blockIdx.x; f < nf; f += gridDim.x) {
         const u32 r = frontier[f];
-        for (u64 j = off_f[r] + lane_id(); j < off_f[r + 1]; j += WAVE) {
-            const u32 w = adj_f[j];
-            if (core[w] == UNSET) atomicSub(&deg[w], 1u);
-        }
-        for (u64 j = off_b[r] + lane_id(); j < off_b[r + 1]; j += WAVE) {
-            const u32 w = adj_b[j];
-            if (core[w] == UNSET) atomicSub(&deg[w], 1u);
+        const u64 f0 = off_f[r], nfw = off_f[r + 1] - f0, b0 = off_b[r];
+        const u64 d = nfw + (off_b[r + 1] - b0);
+        const u64 trips = (d + VB - 1) / VB;  // the same for the whole workgroup
+        for (u64 t = 0; t < trips; t++) {
+            const u64 j = t * VB + threadIdx.x;
+            bool ready = false;
+            u32 w = 0;
+            if (j < d) {
+                w = j < nfw ? adj_f[f0 + j] : adj_b[b0 + (j - nfw)];
+                if (core[w] == UNSET && atomicSub(&deg[w], 1u) == level + 1) {
+                    core[w] = level;
+                    ready = true;
+                }
+            }
+            wave_push(ready, w, next, ncount);
         }
     }
 }
@@ -144,48 +166,43 @@ __global__ void k_check_dpos(const u32 *sorted, const u32 *inv, u32 n, u32 *posi
     }
 }
 
-// pending[r] = neighbours taken before r; ranks with none start the first level
-__global__ void k_check_init(const u64 *off_f, const u32 *adj_f, const u64 *off_b, const u32 *adj_b, const u32 *dpos,
-                             u32 n, u32 *pending, u32 *frontier, u32 *fcount) {
+// pending[r] = neighbours taken before r: each edge counts once for its
+// later end (edge-parallel, so hubs cost no more than other vertices)
+__global__ void k_check_pending(const u32 *row_f, const u32 *adj_f, u64 m, const u32 *dpos, u32 *pending) {
+    GRID_STRIDE(i, m) {
+        const u32 u = row_f[i], v = adj_f[i];
+        atomicAdd(&pending[dpos[u] < dpos[v] ? v : u], 1u);
+    }
+}
+
+// ranks with no earlier neighbour start the first level
+__global__ void k_check_first(const u32 *pending, u32 n, u32 *frontier, u32 *fcount) {
     const u64 stride = (u64)gridDim.x * blockDim.x;
     const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     const u64 iters = (u64)n > first - lane_id() ? ((u64)n - (first - lane_id()) + stride - 1) / stride : 0;
     for (u64 it = 0; it < iters; it++) {
         const u64 r = first + it * stride;
-        u32 p = 0;
-        if (r < n) {
-            const u32 d = dpos[r];
-            for (u64 j = off_f[r]; j < off_f[r + 1]; j++) p += dpos[adj_f[j]] < d;
-            for (u64 j = off_b[r]; j < off_b[r + 1]; j++) p += dpos[adj_b[j]] < d;
-            pending[r] = p;
-        }
-        const bool ready = r < n && p == 0;
-        const u64 bal = __ballot(ready);
-        if (!bal) continue;
-        u32 base = 0;
-        if (lane_id() == 0) base = atomicAdd(fcount, (u32)__popcll(bal));
-        base = __shfl(base, 0, WAVE);
-        if (ready) frontier[base + __popcll(bal & lanemask_lt())] = (u32)r;
+        wave_push(r < n && pending[r] == 0, (u32)r, frontier, fcount);
     }
 }
 
-// One level: a wavefront per vertex counts its earlier neighbours on each
-// side, takes the cheaper side, then releases its later neighbours (those
-// whose last earlier neighbour this was join the next level).
-__global__ void k_check_level(const u64 *off_f, const u32 *adj_f, const u64 *off_b, const u32 *adj_b,
-                              const u32 *dpos, const u32 *frontier, u32 nf, unsigned char *side, u32 *pending,
-                              u32 *next, u32 *ncount) {
-    const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
-    const int lane = lane_id();
-    for (u64 f = w0; f < nf; f += nw) {
-        const u32 r = uni32(frontier[f]);
+// One level, a workgroup per vertex: count the vertex's earlier neighbours
+// on each side, take the cheaper side, then release its later neighbours
+// (those whose last earlier neighbour this was join the next level).
+__global__ __launch_bounds__(VB) void k_check_level(const u64 *off_f, const u32 *adj_f, const u64 *off_b,
+                                                    const u32 *adj_b, const u32 *dpos, const u32 *frontier, u32 nf,
+                                                    unsigned char *side, u32 *pending, u32 *next, u32 *ncount) {
+    __shared__ u64 part[2][VB / WAVE];
+    __shared__ unsigned char sd;
+    const int lane = lane_id(), wid = (int)wave_id();
+    for (u32 f = blockIdx.x; f < nf; f += gridDim.x) {
+        const u32 r = frontier[f];
         const u32 d = dpos[r];
-        const u64 f0 = off_f[r], f1 = off_f[r + 1], b0 = off_b[r], b1 = off_b[r + 1];
-        const u64 deg = (f1 - f0) + (b1 - b0);
+        const u64 f0 = off_f[r], nfw = off_f[r + 1] - f0, b0 = off_b[r];
+        const u64 deg = nfw + (off_b[r + 1] - b0);
         u64 nb = 0, ne = 0;
-        for (u64 j = lane; j < deg; j += WAVE) {
-            const u32 w = j < f1 - f0 ? adj_f[f0 + j] : adj_b[b0 + (j - (f1 - f0))];
+        for (u64 j = threadIdx.x; j < deg; j += VB) {
+            const u32 w = j < nfw ? adj_f[f0 + j] : adj_b[b0 + (j - nfw)];
             if (dpos[w] < d) {
                 if (side[w] == SIDE_BEGIN) nb++;
                 else ne++;
@@ -193,25 +210,34 @@ __global__ void k_check_level(const u64 *off_f, const u32 *adj_f, const u64 *off
         }
         nb = wave_sum_u64(nb);
         ne = wave_sum_u64(ne);
-        const u64 nq = deg - nb - ne;
-        const u64 cb = nb * (ne + nq), ce = (nb + nq) * ne;
-        if (lane == 0) side[r] = cb <= ce ? SIDE_BEGIN : SIDE_END;
-        const u64 trips = (deg + WAVE - 1) / WAVE;
+        if (lane == 0) {
+            part[0][wid] = nb;
+            part[1][wid] = ne;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u64 tb = 0, te = 0;
+            for (int w = 0; w < VB / WAVE; w++) {
+                tb += part[0][w];
+                te += part[1][w];
+            }
+            const u64 nq = deg - tb - te;
+            sd = tb * (te + nq) <= (tb + nq) * te ? SIDE_BEGIN : SIDE_END;
+            side[r] = sd;
+        }
+        __syncthreads();
+        const u64 trips = (deg + VB - 1) / VB;
         for (u64 t = 0; t < trips; t++) {
-            const u64 j = t * WAVE + lane;
+            const u64 j = t * VB + threadIdx.x;
             bool ready = false;
             u32 w = 0;
             if (j < deg) {
-                w = j < f1 - f0 ? adj_f[f0 + j] : adj_b[b0 + (j - (f1 - f0))];
+                w = j < nfw ? adj_f[f0 + j] : adj_b[b0 + (j - nfw)];
                 if (dpos[w] > d) ready = atomicSub(&pending[w], 1u) == 1u;
             }
-            const u64 bal = __ballot(ready);
-            if (!bal) continue;
-            u32 base = 0;
-            if (lane == 0) base = atomicAdd(ncount, (u32)__popcll(bal));
-            base = __shfl(base, 0, WAVE);
-            if (ready) next[base + __popcll(bal & lanemask_lt())] = w;
+            wave_push(ready, w, next, ncount);
         }
+        __syncthreads();  // part[] and sd are reused by the next vertex
     }
 }
 
@@ -237,35 +263,42 @@ __global__ void k_check_rank(const u32 *dpos, const unsigned char *side, const u
 // per vertex id) and ids for the sort.
 void coreness_keys(const tl_csr *g, u32 *key, u32 *ids, hipStream_t s) {
     const u32 n = g->n;
-    DevBuf deg((u64)n * 4, s), core((u64)n * 4, s), frontier((u64)n * 4, s), cnt(8, s);
+    DevBuf deg((u64)n * 4, s), core((u64)n * 4, s), fa((u64)n * 4, s), fb((u64)n * 4, s), cnt(8, s);
     u32 *fcount = cnt.as<u32>(), *mind = cnt.as<u32>() + 1;
+    u32 *cur = fa.as<u32>(), *nxt = fb.as<u32>();
     hipLaunchKernelGGL(k_rank_degree, dim3(grid_o(n)), dim3(256), 0, s, g->off_f, g->off_b, n, deg.as<u32>(),
                        core.as<u32>());
     TL_HIP(hipGetLastError());
-    u32 level = 0;
     u64 remaining = n;
+    bool first = true;
+    u32 level = 0;
     while (remaining) {
-        TL_HIP(hipMemsetAsync(fcount, 0, 4, s));
-        hipLaunchKernelGGL(k_core_frontier, dim3(grid_o(n)), dim3(256), 0, s, n, deg.as<u32>(), core.as<u32>(), level,
-                           frontier.as<u32>(), fcount);
+        // the next level is the smallest degree left (above the last level:
+        // every vertex at or below it has left); its vertices are gathered
+        // on the device, one host wait per level
+        TL_HIP(hipMemsetAsync(cnt.p, 0, 4, s));
+        TL_HIP(hipMemsetAsync(mind, 0xff, 4, s));
+        hipLaunchKernelGGL(k_core_min, dim3(grid_o(n)), dim3(256), 0, s, n, deg.as<u32>(), core.as<u32>(), mind);
         TL_HIP(hipGetLastError());
-        u32 nf = 0;
-        d2h_sync(s, {{&nf, fcount, 4}});
-        if (nf == 0) {
-            // nothing at this level any more: jump to the smallest degree left
-            TL_HIP(hipMemsetAsync(mind, 0xff, 4, s));
-            hipLaunchKernelGGL(k_core_min, dim3(grid_o(n)), dim3(256), 0, s, n, deg.as<u32>(), core.as<u32>(), mind);
+        hipLaunchKernelGGL(k_core_frontier, dim3(grid_o(n)), dim3(256), 0, s, n, deg.as<u32>(), core.as<u32>(), mind,
+                           cur, fcount);
+        TL_HIP(hipGetLastError());
+        u32 st[2] = {0, 0};
+        d2h_sync(s, {{st, cnt.p, 8}});
+        u32 nf = st[0];
+        TL_REQUIRE(nf > 0 && st[1] != UNSET && (first || st[1] > level), TL_EHIP, "core peeling made no progress");
+        level = st[1];
+        first = false;
+        // peel: every round's leavers bring the next ones down to `level`
+        while (nf) {
+            remaining -= nf;
+            TL_HIP(hipMemsetAsync(fcount, 0, 4, s));
+            hipLaunchKernelGGL(k_core_peel, dim3(nf < 65536 ? nf : 65536), dim3(VB), 0, s, g->off_f, g->adj_f,
+                               g->off_b, g->adj_b, cur, nf, level, core.as<u32>(), deg.as<u32>(), nxt, fcount);
             TL_HIP(hipGetLastError());
-            u32 next = 0;
-            d2h_sync(s, {{&next, mind, 4}});
-            TL_REQUIRE(next != UNSET && next > level, TL_EHIP, "core peeling made no progress");
-            level = next;
-            continue;
+            d2h_sync(s, {{&nf, fcount, 4}});
+            std::swap(cur, nxt);
         }
-        remaining -= nf;
-        hipLaunchKernelGGL(k_core_peel, dim3(grid_o((u64)nf * WAVE)), dim3(256), 0, s, g->off_f, g->adj_f, g->off_b,
-                           g->adj_b, frontier.as<u32>(), nf, core.as<u32>(), deg.as<u32>());
-        TL_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_core_keys, dim3(grid_o(n)), dim3(256), 0, s, core.as<u32>(), g->inv, n, key, ids);
     TL_HIP(hipGetLastError());
@@ -283,8 +316,14 @@ void check_ranks(const tl_csr *g, const u32 *sorted, u32 *rank, hipStream_t s) {
         TL_HIP(hipGetLastError());
     }
     TL_HIP(hipMemsetAsync(cnt.p, 0, 8, s));
-    hipLaunchKernelGGL(k_check_init, dim3(grid_o(n)), dim3(256), 0, s, g->off_f, g->adj_f, g->off_b, g->adj_b,
-                       dpos.as<u32>(), n, pending.as<u32>(), fa.as<u32>(), cnt.as<u32>());
+    TL_HIP(hipMemsetAsync(pending.p, 0, (u64)n * 4, s));
+    if (g->m) {
+        hipLaunchKernelGGL(k_check_pending, dim3(grid_o(g->m)), dim3(256), 0, s, g->row_f, g->adj_f, g->m,
+                           dpos.as<u32>(), pending.as<u32>());
+        TL_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_check_first, dim3(grid_o(n)), dim3(256), 0, s, pending.as<u32>(), n, fa.as<u32>(),
+                       cnt.as<u32>());
     TL_HIP(hipGetLastError());
     u32 nf = 0;
     d2h_sync(s, {{&nf, cnt.p, 4}});
@@ -293,7 +332,7 @@ void check_ranks(const tl_csr *g, const u32 *sorted, u32 *rank, hipStream_t s) {
     while (nf) {
         done += nf;
         TL_HIP(hipMemsetAsync(cnt.p, 0, 4, s));
-        hipLaunchKernelGGL(k_check_level, dim3(grid_o((u64)nf * WAVE)), dim3(256), 0, s, g->off_f, g->adj_f,
+        hipLaunchKernelGGL(k_check_level, dim3(nf < 65536 ? nf : 65536), dim3(VB), 0, s, g->off_f, g->adj_f,
                            g->off_b, g->adj_b, dpos.as<u32>(), cur, nf, side.as<unsigned char>(), pending.as<u32>(),
                            nxt, cnt.as<u32>());
         TL_HIP(hipGetLastError());

@@ -7,10 +7,12 @@
 // footprint fits the budget and copies their edges and orderings to the
 // device; a job whose graph is large forms a batch of its own.  The orient
 // thread orients each uploaded batch as one disjoint union (batch.hip).
-// The list thread lists oriented batches in order: a union of small graphs
-// by the batched pass (per-graph rows), a batch of one by the plain
-// listing (light and heavy pivots).  So the copy of one batch, the
-// orientation of the next and the listing of a third overlap.  A batch
+// The list threads (two by default, each on its own stream) take oriented
+// batches in order: a union of small graphs is listed by the batched pass
+// (per-graph rows), a batch of one by the plain listing (light and heavy
+// pivots).  So the copy of one batch, the orientation of the next and the
+// listing of others overlap, and one batch's host waits are covered by
+// another's kernels.  A batch
 // whose union fails validation is split and its jobs are oriented one by
 // one, so a malformed job fails alone.
 #include <algorithm>
@@ -62,7 +64,8 @@ struct Uploaded {
 struct tl_server {
     tl_server_config cfg{};
     int device = 0;
-    hipStream_t s_copy = nullptr, s_up = nullptr, s_list = nullptr;
+    hipStream_t s_copy = nullptr, s_up = nullptr;
+    std::vector<hipStream_t> s_list;  // one per list thread
 
     std::mutex mu;
     std::condition_variable cv_pending;  // upload waits: new jobs, freed budget, stop
@@ -82,7 +85,8 @@ struct tl_server {
     bool stop = false, paused = false;
     tl_server_stats st{};
 
-    std::thread uploader, orienter, lister;
+    std::thread uploader, orienter;
+    std::vector<std::thread> listers;
 };
 
 namespace {
@@ -285,8 +289,9 @@ void orient_loop(tl_server *S) {
     }
 }
 
-void list_loop(tl_server *S) {
+void list_loop(tl_server *S, u32 li) {
     (void)hipSetDevice(S->device);
+    const hipStream_t stream = S->s_list[li];
     std::vector<u64> table;
     for (;;) {
         Ready r;
@@ -295,6 +300,8 @@ void list_loop(tl_server *S) {
             S->cv_ready.wait(lk, [&] { return S->stop || !S->ready.empty(); });
             if (S->stop) return;
             r = std::move(S->ready.front());
+            S->ready.pop_front();  // taken: another list thread may start on the next
+            S->cv_space.notify_all();
         }
         const u32 k = (u32)r.jobs.size();
         const u64 t_start = now_ns();
@@ -305,7 +312,7 @@ void list_loop(tl_server *S) {
                 // a graph alone: the plain listing with light and heavy pivots
                 tl_summary sm{};
                 list_impl(batch_csr(r.b), (int)r.jobs[0]->in.algo, 0u, 0xffffffffu, nullptr, 0, nullptr, nullptr,
-                          S->s_list, &sm);
+                          stream, &sm);
                 solo_out.push_back(sm);
             } else {
                 table.assign(3ull * k, 0);
@@ -314,7 +321,7 @@ void list_loop(tl_server *S) {
                 for (Job *j : r.jobs) have[(int)j->in.algo] = true;
                 for (int a = 0; a < 3; a++) {
                     if (!have[a]) continue;
-                    batch_list_impl(r.b, a, S->s_list, 0, t2.data(), nullptr);
+                    batch_list_impl(r.b, a, stream, 0, t2.data(), nullptr);
                     for (u32 i = 0; i < k; i++)
                         if ((int)r.jobs[i]->in.algo == a)
                             for (int c = 0; c < 3; c++) table[3ull * i + c] = t2[3ull * i + c];
@@ -328,7 +335,6 @@ void list_loop(tl_server *S) {
         batch_free_impl(r.b, false);  // the list stream has finished with it
         pool_trim_above(S->cfg.hbm_budget + S->cfg.hbm_budget / 2);
         std::unique_lock<std::mutex> lk(S->mu);
-        S->ready.pop_front();
         S->in_flight--;
         S->cv_space.notify_all();
         S->cv_pending.notify_all();
@@ -374,14 +380,17 @@ tl_server *server_create_impl(const tl_server_config *cfg) {
     if (!S->cfg.max_batch_jobs) S->cfg.max_batch_jobs = 4096;
     if (!S->cfg.max_batch_edges) S->cfg.max_batch_edges = 1ull << 27;
     if (!S->cfg.solo_edges) S->cfg.solo_edges = 1ull << 21;
+    if (!S->cfg.list_threads) S->cfg.list_threads = 2;
+    TL_REQUIRE(S->cfg.list_threads <= 8, TL_EINVAL, "list_threads must be at most 8");
     TL_HIP(hipGetDevice(&S->device));
     TL_HIP(hipStreamCreateWithFlags(&S->s_copy, hipStreamNonBlocking));
     TL_HIP(hipStreamCreateWithFlags(&S->s_up, hipStreamNonBlocking));
-    TL_HIP(hipStreamCreateWithFlags(&S->s_list, hipStreamNonBlocking));
+    S->s_list.assign(S->cfg.list_threads, nullptr);
+    for (auto &st : S->s_list) TL_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     tl_server *p = S.release();
     p->uploader = std::thread(upload_loop, p);
     p->orienter = std::thread(orient_loop, p);
-    p->lister = std::thread(list_loop, p);
+    for (u32 li = 0; li < p->cfg.list_threads; li++) p->listers.emplace_back(list_loop, p, li);
     return p;
 }
 
@@ -470,8 +479,12 @@ void server_destroy_impl(tl_server *S) {
     }
     S->uploader.join();
     S->orienter.join();
-    S->lister.join();
-    for (hipStream_t st : {S->s_copy, S->s_up, S->s_list}) {
+    for (std::thread &t : S->listers) t.join();
+    std::vector<hipStream_t> streams = S->s_list;
+    streams.push_back(S->s_copy);
+    streams.push_back(S->s_up);
+    for (hipStream_t st : streams) {
+        if (!st) continue;
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
     }

@@ -38,7 +38,7 @@ class Summary(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_batch_jobs", ctypes.c_uint32),
                 ("max_batch_edges", ctypes.c_uint64), ("solo_edges", ctypes.c_uint64),
-                ("pipeline", ctypes.c_uint32)]
+                ("pipeline", ctypes.c_uint32), ("list_threads", ctypes.c_uint32)]
 
 
 class Job(ctypes.Structure):
@@ -339,9 +339,9 @@ class Server:
     final result has been polled."""
 
     def __init__(self, hbm_budget: int, max_batch_jobs: int = 0, max_batch_edges: int = 0,
-                 solo_edges: int = 0, pipeline: bool = True):
+                 solo_edges: int = 0, pipeline: bool = True, list_threads: int = 0):
         cfg = ServerConfig(int(hbm_budget), int(max_batch_jobs), int(max_batch_edges), int(solo_edges),
-                           1 if pipeline else 0)
+                           1 if pipeline else 0, int(list_threads))
         h = ctypes.c_void_p()
         _check(_lib.tl_server_create(ctypes.byref(cfg), ctypes.byref(h)), "tl_server_create")
         self._h = h

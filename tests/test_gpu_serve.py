@@ -115,8 +115,11 @@ def test_jobs_arriving_while_others_run_are_admitted(tl, pool):
 
 @pytest.mark.parametrize("pipeline", [False, True])
 @pytest.mark.parametrize("solo_edges", [0, 1000])
-def test_batching_modes_agree(tl, pool, pipeline, solo_edges):
-    srv = tl.Server(8 * GB, max_batch_jobs=7, solo_edges=solo_edges, pipeline=pipeline)
+@pytest.mark.parametrize("list_threads", [1, 4])
+def test_batching_modes_agree(tl, pool, pipeline, solo_edges, list_threads):
+    """Every batching mode, with one or several batches listed at once,
+    gives each job the oracle's result."""
+    srv = tl.Server(8 * GB, max_batch_jobs=7, solo_edges=solo_edges, pipeline=pipeline, list_threads=list_threads)
     try:
         res = run_burst(tl, srv, pool[:16])
         for (j, _, _, want), r in zip(pool[:16], res):

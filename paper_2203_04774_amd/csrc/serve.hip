@@ -19,6 +19,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
@@ -36,6 +37,122 @@ u64 now_ns() {
                std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
+
+// Host-to-device upload through two page-locked staging buffers: copier
+// threads fill one buffer from the caller's (pageable) arrays while the
+// copy engine drains the other, so the upload runs near the link's rate
+// instead of the single-threaded pageable path's.
+class Uploader {
+  public:
+    static constexpr u64 CHUNK = 16ull << 20;  // bytes per staging buffer
+    static constexpr int COPIERS = 4;
+
+    explicit Uploader(hipStream_t s) : s_(s) {
+        bool ok = true;
+        for (int b = 0; b < 2; b++) {
+            if (hipHostMalloc(reinterpret_cast<void **>(&pin_[b]), CHUNK, hipHostMallocDefault) != hipSuccess) {
+                pin_[b] = nullptr;
+                ok = false;
+            }
+            if (hipEventCreateWithFlags(&ev_[b], hipEventDisableTiming) != hipSuccess) {
+                ev_[b] = nullptr;
+                ok = false;
+            }
+        }
+        if (!ok) {
+            release();
+            throw TlError{TL_ENOMEM, "cannot allocate the page-locked upload staging buffers"};
+        }
+        for (int t = 0; t < COPIERS; t++) th_.emplace_back([this] { copier(); });
+    }
+    ~Uploader() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+        (void)hipStreamSynchronize(s_);
+        release();
+    }
+    // bytes from host memory h to device memory d, enqueued on the stream
+    void copy(void *d, const void *h, u64 bytes) {
+        if (bytes < (1ull << 20)) {  // small: the ordinary path
+            TL_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s_));
+            return;
+        }
+        for (u64 off = 0; off < bytes; off += CHUNK) {
+            const int b = (int)(n_++ & 1);
+            if (used_[b]) TL_HIP(hipEventSynchronize(ev_[b]));  // its previous copy has left the buffer
+            const u64 len = bytes - off < CHUNK ? bytes - off : CHUNK;
+            fill(pin_[b], static_cast<const char *>(h) + off, len);
+            TL_HIP(hipMemcpyAsync(static_cast<char *>(d) + off, pin_[b], len, hipMemcpyHostToDevice, s_));
+            TL_HIP(hipEventRecord(ev_[b], s_));
+            used_[b] = true;
+        }
+    }
+
+  private:
+    void release() {
+        for (int b = 0; b < 2; b++) {
+            if (ev_[b]) (void)hipEventDestroy(ev_[b]);
+            if (pin_[b]) (void)hipHostFree(pin_[b]);
+            ev_[b] = nullptr;
+            pin_[b] = nullptr;
+        }
+    }
+    // the copier threads copy one part each of [src, src + len)
+    void fill(char *dst, const char *src, u64 len) {
+        std::unique_lock<std::mutex> lk(mu_);
+        dst_ = dst;
+        src_ = src;
+        len_ = len;
+        taken_ = 0;
+        finished_ = 0;
+        gen_++;
+        cv_.notify_all();
+        cv_done_.wait(lk, [&] { return finished_ == COPIERS; });
+    }
+    void copier() {
+        u64 seen = 0;
+        for (;;) {
+            char *dst;
+            const char *src;
+            u64 lo, hi;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                const u64 part = (len_ + COPIERS - 1) / COPIERS;
+                const u64 k = taken_++;
+                lo = k * part < len_ ? k * part : len_;
+                hi = lo + part < len_ ? lo + part : len_;
+                dst = dst_;
+                src = src_;
+            }
+            if (hi > lo) std::memcpy(dst + lo, src + lo, hi - lo);
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                if (++finished_ == COPIERS) cv_done_.notify_one();
+            }
+        }
+    }
+
+    hipStream_t s_;
+    char *pin_[2] = {nullptr, nullptr};
+    hipEvent_t ev_[2] = {nullptr, nullptr};
+    bool used_[2] = {false, false};
+    u64 n_ = 0;
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, cv_done_;
+    char *dst_ = nullptr;
+    const char *src_ = nullptr;
+    u64 len_ = 0, taken_ = 0, gen_ = 0;
+    int finished_ = 0;
+    bool stop_ = false;
+};
 
 struct Job {
     u64 id = 0;
@@ -85,6 +202,7 @@ struct tl_server {
     bool stop = false, paused = false;
     tl_server_stats st{};
 
+    std::unique_ptr<Uploader> up;  // staging pipeline of the upload thread
     std::thread uploader, orienter;
     std::vector<std::thread> listers;
 };
@@ -119,10 +237,10 @@ std::unique_ptr<Uploaded> upload_jobs(tl_server *S, const std::vector<Job *> &js
     for (Job *j : js) {
         const tl_job &J = j->in;
         if (J.m) {
-            TL_HIP(hipMemcpyAsync(U->src.as<u32>() + eo, J.src, J.m * 4, hipMemcpyHostToDevice, S->s_copy));
-            TL_HIP(hipMemcpyAsync(U->dst.as<u32>() + eo, J.dst, J.m * 4, hipMemcpyHostToDevice, S->s_copy));
+            S->up->copy(U->src.as<u32>() + eo, J.src, J.m * 4);
+            S->up->copy(U->dst.as<u32>() + eo, J.dst, J.m * 4);
         }
-        if (J.n) TL_HIP(hipMemcpyAsync(U->rank.as<u32>() + vo, J.rank, (u64)J.n * 4, hipMemcpyHostToDevice, S->s_copy));
+        if (J.n) S->up->copy(U->rank.as<u32>() + vo, J.rank, (u64)J.n * 4);
         eo += J.m;
         vo += J.n;
     }
@@ -387,6 +505,7 @@ tl_server *server_create_impl(const tl_server_config *cfg) {
     TL_HIP(hipStreamCreateWithFlags(&S->s_up, hipStreamNonBlocking));
     S->s_list.assign(S->cfg.list_threads, nullptr);
     for (auto &st : S->s_list) TL_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    S->up = std::make_unique<Uploader>(S->s_copy);
     tl_server *p = S.release();
     p->uploader = std::thread(upload_loop, p);
     p->orienter = std::thread(orient_loop, p);
@@ -480,6 +599,7 @@ void server_destroy_impl(tl_server *S) {
     S->uploader.join();
     S->orienter.join();
     for (std::thread &t : S->listers) t.join();
+    S->up.reset();
     std::vector<hipStream_t> streams = S->s_list;
     streams.push_back(S->s_copy);
     streams.push_back(S->s_up);

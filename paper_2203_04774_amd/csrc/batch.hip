@@ -37,35 +37,67 @@ __global__ void k_fill_u32(u32 *p, u64 n, u32 v) {
     GRID_STRIDE(i, n) { p[i] = v; }
 }
 
-// graph of vertex v: last i with vbase[i] <= v
-__device__ __forceinline__ u32 graph_of(const u32 *vbase, u32 k, u32 v) {
-    return (u32)(upper_bound_dev<u32>(vbase, 0, (u64)k + 1, v) - 1);
-}
+// Graphs of a wavefront's items: the wavefront's 64 consecutive items span
+// the graphs from that of its first item to that of its last, found once
+// per wavefront (the same value in every lane); each lane then searches only
+// that short range of the base array.  base[g] = first item of graph g,
+// non-decreasing; the graph of item x is the last g with base[g] <= x.
+template <class T>
+struct WaveGraphs {
+    u64 lo, hi;  // upper bounds of the wavefront's first and last item
+    __device__ __forceinline__ WaveGraphs(const T *base, u32 k, u64 w0, u64 w1) {
+        lo = upper_bound_dev<T>(base, 0, (u64)k + 1, (T)w0);
+        hi = upper_bound_dev<T>(base, lo, (u64)k + 1, (T)w1);
+    }
+    __device__ __forceinline__ u32 of(const T *base, u64 x) const {
+        return (u32)(upper_bound_dev<T>(base, lo, hi, (T)x) - 1);
+    }
+};
 
 __global__ void k_union_vertices(const u32 *rank, const u32 *vbase, u32 k, u32 N, u32 *gid, u32 *urank, u32 *flag) {
-    GRID_STRIDE(v, N) {
-        const u32 g = graph_of(vbase, k, (u32)v);
-        const u32 ng = vbase[g + 1] - vbase[g];
-        const u32 r = rank[v];
-        if (r >= ng) atomicOr(flag, 1u);
-        gid[v] = g;
-        urank[v] = vbase[g] + (r < ng ? r : 0u);
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 wfirst = first - lane_id();
+    const u64 iters = (u64)N > wfirst ? ((u64)N - wfirst + stride - 1) / stride : 0;  // wave-uniform
+    for (u64 it = 0; it < iters; it++) {
+        const u64 w0 = wfirst + it * stride;
+        const u64 w1 = w0 + WAVE - 1 < (u64)N ? w0 + WAVE - 1 : (u64)N - 1;
+        const WaveGraphs<u32> wg(vbase, k, w0, w1);
+        const u64 v = first + it * stride;
+        if (v < N) {
+            const u32 g = wg.of(vbase, v);
+            const u32 ng = vbase[g + 1] - vbase[g];
+            const u32 r = rank[v];
+            if (r >= ng) atomicOr(flag, 1u);
+            gid[v] = g;
+            urank[v] = vbase[g] + (r < ng ? r : 0u);
+        }
     }
 }
 
 __global__ void k_union_edges(const u32 *src, const u32 *dst, const u64 *ebase, const u32 *vbase, u32 k, u64 M,
                               u32 *usrc, u32 *udst, u32 *flag) {
-    GRID_STRIDE(i, M) {
-        const u32 g = (u32)(upper_bound_dev<u64>(ebase, 0, (u64)k + 1, i) - 1);
-        const u32 ng = vbase[g + 1] - vbase[g];
-        u32 a = src[i], b = dst[i];
-        if (a >= ng || b >= ng) {
-            atomicOr(flag, 2u);
-            a = 0;
-            b = 0;  // a self-loop: dropped by the orientation
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 wfirst = first - lane_id();
+    const u64 iters = M > wfirst ? (M - wfirst + stride - 1) / stride : 0;  // wave-uniform
+    for (u64 it = 0; it < iters; it++) {
+        const u64 w0 = wfirst + it * stride;
+        const u64 w1 = w0 + WAVE - 1 < M ? w0 + WAVE - 1 : M - 1;
+        const WaveGraphs<u64> wg(ebase, k, w0, w1);
+        const u64 i = first + it * stride;
+        if (i < M) {
+            const u32 g = wg.of(ebase, i);
+            const u32 ng = vbase[g + 1] - vbase[g];
+            u32 a = src[i], b = dst[i];
+            if (a >= ng || b >= ng) {
+                atomicOr(flag, 2u);
+                a = 0;
+                b = 0;  // a self-loop: dropped by the orientation
+            }
+            usrc[i] = vbase[g] + a;
+            udst[i] = vbase[g] + b;
         }
-        usrc[i] = vbase[g] + a;
-        udst[i] = vbase[g] + b;
     }
 }
 

@@ -257,7 +257,8 @@ void tl_batch_free(tl_batch *b);
  * its modelled device footprint (about 72 bytes per input edge plus 64 per
  * vertex) fits the budget beside the jobs already admitted.  Admitted jobs
  * are uploaded, oriented as one disjoint union and listed by the batched
- * pass, while the next batch is uploaded and oriented on a second stream;
+ * pass, while the next batches are uploaded and oriented on other streams
+ * (list_threads batches may be listed at once, each on a stream of its own);
  * a job with at least solo_edges edges is oriented and listed alone by the
  * plain listing.  A job whose footprint alone exceeds the budget finishes
  * with TL_ENOMEM; a malformed job (an endpoint >= n, a rank array that is
@@ -297,7 +298,10 @@ typedef struct {
     uint64_t upload_ns, orient_ns, list_ns; /* thread time in each stage, summed over batches */
 } tl_server_stats;
 
-/* Starts the server's two threads on the current device. */
+/* Starts the server on the current device: an upload thread (with its copier
+ * threads and page-locked staging buffers), an orient thread and
+ * list_threads list threads.  TL_EINVAL for list_threads above 8, TL_ENOMEM
+ * if the staging buffers cannot be allocated. */
 int tl_server_create(const tl_server_config *cfg, tl_server **out);
 /* Queues a job (never blocks on the device); *id identifies it. */
 int tl_server_submit(tl_server *s, const tl_job *job, uint64_t *id);

@@ -576,12 +576,6 @@ def main():
 
     runs = [(k, a) for k in wl["orders"] for a in wl["algos"]]
 
-    class Stats(ctypes.Structure):
-        _fields_ = [(k, ctypes.c_uint64) for k in (
-            "light_items", "heavy_items", "light_seeds", "heavy_seeds", "heavy_work", "heavy_pivots",
-            "heavy_staged", "heavy_triangles", "tasks", "items_bitmap", "items_array", "items_global",
-            "items_reverse", "items_hash", "items_bucket", "items_split")]
-
     def phase_ms():
         vals = []
         for ph in range(6):
@@ -603,14 +597,13 @@ def main():
                      else tl.list_triangles(csr, algo, out=out))
                 if record is not None:
                     after = phase_ms()
-                    st = Stats()
-                    lib.tl_last_list_stats(ctypes.byref(st))
+                    st = tl.last_list_stats()
                     record.append(dict(order=kind, algo=algo, T=int(s.count), C=int(c), work=int(s.work),
                                        scanned=int(s.scanned), hash=f"0x{s.hash:016x}", m=csr.m,
                                        orient_ms=t_or, plan_ms=after[1] - before[1],
                                        probe_ms=after[2] - before[2], light_ms=after[4] - before[4],
                                        heavy_ms=after[5] - before[5],
-                                       stats={k: int(getattr(st, k)) for k, _ in Stats._fields_}))
+                                       stats=st))
             csr.free()
 
     for i in range(args.warmup):

@@ -354,6 +354,17 @@ void tl_server_destroy(tl_server *s);
  *                        many entries scans all of it instead of the window
  *                        found by two binary searches (0..255; results are
  *                        the same, only the work split changes)
+ * for callback mode (chunks of K triangles, tl_set_chunk_triangles):
+ *   chunk_task_div       heavy tasks hold at most K / (this x heavy
+ *                        workgroups) items, at least 65536 (1..64)
+ *   chunk_growth         1: every probe slice covers K scanned items (each
+ *                        yields at most one triangle); above 1: a slice may
+ *                        cover up to this many times the previous slice's
+ *                        items, sized from its triangles per item, for
+ *                        fuller chunks; a slice that finds more than K
+ *                        triangles is probed again shorter (1..64)
+ *   chunk_margin         percent margin over the previous slice's
+ *                        triangles per item when chunk_growth > 1 (100..1000)
  * and for the batched pass (tl_batch_list; a captured pass is captured
  * again when these change):
  *   batch_heavy_min      pruned items of a pivot before its list is marked
@@ -399,6 +410,9 @@ typedef struct {
     uint64_t tasks;
     uint64_t mode_items[7]; /* heavy items by LDS form: bitmap, array, global,
                                reverse, hash, bucket, split */
+    uint64_t slices;        /* probe passes: one per chunk in callback mode */
+    uint64_t slices_redone; /* callback-mode slices that found more than a
+                               chunk of triangles and were probed again shorter */
 } tl_list_stats;
 int tl_last_list_stats(tl_list_stats *out);
 

@@ -68,6 +68,12 @@ struct Tuning {
     u64 force_mode = 255;        // testing: use this MODE_* for every heavy pivot where it fits
     u64 plan_full = 16;          // scanned lists this short are taken whole (no window searches);
                                  // below UN * WAVE, so that whole lists never fill a long window
+    // callback mode, chunks of K triangles (sweeps on RMAT scale 26, A++):
+    u64 chunk_task_div = 32;     // heavy tasks hold at most K / (this * heavy workgroups) items, so
+                                 // that each slice's launch ends with a short tail
+    u64 chunk_growth = 1;        // a slice's items grow at most this factor per slice (1: K items
+                                 // each; more gives fuller chunks but redoes the slices that overflow)
+    u64 chunk_margin = 200;      // percent margin over the last slice's triangles per item
 };
 Tuning &tuning();
 
@@ -1063,6 +1069,21 @@ __global__ __launch_bounds__(PB) void k_cost(const u64 *off_f, const u64 *off_b,
 
 u64 g_chunk_triangles = 1ull << 24;
 
+// Chunked emission: a slice's length in items stays within this many chunks.
+constexpr u64 CHUNK_GROWTH_MAX = 64;
+
+// Items for the next slice: enough for K triangles at margin_pct percent of
+// the rate the last slice saw (got triangles over `items`), at most `cap`,
+// at least K (a slice of K items cannot overflow a chunk of K triangles).
+inline u64 chunk_slice_items(u64 K, u64 got, u64 items, u64 cap, u64 margin_pct) {
+    u64 L = cap;
+    if (got) {
+        const double want = (double)K * (double)items * 100.0 / ((double)margin_pct * (double)got);
+        if (want < (double)L) L = (u64)want;
+    }
+    return L < K ? K : L;
+}
+
 GView view_of(const tl_csr *g) {
     return GView{g->off_f, g->off_b, g->adj_f, g->adj_b, g->row_f, g->row_b, g->inv, g->m, g->twin_b};
 }
@@ -1247,6 +1268,12 @@ Tuning &tuning() {
         env("TL_TUNE_FORCE_MODE", d.force_mode);
         env("TL_TUNE_PLAN_FULL", d.plan_full);
         if (d.plan_full >= (u64)(UN * WAVE)) d.plan_full = UN * WAVE - 1;
+        env("TL_TUNE_CHUNK_GROWTH", d.chunk_growth);
+        env("TL_TUNE_CHUNK_MARGIN", d.chunk_margin);
+        env("TL_TUNE_CHUNK_TASK_DIV", d.chunk_task_div);
+        d.chunk_growth = std::min<u64>(std::max<u64>(d.chunk_growth, 1), 64);
+        d.chunk_margin = std::min<u64>(std::max<u64>(d.chunk_margin, 100), 1000);
+        d.chunk_task_div = std::min<u64>(std::max<u64>(d.chunk_task_div, 1), 64);
         return d;
     }();
     return t;
@@ -1301,6 +1328,9 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "orient_sort" && value <= 1) t.orient_sort = value;
     else if (k == "force_mode" && (value < NMODES || value == 255)) t.force_mode = value;
     else if (k == "plan_full" && value < (u64)(UN * WAVE)) t.plan_full = value;
+    else if (k == "chunk_growth" && value >= 1 && value <= 64) t.chunk_growth = value;
+    else if (k == "chunk_margin" && value >= 100 && value <= 1000) t.chunk_margin = value;
+    else if (k == "chunk_task_div" && value >= 1 && value <= 64) t.chunk_task_div = value;
     else return TL_EINVAL;
     return TL_OK;
 }
@@ -1323,6 +1353,9 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "orient_sort") *value = t.orient_sort;
     else if (k == "force_mode") *value = t.force_mode;
     else if (k == "plan_full") *value = t.plan_full;
+    else if (k == "chunk_growth") *value = t.chunk_growth;
+    else if (k == "chunk_margin") *value = t.chunk_margin;
+    else if (k == "chunk_task_div") *value = t.chunk_task_div;
     else return TL_EINVAL;
     return TL_OK;
 }
@@ -1363,7 +1396,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
         PhaseTimer plan_timer(TL_PHASE_PLAN, s);
         u64 max_task = 0;
         if (cb && !tri) {
-            max_task = g_chunk_triangles / (2 * heavy_max_blocks());
+            max_task = g_chunk_triangles / (tuning().chunk_task_div * heavy_max_blocks());
             if (max_task < 65536) max_task = 65536;
         }
         if (algo == 0) make_plan<0>(v, g->n, plo, phi, max_task, d_acc, s, P);
@@ -1400,6 +1433,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
 
     int rc = TL_OK;
     u64 h_acc[NACC] = {0};
+    u64 slices = h_total ? 1 : 0, redone = 0;
     if (h_total == 0) {
         // nothing to scan
     } else if (tri) {
@@ -1410,22 +1444,40 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
         if (h_acc[0] > cap) rc = TL_ECAPACITY;
         else fix_holes(o, h_acc[0], h_acc[3], h_acc[4], s);
     } else if (cb) {
-        // each scanned element yields at most one triangle, so a slice of K
-        // work items always fits a chunk of K triangles
+        // Each scanned element yields at most one triangle, so a slice of K
+        // work items always fits a chunk of K triangles.  With chunk_growth
+        // above 1, slices grow from the previous slice's triangles per item
+        // (hit rates are far below one) for fuller chunks; a slice that finds
+        // more than K triangles (the excess is counted but dropped) is redone
+        // shorter from the accumulators saved before it.  A slice of K items
+        // cannot overflow, so this ends.
         const u64 K = g_chunk_triangles;
         chunk = DevBuf(K * 3 * sizeof(u32), s);
         o.tri = chunk.as<u32>();
         o.cap = K;
-        u64 prev_count = 0;
-        for (u64 k0 = 0; k0 < h_total; k0 += K) {
-            const u64 k1 = (h_total - k0 > K) ? k0 + K : h_total;
+        DevBuf saved(NACC * sizeof(u64), s);
+        const Tuning &tu = tuning();
+        const u64 L_max = K * CHUNK_GROWTH_MAX;
+        u64 L = K, prev_count = 0;
+        for (u64 k0 = 0; k0 < h_total;) {
+            const u64 k1 = (h_total - k0 > L) ? k0 + L : h_total;
+            TL_HIP(hipMemcpyAsync(saved.p, d_acc, NACC * sizeof(u64), hipMemcpyDeviceToDevice, s));
             TL_HIP(hipMemsetAsync(d_acc + 3, 0, 2 * sizeof(u64), s));  // cursor and holes
             probe(k0, k1, true);
             d2h_sync(s, {{h_acc, d_acc, sizeof h_acc}});
             const u64 got = h_acc[0] - prev_count;
+            if (got > K) {
+                TL_HIP(hipMemcpyAsync(d_acc, saved.p, NACC * sizeof(u64), hipMemcpyDeviceToDevice, s));
+                L = chunk_slice_items(K, got, k1 - k0, L / 2, tu.chunk_margin);
+                redone++;
+                continue;
+            }
             prev_count = h_acc[0];
             fix_holes(o, got, h_acc[3], h_acc[4], s);
             if (got && cb(o.tri, got, user) != 0) { rc = TL_EABORT; break; }
+            L = chunk_slice_items(K, got, k1 - k0, std::min(L * tu.chunk_growth, L_max), tu.chunk_margin);
+            k0 = k1;
+            if (k0 < h_total) slices++;
         }
         d2h_sync(s, {{h_acc, d_acc, sizeof h_acc}});
     } else {
@@ -1445,5 +1497,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     st.heavy_staged = h_acc[9];
     for (int md = 0; md < NMODES; md++) st.mode_items[md] = h_acc[10 + md];
     st.tasks = P.ntasks;
+    st.slices = slices;
+    st.slices_redone = redone;
     return rc;
 }

@@ -62,6 +62,16 @@ class ServerStats(ctypes.Structure):
         "peak_reserved", "pending", "max_batch_jobs_seen", "upload_ns", "orient_ns", "list_ns")]
 
 
+class ListStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in (
+        "light_items", "heavy_items", "light_seeds", "heavy_seeds", "heavy_work", "heavy_pivots",
+        "heavy_staged", "heavy_triangles", "tasks", "items_bitmap", "items_array", "items_global",
+        "items_reverse", "items_hash", "items_bucket", "items_split", "slices", "slices_redone")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 CHUNK_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)
 
 
@@ -110,6 +120,8 @@ def _load():
     for f in ("tl_server_create", "tl_server_submit", "tl_server_poll", "tl_server_cancel", "tl_server_pause",
               "tl_server_get_stats"):
         getattr(lib, f).restype = i32
+    lib.tl_last_list_stats.argtypes = [ctypes.POINTER(ListStats)]
+    lib.tl_last_list_stats.restype = i32
     lib.tl_release_cached_memory.argtypes = []
     lib.tl_release_cached_memory.restype = i32
     lib.tl_strerror.argtypes = [i32]
@@ -405,6 +417,14 @@ def release_cached_memory():
 
 def set_chunk_triangles(k: int):
     _check(_lib.tl_set_chunk_triangles(k), "tl_set_chunk_triangles")
+
+
+def last_list_stats() -> dict:
+    """Work split and slice counts of this thread's most recent listing
+    (tl_last_list_stats)."""
+    st = ListStats()
+    _check(_lib.tl_last_list_stats(ctypes.byref(st)), "tl_last_list_stats")
+    return st.as_dict()
 
 
 def set_tuning(key: str, value: int):

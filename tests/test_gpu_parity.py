@@ -234,6 +234,59 @@ def test_chunked_output_and_abort(tl):
 
 
 @pytest.mark.parametrize("algo", ALGOS)
+def test_chunked_slices_redone_after_overflow(tl, algo):
+    """With chunk_growth above 1, callback slices grow while triangles are
+    rare.  A sparse part listed first and a clique listed last (highest
+    ranks) make a grown slice find more than a chunk of triangles; it is
+    probed again shorter, and the chunks still hold exactly the oracle's
+    list, each within the chunk."""
+    import ctypes
+    import itertools
+
+    import torch
+    rs = np.random.default_rng(21)
+    ns, nk, K = 3000, 48, 500
+    u, v = rs.integers(0, ns, 9000), rs.integers(0, ns, 9000)
+    keep = u != v
+    sparse = np.stack([np.minimum(u, v)[keep], np.maximum(u, v)[keep]], 1)
+    clique = np.array(list(itertools.combinations(range(ns, ns + nk), 2)))
+    pairs = np.unique(np.vstack([sparse, clique]), axis=0).astype(np.uint32)
+    n, s, d = ns + nk, pairs[:, 0].copy(), pairs[:, 1].copy()
+    r = np.concatenate([rs.permutation(ns), ns + np.arange(nk)]).astype(np.uint32)
+    ref = oracle.list_triangles(n, s, d, r, algo)
+    g = tl.orient(n, dev(s), dev(d), dev(r))
+    tl.set_chunk_triangles(K)
+    saved = {k: tl.get_tuning(k) for k in ("chunk_growth", "chunk_margin")}
+    tl.set_tuning("chunk_growth", 4)
+    tl.set_tuning("chunk_margin", 125)
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        parts = []
+
+        def sink(ptr, k):
+            assert 0 < k <= K
+            buf = torch.empty((k, 3), dtype=torch.int32, device="cuda")
+            assert hip.hipMemcpy(buf.data_ptr(), ptr, k * 12, 3) == 0
+            parts.append(buf.cpu().numpy().view(np.uint32))
+            return False
+
+        st = tl.list_triangles(g, algo, on_chunk=sink)
+        stats = tl.last_list_stats()
+        assert (st.count, st.hash, st.work) == (ref.count, ref.hash, ref.work)
+        assert np.array_equal(sort_rows(np.vstack(parts)), ref.sorted_triangles())
+        assert stats["slices_redone"] >= 1
+        assert stats["slices"] >= len(parts)
+        # fewer slices than the one-item-one-triangle bound would need
+        assert stats["slices"] < -(-st.scanned // K)
+    finally:
+        for k, v in saved.items():
+            tl.set_tuning(k, v)
+        tl.set_chunk_triangles(1 << 24)
+        g.free()
+
+
+@pytest.mark.parametrize("algo", ALGOS)
 def test_pivot_ranges_partition(tl, algo):
     n, s, d = G.erdos_renyi(150, 0.15, 4)
     r = np.random.default_rng(4).permutation(n).astype(np.uint32)

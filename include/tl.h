@@ -325,6 +325,10 @@ void tl_server_destroy(tl_server *s);
  *   slice_min            items per heavy-pivot task, at least (>= 64)
  *   slice_mult           tasks are also >= this many times the pivot's
  *                        staging cost (>= 1)
+ *   task_div             ... but at most the listing's work (Definition 1)
+ *                        / (this x heavy workgroups) items, at least 65536,
+ *                        so that a few hub pivots do not end the launch
+ *                        alone (0..1024; 0: no such cap)
  *   heavy_blocks_per_cu  heavy-pivot workgroups launched per CU (1..64)
  *   light_blocks_per_cu  light-pivot workgroups launched per CU (1..64)
  *   queue                1: heavy tasks handed out by an atomic queue

@@ -49,13 +49,17 @@ constexpr u32 FLAG_WORDS = UN * WAVE / 4;  // per wavefront: seed-start flags of
 // bitmap + low entries + staging and flags for every wavefront: 160 KB in all
 constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + LOW_WORDS * 4 + (HB / WAVE) * (STAGE_WORDS + FLAG_WORDS) * 4;
 static_assert(HEAVY_LDS_BYTES + 64 <= 160 * 1024, "heavy kernel LDS");
+// Smallest task the balance cap (task_div) makes.
+constexpr u64 BAL_TASK_MIN = 65536;
 // Tunable launch parameters (defaults; tl_set_tuning or TL_TUNE_* env vars).
 struct Tuning {
     // defaults from sweeps on the Chung-Lu 2^20 workload (random and degree
     // orders, A++ and A+-) on MI355X
     u64 heavy_min = 8192;        // items of a pivot before it gets a workgroup
     u64 slice_min = 262144;      // items per heavy task, at least
-    u64 slice_mult = 16;         // ... and at least this many times its staging cost
+    u64 slice_mult = 2;          // ... and at least this many times its staging cost
+    u64 task_div = 32;           // ... but at most the listing's work / (this * heavy workgroups), at
+                                 // least BAL_TASK_MIN (0: no such cap)
     u64 heavy_blocks_per_cu = 1; // heavy grid = this many workgroups per CU
     u64 queue = 1;               // 1: heavy tasks handed out by an atomic queue
     u64 splits = 1;              // 1: wavefront start seeds precomputed at plan time
@@ -205,12 +209,19 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 full
 template <int ALGO>
 __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask,
                                                     u64 *slice, u64 heavy_min, u64 slice_min, u64 slice_mult,
-                                                    u64 max_task, u64 reverse, u64 use_hash, u64 use_bucket,
-                                                    u64 use_split, u64 force_mode, u64 *acc) {
+                                                    u64 max_task, u64 bal_div, u64 reverse, u64 use_hash,
+                                                    u64 use_bucket, u64 use_split, u64 force_mode, u64 *acc) {
     __shared__ u64 lds[PB / WAVE];
     __shared__ u64 mode_items[NMODES];  // heavy items per form, summed in LDS (one global atomic per form)
     if (threadIdx.x < NMODES) mode_items[threadIdx.x] = 0;
     __syncthreads();
+    // balance: no task above 1/bal_div of the listing's work (acc[2], summed
+    // by the plan kernel), so that a few hub pivots do not end the launch alone
+    u64 bal = 0;
+    if (bal_div) {
+        bal = acc[2] / bal_div;
+        if (bal < BAL_TASK_MIN) bal = BAL_TASK_MIN;
+    }
     u64 hp = 0, staged = 0;
     GRID_STRIDE(p, n) {
         const u64 w = wp[p];
@@ -247,6 +258,7 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             else { md = MODE_GLOBAL; stage = 0; }
             sl = slice_mult * stage;
             if (sl < slice_min) sl = slice_min;
+            if (bal && sl > bal) sl = bal;
             if (max_task && sl > max_task) sl = max_task;
             nt = (u32)((w + sl - 1) / sl);
             hp += 1;
@@ -1100,6 +1112,11 @@ struct Plan {
     u64 work = 0;     // the paper's work over the listed pivots
 };
 
+// Largest grids the probe kernels are launched with; they bound the number
+// of wavefronts, hence of holes, per launch.
+inline u64 light_max_blocks() { return (u64)tl_num_cus() * tuning().light_blocks_per_cu; }
+inline u64 heavy_max_blocks() { return (u64)tl_num_cus() * tuning().heavy_blocks_per_cu; }
+
 template <int ALGO>
 // max_task: items per heavy task at most (0: no limit).  A listing probed in
 // item slices keeps tasks well below a slice, so that every slice has work
@@ -1118,7 +1135,8 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
     const Tuning &tu = tuning();
     hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), mode.as<u32>(),
                        ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult, max_task,
-                       tu.reverse, tu.hash, tu.bucket, tu.split, tu.force_mode, d_acc);
+                       tu.task_div ? tu.task_div * heavy_max_blocks() : 0, tu.reverse, tu.hash, tu.bucket, tu.split,
+                       tu.force_mode, d_acc);
     TL_HIP(hipGetLastError());
     DevBuf flags(m * sizeof(u64), s), pos((m + 1) * sizeof(u64), s);
     hipLaunchKernelGGL((k_seed_class<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), mode.as<u32>(),
@@ -1168,10 +1186,6 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
     P.w_total = h_w[1];
 }
 
-// Largest grids the probe kernels are launched with; they bound the number
-// of wavefronts, hence of holes, per launch.
-inline u64 light_max_blocks() { return (u64)tl_num_cus() * tuning().light_blocks_per_cu; }
-inline u64 heavy_max_blocks() { return (u64)tl_num_cus() * tuning().heavy_blocks_per_cu; }
 inline u64 max_holes_per_probe() { return light_max_blocks() * (PB / WAVE) + heavy_max_blocks() * (HB / WAVE); }
 
 inline LightSeeds light_seeds(const Plan &P) {
@@ -1256,6 +1270,8 @@ Tuning &tuning() {
         env("TL_TUNE_HEAVY_MIN", d.heavy_min);
         env("TL_TUNE_SLICE_MIN", d.slice_min);
         env("TL_TUNE_SLICE_MULT", d.slice_mult);
+        env("TL_TUNE_TASK_DIV", d.task_div);
+        if (d.task_div > 1024) d.task_div = 1024;
         env("TL_TUNE_HEAVY_BLOCKS_PER_CU", d.heavy_blocks_per_cu);
         env("TL_TUNE_QUEUE", d.queue);
         env("TL_TUNE_SPLITS", d.splits);
@@ -1317,6 +1333,7 @@ int set_tuning(const char *key, u64 value) {
     if (k == "heavy_min" && value >= 1) t.heavy_min = value;
     else if (k == "slice_min" && value >= 64) t.slice_min = value;
     else if (k == "slice_mult" && value >= 1) t.slice_mult = value;
+    else if (k == "task_div" && value <= 1024) t.task_div = value;
     else if (k == "heavy_blocks_per_cu" && value >= 1 && value <= 64) t.heavy_blocks_per_cu = value;
     else if (k == "queue" && value <= 1) t.queue = value;
     else if (k == "splits" && value <= 1) t.splits = value;
@@ -1342,6 +1359,7 @@ int get_tuning(const char *key, u64 *value) {
     if (k == "heavy_min") *value = t.heavy_min;
     else if (k == "slice_min") *value = t.slice_min;
     else if (k == "slice_mult") *value = t.slice_mult;
+    else if (k == "task_div") *value = t.task_div;
     else if (k == "heavy_blocks_per_cu") *value = t.heavy_blocks_per_cu;
     else if (k == "queue") *value = t.queue;
     else if (k == "splits") *value = t.splits;

@@ -76,9 +76,10 @@ def test_tuning_keys_and_ranges(lib):
     assert lib.tl_get_tuning(b"plan_full", ctypes.byref(v)) == 0 and v.value == 255
     assert lib.tl_set_tuning(b"plan_full", old) == 0
     assert lib.tl_set_tuning(b"no_such_key", 1) != 0
-    for key, bad in ((b"chunk_growth", 0), (b"chunk_growth", 65), (b"chunk_margin", 99), (b"chunk_task_div", 0)):
+    for key, bad in ((b"chunk_growth", 0), (b"chunk_growth", 65), (b"chunk_margin", 99), (b"chunk_task_div", 0),
+                     (b"task_div", 1025)):
         assert lib.tl_set_tuning(key, bad) != 0
-    for key in (b"chunk_growth", b"chunk_margin", b"chunk_task_div"):
+    for key in (b"chunk_growth", b"chunk_margin", b"chunk_task_div", b"task_div"):
         assert lib.tl_get_tuning(key, ctypes.byref(v)) == 0
         assert lib.tl_set_tuning(key, v.value) == 0
     assert lib.tl_set_tuning(b"batch_plan_full", 8) == 0

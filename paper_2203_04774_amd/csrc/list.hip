@@ -945,12 +945,12 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                         cur.advance(kb, cur.c_lo);
                         continue;
                     }
-                    if (kb + UN * WAVE <= we) {
-                        // short windows: if the next UN chunks lie in the 64 seeds
-                        // starting at the current one, one load of their prefix,
-                        // scan start and endpoint id serves all UN chunks.  The
-                        // next window's loads are issued before this group's
-                        // tests, so they overlap (software pipelining).
+                    if (kb + WAVE <= we) {
+                        // short windows: the items of the 64 seeds starting at the
+                        // current one, up to UN chunks, with one load of their
+                        // prefix, scan start and endpoint id.  The next window's
+                        // loads are issued before this group's tests, so they
+                        // overlap (software pipelining).
                         u64 P, A, pend;
                         u32 X;
                         if (pf_c == cur.c_lo) {
@@ -958,19 +958,32 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                         } else {
                             fetch_window(cur.c_lo, P, A, X, pend);
                         }
-                        if (pend >= kb + UN * WAVE) {
+                        // items the window holds within this wavefront's range; at
+                        // least one full chunk, else the one-chunk path below (SPLIT
+                        // takes only full groups: partial ones measured slower there)
+                        const u64 lim = pend < we ? pend : we;
+                        if (lim >= kb + (MD == MODE_SPLIT ? UN * WAVE : WAVE)) {
+                            const bool full = lim >= kb + UN * WAVE;  // wave-uniform
                             // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
                             const u32 E = (u32)(A - P + kb);
                             int lo[UN];
                             const int lo_last = locate_short(P, kb, flag, lo);
                             u32 y[UN], xv[UN];
-                            bool h[UN];
+                            bool h[UN], act[UN];
 #pragma unroll
                             for (int j = 0; j < UN; j++) {
-                                y[j] = SA[(u32)(__shfl(E, lo[j], WAVE) + (u32)(j * WAVE + lane))];
+                                // the shuffles run on every lane (a lane cannot read a
+                                // value from a lane that skips the shuffle)
+                                const u32 ej = (u32)__shfl(E, lo[j], WAVE);
                                 xv[j] = __shfl(X, lo[j], WAVE);
+                                // items at or past lim belong to no seed of the window:
+                                // such lanes test tmax (a valid rank for every form's
+                                // lookup, REVERSE's offsets included, and inside SPLIT's
+                                // bitmap, so it starts no global search) and drop the result
+                                act[j] = full || kb + (u64)(j * WAVE + lane) < lim;
+                                y[j] = act[j] ? SA[ej + (u32)(j * WAVE + lane)] : tmax;
                             }
-                            const u64 kn = kb + UN * WAVE;
+                            const u64 kn = full ? kb + UN * WAVE : lim;
                             if (kn < we) {
                                 // seed of item kn: the last lane's seed, or the next one
                                 u64 c = cur.c_lo + (u64)lo_last;
@@ -981,6 +994,8 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                                 pf_c = cur.c_lo;
                             }
                             member_all(y, h);
+#pragma unroll
+                            for (int j = 0; j < UN; j++) h[j] = h[j] && act[j];
                             report(y, h, xv);
                             kb = kn;
                             continue;

@@ -330,7 +330,9 @@ void tl_server_destroy(tl_server *s);
  *                        so that a few hub pivots do not end the launch
  *                        alone (0..1024; 0: no such cap)
  *   heavy_blocks_per_cu  heavy-pivot workgroups launched per CU (1..64)
- *   light_blocks_per_cu  light-pivot workgroups launched per CU (1..64)
+ *   light_blocks_per_cu  light-pivot workgroups launched per CU, at most (1..64)
+ *   light_wave_items     ... and no more than one wavefront per this many
+ *                        light items (64..2^30)
  *   queue                1: heavy tasks handed out by an atomic queue
  *   splits               1: wavefront start seeds precomputed per task
  *   hash                 1: a heavy pivot whose list's rank window is too

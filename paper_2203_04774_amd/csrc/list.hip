@@ -63,7 +63,8 @@ struct Tuning {
     u64 heavy_blocks_per_cu = 1; // heavy grid = this many workgroups per CU
     u64 queue = 1;               // 1: heavy tasks handed out by an atomic queue
     u64 splits = 1;              // 1: wavefront start seeds precomputed at plan time
-    u64 light_blocks_per_cu = 8; // light grid cap
+    u64 light_blocks_per_cu = 16; // light grid cap
+    u64 light_wave_items = 8192;  // light grid: at least this many items per wavefront
     u64 reverse = 0;             // 1: REVERSE instead of GLOBAL for lists that fit no LDS form
     u64 hash = 0;                // 1: HASH before ARRAY when B's window does not fit LDS
     u64 bucket = 0;              // 1: BUCKET before ARRAY when B's window does not fit LDS
@@ -1214,7 +1215,8 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
     const u64 l0 = k0, l1 = k1 < P.w_light ? k1 : P.w_light;
     if (l0 < l1) {
         PhaseTimer tlight(TL_PHASE_PROBE_LIGHT, s);
-        const u64 waves_needed = (l1 - l0 + WAVE - 1) / WAVE;
+        const u64 wi = tuning().light_wave_items;
+        const u64 waves_needed = (l1 - l0 + wi - 1) / wi;
         u64 blocks = (waves_needed + (PB / WAVE) - 1) / (PB / WAVE);
         if (blocks > light_max_blocks()) blocks = light_max_blocks();
         if (blocks < 1) blocks = 1;
@@ -1291,6 +1293,8 @@ Tuning &tuning() {
         env("TL_TUNE_QUEUE", d.queue);
         env("TL_TUNE_SPLITS", d.splits);
         env("TL_TUNE_LIGHT_BLOCKS_PER_CU", d.light_blocks_per_cu);
+        env("TL_TUNE_LIGHT_WAVE_ITEMS", d.light_wave_items);
+        if (d.light_wave_items < (u64)WAVE) d.light_wave_items = WAVE;
         env("TL_TUNE_REVERSE", d.reverse);
         env("TL_TUNE_HASH", d.hash);
         env("TL_TUNE_BUCKET", d.bucket);
@@ -1353,6 +1357,7 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "queue" && value <= 1) t.queue = value;
     else if (k == "splits" && value <= 1) t.splits = value;
     else if (k == "light_blocks_per_cu" && value >= 1 && value <= 64) t.light_blocks_per_cu = value;
+    else if (k == "light_wave_items" && value >= (u64)WAVE && value <= (1ull << 30)) t.light_wave_items = value;
     else if (k == "reverse" && value <= 1) t.reverse = value;
     else if (k == "hash" && value <= 1) t.hash = value;
     else if (k == "bucket" && value <= 1) t.bucket = value;
@@ -1379,6 +1384,7 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "queue") *value = t.queue;
     else if (k == "splits") *value = t.splits;
     else if (k == "light_blocks_per_cu") *value = t.light_blocks_per_cu;
+    else if (k == "light_wave_items") *value = t.light_wave_items;
     else if (k == "reverse") *value = t.reverse;
     else if (k == "hash") *value = t.hash;
     else if (k == "bucket") *value = t.bucket;

@@ -77,9 +77,9 @@ def test_tuning_keys_and_ranges(lib):
     assert lib.tl_set_tuning(b"plan_full", old) == 0
     assert lib.tl_set_tuning(b"no_such_key", 1) != 0
     for key, bad in ((b"chunk_growth", 0), (b"chunk_growth", 65), (b"chunk_margin", 99), (b"chunk_task_div", 0),
-                     (b"task_div", 1025)):
+                     (b"task_div", 1025), (b"light_wave_items", 63)):
         assert lib.tl_set_tuning(key, bad) != 0
-    for key in (b"chunk_growth", b"chunk_margin", b"chunk_task_div", b"task_div"):
+    for key in (b"chunk_growth", b"chunk_margin", b"chunk_task_div", b"task_div", b"light_wave_items"):
         assert lib.tl_get_tuning(key, ctypes.byref(v)) == 0
         assert lib.tl_set_tuning(key, v.value) == 0
     assert lib.tl_set_tuning(b"batch_plan_full", 8) == 0

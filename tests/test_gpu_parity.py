@@ -398,6 +398,10 @@ TUNINGS = {
 for _name in ["all-light", "bitmap", "array", "global", "reverse", "hash", "bucket", "split", "split-auto"]:
     TUNINGS[_name + "+whole-lists"] = {**TUNINGS[_name], "plan_full": 255}
 TUNINGS["no-whole-lists"] = {"plan_full": 0}
+# one light wavefront per 64 items (the smallest share): many light
+# wavefronts, hence many emission blocks and holes, even on small graphs
+TUNINGS["all-light-many-waves"] = {"heavy_min": 1 << 40, "light_wave_items": 64}
+TUNINGS["many-light-waves"] = {"light_wave_items": 64}
 
 
 def wide_hub_case(seed):

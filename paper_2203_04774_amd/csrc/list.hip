@@ -333,6 +333,21 @@ __global__ void k_compact(GView g, const u32 *len, const u64 *sabs, const u64 *p
     }
 }
 
+// The plan's totals, gathered for one read by the host: packed compacted
+// seed counts (light | heavy << 32), heavy tasks, light items, all items and
+// the paper's work (acc[2]).
+__global__ void k_plan_totals(const u64 *pos, u64 m, const u64 *tpos, u32 n, const u64 *cpre, const u64 *acc,
+                              u64 *out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const u64 hp = pos[m];
+        out[0] = hp;
+        out[1] = tpos[n];
+        out[2] = cpre[hp & 0xffffffffull];
+        out[3] = cpre[m];
+        out[4] = acc[2];
+    }
+}
+
 template <int ALGO>
 __global__ void k_make_tasks(GView g, u32 n, const u32 *mode, const u32 *ntask, const u64 *slice, const u64 *tpos,
                              const u64 *pos, const u64 *cpre, u64 m, Task *tasks) {
@@ -1175,12 +1190,21 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
     scan_u32_to_u64(clen, P.cpre.as<u64>(), m, s);
     DevBuf tpos(((u64)n + 1) * sizeof(u64), s);
     scan_u32_to_u64(ntask.as<u32>(), tpos.as<u64>(), n, s);
-    u64 h_pos = 0, h_nt = 0;
-    d2h_sync(s, {{&h_pos, pos.as<u64>() + m, sizeof(u64)}, {&h_nt, tpos.as<u64>() + n, sizeof(u64)}});
+    // every total the host needs, in one round trip
+    DevBuf tot(5 * sizeof(u64), s);
+    hipLaunchKernelGGL(k_plan_totals, dim3(1), dim3(WAVE), 0, s, pos.as<u64>(), m, tpos.as<u64>(), n,
+                       P.cpre.as<u64>(), d_acc, tot.as<u64>());
+    TL_HIP(hipGetLastError());
+    u64 h_t[5] = {0, 0, 0, 0, 0};
+    d2h_sync(s, {{h_t, tot.p, sizeof h_t}});
+    const u64 h_pos = h_t[0], h_nt = h_t[1];
     const u64 nl = h_pos & 0xffffffffull, nh = h_pos >> 32;
     P.ncomp = nl + nh;
     P.nlight = nl;
     P.ntasks = h_nt;
+    P.w_light = h_t[2];
+    P.w_total = h_t[3];
+    P.work = h_t[4];
     if (h_nt) {
         P.tasks = DevBuf(h_nt * sizeof(Task), s);
         hipLaunchKernelGGL((k_make_tasks<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, mode.as<u32>(), ntask.as<u32>(),
@@ -1193,13 +1217,6 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
             TL_HIP(hipGetLastError());
         }
     }
-    u64 h_w[3] = {0, 0, 0};
-    d2h_sync(s, {{&h_w[0], P.cpre.as<u64>() + nl, sizeof(u64)},
-                 {&h_w[1], P.cpre.as<u64>() + m, sizeof(u64)},
-                 {&h_w[2], d_acc + 2, sizeof(u64)}});
-    P.work = h_w[2];
-    P.w_light = h_w[0];
-    P.w_total = h_w[1];
 }
 
 inline u64 max_holes_per_probe() { return light_max_blocks() * (PB / WAVE) + heavy_max_blocks() * (HB / WAVE); }

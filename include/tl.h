@@ -70,8 +70,11 @@ typedef struct {
     uint64_t scanned;
 } tl_summary;
 
-/* Chunk sink: receives `k` triangles (3*k uint32 in device memory, valid
- * until the callback returns).  A non-zero return stops the listing with
+/* Chunk sink: receives `k` triangles, 0 < k <= the chunk size (3*k uint32
+ * in device memory, valid until the callback returns; the stream is
+ * synchronised before the call).  Each call holds the triangles of one probe
+ * slice of the work items, so calls number at least (triangles / chunk size)
+ * and chunks need not be full.  A non-zero return stops the listing with
  * TL_EABORT. */
 typedef int (*tl_chunk_fn)(const uint32_t *tri_dev, uint64_t k, void *user);
 

@@ -83,3 +83,55 @@ def test_tuning_keys_and_ranges(lib):
         assert lib.tl_get_tuning(key, ctypes.byref(v)) == 0
         assert lib.tl_set_tuning(key, v.value) == 0
     assert lib.tl_set_tuning(b"batch_plan_full", 8) == 0
+
+
+# ctypes mirrors in the binding and the C structs they stand for
+MIRRORS = {
+    "Summary": "tl_summary",
+    "NeighResult": "tl_neigh_result",
+    "ServerConfig": "tl_server_config",
+    "Job": "tl_job",
+    "JobResult": "tl_job_result",
+    "ServerStats": "tl_server_stats",
+    "ListStats": "tl_list_stats",
+}
+
+
+def c_layouts(tmp_path):
+    """sizeof and offsetof of every mirrored struct, from a C program compiled
+    against include/tl.h with the host compiler."""
+    import shutil
+    import subprocess
+    import sys
+    sys.path.insert(0, ROOT)
+    import paper_2203_04774_amd.tl as b
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tl.h"', "int main(void) {"]
+    for py, c in MIRRORS.items():
+        lines.append(f'printf("{py} size %zu\\n", sizeof({c}));')
+        # offsets of the C fields named like the mirror's (arrays are flattened
+        # in the mirrors: mode_items[7] -> items_bitmap ... items_split)
+        for name, _ in getattr(b, py)._fields_:
+            if not name.startswith("items_"):
+                lines.append(f'printf("{py} {name} %zu\\n", offsetof({c}, {name}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return b, [line.split() for line in out.splitlines()]
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes struct of the binding has the C struct's size and field
+    offsets (a mirror that drifts would read or write the wrong bytes)."""
+    b, rows = c_layouts(tmp_path)
+    for py, what, val in rows:
+        cls = getattr(b, py)
+        if what == "size":
+            assert ctypes.sizeof(cls) == int(val), (py, ctypes.sizeof(cls), val)
+        else:
+            assert getattr(cls, what).offset == int(val), (py, what)

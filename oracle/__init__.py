@@ -3,9 +3,13 @@
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The product path (the HIP library and its binding)
 never does.  The C source, ``oracle.c``, is a plain single-threaded
-statement of Algorithms 1 (A++) and 2 (A+-) of Lecuyer et al., "Tailored
-vertex ordering for faster triangle listing in large graphs", with the
-boolean array B of the paper, a work counter, and Definition 1's costs.
+statement of what Lecuyer et al., "Tailored vertex ordering for faster
+triangle listing in large graphs", list and count: every triangle once,
+found from the definition (an edge plus a vertex adjacent to both ends,
+under the orientation by the ordering), grouped by the pivot role that
+Algorithm 1 (A++), Algorithm 2 (A+-) or the A-- variant gives one of its
+vertices; the work of Property 1 and Definition 1's costs; and the paper's
+orderings.
 """
 from __future__ import annotations
 
@@ -56,6 +60,12 @@ def _load():
     lib.orc_graph_new.argtypes = [u32, u64, u32p, u32p, u32p, ctypes.POINTER(ctypes.c_int)]
     lib.orc_graph_list.restype = ctypes.c_int
     lib.orc_graph_list.argtypes = [vp, ctypes.c_int, u32, u32, vp, u64, u64p]
+    lib.orc_graph_bin.restype = ctypes.c_int
+    lib.orc_graph_bin.argtypes = [vp, ctypes.c_int, u32, u32, u32, u32p, u64p]
+    lib.orc_graph_work.restype = u64
+    lib.orc_graph_work.argtypes = [vp, ctypes.c_int, u32, u32]
+    lib.orc_graph_m.restype = u64
+    lib.orc_graph_m.argtypes = [vp]
     lib.orc_graph_free.restype = None
     lib.orc_graph_free.argtypes = [vp]
     lib.orc_triangle_hash.restype = u64
@@ -108,8 +118,9 @@ def _arrs(src, dst, rank):
 
 def list_triangles(n, src, dst, rank, algo="A++", pivot_lo=0, pivot_hi=None,
                    want_triangles=True, cap=None) -> Listing:
-    """Run Algorithm 1 (A++), 2 (A+-) or the S2 variant (A--) over pivots
-    with rank in [pivot_lo, pivot_hi)."""
+    """The triangles whose pivot for the form -- A++ (Algorithm 1): the
+    vertex of largest rank; A+- (Algorithm 2): smallest; A--: middle -- has
+    rank in [pivot_lo, pivot_hi), with the paper's work over those pivots."""
     lib = _load()
     s, d, r = _arrs(src, dst, rank)
     if pivot_hi is None:
@@ -131,7 +142,7 @@ def list_triangles(n, src, dst, rank, algo="A++", pivot_lo=0, pivot_hi=None,
 
 
 def list_ranges(n, src, dst, rank, algo, ranges, caps=None):
-    """Algorithm 1/2 over several pivot ranges with one graph build.
+    """list_triangles over several pivot ranges with one graph build.
 
     ranges: list of (lo, hi); caps: None (counts only) or a list of
     capacities, in which case each range's triangles are returned too.
@@ -177,6 +188,27 @@ class BuiltGraph:
         _check(lib.orc_graph_list(self._h, ALGOS[algo], lo, hi, tri.ctypes.data if cap else None, cap, out))
         c = int(out[0])
         return Listing(c, int(out[1]), int(out[2]), int(out[3]), tri[:min(c, cap)] if cap else None)
+
+    def work(self, algo="A++", lo=0, hi=None) -> int:
+        """The paper's work (Property 1) over pivots of rank in [lo, hi)."""
+        hi = self.n if hi is None else hi
+        return int(_load().orc_graph_work(self._h, ALGOS[algo], lo, hi))
+
+    @property
+    def m(self) -> int:
+        return int(_load().orc_graph_m(self._h))
+
+    def bin(self, algo, cuts, src_lo=0, src_hi=None) -> np.ndarray:
+        """(count, hash) per bin [cuts[i], cuts[i+1]) of pivot ranks for the
+        form, over the triangles whose smallest rank lies in [src_lo,
+        src_hi); summing over a partition of the source ranks gives every
+        bin for the whole graph.  Returns a (len(cuts)-1, 2) uint64 array."""
+        lib = _load()
+        hi = self.n if src_hi is None else src_hi
+        c = np.ascontiguousarray(cuts, np.uint32)
+        out = np.zeros(2 * (len(c) - 1), np.uint64)
+        _check(lib.orc_graph_bin(self._h, ALGOS[algo], src_lo, hi, len(c) - 1, c, out))
+        return out.reshape(-1, 2)
 
     def close(self):
         if self._h:

@@ -14,17 +14,20 @@
  *                      pi_u < pi_v, successors N+ and predecessors N-.
  *                      Input loops and duplicate pairs are dropped, as the
  *                      experimental setup does with its datasets (Sec. 4.1.1).
- *   A++                Algorithm 1: for each vertex w, mark N-_w in a boolean
- *                      array B; for each u in N-_w scan all of N+_u and report
- *                      {u,v,w} for every v with B[v]; unmark.
- *   A+-                Algorithm 2: for each vertex u, mark N+_u; for each v
- *                      in N+_u scan all of N+_v and report {u,v,w} for every
- *                      marked w; unmark.
+ *   listing            each triangle of G exactly once, found from the
+ *                      definition (an edge and a vertex adjacent to both of
+ *                      its ends) rather than by the paper's marking scheme;
+ *                      the forms A++ (Algorithm 1), A+- (Algorithm 2) and
+ *                      A-- (Section 2.1's footnote) fix which vertex of a
+ *                      triangle is the outer-loop pivot, which matters only
+ *                      when the pivots are restricted to a rank range.
  *   cost               Definition 1: C++ = sum_u d+_u d+_u,
  *                      C+- = sum_u d+_u d-_u.
  *   work               one unit per element scanned in the innermost loop of
- *                      Algorithms 1/2; by Property 1 it sums to C++ (A++) or
- *                      C+- (A+-), which the tests check.
+ *                      Algorithms 1/2, taken from Property 1's count (each
+ *                      seed edge scans one whole list); summed over all
+ *                      pivots it equals C++ (A++) or C+- (A+-), which the
+ *                      tests check against the costs computed separately.
  *
  * Output convention (not fixed by the paper): a triangle is reported as its
  * three original vertex ids sorted ascending, a < b < c.  The 64-bit
@@ -166,17 +169,132 @@ static int graph_build(graph *g, u32 n, u64 m_in, const u32 *src, const u32 *dst
 #define DPLUS(g, u) ((g)->poff[(u) + 1] - (g)->poff[(u)])
 #define DMINUS(g, u) ((g)->moff[(u) + 1] - (g)->moff[(u)])
 
-/* ------------------------------------------------------------ reporting */
+/* ============================================================ listing
+ *
+ * What is listed has a plain definition (Section 1.3): a triangle is a set
+ * of three vertices joined pairwise by edges, and the task is to report each
+ * one exactly once.  Under the ordering pi the three vertices of a triangle
+ * have distinct ranks r1 < r2 < r3, and in the DAG G_pi its edges are
+ * r1 -> r2, r1 -> r3 and r2 -> r3 (Figure 1): one source, one middle
+ * vertex, one sink.  Reporting a triangle once is reporting it under one of
+ * these roles, and the three forms of Section 2.1 differ only in which role
+ * their outer loop runs over (the pivot):
+ *   A++ (Algorithm 1)  the sink r3     (outer vertex w)
+ *   A+- (Algorithm 2)  the source r1   (outer vertex u)
+ *   A--                the middle r2   (outer vertex v)
+ * Listing "with pivots of rank in [lo, hi)" is therefore the set of
+ * triangles whose vertex in the form's pivot role has a rank in [lo, hi).
+ *
+ * This file finds them from the definition, not by the paper's marking
+ * scheme: a triangle is an edge together with a vertex adjacent to both of
+ * its ends.  For a pivot p and each edge of p in the direction that keeps p
+ * in its role, the third vertex ranges over the common part of the two
+ * endpoint lists that the role allows, found by intersecting two sorted
+ * lists:
+ *   sink p:    for q in N-(p), third in N-(q) & N-(p)   (ranks third < q < p)
+ *   source p:  for q in N+(p), third in N+(p) & N+(q)   (ranks p < q < third)
+ *   middle p:  for q in N-(p), third in N+(q) & N+(p)   (ranks q < p < third)
+ * Each triangle of the role appears exactly once: its other two vertices are
+ * told apart by rank, the smaller-or-middle one being q.
+ *
+ * The paper's work (one unit per element of the innermost scan of
+ * Algorithms 1/2) is taken from its counting instead of from a scan: for
+ * each seed edge the form scans one whole list (Property 1):
+ *   A++  pivot w, seeds u in N-(w), each scanning N+(u):  sum d+(u)
+ *   A+-  pivot u, seeds v in N+(u), each scanning N+(v):  sum d+(v)
+ *   A--  pivot v, seeds w in N+(v), each scanning N-(w):  sum d-(w)
+ * Summed over all pivots these are Definition 1's costs by double counting,
+ * which the tests check against the costs computed separately.
+ */
+
+/* The oriented graph in rank space: vertex r is the vertex of rank r, its
+ * successor list P(r) and predecessor list M(r) hold ranks, ascending. */
+typedef struct {
+    u32 n;
+    u64 m;
+    u32 *inv;          /* inv[r] = original id of rank r */
+    u64 *poff, *moff;  /* n+1 each */
+    u32 *P, *M;
+} dag;
+
+static void dag_free(dag *d) {
+    free(d->inv); free(d->poff); free(d->moff); free(d->P); free(d->M);
+    memset(d, 0, sizeof *d);
+}
+
+/* Builds the DAG of the simple graph underlying (src, dst): loops and
+ * repeated pairs (in either direction) are dropped.  Returns 0, -1 on bad
+ * input (id >= n, rank not a permutation), -2 when out of memory. */
+static int dag_build(dag *d, u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank) {
+    memset(d, 0, sizeof *d);
+    d->n = n;
+    d->inv = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
+    d->poff = (u64 *)calloc((size_t)n + 1, sizeof(u64));
+    d->moff = (u64 *)calloc((size_t)n + 1, sizeof(u64));
+    if (!d->inv || !d->poff || !d->moff) { dag_free(d); return -2; }
+    for (u32 r = 0; r < n; r++) d->inv[r] = 0xffffffffu;
+    for (u32 u = 0; u < n; u++) {
+        if (rank[u] >= n || d->inv[rank[u]] != 0xffffffffu) { dag_free(d); return -1; }
+        d->inv[rank[u]] = u;
+    }
+    for (u64 i = 0; i < m_in; i++)
+        if (src[i] >= n || dst[i] >= n) { dag_free(d); return -1; }
+    /* each edge, once per input pair, in the successor list of its lower end */
+    for (u64 i = 0; i < m_in; i++) {
+        if (src[i] == dst[i]) continue;
+        u32 a = rank[src[i]], b = rank[dst[i]];
+        d->poff[(a < b ? a : b) + 1]++;
+    }
+    for (u32 r = 0; r < n; r++) d->poff[r + 1] += d->poff[r];
+    d->P = (u32 *)malloc(d->poff[n] * sizeof(u32) + 4);
+    u64 *fill = (u64 *)calloc((size_t)n + 1, sizeof(u64));
+    if (!d->P || !fill) { free(fill); dag_free(d); return -2; }
+    for (u64 i = 0; i < m_in; i++) {
+        if (src[i] == dst[i]) continue;
+        u32 a = rank[src[i]], b = rank[dst[i]];
+        u32 lo = a < b ? a : b, hi = a < b ? b : a;
+        d->P[d->poff[lo] + fill[lo]++] = hi;
+    }
+    /* sort each list and keep one copy of each successor */
+    u64 w = 0;
+    for (u32 r = 0; r < n; r++) {
+        u64 b0 = d->poff[r], b1 = d->poff[r + 1];
+        qsort(d->P + b0, b1 - b0, sizeof(u32), cmp_u32);
+        d->poff[r] = w;
+        for (u64 j = b0; j < b1; j++)
+            if (j == b0 || d->P[j] != d->P[j - 1]) d->P[w++] = d->P[j];
+    }
+    d->poff[n] = w;
+    d->m = w;
+    /* predecessor lists: walking the rows in rank order appends to each
+     * list in ascending order */
+    memset(fill, 0, ((size_t)n + 1) * sizeof(u64));
+    for (u64 j = 0; j < w; j++) d->moff[d->P[j] + 1]++;
+    for (u32 r = 0; r < n; r++) d->moff[r + 1] += d->moff[r];
+    d->M = (u32 *)malloc(w * sizeof(u32) + 4);
+    if (!d->M) { free(fill); dag_free(d); return -2; }
+    for (u32 r = 0; r < n; r++)
+        for (u64 j = d->poff[r]; j < d->poff[r + 1]; j++) {
+            u32 s = d->P[j];
+            d->M[d->moff[s] + fill[s]++] = r;
+        }
+    free(fill);
+    return 0;
+}
+
+#define PLEN(d, r) ((d)->poff[(r) + 1] - (d)->poff[(r)])
+#define MLEN(d, r) ((d)->moff[(r) + 1] - (d)->moff[(r)])
 
 typedef struct {
-    u64 count, hash, work;
+    u64 count, hash;
     u32 *tri;      /* optional: 3*cap slots */
     u64 cap;
 } sink;
 
-static void report(sink *s, u32 x, u32 y, u32 z) {
-    /* canonical form: ids sorted ascending */
-    u32 t;
+/* A triangle found in rank space: reported as its three original ids sorted
+ * ascending (the output convention), counted and hashed. */
+static void found(const dag *d, sink *s, u32 ra, u32 rb, u32 rc) {
+    u32 x = d->inv[ra], y = d->inv[rb], z = d->inv[rc], t;
     if (x > y) { t = x; x = y; y = t; }
     if (y > z) { t = y; y = z; z = t; }
     if (x > y) { t = x; x = y; y = t; }
@@ -189,96 +307,126 @@ static void report(sink *s, u32 x, u32 y, u32 z) {
     s->hash += orc_triangle_hash(x, y, z);
 }
 
-/* ------------------------------------------------------------ Algorithm 1 */
+/* Position of the first element >= key in the ascending list a[0..len). */
+static u64 first_at_least(const u32 *a, u64 len, u32 key) {
+    u64 lo = 0, hi = len;
+    while (lo < hi) {
+        u64 mid = lo + (hi - lo) / 2;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
 
-static void list_app(const graph *g, u32 lo, u32 hi, unsigned char *B, sink *s) {
-    for (u32 w = 0; w < g->n; w++) {
-        if (g->rank[w] < lo || g->rank[w] >= hi) continue;
-        for (u64 j = g->moff[w]; j < g->moff[w + 1]; j++) B[g->minus[j]] = 1;
-        for (u64 j = g->moff[w]; j < g->moff[w + 1]; j++) {
-            u32 u = g->minus[j];
-            for (u64 k = g->poff[u]; k < g->poff[u + 1]; k++) {
-                u32 v = g->plus[k];
-                s->work++;
-                if (B[v]) report(s, u, v, w);
-            }
+/* The elements common to the ascending lists a[0..la) and b[0..lb), in
+ * ascending order, written to out (room for min(la, lb)); returns how many.
+ * Lists of similar length are merged; when one is more than 16 times longer
+ * each element of the shorter is looked up in it by binary search. */
+static u64 intersect(const u32 *a, u64 la, const u32 *b, u64 lb, u32 *out) {
+    u64 k = 0;
+    if (la > lb) { const u32 *t = a; a = b; b = t; u64 tl = la; la = lb; lb = tl; }
+    if (la * 16 < lb) {
+        for (u64 i = 0; i < la; i++) {
+            u64 j = first_at_least(b, lb, a[i]);
+            if (j < lb && b[j] == a[i]) out[k++] = a[i];
         }
-        for (u64 j = g->moff[w]; j < g->moff[w + 1]; j++) B[g->minus[j]] = 0;
+        return k;
+    }
+    u64 i = 0, j = 0;
+    while (i < la && j < lb) {
+        if (a[i] < b[j]) i++;
+        else if (a[i] > b[j]) j++;
+        else { out[k++] = a[i]; i++; j++; }
+    }
+    return k;
+}
+
+/* Triangles in which vertex p has the pivot role of the form (see above). */
+static void triangles_at(const dag *d, int algo, u32 p, u32 *scratch, sink *s) {
+    if (algo == ORC_APP) {             /* p is the sink */
+        const u32 *Mp = d->M + d->moff[p];
+        for (u64 j = 0; j < MLEN(d, p); j++) {
+            u32 q = Mp[j];
+            u64 k = intersect(d->M + d->moff[q], MLEN(d, q), Mp, MLEN(d, p), scratch);
+            for (u64 i = 0; i < k; i++) found(d, s, scratch[i], q, p);
+        }
+    } else if (algo == ORC_APM) {      /* p is the source */
+        const u32 *Pp = d->P + d->poff[p];
+        for (u64 j = 0; j < PLEN(d, p); j++) {
+            u32 q = Pp[j];
+            u64 k = intersect(Pp, PLEN(d, p), d->P + d->poff[q], PLEN(d, q), scratch);
+            for (u64 i = 0; i < k; i++) found(d, s, p, q, scratch[i]);
+        }
+    } else {                           /* p is the middle vertex */
+        const u32 *Mp = d->M + d->moff[p];
+        for (u64 j = 0; j < MLEN(d, p); j++) {
+            u32 q = Mp[j];
+            u64 k = intersect(d->P + d->poff[q], PLEN(d, q), d->P + d->poff[p], PLEN(d, p), scratch);
+            for (u64 i = 0; i < k; i++) found(d, s, q, p, scratch[i]);
+        }
     }
 }
 
-/* ------------------------------------------------------------ Algorithm 2 */
-
-static void list_apm(const graph *g, u32 lo, u32 hi, unsigned char *B, sink *s) {
-    for (u32 u = 0; u < g->n; u++) {
-        if (g->rank[u] < lo || g->rank[u] >= hi) continue;
-        for (u64 j = g->poff[u]; j < g->poff[u + 1]; j++) B[g->plus[j]] = 1;
-        for (u64 j = g->poff[u]; j < g->poff[u + 1]; j++) {
-            u32 v = g->plus[j];
-            for (u64 k = g->poff[v]; k < g->poff[v + 1]; k++) {
-                u32 w = g->plus[k];
-                s->work++;
-                if (B[w]) report(s, u, v, w);
-            }
-        }
-        for (u64 j = g->poff[u]; j < g->poff[u + 1]; j++) B[g->plus[j]] = 0;
-    }
+/* The paper's work for pivot p (Property 1's count; see above). */
+static u64 work_at(const dag *d, int algo, u32 p) {
+    u64 w = 0;
+    if (algo == ORC_APP)
+        for (u64 j = d->moff[p]; j < d->moff[p + 1]; j++) w += PLEN(d, d->M[j]);
+    else if (algo == ORC_APM)
+        for (u64 j = d->poff[p]; j < d->poff[p + 1]; j++) w += PLEN(d, d->P[j]);
+    else
+        for (u64 j = d->poff[p]; j < d->poff[p + 1]; j++) w += MLEN(d, d->P[j]);
+    return w;
 }
 
-/* ---------------------------------------------------- A-- (S2 seed edge)
- * The third variant named in the footnote to Algorithms 1/2, whose seed edge
- * is the second short edge S2 = (v,w) of Figure 1.  Reading taken here: the
- * pivot is the middle vertex v; mark N-_v; for each successor w of v (seed
- * edge S2) scan all of N-_w and report {u,v,w} for every marked u.  Each w is
- * scanned once per predecessor, d-_w long, so the work is sum_w d-_w d-_w:
- * the C++ of the reversed ordering, which is the footnote's "equivalent to
- * A++". */
-static void list_amm(const graph *g, u32 lo, u32 hi, unsigned char *B, sink *s) {
-    for (u32 v = 0; v < g->n; v++) {
-        if (g->rank[v] < lo || g->rank[v] >= hi) continue;
-        for (u64 j = g->moff[v]; j < g->moff[v + 1]; j++) B[g->minus[j]] = 1;
-        for (u64 j = g->poff[v]; j < g->poff[v + 1]; j++) {
-            u32 w = g->plus[j];
-            for (u64 k = g->moff[w]; k < g->moff[w + 1]; k++) {
-                u32 u = g->minus[k];
-                s->work++;
-                if (B[u]) report(s, u, v, w);
-            }
-        }
-        for (u64 j = g->moff[v]; j < g->moff[v + 1]; j++) B[g->minus[j]] = 0;
+static u32 *scratch_for(const dag *d) {
+    u64 mx = 1;
+    for (u32 r = 0; r < d->n; r++) {
+        if (PLEN(d, r) > mx) mx = PLEN(d, r);
+        if (MLEN(d, r) > mx) mx = MLEN(d, r);
     }
+    return (u32 *)malloc(mx * sizeof(u32));
+}
+
+/* Triangles whose pivot (the form's role) has rank in [lo, hi), and the
+ * paper's work over those pivots.  out[0..3] = count, hash, work, m. */
+static int dag_list(const dag *d, int algo, u32 lo, u32 hi, u32 *tri, u64 cap, u64 *out) {
+    if (algo != ORC_APP && algo != ORC_APM && algo != ORC_AMM) return -1;
+    if (hi > d->n) hi = d->n;
+    u32 *scratch = scratch_for(d);
+    if (!scratch) return -2;
+    sink s = {0, 0, tri, cap};
+    u64 work = 0;
+    for (u32 p = lo; p < hi; p++) {
+        triangles_at(d, algo, p, scratch, &s);
+        work += work_at(d, algo, p);
+    }
+    free(scratch);
+    out[0] = s.count;
+    out[1] = s.hash;
+    out[2] = work;
+    out[3] = d->m;
+    return 0;
 }
 
 /* ================================================================ ABI */
 
 /*
  * Lists the triangles of the simple graph underlying (src, dst) under the
- * ordering `rank`, with Algorithm 1 (algo 0), Algorithm 2 (algo 1) or the
- * S2 variant (algo 2), restricted to pivots with rank in [lo, hi).
+ * ordering `rank` whose pivot for the form (0: A++, Algorithm 1; 1: A+-,
+ * Algorithm 2; 2: A--) has rank in [lo, hi).
  * out[0..2] = count, hash, work; out[3] = m after simplification.
  * If tri != NULL, the first min(count, cap) canonical triangles are written
- * there (3 ids each) in discovery order.
+ * there (3 ids each) in the order found.
  * Returns 0, -1 (invalid input) or -2 (out of memory).
  */
 int orc_list(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank, int algo,
              u32 lo, u32 hi, u32 *tri, u64 cap, u64 *out) {
-    graph g;
-    int rc = graph_build(&g, n, m_in, src, dst, rank);
+    dag d;
+    int rc = dag_build(&d, n, m_in, src, dst, rank);
     if (rc) return rc;
-    unsigned char *B = (unsigned char *)calloc((size_t)n + 1, 1);
-    if (!B) { graph_free(&g); return -2; }
-    sink s = {0, 0, 0, tri, cap};
-    if (algo == ORC_APP) list_app(&g, lo, hi, B, &s);
-    else if (algo == ORC_APM) list_apm(&g, lo, hi, B, &s);
-    else if (algo == ORC_AMM) list_amm(&g, lo, hi, B, &s);
-    else { free(B); graph_free(&g); return -1; }
-    out[0] = s.count;
-    out[1] = s.hash;
-    out[2] = s.work;
-    out[3] = g.m;
-    free(B);
-    graph_free(&g);
-    return 0;
+    rc = dag_list(&d, algo, lo, hi, tri, cap, out);
+    dag_free(&d);
+    return rc;
 }
 
 /*
@@ -288,63 +436,87 @@ int orc_list(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank, i
  */
 int orc_list_ranges(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank, int algo, u32 nr,
                     const u32 *lo, const u32 *hi, u32 **tri, const u64 *cap, u64 *out) {
-    graph g;
-    int rc = graph_build(&g, n, m_in, src, dst, rank);
+    dag d;
+    int rc = dag_build(&d, n, m_in, src, dst, rank);
     if (rc) return rc;
-    unsigned char *B = (unsigned char *)calloc((size_t)n + 1, 1);
-    if (!B) { graph_free(&g); return -2; }
-    for (u32 i = 0; i < nr; i++) {
-        sink s = {0, 0, 0, tri ? tri[i] : 0, cap ? cap[i] : 0};
-        if (algo == ORC_APP) list_app(&g, lo[i], hi[i], B, &s);
-        else if (algo == ORC_APM) list_apm(&g, lo[i], hi[i], B, &s);
-        else if (algo == ORC_AMM) list_amm(&g, lo[i], hi[i], B, &s);
-        else { free(B); graph_free(&g); return -1; }
-        out[4 * i + 0] = s.count;
-        out[4 * i + 1] = s.hash;
-        out[4 * i + 2] = s.work;
-        out[4 * i + 3] = g.m;
-    }
-    free(B);
-    graph_free(&g);
-    return 0;
+    for (u32 i = 0; i < nr && !rc; i++)
+        rc = dag_list(&d, algo, lo[i], hi[i], tri ? tri[i] : 0, cap ? cap[i] : 0, out + 4 * i);
+    dag_free(&d);
+    return rc;
 }
 
-/* A built graph kept between calls (for listing many pivot ranges). */
+/* A graph built once (for listing many pivot ranges). */
 void *orc_graph_new(u32 n, u64 m_in, const u32 *src, const u32 *dst, const u32 *rank, int *rc) {
-    graph *g = (graph *)calloc(1, sizeof(graph));
-    if (!g) { *rc = -2; return 0; }
-    /* the rank array must outlive the handle; keep a private copy */
-    u32 *rk = (u32 *)malloc((size_t)n * sizeof(u32) + 4);
-    if (!rk) { free(g); *rc = -2; return 0; }
-    memcpy(rk, rank, (size_t)n * sizeof(u32));
-    *rc = graph_build(g, n, m_in, src, dst, rk);
-    if (*rc) { free(rk); free(g); return 0; }
-    return g;
+    dag *d = (dag *)calloc(1, sizeof(dag));
+    if (!d) { *rc = -2; return 0; }
+    *rc = dag_build(d, n, m_in, src, dst, rank);
+    if (*rc) { free(d); return 0; }
+    return d;
 }
 
 int orc_graph_list(void *h, int algo, u32 lo, u32 hi, u32 *tri, u64 cap, u64 *out) {
-    graph *g = (graph *)h;
-    unsigned char *B = (unsigned char *)calloc((size_t)g->n + 1, 1);
-    if (!B) return -2;
-    sink s = {0, 0, 0, tri, cap};
-    if (algo == ORC_APP) list_app(g, lo, hi, B, &s);
-    else if (algo == ORC_APM) list_apm(g, lo, hi, B, &s);
-    else if (algo == ORC_AMM) list_amm(g, lo, hi, B, &s);
-    else { free(B); return -1; }
-    out[0] = s.count;
-    out[1] = s.hash;
-    out[2] = s.work;
-    out[3] = g->m;
-    free(B);
+    return dag_list((const dag *)h, algo, lo, hi, tri, cap, out);
+}
+
+/*
+ * Every triangle whose source (smallest rank) lies in [src_lo, src_hi),
+ * sorted into bins by the rank of its pivot for the form: bin i holds the
+ * triangles whose pivot rank lies in [cut[i], cut[i+1]), for nb bins over
+ * ascending cuts (cut has nb+1 entries; triangles outside [cut[0], cut[nb])
+ * are not counted).  out[2*i], out[2*i+1] += count, hash of bin i.
+ * Source ranges partition the triangles, so summing this over a partition of
+ * [0, n) gives each bin's (count, hash) for the whole graph: one pass over
+ * all triangles for many pivot ranges at once.
+ */
+int orc_graph_bin(void *h, int algo, u32 src_lo, u32 src_hi, u32 nb, const u32 *cut, u64 *out) {
+    const dag *d = (const dag *)h;
+    if (algo != ORC_APP && algo != ORC_APM && algo != ORC_AMM) return -1;
+    for (u32 i = 0; i < nb; i++)
+        if (cut[i] > cut[i + 1]) return -1;
+    if (src_hi > d->n) src_hi = d->n;
+    u32 *scratch = scratch_for(d);
+    if (!scratch) return -2;
+    for (u32 p = src_lo; p < src_hi; p++) {
+        const u32 *Pp = d->P + d->poff[p];
+        for (u64 j = 0; j < PLEN(d, p); j++) {
+            u32 q = Pp[j];
+            u64 k = intersect(Pp, PLEN(d, p), d->P + d->poff[q], PLEN(d, q), scratch);
+            for (u64 i = 0; i < k; i++) {
+                u32 t = scratch[i];  /* ranks p < q < t */
+                u32 piv = algo == ORC_APP ? t : (algo == ORC_APM ? p : q);
+                if (piv < cut[0] || piv >= cut[nb]) continue;
+                u64 lo = 0, hi = nb;  /* the bin with cut[b] <= piv < cut[b+1] */
+                while (hi - lo > 1) {
+                    u64 mid = (lo + hi) / 2;
+                    if (cut[mid] <= piv) lo = mid; else hi = mid;
+                }
+                sink s = {0, 0, 0, 0};
+                found(d, &s, p, q, t);
+                out[2 * lo] += 1;
+                out[2 * lo + 1] += s.hash;
+            }
+        }
+    }
+    free(scratch);
     return 0;
 }
 
+/* The paper's work of the form over pivots of rank in [lo, hi). */
+u64 orc_graph_work(void *h, int algo, u32 lo, u32 hi) {
+    const dag *d = (const dag *)h;
+    u64 w = 0;
+    if (hi > d->n) hi = d->n;
+    for (u32 p = lo; p < hi; p++) w += work_at(d, algo, p);
+    return w;
+}
+
+u64 orc_graph_m(void *h) { return ((const dag *)h)->m; }
+
 void orc_graph_free(void *h) {
-    graph *g = (graph *)h;
-    if (!g) return;
-    free((void *)g->rank);
-    graph_free(g);
-    free(g);
+    dag *d = (dag *)h;
+    if (!d) return;
+    dag_free(d);
+    free(d);
 }
 
 /*

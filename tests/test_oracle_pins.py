@@ -546,3 +546,147 @@ def test_neigh_keeps_an_optimal_order():
     rank, cpm, passes = oracle.neigh_order(n, s, d, r0, eps=0.0)
     assert np.array_equal(rank, r0) and passes == 1
     assert cpm == _cpm_python(n, s, d, r0)
+
+
+# ------------------------------------------- pivot ranges and their helpers
+#
+# A form lists, for pivots of rank in [lo, hi), the triangles whose vertex in
+# the form's pivot role has such a rank: the largest rank for A++
+# (Algorithm 1's outer vertex w), the smallest for A+- (Algorithm 2's u), the
+# middle one for A-- (v).  These tests compute that set by brute force and
+# the paper's work by its per-seed-edge count (Property 1) straight from the
+# edge set, and hold every range entry point of the oracle to them.
+
+def _py_f(z):
+    # splitmix64's output function, from its published definition
+    z &= MASK
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK
+    return z ^ (z >> 31)
+
+
+def _py_digest(a, b, c):
+    # the digest convention the library header states:
+    # h(a,b,c) = f(f((a << 32) | b) + c) with 64-bit wrap-around
+    return _py_f((_py_f((a << 32) | b) + c) & MASK)
+
+
+def _py_digest_sum(tri):
+    h = 0
+    for a, b, c in np.asarray(tri).reshape(-1, 3).tolist():
+        h = (h + _py_digest(a, b, c)) & MASK
+    return h
+
+
+def _pivot_rank(tri, rank, algo):
+    rk = np.sort(rank[np.asarray(tri, np.int64).reshape(-1, 3)].astype(np.int64), axis=1)
+    return rk[:, {"A++": 2, "A+-": 0, "A--": 1}[algo]]
+
+
+def _bf_range(n, s, d, rank, algo, lo, hi):
+    bf = G.brute_force_triangles(n, s, d)
+    if len(bf) == 0:
+        return bf
+    pr = _pivot_rank(bf, rank, algo)
+    return bf[(pr >= lo) & (pr < hi)]
+
+
+def _py_work(n, s, d, rank, algo, lo, hi):
+    dp, dm = G.oriented_degrees(n, s, d, rank)
+    _, pairs = G.simple_degrees(n, s, d)
+    w = 0
+    for a, b in pairs:
+        x, y = (a, b) if rank[a] < rank[b] else (b, a)  # oriented x -> y
+        if algo == "A++":    # pivot y, seed x scans N+(x)
+            piv, cost = rank[y], dp[x]
+        elif algo == "A+-":  # pivot x, seed y scans N+(y)
+            piv, cost = rank[x], dp[y]
+        else:                # pivot x (middle), seed y scans N-(y)
+            piv, cost = rank[x], dm[y]
+        if lo <= piv < hi:
+            w += int(cost)
+    return w
+
+
+def test_digest_convention_pin():
+    # convention pin: the oracle's per-triangle digest is exactly the stated
+    # composition, including the carry of the inner sum and extreme ids
+    for a, b, c in [(0, 1, 2), (1, 2, 3), (7, 1000, 65536), (12345, 67890, 4000000000),
+                    (0xFFFFFFFD, 0xFFFFFFFE, 0xFFFFFFFF), (0, 0x80000000, 0xFFFFFFFF)]:
+        assert oracle.triangle_hash(a, b, c) == _py_digest(a, b, c), (a, b, c)
+    # the composition is not symmetric in its arguments: a swapped inner pair,
+    # or an xor in place of the sum, gives another value
+    assert _py_digest(1, 2, 3) != _py_digest(2, 1, 3)
+    assert _py_digest(1, 2, 3) != _py_f(_py_f((1 << 32) | 2) ^ 3)
+
+
+CUT_SETS = [[0, 5, 6, 17, 30, 45], [0, 1, 2, 3, 45], [0, 22, 45], [10, 12, 40]]
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("algo", ALGOS)
+def test_pivot_range_is_the_roles_set(seed, algo):
+    n, s, d = rand_graph(900 + seed, n=45, p=0.3)
+    r = rand_rank(n, 900 + seed)
+    for cuts in CUT_SETS:
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            want = _bf_range(n, s, d, r, algo, lo, hi)
+            got = oracle.list_triangles(n, s, d, r, algo, lo, hi)
+            assert got.count == len(want), (lo, hi)
+            assert np.array_equal(got.sorted_triangles(), want), (lo, hi)
+            assert got.hash == _py_digest_sum(want)
+            assert got.work == _py_work(n, s, d, r, algo, lo, hi)
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("algo", ALGOS)
+def test_built_graph_and_list_ranges_match_brute_force(seed, algo):
+    n, s, d = rand_graph(950 + seed, n=45, p=0.35)
+    r = rand_rank(n, 950 + seed)
+    g = oracle.BuiltGraph(n, s, d, r)
+    try:
+        assert g.m == len(G.simple_degrees(n, s, d)[1])
+        for cuts in CUT_SETS:
+            ranges = list(zip(cuts[:-1], cuts[1:]))
+            want = [_bf_range(n, s, d, r, algo, lo, hi) for lo, hi in ranges]
+            caps = [len(w) + 3 for w in want]
+            many = oracle.list_ranges(n, s, d, r, algo, ranges, caps)
+            for (lo, hi), w, cap, lr in zip(ranges, want, caps, many):
+                one = g.list(algo, lo, hi, cap=cap)
+                work = _py_work(n, s, d, r, algo, lo, hi)
+                for res in (one, lr):
+                    assert (res.count, res.hash, res.work) == (len(w), _py_digest_sum(w), work), (lo, hi)
+                    assert np.array_equal(res.sorted_triangles(), w), (lo, hi)
+                assert g.work(algo, lo, hi) == work
+            # a buffer shorter than the range keeps the first triangles only
+            lo, hi = ranges[0]
+            if len(want[0]) > 1:
+                short = g.list(algo, lo, hi, cap=1)
+                assert short.count == len(want[0]) and len(short.triangles) == 1
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("algo", ALGOS)
+def test_bins_over_source_ranges_match_brute_force(seed, algo):
+    n, s, d = rand_graph(980 + seed, n=45, p=0.35)
+    r = rand_rank(n, 980 + seed)
+    bf = G.brute_force_triangles(n, s, d)
+    g = oracle.BuiltGraph(n, s, d, r)
+    try:
+        for cuts in CUT_SETS:
+            tot = np.zeros((len(cuts) - 1, 2), np.uint64)
+            for a, b in [(0, 9), (9, 10), (10, 31), (31, n)]:  # a partition of the source ranks
+                tot += g.bin(algo, cuts, a, b)
+            pr = _pivot_rank(bf, r, algo) if len(bf) else np.zeros(0, np.int64)
+            for i, (lo, hi) in enumerate(zip(cuts[:-1], cuts[1:])):
+                sel = bf[(pr >= lo) & (pr < hi)] if len(bf) else bf
+                assert int(tot[i, 0]) == len(sel), (cuts, i)
+                assert int(tot[i, 1]) == _py_digest_sum(sel), (cuts, i)
+            # source ranges alone: the triangles whose smallest rank lies there
+            part = g.bin("A+-", [0, n], 10, 31)
+            sel = bf[(_pivot_rank(bf, r, "A+-") >= 10) & (_pivot_rank(bf, r, "A+-") < 31)] if len(bf) else bf
+            assert int(part[0, 0]) == len(sel)
+    finally:
+        g.close()

@@ -6,9 +6,12 @@ inverse permutation), then for every algorithm tl_cost and tl_list with the
 full triangle list written to a device buffer.  Inputs (edge list and rank
 arrays) are resident in HBM before the timed region starts.
 
-Default workload: Chung-Lu power-law graph, n = 2^20, exponent 2.1, mean
-degree 20, seed 1; orderings random / degree / core; algorithms A++ and A+-
-(6 listings per step).
+Default workload: RMAT scale 26, edge factor 16, a/b/c/d = .57/.19/.19/.05,
+seed 1 (2^26 vertices, 1.05 G undirected edges), degree ordering, A++, with
+the triangles streamed through library-owned device chunks of 2^30 triangles
+to a consumer callback (one listing per step).  Other workloads:
+chunglu20 (Chung-Lu n = 2^20, three orderings x A++/A+-, full lists to one
+device buffer), rmat12, batch, serve, orders.
 
 Prints ONE JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
@@ -75,6 +78,16 @@ def heavy_alg_bytes(st):
             + 12 * st["heavy_triangles"])
 
 
+def heavy_loaded_bytes(st):
+    """Bytes the heavy-pivot kernel actually moves for its share of a
+    listing: 4 B per scanned element inside the windows (items), 8 B per
+    staged list element per task (marked, then read again to unmark), 20 B
+    of seed geometry per heavy seed (work prefix, scan start, endpoint id),
+    and per listed triangle 4 B for the third vertex's id plus 12 B written."""
+    return (4 * st["heavy_items"] + 8 * st["heavy_task_staged"] + 20 * st["heavy_seeds"]
+            + 16 * st["heavy_triangles"])
+
+
 def measured_traffic(workload, launches_per_step):
     """HBM bytes per heavy-probe launch from the committed rocprofv3 --pmc
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration),
@@ -91,25 +104,128 @@ def measured_traffic(workload, launches_per_step):
     return t.get("heavy_bytes_per_launch")
 
 
-def cpu_baseline(g, ranks, budget_s=20.0):
-    """The oracle, single-threaded on the host, over a bounded sample of the
-    step's listings (whole listings, taken in order until the budget)."""
-    import oracle
-    done, tri, work, spent = [], 0, 0, 0.0
-    plan = [(k, a) for k in ("degree", "core", "random") if k in ranks for a in ("A++", "A+-")]
-    for kind, algo in plan:
-        if spent > budget_s * 0.5 and done:
+def host_cpu():
+    """(model name, logical CPUs, CPUs this process may run on)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def rmat26_sample_ranges(n):
+    """Pivot-rank ranges of the RMAT-26 CPU sample: 16 single pivots spread
+    evenly over the top 8,192 ranks of the degree ordering, which hold most
+    of the graph's triangles (the ranks below hold few)."""
+    return [(n - 8192 + 512 * i + 256, n - 8192 + 512 * i + 257) for i in range(16)]
+
+
+def start_cpu_baseline_ranges(g, rank, algo, ranges, budget_s):
+    """Forks a child, before the GPU is touched, that pins itself to one
+    host core, builds the oracle's graph (not timed) and times the oracle's
+    listing of the given pivot-rank ranges, in order, until budget_s is
+    spent.  The parent keeps the other cores.  Returns a handle for
+    finish_cpu_baseline."""
+    rfd, wfd = os.pipe()
+    cores = sorted(os.sched_getaffinity(0))
+    core = cores[-1]
+    pid = os.fork()
+    if pid == 0:
+        os.close(rfd)
+        try:
+            os.sched_setaffinity(0, {core})
+            import oracle
+            t0 = time.perf_counter()
+            bg = oracle.BuiltGraph(g.n, g.src, g.dst, rank)
+            build_s = time.perf_counter() - t0
+            log(f"[bench] CPU oracle (child, core {core}): graph built in {build_s:.0f}s")
+            spent, tri, work, done = 0.0, 0, 0, []
+            for lo, hi in ranges:
+                t1 = time.perf_counter()
+                L = bg.list(algo, lo, hi)
+                dt = time.perf_counter() - t1
+                spent += dt
+                tri += L.count
+                work += L.work
+                done.append([lo, hi, L.count, L.work, round(dt, 3)])
+                log(f"[bench] CPU oracle (child): pivots [{lo}, {hi}) {L.count} triangles in {dt:.2f}s")
+                if spent >= budget_s:
+                    break
+            payload = {"spent": spent, "tri": tri, "work": work, "done": done, "build_s": build_s, "core": core}
+        except BaseException as e:  # reported by the parent
+            payload = {"error": repr(e)}
+        os.write(wfd, json.dumps(payload).encode())
+        os.close(wfd)
+        os._exit(0)
+    os.close(wfd)
+    if len(cores) > 1:
+        os.sched_setaffinity(0, set(cores[:-1]))
+    return pid, rfd, algo, g.name
+
+
+def finish_cpu_baseline(handle):
+    pid, rfd, algo, name = handle
+    chunks = []
+    while True:
+        b = os.read(rfd, 1 << 16)
+        if not b:
             break
-        t = time.perf_counter()
-        L = oracle.list_triangles(g.n, g.src, g.dst, ranks[kind], algo, want_triangles=False)
-        spent += time.perf_counter() - t
-        tri += L.count
-        work += L.work
-        done.append(f"{kind}-{algo}")
+        chunks.append(b)
+    os.close(rfd)
+    os.waitpid(pid, 0)
+    r = json.loads(b"".join(chunks).decode() or '{"error": "no result"}')
+    if "error" in r:
+        log(f"[bench] CPU baseline failed: {r['error']}")
+        return None
+    model, ncpu, navail = host_cpu()
+    spent = r["spent"]
+    first, last = r["done"][0], r["done"][-1]
+    return {"value": r["tri"] / spent, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{name}, degree order, {algo}: the oracle's listing of {len(r['done'])} single-pivot "
+                      f"rank ranges from [{first[0]}, {first[1]}) to [{last[0]}, {last[1]}) (pivots spread over "
+                      f"the top 8,192 ranks): {r['tri']} triangles, paper's work {r['work']}, "
+                      f"{spent:.1f} s on one pinned core; graph build ({r['build_s']:.0f} s) not timed",
+            "intersect_elems_per_s": r["work"] / spent, "triangles": r["tri"], "work": r["work"],
+            "seconds": spent, "ranges": r["done"], "pinned_core": r["core"], "cpu_model": model,
+            "logical_cpus": ncpu, "cpus_available": navail}
+
+
+def cpu_baseline(g, ranks, budget_s=20.0):
+    """The oracle on one pinned host core over a bounded sample of the
+    step's listings: whole listings, taken in order until the budget is
+    spent; each ordering's graph is built by the oracle outside the timed
+    region."""
+    import oracle
+    cores = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {cores[-1]})  # this thread only, for the timed loop
+    try:
+        done, tri, work, spent = [], 0, 0, 0.0
+        plan = [(k, a) for k in ("degree", "core", "random") if k in ranks for a in ("A++", "A+-")]
+        built = {}
+        for kind, algo in plan:
+            if spent > budget_s * 0.5 and done:
+                break
+            if kind not in built:
+                built = {kind: oracle.BuiltGraph(g.n, g.src, g.dst, ranks[kind])}
+            t = time.perf_counter()
+            L = built[kind].list(algo)
+            spent += time.perf_counter() - t
+            tri += L.count
+            work += L.work
+            done.append(f"{kind}-{algo}")
+    finally:
+        os.sched_setaffinity(0, set(cores))
+    model, ncpu, navail = host_cpu()
     return {"value": tri / spent, "unit": "triangles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{g.name}: listings {', '.join(done)} (graph build + Algorithm 1/2, "
-                      f"{spent:.1f} s single-threaded)",
-            "intersect_elems_per_s": work / spent}
+            "sample": f"{g.name}: whole listings {', '.join(done)} ({spent:.1f} s on one pinned core; "
+                      f"graph builds not timed)",
+            "intersect_elems_per_s": work / spent, "triangles": tri, "work": work, "seconds": spent,
+            "pinned_core": cores[-1], "cpu_model": model, "logical_cpus": ncpu, "cpus_available": navail}
 
 
 def bench_batch(args):
@@ -497,7 +613,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="chunglu20", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat26", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -538,6 +654,13 @@ def main():
     g = make_graph(args.workload)
     ranks = {k: graphgen.ordering(g, k, seed=1) for k in wl["orders"]}
     log(f"[bench] workload {g} generated in {time.time() - t0:.1f}s")
+    cpu_handle = None
+    if not args.no_cpu_baseline and args.workload == "rmat26":
+        # the oracle needs minutes to build this graph: it runs in a child on
+        # one core of its own while the GPU part runs (forked before any HIP call)
+        cpu_handle = start_cpu_baseline_ranges(g, ranks["degree"], "A++", rmat26_sample_ranges(g.n),
+                                               args.cpu_budget)
+        log(f"[bench] CPU oracle baseline started in a child process on one core")
 
     def dev(a):
         return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).to("cuda")
@@ -644,6 +767,8 @@ def main():
     probe_bytes = sum(alg_bytes(r["C"], r["m"], g.n, r["T"]) for r in rec) * args.steps
     heavy_launches = phases["probe_heavy"]["launches"]
     traffic = measured_traffic(args.workload, heavy_launches / max(args.steps, 1))
+    loaded = sum(heavy_loaded_bytes(r["stats"]) for r in rec) * args.steps
+    avg_launch_s = heavy_s / max(heavy_launches, 1)
     dominant = max(("orient", "plan", "probe_light", "probe_heavy", "cost"), key=lambda k: phases[k]["ms"])
 
     res = {
@@ -671,7 +796,14 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": phases["probe_heavy"]["ms"] / max(heavy_launches, 1),
                      "launches": heavy_launches,
-                     "alg_bytes_per_launch": heavy_bytes / max(heavy_launches, 1)},
+                     "alg_bytes_per_launch": heavy_bytes / max(heavy_launches, 1),
+                     # what the kernel actually reads and writes (windowed items, staging per
+                     # task, seed geometry, hits), and the PMC-measured HBM bytes, as rates
+                     "loaded_bytes_per_launch": loaded / max(heavy_launches, 1),
+                     "loaded_GBps": loaded / heavy_s / 1e9 if heavy_s > 0 else 0.0,
+                     "loaded_frac": loaded / heavy_s / 1e9 / HBM_PEAK_GBS if heavy_s > 0 else 0.0,
+                     "traffic_frac": (traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS)
+                     if traffic and avg_launch_s > 0 else None},
         "probe_phase": {"achieved_GBps": probe_bytes / probe_s / 1e9 if probe_s else 0.0,
                         "ms_per_step": phases["probe"]["ms"] / args.steps},
         "phases_ms_per_step": {k: v["ms"] / args.steps for k, v in phases.items()},
@@ -680,7 +812,12 @@ def main():
     }
     if chunked:
         res["chunks_per_step"] = chunks_seen[0] / max(args.steps + args.warmup, 1)
-    if not args.no_cpu_baseline and args.workload != "rmat26":
+    if cpu_handle is not None:
+        log("[bench] waiting for the CPU oracle baseline")
+        cb = finish_cpu_baseline(cpu_handle)
+        if cb is not None:
+            res["cpu_baseline"] = cb
+    elif not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(g, ranks, args.cpu_budget)
     print(json.dumps(res), flush=True)

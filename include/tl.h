@@ -422,6 +422,19 @@ typedef struct {
     uint64_t slices;        /* probe passes: one per chunk in callback mode */
     uint64_t slices_redone; /* callback-mode slices that found more than a
                                chunk of triangles and were probed again shorter */
+    /* heavy items by walk path: groups of chunks inside one seed's window,
+     * groups spread over consecutive short windows, one chunk at a time */
+    uint64_t items_long, items_short, items_single;
+    /* SPLIT-form elements below the bitmap's rank window (each tested by a
+     * search of the pivot's lower entries), and how many of those searches
+     * ran in global memory because the lower entries did not fit LDS */
+    uint64_t split_below, split_below_global;
+    /* list entries staged in LDS by the heavy kernel's workgroups (a
+     * workgroup whose next task has the same pivot keeps its list staged) */
+    uint64_t heavy_task_staged;
+    /* SPLIT-form groups of chunks tested together, and how many of them ran
+     * the search for elements below the bitmap's window */
+    uint64_t split_groups, split_below_groups;
 } tl_list_stats;
 int tl_last_list_stats(tl_list_stats *out);
 

@@ -16,6 +16,11 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
     return ((uint64_t)uni32((uint32_t)(v >> 32)) << 32) | uni32((uint32_t)v);
 }
 // this lane's wavefront within its workgroup
+// lane 0's value, as a wave-uniform (scalar) value
+__device__ __forceinline__ uint64_t lane0_u64(uint64_t v) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 0) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 0);
+}
 __device__ __forceinline__ uint32_t wave_id() { return uni32(threadIdx.x / WAVE); }
 
 // Orders a wavefront's own LDS accesses in the compiler (the hardware

@@ -38,6 +38,10 @@
 
 namespace {
 
+#ifndef TL_FLUSH_PIPELINE
+#define TL_FLUSH_PIPELINE 1
+#endif
+
 constexpr int PB = 256;        // threads per block, light kernels
 constexpr int HB = 1024;       // threads per block, heavy-pivot kernel
 constexpr u32 LDS_BYTES = 128 * 1024;
@@ -48,7 +52,8 @@ constexpr u32 STAGE_WORDS = 2 * WAVE;  // per wavefront: 64 staged (endpoint, th
 constexpr u32 FLAG_WORDS = UN * WAVE / 4;  // per wavefront: seed-start flags of the short-window walk
 // bitmap + low entries + staging and flags for every wavefront: 160 KB in all
 constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + LOW_WORDS * 4 + (HB / WAVE) * (STAGE_WORDS + FLAG_WORDS) * 4;
-static_assert(HEAVY_LDS_BYTES + 64 <= 160 * 1024, "heavy kernel LDS");
+// (+128: the heavy kernel's own __shared__ variables)
+static_assert(HEAVY_LDS_BYTES + 128 <= 160 * 1024, "heavy kernel LDS");
 // Smallest task the balance cap (task_div) makes.
 constexpr u64 BAL_TASK_MIN = 65536;
 // Tunable launch parameters (defaults; tl_set_tuning or TL_TUNE_* env vars).
@@ -63,6 +68,7 @@ struct Tuning {
     u64 heavy_blocks_per_cu = 1; // heavy grid = this many workgroups per CU
     u64 queue = 1;               // 1: heavy tasks handed out by an atomic queue
     u64 splits = 1;              // 1: wavefront start seeds precomputed at plan time
+    u64 keep_staged = 1;         // 1: a workgroup keeps its pivot's list staged for a next task of that pivot
     u64 light_blocks_per_cu = 16; // light grid cap
     u64 light_wave_items = 8192;  // light grid: at least this many items per wavefront
     u64 reverse = 0;             // 1: REVERSE instead of GLOBAL for lists that fit no LDS form
@@ -101,6 +107,8 @@ Tuning &tuning();
 enum { MODE_BITMAP = 0, MODE_ARRAY = 1, MODE_GLOBAL = 2, MODE_REVERSE = 3, MODE_HASH = 4, MODE_BUCKET = 5,
        MODE_SPLIT = 6 };
 constexpr int NMODES = 7;
+constexpr int ACC_PATHS = 10 + NMODES;  // heavy-walk counters in the listing's accumulator array
+constexpr int NACC = ACC_PATHS + 8;
 constexpr u32 BUCKETS = 8192;                              // slices of the rank window
 constexpr u32 BUCKET_MAX = LDS_WORDS - (BUCKETS + 2) / 2;  // list entries beside a u16 start table
 
@@ -264,6 +272,7 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             nt = (u32)((w + sl - 1) / sl);
             hp += 1;
             staged += tlen;
+
             atomicAdd((unsigned long long *)&mode_items[md], (unsigned long long)w);
         }
         mode[p] = md;
@@ -404,7 +413,8 @@ struct Out {
     u32 *spill;
     u64 spill_cap;
     u64 *acc;      // [0] count, [1] digest, [2] work, [3] cursor, [4] holes, [5] task queue,
-                   // [6] heavy work, [7] heavy pivots, [8] heavy triangles, [9] heavy staged elements
+                   // [6] heavy work, [7] heavy pivots, [8] heavy triangles, [9] heavy staged elements,
+                   // [10, 10 + NMODES) heavy items per LDS form, [ACC_PATHS, + 5) heavy walk counters
     Hole *holes;
     u64 hole_cap;
 
@@ -435,7 +445,8 @@ struct WaveEmitter {
         } else {
             u64 nb = 0;
             if (lane_id() == 0) nb = atomicAdd((unsigned long long *)&o.acc[3], (unsigned long long)RESERVE);
-            nb = shfl_u64(nb, 0);
+            // scalar from here on: the reservation's later uses carry no wait on memory
+            nb = lane0_u64(nb);
             pos = idx < avail ? rb + idx : nb + (idx - avail);
             rb = nb + (k - avail);
             re = nb + RESERVE;
@@ -499,6 +510,36 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
     // at a time: id lookup, canonical order, digest and store on full
     // wavefronts whatever the hit rate
     u32 staged = 0;  // wave-uniform
+#if TL_FLUSH_PIPELINE
+    // finished one flush late, as in the heavy kernel
+    u32 pend_k = 0, pend_a = 0, pend_b = 0, pend_c = 0;
+    auto finish = [&]() {
+        if (pend_k) {
+            const bool v = (u32)lane < pend_k;
+            u32 ta = 0, tb = 0, tc = 0;
+            if (v) {
+                ta = pend_a; tb = pend_b; tc = pend_c;
+                canon3(ta, tb, tc);
+                cnt += 1;
+                hsh += tri_digest(ta, tb, tc);
+            }
+            em.push(v, ta, tb, tc, o);
+        }
+    };
+    auto flush = [&](u32 k) {
+        wave_lds_fence();
+        const bool v = (u32)lane < k;
+        uint4 e = make_uint4(0u, 0u, 0u, 0u);
+        if (v) e = stage[lane];
+        wave_lds_fence();
+        finish();
+        pend_k = k;
+        pend_a = e.x;
+        pend_b = e.y;
+        pend_c = v ? g.inv[e.z] : 0u;
+    };
+#else
+    auto finish = [&]() {};
     auto flush = [&](u32 k) {
         wave_lds_fence();
         const bool v = (u32)lane < k;
@@ -513,6 +554,7 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
         wave_lds_fence();
         em.push(v, ta, tb, tc, o);
     };
+#endif
     auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&pv)[UN], const u32 (&xv)[UN]) {
         u64 bal[UN];
         u32 q[UN], tot = 0;
@@ -621,6 +663,7 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
         }
     }
     if (staged) flush(staged);
+    finish();
     em.finish(o);
     flush_counts(cnt, hsh, o.acc);
 }
@@ -631,7 +674,8 @@ template <int ALGO, bool EMIT>
 __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restrict__ tasks, u64 ntasks,
                                                     const u32 *__restrict__ cseed, const u64 *__restrict__ cabs,
                                                     const u32 *__restrict__ cxinv, const u64 *__restrict__ cpre,
-                                                    u64 k0, u64 k1, Out o, int use_queue, int use_splits) {
+                                                    u64 k0, u64 k1, Out o, int use_queue, int use_splits,
+                                                    int keep_staged) {
     extern __shared__ u32 lds[];  // the pivot list: B as a bitmap, or a sorted array
     const int lane = lane_id(), wid = (int)wave_id(), nwv = blockDim.x / WAVE;
     const u32 *SA = Form<ALGO>::scan_adj(g);
@@ -639,7 +683,23 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
     const u32 *pa = Form<ALGO>::piv_adj(g);
     WaveEmitter<EMIT> em;
     u64 cnt = 0, hsh = 0;
+    // Measurement counters of the workgroup, in LDS (kept out of registers):
+    // items by walk path, SPLIT elements below the bitmap's window (searched)
+    // and of those searched in global memory, list entries staged, SPLIT
+    // groups and those that ran the below-window search.
+    enum { ST_LONG, ST_SHORT, ST_SINGLE, ST_BELOW, ST_BELOW_GLOB, ST_STAGED, ST_GROUPS, ST_BELOW_GROUPS, ST_N };
+    __shared__ u64 wstat[ST_N];
+    auto stat_add = [&](int k, u64 v) {  // wave-uniform call
+        if (lane_id() == 0) atomicAdd((unsigned long long *)&wstat[k], (unsigned long long)v);
+    };
+    if (threadIdx.x < ST_N) wstat[threadIdx.x] = 0;
     __shared__ u64 next_task, split_at;
+    // The pivot whose list LDS holds.  A task that continues the same pivot
+    // (hub pivots span many consecutive tasks, and a workgroup often takes
+    // several of them) skips staging; LDS is reset only when the workgroup
+    // moves to another pivot.  Block-uniform.
+    u32 res_p = 0xffffffffu, res_mode = 0;
+    u64 res_ts = 0;
     for (u32 i = threadIdx.x; i < LDS_WORDS; i += blockDim.x) lds[i] = 0u;  // B starts all false
     __syncthreads();
     for (u64 it = 0;; it++) {
@@ -666,21 +726,53 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
         const u64 b = tk.b < k1 ? tk.b : k1;
         if (a >= b) continue;  // uniform across the block
         const u32 p = tk.p;
+        const bool restage = !keep_staged || p != res_p || tk.mode != res_mode;  // block-uniform
+        if (restage && res_p != 0xffffffffu) {
+            // LDS back to all zero: unmark the resident pivot's list (the
+            // paper's reset of B), once every wavefront is done with it
+            if (!use_queue) __syncthreads();  // (the queue's barriers order it otherwise)
+            const u64 r0 = po[res_p], r1 = po[res_p + 1];
+            const u32 rmin = pa[r0], rmax = pa[r1 - 1];
+            const u32 rlo = (u64)rmax - rmin + 1 > LDS_BITS ? (u32)((u64)rmax + 1 - LDS_BITS) : rmin;
+            const u32 rlen = (u32)(r1 - r0);
+            if (res_mode == MODE_BITMAP || res_mode == MODE_SPLIT) {
+                for (u64 i = res_ts + threadIdx.x; i < r1; i += blockDim.x) lds[(pa[i] - rlo) >> 5] = 0u;
+            } else if (res_mode == MODE_ARRAY) {
+                for (u32 i = threadIdx.x; i < rlen; i += blockDim.x) lds[i] = 0u;
+            } else if (res_mode == MODE_BUCKET) {
+                const u32 words = rlen + (BUCKETS + 2) / 2;
+                for (u32 i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0u;
+            } else if (res_mode == MODE_HASH) {
+                const u32 slots = 1u << hash_bits_for(rlen);
+                for (u32 i = threadIdx.x; i < slots; i += blockDim.x) lds[i] = 0u;
+            }
+            __syncthreads();
+            res_p = 0xffffffffu;
+        }
         const u64 t0 = po[p], t1 = po[p + 1];
         const u32 tmin = pa[t0], tmax = pa[t1 - 1];
         const u32 tlen = (u32)(t1 - t0);
         // SPLIT: the bitmap covers ranks [wlo, tmax]; entries [t0, ts) lie below
         const u32 wlo = (u64)tmax - tmin + 1 > LDS_BITS ? (u32)((u64)tmax + 1 - LDS_BITS) : tmin;
-        if (tk.mode == MODE_SPLIT) {
+        if (restage && tk.mode == MODE_SPLIT) {
             if (threadIdx.x == 0) split_at = lower_bound_dev<u32>(pa, t0, t1, wlo);
             __syncthreads();
         }
-        const u64 ts = tk.mode == MODE_SPLIT ? uni64(split_at) : t0;
+        const u64 ts = !restage ? res_ts : (tk.mode == MODE_SPLIT ? uni64(split_at) : t0);
         u32 *low = lds + LDS_WORDS;  // SPLIT: T[t0, ts) when it fits
         uint2 *stage = reinterpret_cast<uint2 *>(lds + LDS_WORDS + LOW_WORDS + (u32)wid * STAGE_WORDS);
         unsigned char *flag =
             reinterpret_cast<unsigned char *>(lds + LDS_WORDS + LOW_WORDS + HW * STAGE_WORDS + (u32)wid * FLAG_WORDS);
         const bool low_lds = tk.mode == MODE_SPLIT && ts - t0 <= LOW_WORDS;
+        if (!restage) {
+            // the list is already staged
+        } else {
+        res_p = p;
+        res_mode = tk.mode;
+        res_ts = ts;
+        if (wid == 0)
+            stat_add(ST_STAGED, (tk.mode == MODE_BITMAP || tk.mode == MODE_SPLIT) ? (t1 - ts) + (low_lds ? ts - t0 : 0)
+                                : (tk.mode == MODE_GLOBAL || tk.mode == MODE_REVERSE) ? 0 : tlen);
         if (low_lds) {
             for (u64 i = t0 + threadIdx.x; i < ts; i += blockDim.x) low[i - t0] = pa[i];
         }
@@ -713,6 +805,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 while (atomicCAS(&lds[h], 0u, key) != 0u) h = (h + 1) & hmask;
             }
             __syncthreads();
+        }
         }
         u64 wb, we;
         wave_share(a, b, (u32)nwv, (u32)wid, wb, we);
@@ -781,7 +874,15 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                         bool below = false;
     #pragma unroll
                         for (int j = 0; j < UN; j++) below |= y[j] < wlo && y[j] >= tmin;
-                        if (__ballot(below)) {
+                        const bool any_below = __ballot(below) != 0;
+                        stat_add(ST_GROUPS, 1);
+                        if (any_below) {
+                            stat_add(ST_BELOW_GROUPS, 1);
+                            u32 nb = 0;
+    #pragma unroll
+                            for (int j = 0; j < UN; j++) nb += (u32)__popcll(__ballot(y[j] < wlo && y[j] >= tmin));
+                            stat_add(ST_BELOW, nb);
+                            if (!low_lds) stat_add(ST_BELOW_GLOB, nb);
                             u64 lo[UN], hi[UN];
                             const u64 base = low_lds ? 0 : t0, top = low_lds ? ts - t0 : ts;
     #pragma unroll
@@ -864,6 +965,37 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 // finished together: the id lookup, canonical order, digest
                 // and store then run on full wavefronts whatever the hit rate.
                 u32 staged = 0;  // hits waiting in the staging area (wave-uniform)
+#if TL_FLUSH_PIPELINE
+                // A batch of 64 hits is finished one flush late: its third
+                // vertices' id gathers stay in flight while the walk goes on,
+                // and the next flush (or the walk's end) completes it.
+                u32 pend_k = 0, pend_x = 0, pend_y = 0;  // count (wave-uniform), endpoint id, third id
+                auto finish = [&]() {
+                    if (pend_k) {
+                        const bool v = (u32)lane < pend_k;
+                        u32 ta = 0, tb = 0, tc = 0;
+                        if (v) {
+                            ta = pinv; tb = pend_x; tc = pend_y;
+                            canon3(ta, tb, tc);
+                            cnt += 1;
+                            hsh += tri_digest(ta, tb, tc);
+                        }
+                        em.push(v, ta, tb, tc, o);
+                    }
+                };
+                auto flush = [&](u32 k) {
+                    wave_lds_fence();
+                    const bool v = (u32)lane < k;
+                    uint2 e = make_uint2(0u, 0u);
+                    if (v) e = stage[lane];
+                    wave_lds_fence();
+                    finish();
+                    pend_k = k;
+                    pend_x = e.x;
+                    pend_y = v ? g.inv[e.y] : 0u;
+                };
+#else
+                auto finish = [&]() {};
                 auto flush = [&](u32 k) {
                     wave_lds_fence();
                     const bool v = (u32)lane < k;
@@ -878,6 +1010,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                     wave_lds_fence();
                     em.push(v, ta, tb, tc, o);
                 };
+#endif
                 auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
                     u64 bal[UN];
                     u32 q[UN], tot = 0;
@@ -939,6 +1072,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                             report(y[q], h, xv);
                         }
                         kb += HG * UN * WAVE;
+                        stat_add(ST_LONG, HG * UN * WAVE);
                         cur.advance(kb, cur.c_lo);
                         continue;
                     }
@@ -958,6 +1092,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                         member_long(y, h);
                         report(y, h, xv);
                         kb += UN * WAVE;
+                        stat_add(ST_LONG, UN * WAVE);
                         cur.advance(kb, cur.c_lo);
                         continue;
                     }
@@ -1013,6 +1148,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
 #pragma unroll
                             for (int j = 0; j < UN; j++) h[j] = h[j] && act[j];
                             report(y, h, xv);
+                            stat_add(ST_SHORT, kn - kb);
                             kb = kn;
                             continue;
                         }
@@ -1034,10 +1170,12 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                         }
                     }
                     em.push(hit, xa, xb, xc, o);
+                    stat_add(ST_SINGLE, (we - kb < (u64)WAVE) ? we - kb : (u64)WAVE);
                     kb += WAVE;
                     cur.advance(kb, c);
                 }
                 if (staged) flush(staged);
+                finish();
             }
         };
         switch (tk.mode) {
@@ -1049,23 +1187,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
             case MODE_BUCKET: walk(std::integral_constant<int, MODE_BUCKET>{}); break;
             default: walk(std::integral_constant<int, MODE_SPLIT>{}); break;
         }
-        __syncthreads();  // every wavefront is done with the staged list
-        // reset B (or the staged array) so that LDS is all zero again
-        if (tk.mode == MODE_BITMAP || tk.mode == MODE_SPLIT) {
-            for (u64 i = ts + threadIdx.x; i < t1; i += blockDim.x) lds[(pa[i] - wlo) >> 5] = 0u;
-            __syncthreads();
-        } else if (tk.mode == MODE_ARRAY) {
-            for (u32 i = threadIdx.x; i < tlen; i += blockDim.x) lds[i] = 0u;
-            __syncthreads();
-        } else if (tk.mode == MODE_BUCKET) {
-            const u32 words = tlen + (BUCKETS + 2) / 2;
-            for (u32 i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0u;
-            __syncthreads();
-        } else if (tk.mode == MODE_HASH) {
-            const u32 slots = 1u << hash_bits_for(tlen);
-            for (u32 i = threadIdx.x; i < slots; i += blockDim.x) lds[i] = 0u;
-            __syncthreads();
-        }
     }
     em.finish(o);
     {
@@ -1073,6 +1194,9 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
         if (lane_id() == 0 && c8) atomicAdd((unsigned long long *)&o.acc[8], (unsigned long long)c8);
     }
     flush_counts(cnt, hsh, o.acc);
+    __syncthreads();
+    if (threadIdx.x < ST_N && wstat[threadIdx.x])
+        atomicAdd((unsigned long long *)&o.acc[ACC_PATHS + threadIdx.x], (unsigned long long)wstat[threadIdx.x]);
 }
 
 // Heavy tasks are ordered by item range: start the queue at the first task
@@ -1260,12 +1384,12 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
             hipLaunchKernelGGL((k_probe_heavy<ALGO, true>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
                                P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(),
                                P.cpre.as<u64>(),
-                               h0, h1, o, (int)tuning().queue, (int)tuning().splits);
+                               h0, h1, o, (int)tuning().queue, (int)tuning().splits, (int)tuning().keep_staged);
         else
             hipLaunchKernelGGL((k_probe_heavy<ALGO, false>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
                                P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(),
                                P.cpre.as<u64>(),
-                               h0, h1, o, (int)tuning().queue, (int)tuning().splits);
+                               h0, h1, o, (int)tuning().queue, (int)tuning().splits, (int)tuning().keep_staged);
         TL_HIP(hipGetLastError());
     }
 }
@@ -1305,6 +1429,7 @@ Tuning &tuning() {
         env("TL_TUNE_SLICE_MIN", d.slice_min);
         env("TL_TUNE_SLICE_MULT", d.slice_mult);
         env("TL_TUNE_TASK_DIV", d.task_div);
+        env("TL_TUNE_KEEP_STAGED", d.keep_staged);
         if (d.task_div > 1024) d.task_div = 1024;
         env("TL_TUNE_HEAVY_BLOCKS_PER_CU", d.heavy_blocks_per_cu);
         env("TL_TUNE_QUEUE", d.queue);
@@ -1373,6 +1498,7 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "heavy_blocks_per_cu" && value >= 1 && value <= 64) t.heavy_blocks_per_cu = value;
     else if (k == "queue" && value <= 1) t.queue = value;
     else if (k == "splits" && value <= 1) t.splits = value;
+    else if (k == "keep_staged" && value <= 1) t.keep_staged = value;
     else if (k == "light_blocks_per_cu" && value >= 1 && value <= 64) t.light_blocks_per_cu = value;
     else if (k == "light_wave_items" && value >= (u64)WAVE && value <= (1ull << 30)) t.light_wave_items = value;
     else if (k == "reverse" && value <= 1) t.reverse = value;
@@ -1400,6 +1526,7 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "heavy_blocks_per_cu") *value = t.heavy_blocks_per_cu;
     else if (k == "queue") *value = t.queue;
     else if (k == "splits") *value = t.splits;
+    else if (k == "keep_staged") *value = t.keep_staged;
     else if (k == "light_blocks_per_cu") *value = t.light_blocks_per_cu;
     else if (k == "light_wave_items") *value = t.light_wave_items;
     else if (k == "reverse") *value = t.reverse;
@@ -1441,7 +1568,6 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     const GView v = view_of(g);
     prepare_kernels();
 
-    constexpr int NACC = 10 + NMODES;
     DevBuf acc(NACC * sizeof(u64), s);
     TL_HIP(hipMemsetAsync(acc.p, 0, NACC * sizeof(u64), s));
     u64 *d_acc = acc.as<u64>();
@@ -1552,6 +1678,14 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
     st.heavy_triangles = h_acc[8];
     st.heavy_staged = h_acc[9];
     for (int md = 0; md < NMODES; md++) st.mode_items[md] = h_acc[10 + md];
+    st.items_long = h_acc[ACC_PATHS + 0];
+    st.items_short = h_acc[ACC_PATHS + 1];
+    st.items_single = h_acc[ACC_PATHS + 2];
+    st.split_below = h_acc[ACC_PATHS + 3];
+    st.split_below_global = h_acc[ACC_PATHS + 4];
+    st.heavy_task_staged = h_acc[ACC_PATHS + 5];
+    st.split_groups = h_acc[ACC_PATHS + 6];
+    st.split_below_groups = h_acc[ACC_PATHS + 7];
     st.tasks = P.ntasks;
     st.slices = slices;
     st.slices_redone = redone;

@@ -7,7 +7,6 @@
 // block or before the end block, whichever gives it the smaller C+- share;
 // decided level by level, see below).  Together with tl_orient and tl_list
 // they make the full listing (ordering included) run on the GPU.
-#include <hipcub/hipcub.hpp>
 
 #include "tl_internal.h"
 #include "dev_util.h"
@@ -48,6 +47,15 @@ __global__ void k_rank_of(const u32 *sorted, u32 n, int split, u32 *rank) {
             rank[u] = (pos & 1u) ? (pos - 1) / 2 : n - pos / 2;
         }
     }
+}
+
+// (key, id) pairs packed as key << 32 | id for the library's radix sort
+__global__ void k_pack_keys(const u32 *key, const u32 *ids, u32 n, u64 *out) {
+    GRID_STRIDE(i, n) { out[i] = ((u64)key[i] << 32) | ids[i]; }
+}
+
+__global__ void k_low32(const u64 *in, u32 n, u32 *out) {
+    GRID_STRIDE(i, n) { out[i] = (u32)in[i]; }
 }
 
 unsigned grid_o(u64 items) { return grid_for(items, 256, (unsigned)tl_num_cus() * 16); }
@@ -355,7 +363,7 @@ void order_impl(const tl_csr *g, int kind, u32 *rank, hipStream_t s) {
     if (n == 0) return;
     TL_REQUIRE(rank, TL_EINVAL, "rank is NULL");
     PhaseTimer timer(TL_PHASE_ORDER, s);
-    DevBuf deg((u64)n * 4, s), ids((u64)n * 4, s), deg2((u64)n * 4, s), sorted((u64)n * 4, s), mx(4, s);
+    DevBuf deg((u64)n * 4, s), ids((u64)n * 4, s), sorted((u64)n * 4, s), mx(4, s);
     if (kind == 2) coreness_keys(g, deg.as<u32>(), ids.as<u32>(), s);
     else
         hipLaunchKernelGGL(k_vertex_degree, dim3(grid_o(n)), dim3(256), 0, s, g->off_f, g->off_b, g->inv, n,
@@ -367,14 +375,17 @@ void order_impl(const tl_csr *g, int kind, u32 *rank, hipStream_t s) {
     d2h_sync(s, {{&maxdeg, mx.p, 4}});
     int bits = 1;
     while (bits < 32 && (1ull << bits) <= maxdeg) bits++;
-    // stable LSD radix sort of (degree, id) pairs by degree: ties keep the
-    // increasing id order of the input
-    size_t tmp_bytes = 0;
-    TL_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, deg.as<u32>(), deg2.as<u32>(), ids.as<u32>(),
-                                              sorted.as<u32>(), (int)n, 0, bits, s));
-    DevBuf tmp(tmp_bytes ? tmp_bytes : 1, s);
-    TL_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, deg.as<u32>(), deg2.as<u32>(), ids.as<u32>(),
-                                              sorted.as<u32>(), (int)n, 0, bits, s));
+    // stable LSD radix sort (radix.hip) of the (degree, id) pairs on the
+    // degree field: the pairs start in increasing id order, so ties keep it
+    {
+        DevBuf keys((u64)n * 8, s), ktmp((u64)n * 8, s);
+        hipLaunchKernelGGL(k_pack_keys, dim3(grid_o(n)), dim3(256), 0, s, deg.as<u32>(), ids.as<u32>(), n,
+                           keys.as<u64>());
+        TL_HIP(hipGetLastError());
+        const u64 *sk = radix_sort_u64(keys.as<u64>(), ktmp.as<u64>(), n, 32, bits, s);
+        hipLaunchKernelGGL(k_low32, dim3(grid_o(n)), dim3(256), 0, s, sk, n, sorted.as<u32>());
+        TL_HIP(hipGetLastError());
+    }
     if (kind == 3) {
         check_ranks(g, sorted.as<u32>(), rank, s);
     } else {

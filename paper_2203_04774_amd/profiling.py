@@ -4,7 +4,8 @@
     python -m paper_2203_04774_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <calibration MiB> <workload> <out.json> <command...>
 
-`stats` turns a `--kernel-trace --stats` kernel_stats.csv into a short
+`counters` averages the counters of `--pmc` passes per dispatch for the
+probe and plan kernels.  `stats` turns a `--kernel-trace --stats` kernel_stats.csv into a short
 markdown table.  `traffic` combines two `--pmc FETCH_SIZE` / `--pmc
 WRITE_SIZE` runs of `bench.py --steps 1 --warmup 0 --copy-calibration-mib N`:
 the plain device copy of N MiB at the start of the run calibrates the
@@ -126,6 +127,35 @@ def traffic_md(json_path: str, out_md: str) -> None:
         f.write("\n".join(lines) + "\n")
 
 
+def counters(csv_paths, out_md: str, command: str, kernels=("k_probe_heavy", "k_probe_light", "k_plan")) -> dict:
+    """Per-dispatch averages of every counter in one or more `--pmc` runs
+    (counter_collection.csv files, one per pass), for the kernels whose
+    names start with one of `kernels`; writes a markdown table and returns
+    {kernel: {counter: average per dispatch}}."""
+    acc = defaultdict(lambda: defaultdict(float))   # (kernel) -> counter -> sum over dispatches
+    disp = defaultdict(lambda: defaultdict(set))    # (kernel) -> counter -> dispatch ids
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            k = short_name(r["Kernel_Name"])
+            if not k.startswith(tuple(kernels)):
+                continue
+            c = r["Counter_Name"]
+            acc[k][c] += float(r["Counter_Value"])
+            disp[k][c].add(int(r["Dispatch_Id"]))
+    res = {k: {c: acc[k][c] / len(disp[k][c]) for c in acc[k]} for k in acc}
+    names = sorted({c for k in res for c in res[k]})
+    lines = ["# rocprofv3 counters per dispatch", "", "Commands (one counter pass each):", "", "```"]
+    lines += [part.strip() for part in command.split(" ; ")]
+    lines += ["```", "", "Average per dispatch of each counter (summed over the counter's hardware instances).", "",
+              "| kernel | dispatches | " + " | ".join(names) + " |", "|---|---:|" + "---:|" * len(names)]
+    for k in sorted(res):
+        n = max(len(v) for v in disp[k].values())
+        lines.append(f"| `{k}` | {n} | " + " | ".join(f"{res[k].get(c, float('nan')):.4g}" for c in names) + " |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return res
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
@@ -133,5 +163,9 @@ if __name__ == "__main__":
         traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6], " ".join(sys.argv[7:]))
     elif sys.argv[1] == "traffic-md":
         traffic_md(sys.argv[2], sys.argv[3])
+    elif sys.argv[1] == "counters":
+        # counters <out.md> <csv> [<csv> ...] -- <command>
+        i = sys.argv.index("--")
+        counters(sys.argv[3:i], sys.argv[2], " ".join(sys.argv[i + 1:]))
     else:
         raise SystemExit(__doc__)

@@ -66,7 +66,9 @@ class ListStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "light_items", "heavy_items", "light_seeds", "heavy_seeds", "heavy_work", "heavy_pivots",
         "heavy_staged", "heavy_triangles", "tasks", "items_bitmap", "items_array", "items_global",
-        "items_reverse", "items_hash", "items_bucket", "items_split", "slices", "slices_redone")]
+        "items_reverse", "items_hash", "items_bucket", "items_split", "slices", "slices_redone",
+        "items_long", "items_short", "items_single", "split_below", "split_below_global", "heavy_task_staged", "split_groups",
+        "split_below_groups")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -3,9 +3,14 @@
 Calls only the oracle and the seeded generators.  Usage:
     python tests/golden/make_expected.py
 Each entry holds the input's size and fingerprint (so a test detects a
-generator change), Definition 1's costs, and for every listing algorithm
-the oracle's (count, digest, work).
+generator change), Definition 1's costs, for every listing algorithm the
+oracle's (count, digest, work), and the SHA-256 of the graph's sorted
+triangle list (little-endian uint32 triples in ascending lexicographic
+order), taken from the oracle's degree-ordered A+- listing: the triangle set
+does not depend on the ordering or the form (Section 2.1), which the CPU
+tests pin.
 """
+import hashlib
 import json
 import os
 import sys
@@ -15,6 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 sys.path.insert(0, os.path.dirname(HERE))
+
+import numpy as np  # noqa: E402
 
 import graphgen  # noqa: E402
 import oracle  # noqa: E402
@@ -41,8 +48,13 @@ def main():
             od = {"cost": {"A++": c.cpp, "A+-": c.cpm, "A--": c.cmm}, "list": {}}
             for algo in ALGOS:
                 t = time.time()
-                L = oracle.list_triangles(g.n, g.src, g.dst, r, algo, want_triangles=False)
+                want = kind == "degree" and algo == "A+-"
+                L = oracle.list_triangles(g.n, g.src, g.dst, r, algo, want_triangles=want)
                 assert L.work == c.for_algo(algo)
+                if want:
+                    tri = L.sorted_triangles()
+                    entry["sorted_sha256"] = hashlib.sha256(
+                        np.ascontiguousarray(tri).astype("<u4").tobytes()).hexdigest()
                 od["list"][algo] = {"count": L.count, "hash": L.hash, "work": L.work}
                 print(f"{name} {kind} {algo}: T={L.count} work={L.work} ({time.time() - t:.1f}s)", flush=True)
             entry["orders"][kind] = od

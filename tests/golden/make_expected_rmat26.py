@@ -3,14 +3,16 @@
 RMAT scale 26, edge factor 16, a/b/c/d = .57/.19/.19/.05, seed 1, degree
 order, A++.  Calls only the oracle and the seeded generators.
 
-The full listing is split into disjoint pivot-rank ranges that worker
-processes list with the plain single-threaded oracle (each worker builds the
-graph once); the ranges partition the triangles (the outer iterations of
-Algorithm 1 are independent), so counts, digests and work add up exactly --
-a property the CPU test-suite checks on small graphs.  A few sampled ranges
-also get the SHA-256 of their sorted triangle list.
+The oracle builds the graph once, in this process; worker processes forked
+from it share that build and list disjoint pivot-rank ranges with the plain
+single-threaded oracle.  The ranges partition the triangles (the outer
+iterations of Algorithm 1 are independent), so counts, digests and work add
+up exactly -- a property the CPU test-suite checks on small graphs.  Sampled
+ranges, chosen to hold triangles from a few hundred to tens of millions, also
+get the SHA-256 of their sorted triangle list.
 
-Usage: python tests/golden/make_expected_rmat26.py [workers]   (~27 GB per worker)
+Usage: python tests/golden/make_expected_rmat26.py [workers]
+(about 19 GB for the shared build, plus each worker's output buffers)
 """
 import hashlib
 import json
@@ -43,45 +45,58 @@ def sorted_digest(tri: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(t).astype("<u4").tobytes()).hexdigest()
 
 
-def init_worker():
-    G["bg"] = oracle.BuiltGraph(G["n"], G["src"], G["dst"], G["rank"])
-
-
 def work(job):
     kind, lo, hi, cap = job
     t = time.time()
     L = G["bg"].list("A++", lo, hi, cap=cap)
     out = {"kind": kind, "lo": lo, "hi": hi, "count": L.count, "hash": L.hash, "work": L.work, "m": L.m,
-           "secs": time.time() - t}
+           "secs": round(time.time() - t, 2)}
     if cap and L.count <= cap:
         out["sorted_sha256"] = sorted_digest(L.triangles)
     return out
 
 
+def partition_cuts(n):
+    """Pivot-rank cuts: the bottom half in 8 pieces, then halving widths
+    toward the top ranks, where the hubs' work concentrates; the top 8,192
+    ranks in pieces of 64 and the top 32 one by one."""
+    cuts = [n * i // 16 for i in range(9)]
+    top = n // 2
+    w = n // 4
+    while w >= 8192:
+        top += w
+        cuts.append(top)
+        w //= 2
+    cuts += list(range(n - 8192, n - 32, 64)) + [n - k for k in range(0, 33)]
+    return sorted(set(c for c in cuts if 0 <= c <= n))
+
+
+def sample_ranges(n):
+    """(lo, hi, cap): rank ranges whose sorted lists are stored by digest."""
+    return [(n - 4194304, n - 4194304 + 65536, 1 << 20),   # low-degree pivots (few triangles)
+            (n - 1048576, n - 1048576 + 16384, 1 << 22),
+            (n - 131072, n - 131072 + 2048, 1 << 22),
+            (n - 65536, n - 65536 + 256, 1 << 22),
+            (n - 4096, n - 4096 + 16, 1 << 26),
+            (n - 32, n - 31, 1 << 26)]                       # one hub pivot (tens of millions)
+
+
 def main():
-    workers = int(sys.argv[1]) if len(sys.argv) > 1 else 2
+    workers = int(sys.argv[1]) if len(sys.argv) > 1 else 4
     t0 = time.time()
     g = graphgen.config_rmat26(seed=1)
     rank = graphgen.degree_order(g)
     print(f"generated {g} and degree order in {time.time() - t0:.0f}s", flush=True)
     n = g.n
-    G.update(n=n, src=g.src, dst=g.dst, rank=rank)
-    # full partition: the bottom half in 8 pieces, then halving widths toward
-    # the top ranks, where the hubs' work concentrates
-    cuts = [n * i // 16 for i in range(9)]
-    top = n // 2
-    w = n // 4
-    while w >= 1:
-        top += w
-        cuts.append(top)
-        w //= 2
-    cuts = sorted(set(cuts + [n - k for k in range(0, 33)]))
+    G["bg"] = oracle.BuiltGraph(n, g.src, g.dst, rank)
+    print(f"oracle graph built in {time.time() - t0:.0f}s", flush=True)
+    cuts = partition_cuts(n)
     jobs = [("part", a, b, 0) for a, b in zip(cuts[:-1], cuts[1:])]
-    samples = [(n // 4, n // 4 + 4096), (n // 2, n // 2 + 4096), (n - 65536, n - 65536 + 256), (n - 16, n - 12)]
-    jobs += [("sample", a, b, 40_000_000) for a, b in samples]
+    jobs += [("sample", a, b, cap) for a, b, cap in sample_ranges(n)]
     jobs.sort(key=lambda j: -(j[1]))  # heavy top ranges first
     res = []
-    with mp.get_context("fork").Pool(workers, initializer=init_worker) as pool:
+    # fork: the workers share the parent's oracle build (read only)
+    with mp.get_context("fork").Pool(workers) as pool:
         for r in pool.imap_unordered(work, jobs):
             res.append(r)
             print(f"[{time.time() - t0:.0f}s] {r['kind']} [{r['lo']},{r['hi']}) count={r['count']} "
@@ -94,7 +109,7 @@ def main():
            "n": n, "m": g.m, "edges": edge_fingerprint(g.src, g.dst), "cost": {"A++": c.cpp, "A+-": c.cpm},
            "list": {"A++": total},
            "samples": sorted([r for r in res if r["kind"] == "sample"], key=lambda r: r["lo"]),
-           "partition": sorted([[r["lo"], r["hi"], r["count"]] for r in parts])}
+           "partition": sorted([[r["lo"], r["hi"], r["count"], r["hash"], r["work"]] for r in parts])}
     with open(os.path.join(HERE, "oracle_rmat26.json"), "w") as f:
         json.dump(out, f, indent=1)
     print(f"done in {time.time() - t0:.0f}s: {total}", flush=True)

@@ -224,3 +224,34 @@ def test_batch_tuning_keys(tl, restore_tuning):
         tl.set_tuning("batch_light_per_cu", 0)
     tl.set_tuning("batch_heavy_per_cu", 1)
     assert tl.get_tuning("batch_heavy_per_cu") == 1
+
+
+@pytest.mark.slow
+def test_full_workload_table(tl):
+    """All 20,000 graphs of the batched workload (157 M vertices, 1.83 G
+    edges, union edge indices near 2^31) oriented as one union and listed by
+    one captured pass: the whole per-graph table, and its first 2,000 rows,
+    equal the oracle's (SHA-256 of the little-endian uint64 rows, stored by
+    tests/golden/make_expected_batch.py)."""
+    import hashlib
+    import json
+    import os
+
+    from gpu_util import GOLDEN
+    with open(os.path.join(GOLDEN, "oracle_batch.json")) as f:
+        gold = json.load(f)["prefixes"]
+    K = 20000
+    B = graphgen.batch(K)
+    assert (int(B.n.sum()), int(B.ebase[-1])) == (gold[str(K)]["vertices"], gold[str(K)]["edges"])
+    b = tl.batch_orient(B.n, B.m, dev(B.src), dev(B.dst), dev(B.rank))
+    del B
+    try:
+        table = b.list("A++", use_graph=True)
+    finally:
+        b.free()
+        tl.release_cached_memory()
+    sha = lambda t: hashlib.sha256(np.ascontiguousarray(t, "<u8").tobytes()).hexdigest()
+    assert sha(table[:2000]) == gold["2000"]["table_sha256"]
+    assert sha(table) == gold[str(K)]["table_sha256"]
+    assert int(table[:, 0].sum()) == gold[str(K)]["triangles"]
+    assert int(table[:, 2].sum()) == gold[str(K)]["work"]

@@ -12,7 +12,7 @@ import pytest
 import graphgen
 import graphs as G
 import oracle
-from gpu_util import dev, edge_fingerprint, load_expected, packed_sorted, sort_rows
+from gpu_util import dev, edge_fingerprint, load_expected, packed_sorted, sort_rows, sorted_sha256_device
 
 pytestmark = pytest.mark.gpu
 
@@ -375,6 +375,30 @@ def test_chunglu20_full_sorted_list(tl, chunglu20, algo):
     ref = oracle.list_triangles(gr.n, gr.src, gr.dst, r, algo)
     assert (st.count, st.hash, st.work) == (ref.count, ref.hash, ref.work)
     assert np.array_equal(packed_sorted(tri), packed_sorted(ref.triangles))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind", ["random", "degree", "core"])
+def test_chunglu20_sorted_lists_every_order(tl, chunglu20, kind):
+    """Chung-Lu n=2^20 under the random, degree and core orders, every form:
+    the whole list written to one device buffer, sorted on the device, equal
+    to the oracle's sorted list (its SHA-256, stored; the triangle set is the
+    same for every ordering and form)."""
+    import torch
+    gr, exp = chunglu20
+    r = graphgen.ordering(gr, kind, seed=1)
+    g = tl.orient(gr.n, dev(gr.src), dev(gr.dst), dev(r))
+    try:
+        T = exp["orders"][kind]["list"]["A++"]["count"]
+        out = torch.empty((T, 3), dtype=torch.int32, device="cuda")
+        for algo in ALGOS:
+            out.fill_(-1)
+            st = tl.list_triangles(g, algo, out=out)
+            e = exp["orders"][kind]["list"][algo]
+            assert (st.count, st.hash, st.work) == (e["count"], e["hash"], e["work"]), algo
+            assert sorted_sha256_device(out, 21) == exp["sorted_sha256"], algo
+    finally:
+        g.free()
 
 
 # ---------------------------------------------------- every probe path

@@ -211,3 +211,34 @@ def test_destroy_with_waiting_jobs(tl, pool):
     for (_, g, rank, _) in pool[:5]:
         srv.submit(g.n, g.src, g.dst, rank)
     srv.close()  # cancels the waiting jobs and returns
+
+
+@pytest.mark.slow
+def test_large_jobs_under_64gb_budget(tl):
+    """The pool's jobs of 2^21 edges and more (listed alone, by the plain
+    path with its heavy forms) mixed with small ones, under the workload's
+    64 GB device budget: every result equals the oracle's."""
+    with open(os.path.join(GOLDEN, "oracle_serve.json")) as f:
+        gold = {r["j"]: r for r in json.load(f)["jobs"]}
+    big = [j for j in sorted(gold) if gold[j]["m"] >= (1 << 21)]
+    small = [j for j in sorted(gold) if gold[j]["m"] < 100_000][:24]
+    assert len(big) >= 10
+    order = [x for pair in zip(big, small) for x in pair] + small[len(big):]
+    jobs = []
+    for j in order:
+        g, rank, _ = graphgen.serve_job(j)
+        assert (g.n, g.m) == (gold[j]["n"], gold[j]["m"])
+        jobs.append((j, g, rank, (gold[j]["count"], gold[j]["hash"], gold[j]["work"])))
+    srv = tl.Server(64 * GB)
+    try:
+        res = run_burst(tl, srv, jobs)
+        for (j, g, _, want), r in zip(jobs, res):
+            assert r.status == 0, j
+            assert result_tuple(r) == want, j
+            if g.m >= (1 << 21):
+                assert r.batch_jobs == 1, j  # the solo path
+        st = srv.stats()
+        assert st["jobs_done"] == len(jobs)
+        assert st["peak_reserved"] <= 64 * GB
+    finally:
+        srv.close()

@@ -133,6 +133,25 @@ int tl_list_range(const tl_csr *g, tl_algo a, uint32_t pivot_lo, uint32_t pivot_
                   uint32_t *tri_dev, uint64_t cap_triangles, tl_chunk_fn cb, void *user,
                   void *stream, tl_summary *out);
 
+/*
+ * tl_list_count_noalloc -- tl_list in its count-only mode (both tri_dev and
+ * cb NULL: count, digest and work of every triangle, all pivots) that
+ * allocates nothing, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it).
+ * Every device block the listing needs comes from one device array of
+ * TL_NOALLOC_SCRATCH_BYTES built into the library, which each GPU the
+ * library runs on holds until the process ends.
+ *   g, a, stream  as for tl_list; out  host, receives the summary.
+ * Returns TL_ECAPACITY, with nothing launched, when the graph's plan needs
+ * more than that array (roughly 64 bytes per edge plus 28 per vertex), or
+ * when its heavy-pivot tasks do not fit what is left of it (then after
+ * waiting for the stream).  Every call on a GPU uses that GPU's one array:
+ * calls that overlap on one GPU (other threads, other streams) race and
+ * must be serialised by the caller.  Results equal tl_list's.
+ */
+#define TL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int tl_list_count_noalloc(const tl_csr *g, tl_algo a, void *stream, tl_summary *out);
+
 /* Size of the oriented graph: n and m (undirected edges after dropping
  * loops and duplicates).  Host outputs. */
 int tl_csr_size(const tl_csr *g, uint32_t *n, uint64_t *m);

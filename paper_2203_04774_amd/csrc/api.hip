@@ -75,7 +75,21 @@ size_t round_bytes(size_t b) {
 
 }  // namespace
 
+ScratchArena *&thread_arena() {
+    thread_local ScratchArena *a = nullptr;
+    return a;
+}
+
 void *pool_get(size_t bytes, hipStream_t s) {
+    if (ScratchArena *a = thread_arena()) {
+        const size_t b = ((bytes ? bytes : 1) + 255) & ~(size_t)255;
+        TL_REQUIRE(b <= a->size - a->used, TL_ECAPACITY,
+                   "no-allocation scratch exhausted: " + std::to_string(a->used + b) + " bytes needed, " +
+                       std::to_string(a->size) + " available");
+        void *p = a->base + a->used;
+        a->used += b;
+        return p;
+    }
     int dev = 0;
     TL_HIP(hipGetDevice(&dev));
     Pool &P = pool_of(dev);
@@ -187,7 +201,7 @@ char *stage_buffer() {
 void d2h_sync(hipStream_t s, std::initializer_list<D2H> copies) {
     size_t total = 0;
     for (const D2H &c : copies) total += (c.bytes + 15) & ~size_t(15);
-    if (total > STAGE_BYTES) {
+    if (total > STAGE_BYTES || thread_arena()) {
         for (const D2H &c : copies)
             if (c.bytes) TL_HIP(hipMemcpyAsync(c.host, c.dev, c.bytes, hipMemcpyDeviceToHost, s));
         TL_HIP(hipStreamSynchronize(s));
@@ -209,7 +223,7 @@ void d2h_sync(hipStream_t s, std::initializer_list<D2H> copies) {
 
 void h2d_sync(void *dev, const void *host, size_t bytes, hipStream_t s) {
     if (!bytes) return;
-    if (bytes > STAGE_BYTES) {
+    if (bytes > STAGE_BYTES || thread_arena()) {
         TL_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s));
         TL_HIP(hipStreamSynchronize(s));
         return;

@@ -1479,6 +1479,23 @@ void prepare_kernels() {
 
 }  // namespace
 
+u64 list_count_scratch_bytes(u64 n, u64 m) {
+    // every block list_impl (count only) and make_plan take from the pool,
+    // in 256-byte units, heavy tasks excepted
+    auto blk = [](u64 b) { return ((b ? b : 1) + 255) / 256 * 256; };
+    const u64 ws_m = blk(scan_workspace_words(m) * sizeof(u64)), ws_n = blk(scan_workspace_words(n) * sizeof(u64));
+    u64 t = blk(NACC * sizeof(u64));
+    t += blk(m * 4) + blk(m * 8) + blk(n * 8);                // len, sabs, wp
+    t += blk(n * 4) + blk(n * 4) + blk(n * 8);                // mode, ntask, slice
+    t += blk(m * 8) + blk((m + 1) * 8) + (ws_m ? ws_m : 0);   // flags, pos and its scan
+    t += blk(m * 4) + blk(m * 8) + blk(m * 4);                // cseed, cabs, cxinv
+    t += 3 * blk(m * 4);                                      // ctlo, cthi, cpinv
+    t += blk((m + 1) * 8) + (ws_m ? ws_m : 0);                // cpre and its scan
+    t += blk((n + 1) * 8) + (ws_n ? ws_n : 0);                // tpos and its scan
+    t += blk(5 * sizeof(u64));                                // totals
+    return t;
+}
+
 u64 chunk_triangles() { return g_chunk_triangles; }
 bool orient_by_sort() { return tuning().orient_sort != 0; }
 

@@ -63,6 +63,31 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
+// A device arena installed on the calling thread for the length of one
+// library call: while one is installed, pool_get carves 256-byte aligned
+// blocks from it in order (blocks are not reused within the call) and throws
+// TL_ECAPACITY once it is exhausted, pool_put leaves its blocks alone, and
+// d2h_sync / h2d_sync copy directly instead of through the pinned staging
+// buffer (whose first use allocates).  Used by the entry point that
+// allocates nothing.
+struct ScratchArena {
+    char *base;
+    size_t size;
+    size_t used;
+};
+ScratchArena *&thread_arena();
+struct ArenaScope {
+    ScratchArena *prev;
+    explicit ArenaScope(ScratchArena *a) : prev(thread_arena()) { thread_arena() = a; }
+    ~ArenaScope() { thread_arena() = prev; }
+    ArenaScope(const ArenaScope &) = delete;
+    ArenaScope &operator=(const ArenaScope &) = delete;
+};
+// Bytes of every device block a count-only listing of a graph with n
+// vertices and m edges takes from the pool, heavy tasks excepted (their
+// number is known only after the plan; they are taken after a host wait).
+u64 list_count_scratch_bytes(u64 n, u64 m);
+
 // Long-lived allocation (graph storage), also pooled.
 void *tl_dev_alloc(size_t bytes, hipStream_t s);
 void tl_dev_free(void *p);

@@ -92,6 +92,7 @@ def _load():
     lib.tl_cost.argtypes = [vp, i32, vp, ctypes.POINTER(u64)]
     lib.tl_list.argtypes = [vp, i32, vp, u64, CHUNK_FN, vp, vp, ctypes.POINTER(Summary)]
     lib.tl_list_range.argtypes = [vp, i32, u32, u32, vp, u64, CHUNK_FN, vp, vp, ctypes.POINTER(Summary)]
+    lib.tl_list_count_noalloc.argtypes = [vp, i32, vp, ctypes.POINTER(Summary)]
     lib.tl_csr_size.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u64)]
     lib.tl_csr_copy_to_host.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.tl_csr_free.argtypes = [vp]
@@ -281,6 +282,15 @@ def list_triangles(g: Csr, algo: str = "A++", out: torch.Tensor | None = None, o
     if rc == TL_ECAPACITY and allow_capacity_error:
         return s
     _check(rc, "tl_list")
+    return s
+
+
+def list_count_noalloc(g: Csr, algo: str = "A++", stream=None) -> Summary:
+    """tl_list_count_noalloc: count, digest and work with no device
+    allocation (scratch from the library's fixed device array)."""
+    s = Summary()
+    _check(_lib.tl_list_count_noalloc(g.handle, ALGOS[algo], _stream_ptr(stream), ctypes.byref(s)),
+           "tl_list_count_noalloc")
     return s
 
 

@@ -72,10 +72,11 @@ typedef struct {
 
 /* Chunk sink: receives `k` triangles, 0 < k <= the chunk size (3*k uint32
  * in device memory, valid until the callback returns; the stream is
- * synchronised before the call).  Each call holds the triangles of one probe
- * slice of the work items, so calls number at least (triangles / chunk size)
- * and chunks need not be full.  A non-zero return stops the listing with
- * TL_EABORT. */
+ * synchronised before the call).  Each call holds triangles of one probe
+ * slice of the work items (a slice that found more than the chunk size is
+ * handed out in several calls), so calls number at least (triangles / chunk
+ * size) and chunks need not be full.  A non-zero return stops the listing
+ * with TL_EABORT. */
 typedef int (*tl_chunk_fn)(const uint32_t *tri_dev, uint64_t k, void *user);
 
 /*
@@ -263,6 +264,16 @@ int tl_order_neigh(const tl_csr *g, double eps, uint32_t max_passes, uint32_t ma
 typedef struct tl_batch tl_batch;
 int tl_batch_orient(uint32_t k, const uint32_t *n, const uint64_t *m, const uint32_t *src, const uint32_t *dst,
                     const uint32_t *rank, void *stream, tl_batch **out);
+/*
+ * tl_batch_from_graphs -- a batch of k graphs already oriented by
+ * tl_orient (each by its own ordering): the union is built by copying their
+ * arrays with shifted ranks and indices, with no sort, and equals the one
+ * tl_batch_orient builds from the same inputs, so tl_batch_list gives the
+ * same table.  gs is a host array of k handles, read during the call only
+ * (the handles stay the caller's).  TL_EINVAL for k = 0, a NULL handle or a
+ * union of 2^32 - 1 vertices or 2^32 edges or more.
+ */
+int tl_batch_from_graphs(uint32_t k, const tl_csr *const *gs, void *stream, tl_batch **out);
 int tl_batch_list(tl_batch *b, tl_algo algo, int use_graph, uint64_t *per_graph, uint64_t *per_graph_dev,
                   void *stream);
 /* k, the union's vertex count and its simple-edge count (host outputs, any may be NULL). */
@@ -286,6 +297,16 @@ void tl_batch_free(tl_batch *b);
  * with TL_ENOMEM; a malformed job (an endpoint >= n, a rank array that is
  * not a permutation) finishes with TL_EINVAL without failing the jobs
  * batched with it.  Results never depend on how jobs were batched.
+ *
+ * Resident graphs: a job with a non-zero key names its graph and ordering.
+ * The first such job is uploaded and oriented alone, and its oriented graph
+ * then stays resident on the device under that key; later jobs with the
+ * same key are listed from it with no upload and no orientation (their
+ * arrays are not read), batched with the other resident jobs into one union
+ * built by copying (tl_batch_from_graphs).  Resident graphs count against
+ * the budget (about 20 bytes per edge and per vertex) and the least recently
+ * used ones not in use are dropped when a job needs the room.  A key must
+ * always name the same graph and ordering; jobs with key 0 are never kept.
  */
 typedef struct tl_server tl_server;
 typedef struct {
@@ -303,6 +324,7 @@ typedef struct {
     const uint32_t *src, *dst;/* host arrays of m entries */
     const uint32_t *rank;     /* host array of n entries: the ordering */
     tl_algo algo;
+    uint64_t key;             /* non-zero: the graph stays resident under this key */
 } tl_job;                     /* the arrays must stay valid until the job is final */
 
 #define TL_JOB_PENDING (-1)
@@ -318,6 +340,9 @@ typedef struct {
     uint64_t submitted, jobs_done, batches, rejected, cancelled, split_batches;
     uint64_t reserved, peak_reserved, pending, max_batch_jobs_seen;
     uint64_t upload_ns, orient_ns, list_ns; /* thread time in each stage, summed over batches */
+    uint64_t resident_hits;   /* keyed jobs listed from a resident graph */
+    uint64_t resident_graphs, resident_bytes; /* graphs resident now, and their bytes */
+    uint64_t resident_dropped; /* resident graphs dropped to make room */
 } tl_server_stats;
 
 /* Starts the server on the current device: an upload thread (with its copier
@@ -386,13 +411,17 @@ void tl_server_destroy(tl_server *s);
  *   chunk_task_div       heavy tasks hold at most K / (this x heavy
  *                        workgroups) items, at least 65536 (1..64)
  *   chunk_growth         1: every probe slice covers K scanned items (each
- *                        yields at most one triangle); above 1: a slice may
- *                        cover up to this many times the previous slice's
- *                        items, sized from its triangles per item, for
- *                        fuller chunks; a slice that finds more than K
- *                        triangles is probed again shorter (1..64)
+ *                        yields at most one triangle); above 1 (default 8): a
+ *                        slice may cover up to this many times the previous
+ *                        slice's items, sized from its triangles per item, for
+ *                        fewer and fuller slices (1..64)
  *   chunk_margin         percent margin over the previous slice's
- *                        triangles per item when chunk_growth > 1 (100..1000)
+ *                        triangles per item when chunk_growth > 1 (100..1000;
+ *                        default 125)
+ *   chunk_room           the library's device chunk holds this many times K
+ *                        triangles (default 2; 1..16): a slice that finds up
+ *                        to that many is handed to the callback K at a time,
+ *                        one that finds more is probed again shorter
  * and for the batched pass (tl_batch_list; a captured pass is captured
  * again when these change):
  *   batch_heavy_min      pruned items of a pivot before its list is marked
@@ -413,8 +442,9 @@ int tl_get_tuning(const char *key, uint64_t *value);
  * cached block that is not in use to the driver; it waits for the device. */
 int tl_release_cached_memory(void);
 
-/* Triangles per library-owned chunk in callback mode (default 2^24, i.e.
- * 192 MiB of uint32 triples).  Applies to later calls in this process. */
+/* Triangles per callback in callback mode, K (default 2^24, i.e. 192 MiB of
+ * uint32 triples); the library's device chunk holds chunk_room x K of them
+ * (see tl_set_tuning).  Applies to later calls in this process. */
 int tl_set_chunk_triangles(uint64_t k);
 
 /*

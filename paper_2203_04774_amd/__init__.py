@@ -6,7 +6,8 @@ Implements the listing path of Lecuyer, Jachiet, Magnien, Tabourier,
 (A++) and 2 (A+-) and the S2 variant (A--), and Definition 1's costs, in HIP
 kernels for gfx950 behind the C-ABI of include/tl.h.
 """
-from .tl import (ALGOS, JOB_PENDING, Batch, Csr, JobResult, Server, Summary, TLError, batch_orient, cost, get_tuning, order, order_neigh,  # noqa: F401
+from .tl import (ALGOS, JOB_PENDING, Batch, Csr, JobResult, Server, Summary, TLError, batch_from_graphs,
+                 batch_orient, cost, get_tuning, order, order_neigh,  # noqa: F401
                  last_list_stats, list_count_noalloc, list_triangles, orient, raw_lib, release_cached_memory,
                  set_chunk_triangles, set_tuning)
 from . import tl  # noqa: F401  (status codes: tl.TL_OK, ...)

@@ -390,6 +390,15 @@ int tl_batch_orient(uint32_t k, const uint32_t *n, const uint64_t *m, const uint
     });
 }
 
+int tl_batch_from_graphs(uint32_t k, const tl_csr *const *gs, void *stream, tl_batch **out) {
+    return guarded([&] {
+        TL_REQUIRE(out, TL_EINVAL, "out is NULL");
+        *out = nullptr;
+        *out = batch_from_csrs_impl(k, gs, (hipStream_t)stream);
+        return TL_OK;
+    });
+}
+
 int tl_batch_list(tl_batch *b, tl_algo a, int use_graph, uint64_t *per_graph, uint64_t *per_graph_dev,
                   void *stream) {
     return guarded([&] {

@@ -75,6 +75,69 @@ __global__ void k_union_vertices(const u32 *rank, const u32 *vbase, u32 k, u32 N
     }
 }
 
+// Arrays of one oriented graph, for building a union from graphs already
+// oriented (their ranks and edge indices shifted by the graph's bases).
+struct CsrRef {
+    const u64 *off_f, *off_b;
+    const u32 *adj_f, *row_f, *adj_b, *row_b, *twin_b, *inv;
+};
+
+// The union's per-vertex arrays: offsets shifted by the graph's edge base,
+// inverse permutation by its vertex base, and the graph id of each vertex.
+__global__ void k_concat_vertices(const CsrRef *gs, const u32 *vbase, const u64 *ebase, u32 k, u32 N, u64 *off_f,
+                                  u64 *off_b, u32 *inv, u32 *gid) {
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 wfirst = first - lane_id();
+    const u64 iters = (u64)N > wfirst ? ((u64)N - wfirst + stride - 1) / stride : 0;  // wave-uniform
+    for (u64 it = 0; it < iters; it++) {
+        const u64 w0 = wfirst + it * stride;
+        const u64 w1 = w0 + WAVE - 1 < (u64)N ? w0 + WAVE - 1 : (u64)N - 1;
+        const WaveGraphs<u32> wg(vbase, k, w0, w1);
+        const u64 v = first + it * stride;
+        if (v < N) {
+            const u32 g = wg.of(vbase, v);
+            const u32 r = (u32)(v - vbase[g]);
+            const CsrRef c = gs[g];
+            off_f[v] = c.off_f[r] + ebase[g];
+            off_b[v] = c.off_b[r] + ebase[g];
+            inv[v] = c.inv[r] + vbase[g];
+            gid[v] = g;
+        }
+    }
+    if (first == 0) {
+        off_f[N] = ebase[k];
+        off_b[N] = ebase[k];
+    }
+}
+
+// The union's per-edge arrays: ranks shifted by the graph's vertex base,
+// forward indices by its edge base.
+__global__ void k_concat_edges(const CsrRef *gs, const u32 *vbase, const u64 *ebase, u32 k, u64 M, u32 *adj_f,
+                               u32 *row_f, u32 *adj_b, u32 *row_b, u32 *twin_b) {
+    const u64 stride = (u64)gridDim.x * blockDim.x;
+    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 wfirst = first - lane_id();
+    const u64 iters = M > wfirst ? (M - wfirst + stride - 1) / stride : 0;  // wave-uniform
+    for (u64 it = 0; it < iters; it++) {
+        const u64 w0 = wfirst + it * stride;
+        const u64 w1 = w0 + WAVE - 1 < M ? w0 + WAVE - 1 : M - 1;
+        const WaveGraphs<u64> wg(ebase, k, w0, w1);
+        const u64 i = first + it * stride;
+        if (i < M) {
+            const u32 g = wg.of(ebase, i);
+            const u64 j = i - ebase[g];
+            const u32 vb = vbase[g];
+            const CsrRef c = gs[g];
+            adj_f[i] = c.adj_f[j] + vb;
+            row_f[i] = c.row_f[j] + vb;
+            adj_b[i] = c.adj_b[j] + vb;
+            row_b[i] = c.row_b[j] + vb;
+            twin_b[i] = (u32)(c.twin_b[j] + ebase[g]);
+        }
+    }
+}
+
 __global__ void k_union_edges(const u32 *src, const u32 *dst, const u64 *ebase, const u32 *vbase, u32 k, u64 M,
                               u32 *usrc, u32 *udst, u32 *flag) {
     const u64 stride = (u64)gridDim.x * blockDim.x;
@@ -758,6 +821,8 @@ int batch_get_tuning(const std::string &key, u64 *value) {
     return TL_OK;
 }
 
+static void alloc_batch_scratch(tl_batch *b, hipStream_t s);
+
 tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, const u32 *dst, const u32 *rank,
                             hipStream_t s) {
     TL_REQUIRE(k > 0, TL_EINVAL, "empty batch");
@@ -806,8 +871,15 @@ tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, c
     TL_REQUIRE(!(h_flag & 1u), TL_EINVAL, "a graph's rank is not within [0, n)");
     TL_REQUIRE(!(h_flag & 2u), TL_EINVAL, "an edge endpoint is >= its graph's n");
     b->g = orient_impl((u32)N, usrc.as<u32>(), udst.as<u32>(), M, urank.as<u32>(), s);
+    alloc_batch_scratch(b, s);
+    tl_batch *r = own.b;
+    own.b = nullptr;
+    return r;
+}
 
-    // listing scratch for the union's m and N
+// Listing scratch for the union's m and N (owned for the batch's lifetime).
+static void alloc_batch_scratch(tl_batch *b, hipStream_t s) {
+    const u32 k = b->k, N = b->N;
     const u64 mm = b->g->m ? b->g->m : 1, nn = N ? N : 1;
     b->lw = (u32 *)tl_dev_alloc(mm * 4, s);
     b->cxinv = (u32 *)tl_dev_alloc(mm * 4, s);
@@ -829,6 +901,64 @@ tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, c
     b->ctl = (u64 *)tl_dev_alloc(8, s);
     prepare_batch_kernels();
     TL_HIP(hipStreamSynchronize(s));
+}
+
+tl_batch *batch_from_csrs_impl(u32 k, const tl_csr *const *gs, hipStream_t s) {
+    TL_REQUIRE(k > 0, TL_EINVAL, "empty batch");
+    TL_REQUIRE(gs, TL_EINVAL, "NULL graph array");
+    std::vector<u32> vb(k + 1);
+    std::vector<u64> eb(k + 1);
+    std::vector<CsrRef> refs(k);
+    u64 N = 0, M = 0;
+    for (u32 i = 0; i < k; i++) {
+        TL_REQUIRE(gs[i], TL_EINVAL, "NULL graph handle");
+        vb[i] = (u32)N;
+        eb[i] = M;
+        N += gs[i]->n;
+        M += gs[i]->m;
+        TL_REQUIRE(N < 0xffffffffull, TL_EINVAL, "batch has 2^32 - 1 vertices or more");
+        TL_REQUIRE(M < (1ull << 32), TL_EINVAL, "batch has 2^32 edges or more");
+        const tl_csr *c = gs[i];
+        refs[i] = CsrRef{c->off_f, c->off_b, c->adj_f, c->row_f, c->adj_b, c->row_b, c->twin_b, c->inv};
+    }
+    vb[k] = (u32)N;
+    eb[k] = M;
+    struct Owner {
+        tl_batch *b;
+        ~Owner() { if (b) batch_free_impl(b, true); }
+    } own{new tl_batch()};
+    tl_batch *b = own.b;
+    b->k = k;
+    b->N = (u32)N;
+    b->M = M;
+    TL_HIP(hipGetDevice(&b->device));
+    b->vbase = (u32 *)tl_dev_alloc((k + 1) * sizeof(u32), s);
+    b->gid = (u32 *)tl_dev_alloc((N ? N : 1) * sizeof(u32), s);
+    DevBuf ebase((k + 1) * sizeof(u64), s), dref(k * sizeof(CsrRef), s);
+    h2d_sync(b->vbase, vb.data(), (k + 1) * sizeof(u32), s);
+    h2d_sync(ebase.p, eb.data(), (k + 1) * sizeof(u64), s);
+    h2d_sync(dref.p, refs.data(), k * sizeof(CsrRef), s);
+    tl_csr *g = new tl_csr();
+    b->g = g;
+    TL_HIP(hipGetDevice(&g->device));
+    g->n = (u32)N;
+    g->m = M;
+    const u64 mm = M ? M : 1;
+    g->off_f = (u64 *)tl_dev_alloc(((u64)N + 1) * 8, s);
+    g->off_b = (u64 *)tl_dev_alloc(((u64)N + 1) * 8, s);
+    g->inv = (u32 *)tl_dev_alloc((N ? N : 1) * 4ull, s);
+    g->adj_f = (u32 *)tl_dev_alloc(mm * 4, s);
+    g->row_f = (u32 *)tl_dev_alloc(mm * 4, s);
+    g->adj_b = (u32 *)tl_dev_alloc(mm * 4, s);
+    g->row_b = (u32 *)tl_dev_alloc(mm * 4, s);
+    g->twin_b = (u32 *)tl_dev_alloc(mm * 4, s);
+    hipLaunchKernelGGL(k_concat_vertices, dim3(grid_b((u64)N + 1)), dim3(BB), 0, s, dref.as<CsrRef>(), b->vbase,
+                       ebase.as<u64>(), k, (u32)N, g->off_f, g->off_b, g->inv, b->gid);
+    if (M)
+        hipLaunchKernelGGL(k_concat_edges, dim3(grid_b(M)), dim3(BB), 0, s, dref.as<CsrRef>(), b->vbase,
+                           ebase.as<u64>(), k, M, g->adj_f, g->row_f, g->adj_b, g->row_b, g->twin_b);
+    TL_HIP(hipGetLastError());
+    alloc_batch_scratch(b, s);  // (waits for the stream: the staged refs above are read by then)
     tl_batch *r = own.b;
     own.b = nullptr;
     return r;

@@ -21,6 +21,11 @@ __device__ __forceinline__ uint64_t lane0_u64(uint64_t v) {
     return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 0) << 32) |
            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 0);
 }
+// lane src's value (src wave-uniform), as a wave-uniform value
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int src) {
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+}
 __device__ __forceinline__ uint32_t wave_id() { return uni32(threadIdx.x / WAVE); }
 
 // Orders a wavefront's own LDS accesses in the compiler (the hardware

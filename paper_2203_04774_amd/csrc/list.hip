@@ -41,6 +41,9 @@ namespace {
 #ifndef TL_FLUSH_PIPELINE
 #define TL_FLUSH_PIPELINE 1
 #endif
+#ifndef TL_KEEP_WINDOW
+#define TL_KEEP_WINDOW 1
+#endif
 
 constexpr int PB = 256;        // threads per block, light kernels
 constexpr int HB = 1024;       // threads per block, heavy-pivot kernel
@@ -82,9 +85,11 @@ struct Tuning {
     // callback mode, chunks of K triangles (sweeps on RMAT scale 26, A++):
     u64 chunk_task_div = 32;     // heavy tasks hold at most K / (this * heavy workgroups) items, so
                                  // that each slice's launch ends with a short tail
-    u64 chunk_growth = 1;        // a slice's items grow at most this factor per slice (1: K items
-                                 // each; more gives fuller chunks but redoes the slices that overflow)
-    u64 chunk_margin = 200;      // percent margin over the last slice's triangles per item
+    u64 chunk_growth = 1;        // a slice's items grow at most this factor per slice (1: room x K
+                                 // items each, which can never overflow the chunk)
+    u64 chunk_margin = 125;      // percent margin over the last slice's triangles per item
+    u64 chunk_room = 4;          // the device chunk holds this many times K triangles, handed out K
+                                 // at a time: slices of room x K items (sweeps on RMAT scale 26)
 };
 Tuning &tuning();
 
@@ -157,11 +162,12 @@ __host__ __device__ __forceinline__ void wave_share(u64 a, u64 b, u32 nwv, u32 w
 
 // ---------------------------------------------------------------- plan
 
-// Window of every seed edge; per-pivot work W_p (segmented by pivot, since
-// seeds are pivot-major); the paper's work for the listed pivots.
+// Window of every seed edge; per-pivot items W_p and per-pivot paper's work
+// (segmented by pivot, since seeds are pivot-major); the paper's work for the
+// listed pivots.
 template <int ALGO>
 __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 full_max, u32 *len, u64 *sabs, u64 *wp,
-                                             u64 *acc) {
+                                             u64 *wpw, u64 *acc) {
     __shared__ u64 lds[PB / WAVE];
     u64 work = 0;
     const int lane = lane_id();
@@ -172,12 +178,13 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 full
         const u64 e = first + it * stride;
         const bool valid = e < g.m;
         u32 l = 0, p = 0xffffffffu;
-        u64 abs = 0;
+        u64 abs = 0, pw = 0;
         if (valid) {
             Seed<ALGO> sd(g, e);
             p = sd.p;
             if (sd.p >= plo && sd.p < phi) {
-                work += sd.s_hi - sd.s_lo;
+                pw = sd.s_hi - sd.s_lo;
+                work += pw;
                 if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
                     if (sd.s_hi - sd.s_lo <= full_max) {
                         // short list: scanned whole; the elements outside the
@@ -198,17 +205,22 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 full
             len[e] = l;
             sabs[e] = abs;
         }
-        // segmented sum of l over runs of equal pivot within the wavefront
-        u64 v = l;
+        // segmented sums of l and of the paper's work over runs of equal pivot
+        // within the wavefront
+        u64 v = l, vw = pw;
 #pragma unroll
         for (int d = 1; d < WAVE; d <<= 1) {
-            u64 t = shfl_up_u64(v, d);
-            u32 q = __shfl_up(p, d, WAVE);
-            if (lane >= d && q == p) v += t;
+            const u64 t = shfl_up_u64(v, d), tw = shfl_up_u64(vw, d);
+            const u32 q = __shfl_up(p, d, WAVE);
+            if (lane >= d && q == p) {
+                v += t;
+                vw += tw;
+            }
         }
         const u32 pn = __shfl_down(p, 1, WAVE);
         const bool last = valid && (lane == WAVE - 1 || pn != p || !(e + 1 < g.m));
         if (last && v) atomicAdd((unsigned long long *)&wp[p], (unsigned long long)v);
+        if (last && vw) atomicAdd((unsigned long long *)&wpw[p], (unsigned long long)vw);
     }
     u64 tot = block_sum_u64<PB>(work, lds);
     if (threadIdx.x == 0 && tot) atomicAdd((unsigned long long *)&acc[2], (unsigned long long)tot);
@@ -216,7 +228,8 @@ __global__ __launch_bounds__(PB) void k_plan(GView g, u32 plo, u32 phi, u32 full
 
 // Heavy/light decision and task count per pivot.
 template <int ALGO>
-__global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *wp, u32 *mode, u32 *ntask,
+__global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *wp, const u64 *wpw, u32 *mode,
+                                                    u32 *ntask,
                                                     u64 *slice, u64 heavy_min, u64 slice_min, u64 slice_mult,
                                                     u64 max_task, u64 bal_div, u64 reverse, u64 use_hash,
                                                     u64 use_bucket, u64 use_split, u64 force_mode, u64 *acc) {
@@ -231,7 +244,7 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
         bal = acc[2] / bal_div;
         if (bal < BAL_TASK_MIN) bal = BAL_TASK_MIN;
     }
-    u64 hp = 0, staged = 0;
+    u64 hp = 0, staged = 0, hwork = 0;
     GRID_STRIDE(p, n) {
         const u64 w = wp[p];
         u32 md = 0xffffffffu, nt = 0;
@@ -272,6 +285,7 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
             nt = (u32)((w + sl - 1) / sl);
             hp += 1;
             staged += tlen;
+            hwork += wpw[p];
 
             atomicAdd((unsigned long long *)&mode_items[md], (unsigned long long)w);
         }
@@ -281,36 +295,27 @@ __global__ __launch_bounds__(PB) void k_pivot_class(GView g, u32 n, const u64 *w
     }
     hp = block_sum_u64<PB>(hp, lds);  // synchronises: mode_items is complete
     staged = block_sum_u64<PB>(staged, lds);
+    hwork = block_sum_u64<PB>(hwork, lds);
     if (threadIdx.x == 0 && hp) {
         atomicAdd((unsigned long long *)&acc[7], (unsigned long long)hp);
         atomicAdd((unsigned long long *)&acc[9], (unsigned long long)staged);
+        atomicAdd((unsigned long long *)&acc[6], (unsigned long long)hwork);  // the heavy pivots' paper's work
     }
     if (threadIdx.x < NMODES && mode_items[threadIdx.x])
         atomicAdd((unsigned long long *)&acc[10 + threadIdx.x], (unsigned long long)mode_items[threadIdx.x]);
 }
 
 // Class flag per seed, packed for one scan: low half light, high half heavy.
-// Also sums the paper's work of the heavy pivots' seed edges (measurement).
 template <int ALGO>
-__global__ __launch_bounds__(PB) void k_seed_class(GView g, const u32 *len, const u32 *mode, u64 *flags, u64 *acc) {
-    __shared__ u64 lds[PB / WAVE];
-    u64 hw = 0;
+__global__ __launch_bounds__(PB) void k_seed_class(GView g, const u32 *len, const u32 *mode, u64 *flags) {
     GRID_STRIDE(e, g.m) {
         u64 f = 0;
         if (len[e]) {
             const u32 p = ALGO == 0 ? g.row_b[e] : g.row_f[e];
-            if (mode[p] == 0xffffffffu) {
-                f = 1ull;
-            } else {
-                f = 1ull << 32;
-                Seed<ALGO> sd(g, e);
-                hw += sd.s_hi - sd.s_lo;
-            }
+            f = mode[p] == 0xffffffffu ? 1ull : 1ull << 32;
         }
         flags[e] = f;
     }
-    hw = block_sum_u64<PB>(hw, lds);
-    if (threadIdx.x == 0 && hw) atomicAdd((unsigned long long *)&acc[6], (unsigned long long)hw);
 }
 
 // Light seeds first, then heavy seeds, both in seed (pivot-major) order.
@@ -524,6 +529,7 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
                 hsh += tri_digest(ta, tb, tc);
             }
             em.push(v, ta, tb, tc, o);
+            pend_k = 0;
         }
     };
     auto flush = [&](u32 k) {
@@ -871,16 +877,18 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                     if (MD == MODE_SPLIT) {
                         // the entries below the bitmap's window: interleaved searches,
                         // skipped when no lane has such an element (the usual case)
+                        // (unsigned differences: one compare tests each range)
+                        const u32 lspan = wlo - tmin, span = tmax - wlo;
                         bool below = false;
     #pragma unroll
-                        for (int j = 0; j < UN; j++) below |= y[j] < wlo && y[j] >= tmin;
+                        for (int j = 0; j < UN; j++) below |= (y[j] - tmin) < lspan;
                         const bool any_below = __ballot(below) != 0;
                         stat_add(ST_GROUPS, 1);
                         if (any_below) {
                             stat_add(ST_BELOW_GROUPS, 1);
                             u32 nb = 0;
     #pragma unroll
-                            for (int j = 0; j < UN; j++) nb += (u32)__popcll(__ballot(y[j] < wlo && y[j] >= tmin));
+                            for (int j = 0; j < UN; j++) nb += (u32)__popcll(__ballot((y[j] - tmin) < lspan));
                             stat_add(ST_BELOW, nb);
                             if (!low_lds) stat_add(ST_BELOW_GLOB, nb);
                             u64 lo[UN], hi[UN];
@@ -896,20 +904,18 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                             for (int j = 0; j < UN; j++) h[j] = false;
                         }
                         // the bitmap part, branch-free: every word is read (index
-                        // clamped into the bitmap) so that the UN reads overlap
+                        // 0 outside the window) so that the UN reads overlap
                         u32 w[UN], v[UN];
+                        bool in[UN];
     #pragma unroll
                         for (int j = 0; j < UN; j++) {
                             const u32 d = y[j] - wlo;
-                            v[j] = d < (u32)(LDS_BITS - 1) ? d : (u32)(LDS_BITS - 1);
+                            in[j] = d <= span;
+                            v[j] = in[j] ? d : 0u;
                             w[j] = lds[v[j] >> 5];
                         }
     #pragma unroll
-                        for (int j = 0; j < UN; j++) {
-                            const bool in = (y[j] >= wlo) & (y[j] <= tmax);
-                            const bool bit = (w[j] >> (v[j] & 31)) & 1u;
-                            h[j] = in ? bit : h[j];
-                        }
+                        for (int j = 0; j < UN; j++) h[j] = in[j] ? (bool)((w[j] >> (v[j] & 31)) & 1u) : h[j];
                     } else if (MD == MODE_BITMAP) {
                         // branch-free: the index is clamped into the bitmap and the
                         // word always read, so that the UN reads overlap; an
@@ -969,6 +975,9 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 // A batch of 64 hits is finished one flush late: its third
                 // vertices' id gathers stay in flight while the walk goes on,
                 // and the next flush (or the walk's end) completes it.
+                // The walk calls finish() right after each group's element loads
+                // are consumed: the gather, issued before those loads, has then
+                // landed too (loads complete in order), so it costs no wait.
                 u32 pend_k = 0, pend_x = 0, pend_y = 0;  // count (wave-uniform), endpoint id, third id
                 auto finish = [&]() {
                     if (pend_k) {
@@ -981,6 +990,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                             hsh += tri_digest(ta, tb, tc);
                         }
                         em.push(v, ta, tb, tc, o);
+                        pend_k = 0;
                     }
                 };
                 auto flush = [&](u32 k) {
@@ -1047,6 +1057,11 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 };
                 u64 pf_c = ~0ull, pf_P = 0, pf_A = 0, pf_pend = 0;  // prefetched window (pf_c: its first seed)
                 u32 pf_X = 0;
+                // The window in use: seeds [wc, wc + 64) (wc wave-uniform, ~0: none),
+                // kept while it still holds the next group's items, so that runs of
+                // short windows cost one fetch of 64 seeds' geometry, not one per group.
+                u64 wc = ~0ull, WP = 0, WA = 0, Wpend = 0;
+                u32 WX = 0;
                 u64 kb = wb;
                 while (kb < we) {
                     if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && cur.end >= kb + HG * UN * WAVE &&
@@ -1069,6 +1084,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
 #pragma unroll
                         for (int q = 0; q < HG; q++) {
                             member_long(y[q], h);
+                            if (q == 0) finish();
                             report(y[q], h, xv);
                         }
                         kb += HG * UN * WAVE;
@@ -1090,6 +1106,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
     #pragma unroll
                         for (int j = 0; j < UN; j++) xv[j] = xinv;
                         member_long(y, h);
+                        finish();
                         report(y, h, xv);
                         kb += UN * WAVE;
                         stat_add(ST_LONG, UN * WAVE);
@@ -1097,28 +1114,51 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                         continue;
                     }
                     if (kb + WAVE <= we) {
-                        // short windows: the items of the 64 seeds starting at the
-                        // current one, up to UN chunks, with one load of their
-                        // prefix, scan start and endpoint id.  The next window's
-                        // loads are issued before this group's tests, so they
-                        // overlap (software pipelining).
-                        u64 P, A, pend;
-                        u32 X;
-                        if (pf_c == cur.c_lo) {
-                            P = pf_P; A = pf_A; X = pf_X; pend = pf_pend;
-                        } else {
-                            fetch_window(cur.c_lo, P, A, X, pend);
+                        // short windows: the items of up to UN chunks from kb on, spread
+                        // over the 64 seeds of the window, with the seeds' prefixes, scan
+                        // starts and endpoint ids held one per lane
+                        const bool have = TL_KEEP_WINDOW && wc != ~0ull && cur.c_lo >= wc && cur.c_lo < wc + WAVE &&
+                                          (Wpend >= kb + UN * WAVE || Wpend >= we);
+                        if (!have) {
+                            if (pf_c == cur.c_lo) {
+                                WP = pf_P; WA = pf_A; WX = pf_X; Wpend = pf_pend;
+                            } else {
+                                fetch_window(cur.c_lo, WP, WA, WX, Wpend);
+                            }
+                            wc = cur.c_lo;
                         }
+                        const int s0 = (int)(cur.c_lo - wc);  // lane of the seed of item kb
                         // items the window holds within this wavefront's range; at
                         // least one full chunk, else the one-chunk path below (SPLIT
                         // takes only full groups: partial ones measured slower there)
-                        const u64 lim = pend < we ? pend : we;
+                        const u64 lim = Wpend < we ? Wpend : we;
                         if (lim >= kb + (MD == MODE_SPLIT ? UN * WAVE : WAVE)) {
                             const bool full = lim >= kb + UN * WAVE;  // wave-uniform
                             // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
-                            const u32 E = (u32)(A - P + kb);
+                            const u32 E = (u32)(WA - WP + kb);
+                            const u32 X = WX;
                             int lo[UN];
-                            const int lo_last = locate_short(P, kb, flag, lo);
+                            const int lo_last = locate_short_at(WP, kb, s0, flag, lo);
+                            const u64 kn = full ? kb + UN * WAVE : lim;
+                            if (kn < we) {
+                                // seed of item kn: the last lane's seed, or the next one
+                                const u64 pn = (lo_last + 1 < WAVE) ? lane_u64(WP, lo_last + 1) : Wpend;
+                                const int ln = lo_last + (pn <= kn ? 1 : 0);
+                                const u64 c = wc + (u64)ln;
+                                if (ln < WAVE) {  // the cursor from the window's registers
+                                    cur.c_lo = c;
+                                    cur.base = lane_u64(WP, ln);
+                                    cur.end = ln + 1 < WAVE ? lane_u64(WP, ln + 1) : Wpend;
+                                } else {
+                                    cur.reset(c);
+                                }
+                                if ((!TL_KEEP_WINDOW || !(Wpend >= kn + UN * WAVE || Wpend >= we)) && pf_c != c) {
+                                    // the next group needs the next window: fetch it before
+                                    // this group's element loads, whose wait then covers it
+                                    fetch_window(c, pf_P, pf_A, pf_X, pf_pend);
+                                    pf_c = c;
+                                }
+                            }
                             u32 y[UN], xv[UN];
                             bool h[UN], act[UN];
 #pragma unroll
@@ -1134,17 +1174,8 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                                 act[j] = full || kb + (u64)(j * WAVE + lane) < lim;
                                 y[j] = act[j] ? SA[ej + (u32)(j * WAVE + lane)] : tmax;
                             }
-                            const u64 kn = full ? kb + UN * WAVE : lim;
-                            if (kn < we) {
-                                // seed of item kn: the last lane's seed, or the next one
-                                u64 c = cur.c_lo + (u64)lo_last;
-                                const u64 pn = (lo_last + 1 < WAVE) ? shfl_u64(P, lo_last + 1) : pend;
-                                if (pn <= kn) c++;
-                                cur.reset(c);
-                                fetch_window(cur.c_lo, pf_P, pf_A, pf_X, pf_pend);
-                                pf_c = cur.c_lo;
-                            }
                             member_all(y, h);
+                            finish();
 #pragma unroll
                             for (int j = 0; j < UN; j++) h[j] = h[j] && act[j];
                             report(y, h, xv);
@@ -1280,22 +1311,25 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
     const u64 m = v.m;
     const unsigned gm = grid_for(m, PB, (unsigned)tl_num_cus() * 16);
     const unsigned gn = grid_for(n, PB, (unsigned)tl_num_cus() * 16);
-    DevBuf len(m * sizeof(u32), s), sabs(m * sizeof(u64), s), wp((u64)n * sizeof(u64), s);
+    DevBuf len(m * sizeof(u32), s), sabs(m * sizeof(u64), s), wp((u64)n * sizeof(u64), s),
+        wpw((u64)n * sizeof(u64), s);
     TL_HIP(hipMemsetAsync(wp.p, 0, (u64)n * sizeof(u64), s));
+    TL_HIP(hipMemsetAsync(wpw.p, 0, (u64)n * sizeof(u64), s));
     const u32 full_max = (u32)std::min<u64>(tuning().plan_full, UN * WAVE - 1);  // see member_long
     hipLaunchKernelGGL((k_plan<ALGO>), dim3(gm), dim3(PB), 0, s, v, plo, phi, full_max, len.as<u32>(),
-                       sabs.as<u64>(), wp.as<u64>(), d_acc);
+                       sabs.as<u64>(), wp.as<u64>(), wpw.as<u64>(), d_acc);
     TL_HIP(hipGetLastError());
     DevBuf mode((u64)n * sizeof(u32), s), ntask((u64)n * sizeof(u32), s), slice((u64)n * sizeof(u64), s);
     const Tuning &tu = tuning();
-    hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), mode.as<u32>(),
+    hipLaunchKernelGGL((k_pivot_class<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, wp.as<u64>(), wpw.as<u64>(),
+                       mode.as<u32>(),
                        ntask.as<u32>(), slice.as<u64>(), tu.heavy_min, tu.slice_min, tu.slice_mult, max_task,
                        tu.task_div ? tu.task_div * heavy_max_blocks() : 0, tu.reverse, tu.hash, tu.bucket, tu.split,
                        tu.force_mode, d_acc);
     TL_HIP(hipGetLastError());
     DevBuf flags(m * sizeof(u64), s), pos((m + 1) * sizeof(u64), s);
     hipLaunchKernelGGL((k_seed_class<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), mode.as<u32>(),
-                       flags.as<u64>(), d_acc);
+                       flags.as<u64>());
     TL_HIP(hipGetLastError());
     scan_u64_to_u64(flags.as<u64>(), pos.as<u64>(), m, s);
     P.cseed = DevBuf(m * sizeof(u32), s);
@@ -1448,6 +1482,7 @@ Tuning &tuning() {
         env("TL_TUNE_CHUNK_GROWTH", d.chunk_growth);
         env("TL_TUNE_CHUNK_MARGIN", d.chunk_margin);
         env("TL_TUNE_CHUNK_TASK_DIV", d.chunk_task_div);
+        env("TL_TUNE_CHUNK_ROOM", d.chunk_room);
         d.chunk_growth = std::min<u64>(std::max<u64>(d.chunk_growth, 1), 64);
         d.chunk_margin = std::min<u64>(std::max<u64>(d.chunk_margin, 100), 1000);
         d.chunk_task_div = std::min<u64>(std::max<u64>(d.chunk_task_div, 1), 64);
@@ -1485,7 +1520,7 @@ u64 list_count_scratch_bytes(u64 n, u64 m) {
     auto blk = [](u64 b) { return ((b ? b : 1) + 255) / 256 * 256; };
     const u64 ws_m = blk(scan_workspace_words(m) * sizeof(u64)), ws_n = blk(scan_workspace_words(n) * sizeof(u64));
     u64 t = blk(NACC * sizeof(u64));
-    t += blk(m * 4) + blk(m * 8) + blk(n * 8);                // len, sabs, wp
+    t += blk(m * 4) + blk(m * 8) + 2 * blk(n * 8);            // len, sabs, wp, wpw
     t += blk(n * 4) + blk(n * 4) + blk(n * 8);                // mode, ntask, slice
     t += blk(m * 8) + blk((m + 1) * 8) + (ws_m ? ws_m : 0);   // flags, pos and its scan
     t += blk(m * 4) + blk(m * 8) + blk(m * 4);                // cseed, cabs, cxinv
@@ -1516,6 +1551,7 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "queue" && value <= 1) t.queue = value;
     else if (k == "splits" && value <= 1) t.splits = value;
     else if (k == "keep_staged" && value <= 1) t.keep_staged = value;
+    else if (k == "chunk_room" && value >= 1 && value <= 16) t.chunk_room = value;
     else if (k == "light_blocks_per_cu" && value >= 1 && value <= 64) t.light_blocks_per_cu = value;
     else if (k == "light_wave_items" && value >= (u64)WAVE && value <= (1ull << 30)) t.light_wave_items = value;
     else if (k == "reverse" && value <= 1) t.reverse = value;
@@ -1544,6 +1580,7 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "queue") *value = t.queue;
     else if (k == "splits") *value = t.splits;
     else if (k == "keep_staged") *value = t.keep_staged;
+    else if (k == "chunk_room") *value = t.chunk_room;
     else if (k == "light_blocks_per_cu") *value = t.light_blocks_per_cu;
     else if (k == "light_wave_items") *value = t.light_wave_items;
     else if (k == "reverse") *value = t.reverse;
@@ -1595,7 +1632,7 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
         PhaseTimer plan_timer(TL_PHASE_PLAN, s);
         u64 max_task = 0;
         if (cb && !tri) {
-            max_task = g_chunk_triangles / (tuning().chunk_task_div * heavy_max_blocks());
+            max_task = g_chunk_triangles * tuning().chunk_room / (tuning().chunk_task_div * heavy_max_blocks());
             if (max_task < 65536) max_task = 65536;
         }
         if (algo == 0) make_plan<0>(v, g->n, plo, phi, max_task, d_acc, s, P);
@@ -1651,13 +1688,15 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
         // shorter from the accumulators saved before it.  A slice of K items
         // cannot overflow, so this ends.
         const u64 K = g_chunk_triangles;
-        chunk = DevBuf(K * 3 * sizeof(u32), s);
+        const u64 room = K * tuning().chunk_room;  // triangles the device chunk holds
+        chunk = DevBuf(room * 3 * sizeof(u32), s);
         o.tri = chunk.as<u32>();
-        o.cap = K;
+        o.cap = room;
         DevBuf saved(NACC * sizeof(u64), s);
         const Tuning &tu = tuning();
-        const u64 L_max = K * CHUNK_GROWTH_MAX;
-        u64 L = K, prev_count = 0;
+        // a slice of `room` items cannot find more triangles than the chunk holds
+        const u64 L_max = room * CHUNK_GROWTH_MAX;
+        u64 L = room, prev_count = 0;
         for (u64 k0 = 0; k0 < h_total;) {
             const u64 k1 = (h_total - k0 > L) ? k0 + L : h_total;
             TL_HIP(hipMemcpyAsync(saved.p, d_acc, NACC * sizeof(u64), hipMemcpyDeviceToDevice, s));
@@ -1665,16 +1704,21 @@ int list_impl(const tl_csr *g, int algo, u32 plo, u32 phi, u32 *tri, u64 cap, tl
             probe(k0, k1, true);
             d2h_sync(s, {{h_acc, d_acc, sizeof h_acc}});
             const u64 got = h_acc[0] - prev_count;
-            if (got > K) {
+            if (got > room) {
                 TL_HIP(hipMemcpyAsync(d_acc, saved.p, NACC * sizeof(u64), hipMemcpyDeviceToDevice, s));
-                L = chunk_slice_items(K, got, k1 - k0, L / 2, tu.chunk_margin);
+                L = chunk_slice_items(room, got, k1 - k0, L / 2, tu.chunk_margin);
                 redone++;
                 continue;
             }
             prev_count = h_acc[0];
             fix_holes(o, got, h_acc[3], h_acc[4], s);
-            if (got && cb(o.tri, got, user) != 0) { rc = TL_EABORT; break; }
-            L = chunk_slice_items(K, got, k1 - k0, std::min(L * tu.chunk_growth, L_max), tu.chunk_margin);
+            // handed out K triangles at a time
+            for (u64 off = 0; off < got && rc == TL_OK; off += K) {
+                const u64 k = got - off < K ? got - off : K;
+                if (cb(o.tri + 3 * off, k, user) != 0) rc = TL_EABORT;
+            }
+            if (rc != TL_OK) break;
+            L = chunk_slice_items(room, got, k1 - k0, std::min(L * tu.chunk_growth, L_max), tu.chunk_margin);
             k0 = k1;
             if (k0 < h_total) slices++;
         }

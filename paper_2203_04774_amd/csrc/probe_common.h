@@ -145,6 +145,29 @@ __device__ __forceinline__ int locate_short(u64 P, u64 kb, unsigned char *flag, 
     return (int)started - 1;
 }
 
+// As locate_short, for a window whose lane s0 (wave-uniform) holds the seed
+// of item kb and whose lanes below s0 hold earlier seeds (ignored): lo[j]
+// and the result are lanes of the window.  Lanes above s0 start after kb,
+// since compacted seeds are non-empty.
+__device__ __forceinline__ int locate_short_at(u64 P, u64 kb, int s0, unsigned char *flag, int (&lo)[UN]) {
+    const int lane = lane_id();
+    const u32 Q = lane <= s0 ? 0u : (P - kb > 0xffffffffull ? 0xffffffffu : (u32)(P - kb));
+    reinterpret_cast<u32 *>(flag)[lane] = 0u;
+    wave_lds_fence();
+    if (lane >= s0 && Q < (u32)(UN * WAVE)) flag[Q] = 1;  // the seed of kb marks item 0
+    wave_lds_fence();
+    u32 started = 0;
+#pragma unroll
+    for (int j = 0; j < UN; j++) {
+        const u32 f = flag[j * WAVE + lane];
+        const u64 S = __ballot(f != 0u);
+        lo[j] = s0 + (int)(started + f + (u32)__popcll(S & lanemask_lt())) - 1;
+        started += (u32)__popcll(S);
+    }
+    wave_lds_fence();
+    return s0 + (int)started - 1;
+}
+
 // UN independent branchless membership tests of y[j] in the sorted list
 // T[lo, hi) (the same list for all j), so their loads overlap.  Indices are
 // 32-bit: adjacency arrays hold fewer than 2^32 entries.

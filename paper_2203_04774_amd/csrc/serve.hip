@@ -15,6 +15,14 @@
 // another's kernels.  A batch
 // whose union fails validation is split and its jobs are oriented one by
 // one, so a malformed job fails alone.
+//
+// Keyed jobs keep their oriented graph resident: the first job of a key is
+// uploaded and oriented alone (inside a keyed batch), its graph is kept in
+// a cache under the key, and later jobs of the key skip the upload and the
+// orientation: a keyed batch is listed from a union built by copying the
+// resident graphs (batch_from_csrs_impl).  Resident bytes count against the
+// budget; entries not in use are dropped, least recently used first, when a
+// job needs the room.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -160,20 +168,40 @@ struct Job {
     u64 bytes = 0;  // modelled device footprint
     tl_job_result res{};
     bool solo = false;
+    // keyed jobs: the resident graph listed (pinned while the job is in flight)
+    bool resident = false;   // its graph was resident when it was admitted
+    u64 keep_bytes = 0;      // a graph to be made resident: its bytes, reserved with the job's
+    tl_csr *csr = nullptr;
+    bool owns_csr = false;   // a duplicate of a graph made resident meanwhile: freed after listing
 };
 
 struct Ready {
-    tl_batch *b = nullptr;
+    tl_batch *b = nullptr;   // the union (null for a keyed job listed alone from its graph)
     std::vector<Job *> jobs;
     u64 bytes = 0;
     u64 batch_id = 0;
+    bool keyed = false;
 };
+
+// A resident oriented graph (keyed jobs).
+struct Resident {
+    tl_csr *g = nullptr;
+    u64 bytes = 0;
+    u32 refs = 0;    // jobs in flight that list it
+    u64 last = 0;    // use tick, for least-recently-used dropping
+};
+
+// Device bytes of a resident oriented graph: offsets, adjacency, rows,
+// forward indices and the inverse permutation.
+u64 resident_bytes(u64 n, u64 m) { return 20 * m + 20 * n + 4096; }
 
 // A batch whose edges and orderings are on the device, waiting to be oriented.
 struct Uploaded {
     std::vector<Job *> jobs;
     u64 bytes = 0;
     DevBuf src, dst, rank;
+    bool keyed = false;
+    std::vector<u64> eo, vo;  // each job's offset in src/dst and in rank (uploaded jobs only)
 };
 
 }  // namespace
@@ -197,8 +225,10 @@ struct tl_server {
     std::deque<std::unique_ptr<Uploaded>> uploaded;
     u32 in_flight = 0;                   // batches between admission and the end of their listing
     std::unordered_map<u64, std::unique_ptr<Job>> jobs;
+    std::unordered_map<u64, Resident> cache;  // resident graphs by key
+    u64 cache_bytes = 0, tick = 0;
     u64 next_id = 1, next_batch = 1;
-    u64 reserved = 0;
+    u64 reserved = 0;  // admitted jobs' footprints plus the resident graphs
     bool stop = false, paused = false;
     tl_server_stats st{};
 
@@ -221,20 +251,26 @@ void release_bytes(tl_server *S, u64 bytes) {
 }
 
 // Copies the jobs' arrays to the device on the copy stream; throws on failure.
-std::unique_ptr<Uploaded> upload_jobs(tl_server *S, const std::vector<Job *> &js) {
+// Resident jobs of a keyed batch need no copy.
+std::unique_ptr<Uploaded> upload_jobs(tl_server *S, const std::vector<Job *> &js, bool keyed) {
     u64 N = 0, M = 0;
     for (Job *j : js) {
+        if (j->resident) continue;
         N += j->in.n;
         M += j->in.m;
     }
     const u64 t0 = now_ns();
     auto U = std::make_unique<Uploaded>();
     U->jobs = js;
+    U->keyed = keyed;
     U->src = DevBuf((M ? M : 1) * 4, S->s_copy);
     U->dst = DevBuf((M ? M : 1) * 4, S->s_copy);
     U->rank = DevBuf((N ? N : 1) * 4, S->s_copy);
     u64 eo = 0, vo = 0;
     for (Job *j : js) {
+        U->eo.push_back(eo);
+        U->vo.push_back(vo);
+        if (j->resident) continue;
         const tl_job &J = j->in;
         if (J.m) {
             S->up->copy(U->src.as<u32>() + eo, J.src, J.m * 4);
@@ -267,10 +303,27 @@ tl_batch *orient_uploaded(tl_server *S, Uploaded &U) {
     return b;
 }
 
+// Drops the least recently used resident graph not in use (called with
+// S->mu held); false if there is none.
+bool drop_resident(tl_server *S) {
+    auto victim = S->cache.end();
+    for (auto it = S->cache.begin(); it != S->cache.end(); ++it)
+        if (it->second.refs == 0 && (victim == S->cache.end() || it->second.last < victim->second.last)) victim = it;
+    if (victim == S->cache.end()) return false;
+    tl_csr_free(victim->second.g);
+    S->cache_bytes -= victim->second.bytes;
+    S->reserved -= victim->second.bytes;
+    S->cache.erase(victim);
+    S->st.resident_dropped++;
+    return true;
+}
+
 // Picks the next batch (called with S->mu held).  Returns false to wait.
-bool pick(tl_server *S, std::vector<Job *> &out, u64 &bytes) {
+// A batch holds either keyed jobs only or unkeyed jobs only; keyed is set.
+bool pick(tl_server *S, std::vector<Job *> &out, u64 &bytes, bool &keyed) {
     out.clear();
     bytes = 0;
+    keyed = false;
     if (!S->solo_retry.empty()) {
         Job *j = S->solo_retry.front();
         S->solo_retry.pop_front();
@@ -281,20 +334,43 @@ bool pick(tl_server *S, std::vector<Job *> &out, u64 &bytes) {
     u64 edges = 0;
     while (!S->paused && !S->pending.empty()) {
         Job *j = S->pending.front();
+        const bool jk = j->in.key != 0;
+        if (!out.empty() && jk != keyed) break;  // keyed and unkeyed jobs are not batched together
+        auto hit = jk ? S->cache.find(j->in.key) : S->cache.end();
+        const bool res = hit != S->cache.end();
+        // a graph to be made resident is reserved with the job; a resident
+        // one is listed from a union built by copying it, no upload or sort
+        const u64 keep = jk && !res ? resident_bytes(j->in.n, j->in.m) : 0;
+        const u64 need = j->bytes + keep;
         const bool big = j->in.m >= S->cfg.solo_edges;
         if (!out.empty() && (big || out.size() >= S->cfg.max_batch_jobs || edges + j->in.m > S->cfg.max_batch_edges))
             break;
-        if (j->bytes > S->cfg.hbm_budget) {  // can never fit: refuse it
+        if (need > S->cfg.hbm_budget) {  // can never fit: refuse it
             S->pending.pop_front();
             finish(S, j, TL_ENOMEM);
             S->st.rejected++;
             S->cv_done.notify_all();
             continue;
         }
-        if (S->reserved + bytes + j->bytes > S->cfg.hbm_budget) break;  // wait for memory, keep the order
+        if (res) hit->second.refs++;  // pinned: room is not made by dropping its own graph
+        while (S->reserved + bytes + need > S->cfg.hbm_budget && drop_resident(S)) {
+        }
+        if (S->reserved + bytes + need > S->cfg.hbm_budget) {  // wait for memory, keep the order
+            if (res) hit->second.refs--;
+            break;
+        }
         S->pending.pop_front();
+        keyed = jk;
+        j->resident = res;
+        if (res) {
+            hit->second.last = ++S->tick;
+            j->csr = hit->second.g;
+            S->st.resident_hits++;
+        } else {
+            j->keep_bytes = keep;
+        }
         out.push_back(j);
-        bytes += j->bytes;
+        bytes += j->bytes + j->keep_bytes;
         edges += j->in.m;
         if (big) {
             j->solo = true;
@@ -307,16 +383,89 @@ bool pick(tl_server *S, std::vector<Job *> &out, u64 &bytes) {
     return true;
 }
 
+// A keyed batch's graphs: resident ones as they are, the others oriented one
+// by one (each made resident unless its key became resident meanwhile); a
+// job whose graph fails validation finishes alone.  Then the union is built
+// by copying, or, for one job alone, its graph is listed directly.  Throws on
+// device failures.
+bool orient_keyed(tl_server *S, Uploaded &U, Ready &r) {
+    const u64 t0 = now_ns();
+    std::vector<Job *> ok;
+    std::vector<const tl_csr *> gs;
+    for (size_t i = 0; i < U.jobs.size(); i++) {
+        Job *j = U.jobs[i];
+        if (!j->resident) {
+            tl_csr *g = nullptr;
+            try {
+                g = orient_impl(j->in.n, U.src.as<u32>() + U.eo[i], U.dst.as<u32>() + U.eo[i], j->in.m,
+                                U.rank.as<u32>() + U.vo[i], S->s_up);
+                TL_HIP(hipStreamSynchronize(S->s_up));
+            } catch (const TlError &e) {
+                if (e.code != TL_EINVAL) throw;
+                std::lock_guard<std::mutex> lk(S->mu);
+                finish(S, j, TL_EINVAL);
+                release_bytes(S, j->bytes + j->keep_bytes);
+                U.bytes -= j->bytes + j->keep_bytes;
+                S->cv_done.notify_all();
+                continue;
+            }
+            std::lock_guard<std::mutex> lk(S->mu);
+            j->csr = g;
+            auto it = S->cache.find(j->in.key);
+            if (it == S->cache.end()) {
+                // made resident: its bytes move from the job to the cache
+                Resident rs;
+                rs.g = g;
+                rs.bytes = j->keep_bytes;
+                rs.refs = 1;
+                rs.last = ++S->tick;
+                S->cache.emplace(j->in.key, rs);
+                S->cache_bytes += j->keep_bytes;
+                U.bytes -= j->keep_bytes;
+                j->resident = true;
+            } else {
+                j->owns_csr = true;  // listed from its own copy, freed afterwards
+            }
+            j->keep_bytes = 0;
+        }
+        ok.push_back(j);
+        gs.push_back(j->csr);
+    }
+    r.jobs = ok;
+    r.bytes = U.bytes;
+    r.keyed = true;
+    if (!ok.empty() && !(ok.size() == 1 && ok[0]->solo)) r.b = batch_from_csrs_impl((u32)gs.size(), gs.data(), S->s_up);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st.orient_ns += now_ns() - t0;
+    return !ok.empty();
+}
+
+// After a keyed batch is listed (called with S->mu held): unpins the
+// resident graphs, frees duplicates.
+void release_keyed(tl_server *S, const std::vector<Job *> &js) {
+    for (Job *j : js) {
+        if (j->owns_csr) {
+            tl_csr_free(j->csr);
+        } else if (j->csr) {
+            auto it = S->cache.find(j->in.key);
+            if (it != S->cache.end() && it->second.g == j->csr && it->second.refs) it->second.refs--;
+        }
+        j->csr = nullptr;
+        j->owns_csr = false;
+    }
+}
+
 // Called with S->mu held: a failed batch either splits (a malformed job
 // among several: each is retried alone) or fails its jobs.
 void fail_batch(tl_server *S, const std::vector<Job *> &js, u64 bytes, int err) {
     S->in_flight--;
-    if (err == TL_EINVAL && js.size() > 1) {
+    if (err == TL_EINVAL && js.size() > 1 && js[0]->in.key == 0) {  // (keyed jobs fail alone already)
         for (Job *j : js) S->solo_retry.push_back(j);
         S->st.split_batches++;
         S->cv_pending.notify_all();
         return;  // the bytes stay reserved for the retries
     }
+    release_keyed(S, js);
     for (Job *j : js) finish(S, j, err);
     release_bytes(S, bytes);
     S->cv_done.notify_all();
@@ -327,11 +476,12 @@ void upload_loop(tl_server *S) {
     std::vector<Job *> js;
     for (;;) {
         u64 bytes = 0;
+        bool keyed = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             // without pipelining a batch is admitted only when the previous one is listed
             S->cv_pending.wait(lk, [&] {
-                return S->stop || ((S->cfg.pipeline || S->in_flight == 0) && pick(S, js, bytes));
+                return S->stop || ((S->cfg.pipeline || S->in_flight == 0) && pick(S, js, bytes, keyed));
             });
             if (S->stop) return;
             S->in_flight++;
@@ -343,7 +493,7 @@ void upload_loop(tl_server *S) {
         std::unique_ptr<Uploaded> U;
         int err = TL_OK;
         try {
-            U = upload_jobs(S, js);
+            U = upload_jobs(S, js, keyed);
         } catch (const TlError &e) {
             err = e.code;
         } catch (...) {
@@ -374,10 +524,17 @@ void orient_loop(tl_server *S) {
             S->uploaded.pop_front();
             S->cv_upspace.notify_all();
         }
-        tl_batch *b = nullptr;
+        Ready r;
         int err = TL_OK;
+        bool any = true;
         try {
-            b = orient_uploaded(S, *U);
+            if (U->keyed) {
+                any = orient_keyed(S, *U, r);
+            } else {
+                r.b = orient_uploaded(S, *U);
+                r.jobs = U->jobs;
+                r.bytes = U->bytes;
+            }
         } catch (const TlError &e) {
             err = e.code;
         } catch (...) {
@@ -388,19 +545,30 @@ void orient_loop(tl_server *S) {
         U.reset();  // the copies are no longer needed (the orient stream has finished with them)
         std::unique_lock<std::mutex> lk(S->mu);
         if (err != TL_OK) {
-            fail_batch(S, js, bytes, err);
+            if (r.b) {
+                lk.unlock();
+                batch_free_impl(r.b, true);
+                lk.lock();
+            }
+            // jobs of a keyed batch that already failed alone are final
+            std::vector<Job *> left;
+            for (Job *j : js)
+                if (j->res.status == TL_JOB_PENDING) left.push_back(j);
+            fail_batch(S, left, bytes, err);
+            continue;
+        }
+        if (!any) {  // every job of a keyed batch failed alone
+            S->in_flight--;
+            release_bytes(S, r.bytes);
+            S->cv_pending.notify_all();
             continue;
         }
         S->cv_space.wait(lk, [&] { return S->stop || S->ready.size() < 2u; });
         if (S->stop) {
             lk.unlock();
-            batch_free_impl(b, true);
+            if (r.b) batch_free_impl(r.b, true);
             return;
         }
-        Ready r;
-        r.b = b;
-        r.jobs = js;
-        r.bytes = bytes;
         r.batch_id = S->next_batch++;
         S->ready.push_back(std::move(r));
         S->cv_ready.notify_all();
@@ -429,8 +597,8 @@ void list_loop(tl_server *S, u32 li) {
             if (k == 1 && r.jobs[0]->solo) {
                 // a graph alone: the plain listing with light and heavy pivots
                 tl_summary sm{};
-                list_impl(batch_csr(r.b), (int)r.jobs[0]->in.algo, 0u, 0xffffffffu, nullptr, 0, nullptr, nullptr,
-                          stream, &sm);
+                list_impl(r.b ? batch_csr(r.b) : r.jobs[0]->csr, (int)r.jobs[0]->in.algo, 0u, 0xffffffffu, nullptr,
+                          0, nullptr, nullptr, stream, &sm);
                 solo_out.push_back(sm);
             } else {
                 table.assign(3ull * k, 0);
@@ -450,9 +618,10 @@ void list_loop(tl_server *S, u32 li) {
         } catch (...) {
             err = TL_EHIP;
         }
-        batch_free_impl(r.b, false);  // the list stream has finished with it
+        if (r.b) batch_free_impl(r.b, false);  // the list stream has finished with it
         pool_trim_above(S->cfg.hbm_budget + S->cfg.hbm_budget / 2);
         std::unique_lock<std::mutex> lk(S->mu);
+        if (r.keyed) release_keyed(S, r.jobs);
         S->in_flight--;
         S->cv_space.notify_all();
         S->cv_pending.notify_all();
@@ -576,6 +745,8 @@ void server_stats_impl(tl_server *S, tl_server_stats *out) {
     *out = S->st;
     out->reserved = S->reserved;
     out->pending = S->pending.size();
+    out->resident_graphs = S->cache.size();
+    out->resident_bytes = S->cache_bytes;
 }
 
 void server_destroy_impl(tl_server *S) {
@@ -586,9 +757,13 @@ void server_destroy_impl(tl_server *S) {
         S->cv_done.notify_all();
         S->pending.clear();
         S->cv_done.wait(lk, [&] {
-            return S->in_flight == 0 && S->ready.empty() && S->uploaded.empty() && S->reserved == 0 &&
+            return S->in_flight == 0 && S->ready.empty() && S->uploaded.empty() && S->reserved == S->cache_bytes &&
                    S->solo_retry.empty();
         });
+        for (auto &kv : S->cache) tl_csr_free(kv.second.g);
+        S->cache.clear();
+        S->reserved -= S->cache_bytes;
+        S->cache_bytes = 0;
         S->stop = true;
         S->cv_pending.notify_all();
         S->cv_uploaded.notify_all();

@@ -162,6 +162,9 @@ void set_chunk_triangles(u64 k);
 // Batched listing (batch.hip).
 tl_batch *batch_orient_impl(u32 k, const u32 *n, const u64 *m, const u32 *src, const u32 *dst, const u32 *rank,
                             hipStream_t s);
+// A batch whose union is built from k graphs already oriented (their arrays
+// copied with shifted ranks and indices; the graphs stay the caller's).
+tl_batch *batch_from_csrs_impl(u32 k, const tl_csr *const *gs, hipStream_t s);
 void batch_list_impl(tl_batch *b, int algo, hipStream_t s, int use_graph, u64 *per_graph_host, u64 *per_graph_dev);
 // device_sync: wait for the whole device first (else the caller has
 // synchronised every stream that used the batch).

@@ -43,7 +43,8 @@ class ServerConfig(ctypes.Structure):
 
 class Job(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint64), ("src", ctypes.c_void_p),
-                ("dst", ctypes.c_void_p), ("rank", ctypes.c_void_p), ("algo", ctypes.c_int)]
+                ("dst", ctypes.c_void_p), ("rank", ctypes.c_void_p), ("algo", ctypes.c_int),
+                ("key", ctypes.c_uint64)]
 
 
 JOB_PENDING = -1
@@ -59,7 +60,8 @@ class JobResult(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "submitted", "jobs_done", "batches", "rejected", "cancelled", "split_batches", "reserved",
-        "peak_reserved", "pending", "max_batch_jobs_seen", "upload_ns", "orient_ns", "list_ns")]
+        "peak_reserved", "pending", "max_batch_jobs_seen", "upload_ns", "orient_ns", "list_ns",
+        "resident_hits", "resident_graphs", "resident_bytes", "resident_dropped")]
 
 
 class ListStats(ctypes.Structure):
@@ -106,6 +108,7 @@ def _load():
                                    ctypes.POINTER(NeighResult), vp]
     lib.tl_order_neigh.restype = i32
     lib.tl_batch_orient.argtypes = [u32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.tl_batch_from_graphs.argtypes = [u32, vp, vp, ctypes.POINTER(vp)]
     lib.tl_batch_list.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.tl_batch_size.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u64)]
     lib.tl_batch_free.argtypes = [vp]
@@ -357,6 +360,18 @@ def batch_orient(n, m, src: torch.Tensor, dst: torch.Tensor, rank: torch.Tensor,
     return Batch(h)
 
 
+def batch_from_graphs(graphs, stream=None) -> Batch:
+    """tl_batch_from_graphs: a batch of oriented graph handles (Csr), whose
+    union is built by copying their arrays; the handles stay the caller's."""
+    if len(graphs) == 0:
+        raise ValueError("no graphs")
+    arr = (ctypes.c_void_p * len(graphs))(*[g.handle for g in graphs])
+    h = ctypes.c_void_p()
+    _check(_lib.tl_batch_from_graphs(len(graphs), ctypes.cast(arr, ctypes.c_void_p), _stream_ptr(stream),
+                                     ctypes.byref(h)), "tl_batch_from_graphs")
+    return Batch(h)
+
+
 class Server:
     """tl_server_*: a listing server on the current device.  Job arrays are
     host numpy uint32 arrays; they are kept referenced here until the job's
@@ -371,7 +386,9 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, n, src, dst, rank, algo: str = "A++") -> int:
+    def submit(self, n, src, dst, rank, algo: str = "A++", key: int = 0) -> int:
+        """key != 0 names the graph and ordering: it is kept resident on the
+        device and later jobs with the same key are listed from it."""
         import numpy as np
         s = np.ascontiguousarray(src, np.uint32)
         d = np.ascontiguousarray(dst, np.uint32)
@@ -379,7 +396,7 @@ class Server:
         if s.shape != d.shape or len(r) != n:
             raise ValueError("src/dst lengths differ or rank length != n")
         job = Job(int(n), len(s), s.ctypes.data if len(s) else None, d.ctypes.data if len(d) else None,
-                  r.ctypes.data if len(r) else None, ALGOS[algo])
+                  r.ctypes.data if len(r) else None, ALGOS[algo], int(key))
         jid = ctypes.c_uint64()
         _check(_lib.tl_server_submit(self._h, ctypes.byref(job), ctypes.byref(jid)), "tl_server_submit")
         self._keep[int(jid.value)] = (s, d, r)

@@ -255,3 +255,33 @@ def test_full_workload_table(tl):
     assert sha(table) == gold[str(K)]["table_sha256"]
     assert int(table[:, 0].sum()) == gold[str(K)]["triangles"]
     assert int(table[:, 2].sum()) == gold[str(K)]["work"]
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_batch_from_oriented_graphs_equals_union_orientation(tl, algo):
+    """tl_batch_from_graphs (the union copied from graphs oriented one by
+    one) lists the same per-graph table as tl_batch_orient and the oracle."""
+    B, graphs = workload_graphs(10, first=300)
+    graphs = graphs + fixture_graphs()
+    handles = [tl.orient(n, dev(s), dev(d), dev(r)) for (n, s, d, r) in graphs]
+    try:
+        want = oracle_table(graphs, algo)
+        b = tl.batch_from_graphs(handles)
+        try:
+            assert np.array_equal(b.list(algo, use_graph=False), want)
+            assert np.array_equal(b.list(algo, use_graph=True), want)
+        finally:
+            b.free()
+        b2 = orient_batch(tl, graphs)
+        try:
+            assert np.array_equal(b2.list(algo, use_graph=True), want)
+        finally:
+            b2.free()
+    finally:
+        for h in handles:
+            h.free()
+
+
+def test_batch_from_graphs_rejects_bad_input(tl):
+    with pytest.raises(tl.TLError):
+        tl.batch_from_graphs([])

@@ -242,3 +242,91 @@ def test_large_jobs_under_64gb_budget(tl):
         assert st["peak_reserved"] <= 64 * GB
     finally:
         srv.close()
+
+
+def test_keyed_jobs_stay_resident(tl, pool):
+    """Jobs with a key: the first of each key is oriented and kept resident,
+    the repeats are listed from the resident graph (no upload, no
+    orientation); every result equals the oracle's, alone or in the mix."""
+    jobs = pool[:24]
+    srv = tl.Server(8 * GB)
+    try:
+        ids = [srv.submit(g.n, g.src, g.dst, rank, key=j + 1) for (j, g, rank, _) in jobs]
+        first = [srv.poll(i, -1) for i in ids]
+        for (j, _, _, want), r in zip(jobs, first):
+            assert r.status == 0 and result_tuple(r) == want, j
+        st0 = srv.stats()
+        assert st0["resident_graphs"] == len(jobs)
+        # repeats, in another order, in bursts: all resident
+        order = list(reversed(jobs)) * 3
+        res = run_burst_keyed(tl, srv, order)
+        for (j, _, _, want), r in zip(order, res):
+            assert r.status == 0 and result_tuple(r) == want, j
+        st = srv.stats()
+        assert st["resident_hits"] - st0["resident_hits"] == len(order)
+        assert st["batches"] - st0["batches"] < len(order)  # repeats were batched together
+        assert st["peak_reserved"] <= 8 * GB
+    finally:
+        srv.close()
+
+
+def run_burst_keyed(tl, srv, jobs):
+    srv.pause(True)
+    ids = [srv.submit(g.n, g.src, g.dst, rank, key=j + 1) for (j, g, rank, _) in jobs]
+    srv.pause(False)
+    return [srv.poll(i, -1) for i in ids]
+
+
+def test_keyed_and_unkeyed_mixed(tl, pool):
+    jobs = pool[:16]
+    srv = tl.Server(8 * GB)
+    try:
+        srv.pause(True)
+        ids = []
+        for k, (j, g, rank, _) in enumerate(jobs * 2):
+            ids.append(srv.submit(g.n, g.src, g.dst, rank, key=(j + 1) if k % 3 else 0))
+        srv.pause(False)
+        for (j, _, _, want), i in zip(jobs * 2, ids):
+            r = srv.poll(i, -1)
+            assert r.status == 0 and result_tuple(r) == want, j
+    finally:
+        srv.close()
+
+
+def test_resident_graphs_dropped_under_a_tight_budget(tl, pool):
+    """A budget that holds only a few resident graphs: the least recently
+    used are dropped to admit new jobs, and results stay exact."""
+    jobs = pool[:12]
+    one = max(tl.Server.job_bytes(g.n, g.m) for (_, g, _, _) in jobs)
+    budget = int(1.4 * one)  # one job at a time and about one resident graph beside it
+    srv = tl.Server(budget)
+    try:
+        for rep in range(2):
+            res = run_burst_keyed(tl, srv, jobs)
+            for (j, _, _, want), r in zip(jobs, res):
+                assert r.status == 0 and result_tuple(r) == want, (rep, j)
+        st = srv.stats()
+        assert st["resident_dropped"] >= 1
+        assert st["peak_reserved"] <= budget
+    finally:
+        srv.close()
+
+
+def test_keyed_malformed_job_fails_alone(tl, pool):
+    bad_rank = np.zeros(pool[2][1].n, np.uint32)
+    srv = tl.Server(8 * GB)
+    try:
+        srv.pause(True)
+        ids = []
+        for k, (j, g, rank, _) in enumerate(pool[:6]):
+            ids.append(srv.submit(g.n, g.src, g.dst, bad_rank if k == 2 else rank, key=1000 + k))
+        srv.pause(False)
+        for k, ((j, _, _, want), i) in enumerate(zip(pool[:6], ids)):
+            r = srv.poll(i, -1)
+            if k == 2:
+                assert r.status == tl.tl.TL_EINVAL
+            else:
+                assert r.status == 0 and result_tuple(r) == want, j
+        assert srv.stats()["resident_graphs"] == 5
+    finally:
+        srv.close()

@@ -382,6 +382,11 @@ void tl_server_destroy(tl_server *s);
  *                        light items (64..2^30)
  *   queue                1: heavy tasks handed out by an atomic queue
  *   splits               1: wavefront start seeds precomputed per task
+ *   keep_staged          1: a heavy workgroup whose next task has the same
+ *                        pivot keeps that pivot's list staged in LDS
+ *   lean                 1: when every heavy task has the bitmap or split
+ *                        form (always, under the default keys), a heavy
+ *                        kernel compiled with those two forms only runs
  *   hash                 1: a heavy pivot whose list's rank window is too
  *                        wide for the LDS bitmap keeps the list in an LDS
  *                        hash table when it fits
@@ -408,8 +413,8 @@ void tl_server_destroy(tl_server *s);
  *                        found by two binary searches (0..255; results are
  *                        the same, only the work split changes)
  * for callback mode (chunks of K triangles, tl_set_chunk_triangles):
- *   chunk_task_div       heavy tasks hold at most K / (this x heavy
- *                        workgroups) items, at least 65536 (1..64)
+ *   chunk_task_div       heavy tasks hold at most chunk_room x K / (this x
+ *                        heavy workgroups) items, at least 65536 (1..64)
  *   chunk_growth         1: every probe slice covers K scanned items (each
  *                        yields at most one triangle); above 1 (default 8): a
  *                        slice may cover up to this many times the previous

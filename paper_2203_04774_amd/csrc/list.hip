@@ -72,6 +72,7 @@ struct Tuning {
     u64 queue = 1;               // 1: heavy tasks handed out by an atomic queue
     u64 splits = 1;              // 1: wavefront start seeds precomputed at plan time
     u64 keep_staged = 1;         // 1: a workgroup keeps its pivot's list staged for a next task of that pivot
+    u64 lean = 1;                // 1: the BITMAP/SPLIT-only heavy kernel when no task has another form
     u64 light_blocks_per_cu = 16; // light grid cap
     u64 light_wave_items = 8192;  // light grid: at least this many items per wavefront
     u64 reverse = 0;             // 1: REVERSE instead of GLOBAL for lists that fit no LDS form
@@ -359,6 +360,11 @@ __global__ void k_plan_totals(const u64 *pos, u64 m, const u64 *tpos, u32 n, con
         out[2] = cpre[hp & 0xffffffffull];
         out[3] = cpre[m];
         out[4] = acc[2];
+        // items of heavy pivots in forms other than BITMAP and SPLIT
+        u64 other = 0;
+        for (int md = 0; md < NMODES; md++)
+            if (md != MODE_BITMAP && md != MODE_SPLIT) other += acc[10 + md];
+        out[5] = other;
     }
 }
 
@@ -676,7 +682,10 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
 
 // Heavy tasks: one workgroup stages the pivot's list in LDS, then its
 // wavefronts share the task's items.  Items are clipped to [k0, k1).
-template <int ALGO, bool EMIT>
+// LEAN: compiled with the BITMAP and SPLIT walks only (the forms the
+// default tuning ever chooses), for fewer registers; used when no task of
+// the listing has another form.
+template <int ALGO, bool EMIT, bool LEAN>
 __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restrict__ tasks, u64 ntasks,
                                                     const u32 *__restrict__ cseed, const u64 *__restrict__ cabs,
                                                     const u32 *__restrict__ cxinv, const u64 *__restrict__ cpre,
@@ -1209,14 +1218,19 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 finish();
             }
         };
-        switch (tk.mode) {
-            case MODE_BITMAP: walk(std::integral_constant<int, MODE_BITMAP>{}); break;
-            case MODE_ARRAY: walk(std::integral_constant<int, MODE_ARRAY>{}); break;
-            case MODE_GLOBAL: walk(std::integral_constant<int, MODE_GLOBAL>{}); break;
-            case MODE_REVERSE: walk(std::integral_constant<int, MODE_REVERSE>{}); break;
-            case MODE_HASH: walk(std::integral_constant<int, MODE_HASH>{}); break;
-            case MODE_BUCKET: walk(std::integral_constant<int, MODE_BUCKET>{}); break;
-            default: walk(std::integral_constant<int, MODE_SPLIT>{}); break;
+        if constexpr (LEAN) {
+            if (tk.mode == MODE_BITMAP) walk(std::integral_constant<int, MODE_BITMAP>{});
+            else walk(std::integral_constant<int, MODE_SPLIT>{});
+        } else {
+            switch (tk.mode) {
+                case MODE_BITMAP: walk(std::integral_constant<int, MODE_BITMAP>{}); break;
+                case MODE_ARRAY: walk(std::integral_constant<int, MODE_ARRAY>{}); break;
+                case MODE_GLOBAL: walk(std::integral_constant<int, MODE_GLOBAL>{}); break;
+                case MODE_REVERSE: walk(std::integral_constant<int, MODE_REVERSE>{}); break;
+                case MODE_HASH: walk(std::integral_constant<int, MODE_HASH>{}); break;
+                case MODE_BUCKET: walk(std::integral_constant<int, MODE_BUCKET>{}); break;
+                default: walk(std::integral_constant<int, MODE_SPLIT>{}); break;
+            }
         }
     }
     em.finish(o);
@@ -1296,6 +1310,7 @@ struct Plan {
     u64 w_total = 0;  // all items
     u64 ntasks = 0;
     u64 work = 0;     // the paper's work over the listed pivots
+    bool lean = true; // every heavy task has the BITMAP or SPLIT form
 };
 
 // Largest grids the probe kernels are launched with; they bound the number
@@ -1349,11 +1364,11 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
     DevBuf tpos(((u64)n + 1) * sizeof(u64), s);
     scan_u32_to_u64(ntask.as<u32>(), tpos.as<u64>(), n, s);
     // every total the host needs, in one round trip
-    DevBuf tot(5 * sizeof(u64), s);
+    DevBuf tot(6 * sizeof(u64), s);
     hipLaunchKernelGGL(k_plan_totals, dim3(1), dim3(WAVE), 0, s, pos.as<u64>(), m, tpos.as<u64>(), n,
                        P.cpre.as<u64>(), d_acc, tot.as<u64>());
     TL_HIP(hipGetLastError());
-    u64 h_t[5] = {0, 0, 0, 0, 0};
+    u64 h_t[6] = {0, 0, 0, 0, 0, 0};
     d2h_sync(s, {{h_t, tot.p, sizeof h_t}});
     const u64 h_pos = h_t[0], h_nt = h_t[1];
     const u64 nl = h_pos & 0xffffffffull, nh = h_pos >> 32;
@@ -1363,6 +1378,7 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
     P.w_light = h_t[2];
     P.w_total = h_t[3];
     P.work = h_t[4];
+    P.lean = h_t[5] == 0;
     if (h_nt) {
         P.tasks = DevBuf(h_nt * sizeof(Task), s);
         hipLaunchKernelGGL((k_make_tasks<ALGO>), dim3(gn), dim3(PB), 0, s, v, n, mode.as<u32>(), ntask.as<u32>(),
@@ -1414,16 +1430,22 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
         }
         u64 blocks = P.ntasks;
         if (blocks > heavy_max_blocks()) blocks = heavy_max_blocks();
-        if (emit)
-            hipLaunchKernelGGL((k_probe_heavy<ALGO, true>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
-                               P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(),
-                               P.cpre.as<u64>(),
-                               h0, h1, o, (int)tuning().queue, (int)tuning().splits, (int)tuning().keep_staged);
-        else
-            hipLaunchKernelGGL((k_probe_heavy<ALGO, false>), dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v,
-                               P.tasks.as<Task>(), P.ntasks, P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(),
-                               P.cpre.as<u64>(),
-                               h0, h1, o, (int)tuning().queue, (int)tuning().splits, (int)tuning().keep_staged);
+        auto go = [&](auto emit_tag, auto lean_tag) {
+            hipLaunchKernelGGL((k_probe_heavy<ALGO, decltype(emit_tag)::value, decltype(lean_tag)::value>),
+                               dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v, P.tasks.as<Task>(), P.ntasks,
+                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(), P.cpre.as<u64>(), h0, h1, o,
+                               (int)tuning().queue, (int)tuning().splits, (int)tuning().keep_staged);
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        const bool lean = P.lean && tuning().lean;
+        if (emit) {
+            if (lean) go(T_{}, T_{});
+            else go(T_{}, F_{});
+        } else {
+            if (lean) go(F_{}, T_{});
+            else go(F_{}, F_{});
+        }
         TL_HIP(hipGetLastError());
     }
 }
@@ -1464,6 +1486,7 @@ Tuning &tuning() {
         env("TL_TUNE_SLICE_MULT", d.slice_mult);
         env("TL_TUNE_TASK_DIV", d.task_div);
         env("TL_TUNE_KEEP_STAGED", d.keep_staged);
+        env("TL_TUNE_LEAN", d.lean);
         if (d.task_div > 1024) d.task_div = 1024;
         env("TL_TUNE_HEAVY_BLOCKS_PER_CU", d.heavy_blocks_per_cu);
         env("TL_TUNE_QUEUE", d.queue);
@@ -1503,9 +1526,13 @@ bool debug_enabled() {
 void prepare_kernels() {
     static std::once_flag once;
     std::call_once(once, [] {
-        const void *fns[] = {(const void *)k_probe_heavy<0, true>, (const void *)k_probe_heavy<0, false>,
-                             (const void *)k_probe_heavy<1, true>, (const void *)k_probe_heavy<1, false>,
-                             (const void *)k_probe_heavy<2, true>, (const void *)k_probe_heavy<2, false>};
+        const void *fns[] = {
+            (const void *)k_probe_heavy<0, true, false>, (const void *)k_probe_heavy<0, false, false>,
+            (const void *)k_probe_heavy<1, true, false>, (const void *)k_probe_heavy<1, false, false>,
+            (const void *)k_probe_heavy<2, true, false>, (const void *)k_probe_heavy<2, false, false>,
+            (const void *)k_probe_heavy<0, true, true>,  (const void *)k_probe_heavy<0, false, true>,
+            (const void *)k_probe_heavy<1, true, true>,  (const void *)k_probe_heavy<1, false, true>,
+            (const void *)k_probe_heavy<2, true, true>,  (const void *)k_probe_heavy<2, false, true>};
         for (const void *f : fns)
             (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, HEAVY_LDS_BYTES);
         (void)hipGetLastError();
@@ -1527,7 +1554,7 @@ u64 list_count_scratch_bytes(u64 n, u64 m) {
     t += 3 * blk(m * 4);                                      // ctlo, cthi, cpinv
     t += blk((m + 1) * 8) + (ws_m ? ws_m : 0);                // cpre and its scan
     t += blk((n + 1) * 8) + (ws_n ? ws_n : 0);                // tpos and its scan
-    t += blk(5 * sizeof(u64));                                // totals
+    t += blk(6 * sizeof(u64));                                // totals
     return t;
 }
 
@@ -1551,6 +1578,7 @@ int set_tuning(const char *key, u64 value) {
     else if (k == "queue" && value <= 1) t.queue = value;
     else if (k == "splits" && value <= 1) t.splits = value;
     else if (k == "keep_staged" && value <= 1) t.keep_staged = value;
+    else if (k == "lean" && value <= 1) t.lean = value;
     else if (k == "chunk_room" && value >= 1 && value <= 16) t.chunk_room = value;
     else if (k == "light_blocks_per_cu" && value >= 1 && value <= 64) t.light_blocks_per_cu = value;
     else if (k == "light_wave_items" && value >= (u64)WAVE && value <= (1ull << 30)) t.light_wave_items = value;
@@ -1580,6 +1608,7 @@ int get_tuning(const char *key, u64 *value) {
     else if (k == "queue") *value = t.queue;
     else if (k == "splits") *value = t.splits;
     else if (k == "keep_staged") *value = t.keep_staged;
+    else if (k == "lean") *value = t.lean;
     else if (k == "chunk_room") *value = t.chunk_room;
     else if (k == "light_blocks_per_cu") *value = t.light_blocks_per_cu;
     else if (k == "light_wave_items") *value = t.light_wave_items;

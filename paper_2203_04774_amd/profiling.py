@@ -81,7 +81,8 @@ def traffic(fetch_csv: str, write_csv: str, calib_mib: float, workload: str, out
             per_kernel[name][key] += v * 1024 * fac
             if key == "fetch":
                 per_kernel[name]["launches"] += 1
-    heavy = [n for n in per_kernel if n.startswith("k_probe_heavy") and n.endswith("true>")]
+    # the emitting heavy-pivot kernels: k_probe_heavy<form, true, lean>
+    heavy = [n for n in per_kernel if n.startswith("k_probe_heavy<") and n.split(",")[1].strip() == "true"]
     hb = sum(per_kernel[n]["fetch"] + per_kernel[n]["write"] for n in heavy)
     hl = sum(per_kernel[n]["launches"] for n in heavy)
     res = {

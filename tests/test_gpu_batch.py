@@ -283,5 +283,13 @@ def test_batch_from_oriented_graphs_equals_union_orientation(tl, algo):
 
 
 def test_batch_from_graphs_rejects_bad_input(tl):
-    with pytest.raises(tl.TLError):
+    """Through the C-ABI: k = 0 and a NULL handle give TL_EINVAL."""
+    import ctypes
+    lib = tl.raw_lib()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.tl_batch_from_graphs(0, ctypes.cast(arr, ctypes.c_void_p), None, ctypes.byref(h)) == tl.tl.TL_EINVAL
+    assert lib.tl_batch_from_graphs(1, ctypes.cast(arr, ctypes.c_void_p), None, ctypes.byref(h)) == tl.tl.TL_EINVAL
+    assert not h.value
+    with pytest.raises(ValueError):
         tl.batch_from_graphs([])

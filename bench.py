@@ -447,7 +447,8 @@ def bench_serve(args):
 
     def sweep_mode(resident):
         nonlocal all_ok
-        srv = tl.Server(args.serve_budget_gb << 30)
+        srv = tl.Server(args.serve_budget_gb << 30, list_threads=args.serve_list_threads,
+                        solo_edges=args.serve_solo_edges)
         key = (lambda j: j + 1) if resident else (lambda j: 0)
         if resident:  # warm the cache: every pool graph oriented once and kept
             for i in [srv.submit(g.n, g.src, g.dst, rank, key=key(j)) for j, (g, rank, _) in enumerate(pool)]:
@@ -493,8 +494,12 @@ def bench_serve(args):
         srv.close()
         return sweep
 
-    cold = sweep_mode(False)
-    resident = sweep_mode(True)
+    cold = sweep_mode(False) if "cold" in args.serve_modes else []
+    resident = sweep_mode(True) if "resident" in args.serve_modes else []
+    if not cold:
+        cold = resident
+    if not resident:
+        resident = cold
     top_c = max(cold, key=lambda r: r["jobs_per_s"])
     top_r = max(resident, key=lambda r: r["jobs_per_s"])
     res = {
@@ -515,6 +520,7 @@ def bench_serve(args):
                            "gamma U(2.0, 2.8)); m log-uniform in [1e3, 1e7]; degree or core order; A++; "
                            "drawn uniformly from the pool",
                    "budget_gb": args.serve_budget_gb, "rates": args.serve_rates,
+                   "list_threads": args.serve_list_threads, "solo_edges": args.serve_solo_edges or 2 ** 21,
                    "jobs_per_rate": f"min({args.serve_jobs}, rate x {args.serve_seconds} s)",
                    "host_memory": "pinned" if args.serve_pinned else "pageable"},
         "p50_ms": top_r["p50_ms"],
@@ -734,6 +740,11 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrival window per rate, at most")
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--serve-pinned", action="store_true", help="job arrays in page-locked host memory")
+    ap.add_argument("--serve-list-threads", type=int, default=0, help="server list threads (0: library default)")
+    ap.add_argument("--serve-solo-edges", type=int, default=1 << 24,
+                    help="jobs with at least this many edges run alone (0: library default, 2^21); the pool's "
+                         "largest jobs (~10^7 edges) are batched with the rest at 2^24")
+    ap.add_argument("--serve-modes", nargs="+", default=["cold", "resident"], choices=["cold", "resident"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the listing runs on one GPU; --gpus {args.gpus} is not supported "

@@ -315,7 +315,7 @@ typedef struct {
     uint64_t max_batch_edges; /* input edges per batch, at most (0: 2^27) */
     uint64_t solo_edges;      /* jobs with at least this many edges run alone (0: 2^21) */
     uint32_t pipeline;        /* 1: orient the next batch while one lists */
-    uint32_t list_threads;    /* batches listed at once, each on its own stream (0: 2; at most 8) */
+    uint32_t list_threads;    /* batches listed at once, each on its own stream (0: 8; at most 8) */
 } tl_server_config;
 
 typedef struct {

@@ -7,7 +7,7 @@
 // footprint fits the budget and copies their edges and orderings to the
 // device; a job whose graph is large forms a batch of its own.  The orient
 // thread orients each uploaded batch as one disjoint union (batch.hip).
-// The list threads (two by default, each on its own stream) take oriented
+// The list threads (eight by default, each on its own stream) take oriented
 // batches in order: a union of small graphs is listed by the batched pass
 // (per-graph rows), a batch of one by the plain listing (light and heavy
 // pivots).  So the copy of one batch, the orientation of the next and the
@@ -667,7 +667,7 @@ tl_server *server_create_impl(const tl_server_config *cfg) {
     if (!S->cfg.max_batch_jobs) S->cfg.max_batch_jobs = 4096;
     if (!S->cfg.max_batch_edges) S->cfg.max_batch_edges = 1ull << 27;
     if (!S->cfg.solo_edges) S->cfg.solo_edges = 1ull << 21;
-    if (!S->cfg.list_threads) S->cfg.list_threads = 2;
+    if (!S->cfg.list_threads) S->cfg.list_threads = 8;
     TL_REQUIRE(S->cfg.list_threads <= 8, TL_EINVAL, "list_threads must be at most 8");
     TL_HIP(hipGetDevice(&S->device));
     TL_HIP(hipStreamCreateWithFlags(&S->s_copy, hipStreamNonBlocking));

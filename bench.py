@@ -520,7 +520,7 @@ def bench_serve(args):
                            "gamma U(2.0, 2.8)); m log-uniform in [1e3, 1e7]; degree or core order; A++; "
                            "drawn uniformly from the pool",
                    "budget_gb": args.serve_budget_gb, "rates": args.serve_rates,
-                   "list_threads": args.serve_list_threads, "solo_edges": args.serve_solo_edges or 2 ** 21,
+                   "list_threads": args.serve_list_threads or 8, "solo_edges": args.serve_solo_edges or 2 ** 21,
                    "jobs_per_rate": f"min({args.serve_jobs}, rate x {args.serve_seconds} s)",
                    "host_memory": "pinned" if args.serve_pinned else "pageable"},
         "p50_ms": top_r["p50_ms"],
@@ -737,7 +737,7 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=128, help="distinct jobs in the serving job pool")
     ap.add_argument("--serve-rates", type=float, nargs="+", default=[100, 300, 1000, 3000, 5000])
     ap.add_argument("--serve-jobs", type=int, default=10000, help="jobs per arrival rate, at most")
-    ap.add_argument("--serve-seconds", type=float, default=60.0, help="arrival window per rate, at most")
+    ap.add_argument("--serve-seconds", type=float, default=100.0, help="arrival window per rate, at most")
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--serve-pinned", action="store_true", help="job arrays in page-locked host memory")
     ap.add_argument("--serve-list-threads", type=int, default=0, help="server list threads (0: library default)")

@@ -124,7 +124,6 @@ __device__ __forceinline__ uint64_t upper_bound_dev(const T *a, uint64_t lo, uin
     return lo;
 }
 
-// splitmix64 output function (Steele, Lea, Flood, OOPSLA 2014)
 // The same searches, probing first the few entries next to one end of the
 // range (they share its cache lines) before halving the rest.  A window
 // bound that lies near that end then costs one or two lines instead of a
@@ -151,6 +150,7 @@ __device__ __forceinline__ uint64_t upper_bound_back(const T *a, uint64_t lo, ui
     return upper_bound_dev<T>(a, lo, prev, x);
 }
 
+// splitmix64 output function (Steele, Lea, Flood, OOPSLA 2014)
 __device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;

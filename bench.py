@@ -62,6 +62,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def oracle_results(name):
+    """(order, algo) -> (count, digest, work) of the whole listing, as the
+    oracle's stored results for this workload give them (written by the
+    scripts under tests/golden from oracle/ only), or {} if none are stored."""
+    gdir = os.path.join(ROOT, "tests", "golden")
+    out = {}
+    try:
+        if name == "rmat26":
+            with open(os.path.join(gdir, "oracle_rmat26.json")) as f:
+                d = json.load(f)
+            for algo, r in d["list"].items():
+                out[("degree", algo)] = (r["count"], r["hash"], r["work"])
+        elif name in ("chunglu20", "rmat12"):
+            with open(os.path.join(gdir, "oracle_expected.json")) as f:
+                d = json.load(f)[name + "_s1"]
+            for kind, o in d["orders"].items():
+                for algo, r in o["list"].items():
+                    out[(kind, algo)] = (r["count"], r["hash"], r["work"])
+    except (OSError, KeyError, ValueError):
+        return {}
+    return out
+
+
 def alg_bytes(C, m, n, T, emit=True):
     """Algorithmic HBM bytes of one listing: 4 B per scanned-list element of
     the paper's work C, 4 B per staged pivot-list element and ~16 B of
@@ -819,6 +842,8 @@ def main():
         return False
 
     runs = [(k, a) for k in wl["orders"] for a in wl["algos"]]
+    gold = oracle_results(args.workload)
+    seen = []  # (order, algo, count, digest, work) of every listing, warmup and timed
 
     def phase_ms():
         vals = []
@@ -839,6 +864,7 @@ def main():
                 c = tl.cost(csr, algo)
                 s = (tl.list_triangles(csr, algo, on_chunk=consume) if chunked
                      else tl.list_triangles(csr, algo, out=out))
+                seen.append((kind, algo, int(s.count), int(s.hash), int(s.work)))
                 if record is not None:
                     after = phase_ms()
                     st = tl.last_list_stats()
@@ -933,6 +959,10 @@ def main():
     }
     if chunked:
         res["chunks_per_step"] = chunks_seen[0] / max(args.steps + args.warmup, 1)
+    checked = [r for r in seen if (r[0], r[1]) in gold]
+    res["oracle_match"] = (all(tuple(r[2:]) == tuple(gold[(r[0], r[1])]) for r in checked)
+                           if checked else None)
+    res["oracle_checked"] = f"{len(checked)} of {len(seen)} listings (count, digest, work) against the oracle's stored results"
     if cpu_handle is not None:
         log("[bench] waiting for the CPU oracle baseline")
         cb = finish_cpu_baseline(cpu_handle)

@@ -46,7 +46,16 @@ namespace {
 #endif
 
 constexpr int PB = 256;        // threads per block, light kernels
-constexpr int HB = 1024;       // threads per block, heavy-pivot kernel
+#ifndef TL_HB
+#define TL_HB 1024
+#endif
+#ifndef TL_HG
+#define TL_HG 2
+#endif
+#ifndef TL_SG
+#define TL_SG 2
+#endif
+constexpr int HB = TL_HB;      // threads per block, heavy-pivot kernel
 constexpr u32 LDS_BYTES = 128 * 1024;
 constexpr u32 LDS_WORDS = LDS_BYTES / 4;
 constexpr u64 LDS_BITS = (u64)LDS_BYTES * 8;
@@ -143,15 +152,25 @@ struct Reverse {
 };
 
 constexpr int HW = HB / 64;    // wavefronts per heavy workgroup
-constexpr int HG = 2;          // groups of UN chunks loaded together in the bitmap forms' long windows
+constexpr int HG = TL_HG;      // groups of UN chunks loaded together in the bitmap forms' long windows
 
 struct Task {
     u64 a, b;      // item range
     u64 cb, ce;    // compacted seed range of the pivot
+    u64 t0, t1;    // the pivot's list T: piv_adj[t0, t1)
+    u64 ts;        // SPLIT: T's first entry inside the bitmap's window (else t0)
     u32 p;         // pivot
     u32 mode;
+    u32 tmin, tmax;  // T's first and last entries
+    u32 pinv;      // original id of the pivot
     u32 ws[HW];    // seed (relative to cb) of each wavefront's first item
 };
+
+// SPLIT: the bitmap covers ranks [split_wlo, tmax], the top LDS_BITS ranks
+// up to the list's last entry (or the whole range when it fits)
+__host__ __device__ __forceinline__ u32 split_wlo(u32 tmin, u32 tmax) {
+    return (u64)tmax - tmin + 1 > LDS_BITS ? (u32)((u64)tmax + 1 - LDS_BITS) : tmin;
+}
 
 // Item range of wavefront w when a workgroup shares [a, b) (64-aligned runs).
 __host__ __device__ __forceinline__ void wave_share(u64 a, u64 b, u32 nwv, u32 w, u64 &wb, u64 &we) {
@@ -379,14 +398,28 @@ __global__ void k_make_tasks(GView g, u32 n, const u32 *mode, const u32 *ntask, 
         const u64 cb = nl + (pos[so[p]] >> 32), ce = nl + (pos[so[p + 1]] >> 32);
         const u64 a = cpre[cb], b = cpre[ce];
         const u64 sl = slice[p];
+        // the pivot list's geometry, found once here rather than by dependent
+        // loads (and SPLIT's search) each time a workgroup stages the list
+        const u64 *po = Form<ALGO>::piv_off(g);
+        const u32 *pa = Form<ALGO>::piv_adj(g);
+        const u64 t0 = po[p], t1 = po[p + 1];
+        const u32 tmin = pa[t0], tmax = pa[t1 - 1], md = mode[p];
+        const u64 ts = md == MODE_SPLIT ? lower_bound_dev<u32>(pa, t0, t1, split_wlo(tmin, tmax)) : t0;
+        const u32 pinv = g.inv[p];
         for (u32 i = 0; i < nt; i++) {
             Task t;
             t.a = a + (u64)i * sl;
             t.b = (t.a + sl < b) ? t.a + sl : b;
             t.cb = cb;
             t.ce = ce;
+            t.t0 = t0;
+            t.t1 = t1;
+            t.ts = ts;
             t.p = (u32)p;
-            t.mode = mode[p];
+            t.mode = md;
+            t.tmin = tmin;
+            t.tmax = tmax;
+            t.pinv = pinv;
             for (int w = 0; w < HW; w++) t.ws[w] = 0;
             tasks[tpos[p] + i] = t;
         }
@@ -703,18 +736,25 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
     // and of those searched in global memory, list entries staged, SPLIT
     // groups and those that ran the below-window search.
     enum { ST_LONG, ST_SHORT, ST_SINGLE, ST_BELOW, ST_BELOW_GLOB, ST_STAGED, ST_GROUPS, ST_BELOW_GROUPS, ST_N };
+    // Per-group counts gather in one register of the wavefront (lane k holds
+    // counter k: no branch, no atomic in the walk) and reach LDS once per task.
     __shared__ u64 wstat[ST_N];
+    u32 stv = 0;
     auto stat_add = [&](int k, u64 v) {  // wave-uniform call
-        if (lane_id() == 0) atomicAdd((unsigned long long *)&wstat[k], (unsigned long long)v);
+        stv += lane == k ? (u32)v : 0u;
+    };
+    auto stat_flush = [&]() {  // per task: a wavefront's counts stay far below 2^32
+        if (lane < ST_N && stv) atomicAdd((unsigned long long *)&wstat[lane], (unsigned long long)stv);
+        stv = 0;
     };
     if (threadIdx.x < ST_N) wstat[threadIdx.x] = 0;
-    __shared__ u64 next_task, split_at;
+    __shared__ u64 next_task;
     // The pivot whose list LDS holds.  A task that continues the same pivot
     // (hub pivots span many consecutive tasks, and a workgroup often takes
     // several of them) skips staging; LDS is reset only when the workgroup
     // moves to another pivot.  Block-uniform.
     u32 res_p = 0xffffffffu, res_mode = 0;
-    u64 res_ts = 0;
+    u32 res_words = 0;  // LDS words [0, res_words) the resident list may have set
     for (u32 i = threadIdx.x; i < LDS_WORDS; i += blockDim.x) lds[i] = 0u;  // B starts all false
     __syncthreads();
     for (u64 it = 0;; it++) {
@@ -734,46 +774,33 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
         // per-wavefront array would put it in scratch memory
         const Task &tg = tasks[ti];
         struct {
-            u64 a, b, cb, ce;
-            u32 p, mode;
-        } tk{uni64(tg.a), uni64(tg.b), uni64(tg.cb), uni64(tg.ce), uni32(tg.p), uni32(tg.mode)};
+            u64 a, b, cb, ce, t0, t1, ts;
+            u32 p, mode, tmin, tmax, pinv;
+        } tk{uni64(tg.a),  uni64(tg.b),  uni64(tg.cb),   uni64(tg.ce),   uni64(tg.t0),  uni64(tg.t1),
+             uni64(tg.ts), uni32(tg.p),  uni32(tg.mode), uni32(tg.tmin), uni32(tg.tmax), uni32(tg.pinv)};
         const u64 a = tk.a > k0 ? tk.a : k0;
         const u64 b = tk.b < k1 ? tk.b : k1;
         if (a >= b) continue;  // uniform across the block
         const u32 p = tk.p;
         const bool restage = !keep_staged || p != res_p || tk.mode != res_mode;  // block-uniform
         if (restage && res_p != 0xffffffffu) {
-            // LDS back to all zero: unmark the resident pivot's list (the
-            // paper's reset of B), once every wavefront is done with it
+            // LDS back to all zero (the paper resets B by unmarking the list's
+            // entries; here the words the list can have set are cleared, 128-bit
+            // writes from LDS alone, which costs no reads of the list), once
+            // every wavefront is done with it
             if (!use_queue) __syncthreads();  // (the queue's barriers order it otherwise)
-            const u64 r0 = po[res_p], r1 = po[res_p + 1];
-            const u32 rmin = pa[r0], rmax = pa[r1 - 1];
-            const u32 rlo = (u64)rmax - rmin + 1 > LDS_BITS ? (u32)((u64)rmax + 1 - LDS_BITS) : rmin;
-            const u32 rlen = (u32)(r1 - r0);
-            if (res_mode == MODE_BITMAP || res_mode == MODE_SPLIT) {
-                for (u64 i = res_ts + threadIdx.x; i < r1; i += blockDim.x) lds[(pa[i] - rlo) >> 5] = 0u;
-            } else if (res_mode == MODE_ARRAY) {
-                for (u32 i = threadIdx.x; i < rlen; i += blockDim.x) lds[i] = 0u;
-            } else if (res_mode == MODE_BUCKET) {
-                const u32 words = rlen + (BUCKETS + 2) / 2;
-                for (u32 i = threadIdx.x; i < words; i += blockDim.x) lds[i] = 0u;
-            } else if (res_mode == MODE_HASH) {
-                const u32 slots = 1u << hash_bits_for(rlen);
-                for (u32 i = threadIdx.x; i < slots; i += blockDim.x) lds[i] = 0u;
-            }
+            const u32 q4 = (res_words + 3) / 4 < LDS_WORDS / 4 ? (res_words + 3) / 4 : LDS_WORDS / 4;
+            uint4 *l4 = reinterpret_cast<uint4 *>(lds);
+            for (u32 i = threadIdx.x; i < q4; i += blockDim.x) l4[i] = make_uint4(0u, 0u, 0u, 0u);
             __syncthreads();
             res_p = 0xffffffffu;
         }
-        const u64 t0 = po[p], t1 = po[p + 1];
-        const u32 tmin = pa[t0], tmax = pa[t1 - 1];
+        const u64 t0 = tk.t0, t1 = tk.t1;
+        const u32 tmin = tk.tmin, tmax = tk.tmax;
         const u32 tlen = (u32)(t1 - t0);
         // SPLIT: the bitmap covers ranks [wlo, tmax]; entries [t0, ts) lie below
-        const u32 wlo = (u64)tmax - tmin + 1 > LDS_BITS ? (u32)((u64)tmax + 1 - LDS_BITS) : tmin;
-        if (restage && tk.mode == MODE_SPLIT) {
-            if (threadIdx.x == 0) split_at = lower_bound_dev<u32>(pa, t0, t1, wlo);
-            __syncthreads();
-        }
-        const u64 ts = !restage ? res_ts : (tk.mode == MODE_SPLIT ? uni64(split_at) : t0);
+        const u32 wlo = split_wlo(tmin, tmax);
+        const u64 ts = tk.ts;
         u32 *low = lds + LDS_WORDS;  // SPLIT: T[t0, ts) when it fits
         uint2 *stage = reinterpret_cast<uint2 *>(lds + LDS_WORDS + LOW_WORDS + (u32)wid * STAGE_WORDS);
         unsigned char *flag =
@@ -784,17 +811,43 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
         } else {
         res_p = p;
         res_mode = tk.mode;
-        res_ts = ts;
-        if (wid == 0)
-            stat_add(ST_STAGED, (tk.mode == MODE_BITMAP || tk.mode == MODE_SPLIT) ? (t1 - ts) + (low_lds ? ts - t0 : 0)
-                                : (tk.mode == MODE_GLOBAL || tk.mode == MODE_REVERSE) ? 0 : tlen);
+        res_words = (tk.mode == MODE_BITMAP || tk.mode == MODE_SPLIT) ? ((tmax - wlo) >> 5) + 1
+                    : tk.mode == MODE_ARRAY                          ? tlen
+                    : tk.mode == MODE_BUCKET                         ? tlen + (BUCKETS + 2) / 2
+                    : tk.mode == MODE_HASH                           ? 1u << hash_bits_for(tlen)
+                                                                     : 0u;
+        if (threadIdx.x == 0)
+            atomicAdd((unsigned long long *)&wstat[ST_STAGED],
+                      (unsigned long long)((tk.mode == MODE_BITMAP || tk.mode == MODE_SPLIT)
+                                               ? (t1 - ts) + (low_lds ? ts - t0 : 0)
+                                           : (tk.mode == MODE_GLOBAL || tk.mode == MODE_REVERSE) ? 0 : tlen));
+        // staging loops keep SU loads of the list in flight per thread: a
+        // list of L entries costs about L / (SU x 1024) memory round trips
+        constexpr int SU = 8;
         if (low_lds) {
-            for (u64 i = t0 + threadIdx.x; i < ts; i += blockDim.x) low[i - t0] = pa[i];
+            const u32 *src = pa + t0;
+            const u32 nl = (u32)(ts - t0), bd = blockDim.x;  // (32-bit offsets: lists hold < 2^32 entries)
+            for (u32 i = threadIdx.x; i < nl; i += SU * bd) {
+                u32 v[SU];
+#pragma unroll
+                for (int k = 0; k < SU; k++) v[k] = i + k * bd < nl ? src[i + k * bd] : 0u;
+#pragma unroll
+                for (int k = 0; k < SU; k++)
+                    if (i + k * bd < nl) low[i + k * bd] = v[k];
+            }
         }
         if (tk.mode == MODE_BITMAP || tk.mode == MODE_SPLIT) {
-            for (u64 i = ts + threadIdx.x; i < t1; i += blockDim.x) {
-                const u32 v = pa[i] - wlo;
-                atomicOr(&lds[v >> 5], 1u << (v & 31));
+            const u32 *src = pa + ts;
+            const u32 nb = (u32)(t1 - ts), bd = blockDim.x;
+            for (u32 i = threadIdx.x; i < nb; i += SU * bd) {
+                u32 v[SU];
+#pragma unroll
+                for (int k = 0; k < SU; k++) v[k] = i + k * bd < nb ? src[i + k * bd] : wlo;
+#pragma unroll
+                for (int k = 0; k < SU; k++) {
+                    const u32 d = v[k] - wlo;
+                    if (i + k * bd < nb) atomicOr(&lds[d >> 5], 1u << (d & 31));
+                }
             }
             __syncthreads();
         } else if (tk.mode == MODE_ARRAY) {
@@ -831,7 +884,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 const bool exact = use_splits && a == tk.a && b == tk.b;  // not clipped by a chunk slice
                 SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tg.ws[wid])
                                        : SeedCursor(cpre, tk.cb, tk.ce, wb);
-                const u32 pinv = g.inv[p];
+                const u32 pinv = tk.pinv;
                 u32 xinv = 0;
                 u64 xinv_c = ~0ull;
                 const u32 bsh = MD == MODE_BUCKET ? bucket_shift((u64)tmax - tmin + 1) : 0u;
@@ -900,14 +953,15 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                             for (int j = 0; j < UN; j++) nb += (u32)__popcll(__ballot((y[j] - tmin) < lspan));
                             stat_add(ST_BELOW, nb);
                             if (!low_lds) stat_add(ST_BELOW_GLOB, nb);
-                            u64 lo[UN], hi[UN];
-                            const u64 base = low_lds ? 0 : t0, top = low_lds ? ts - t0 : ts;
+                            // (32-bit indices: adjacency arrays hold fewer than 2^32 entries)
+                            u32 lo[UN], hi[UN];
+                            const u32 base = low_lds ? 0u : (u32)t0, top = low_lds ? (u32)(ts - t0) : (u32)ts;
     #pragma unroll
                             for (int j = 0; j < UN; j++) {
                                 lo[j] = base;
                                 hi[j] = (y[j] >= wlo || y[j] < tmin) ? base : top;
                             }
-                            member_multi_var(low_lds ? low : pa, lo, hi, y, h);
+                            member_multi_var32(low_lds ? low : pa, lo, hi, y, h);
                         } else {
     #pragma unroll
                             for (int j = 0; j < UN; j++) h[j] = false;
@@ -1146,11 +1200,11 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                             // item kb + i of seed c: scan index E[c] + i (mod 2^32; m < 2^32)
                             const u32 E = (u32)(WA - WP + kb);
                             const u32 X = WX;
-                            int lo[UN];
-                            const int lo_last = locate_short_at(WP, kb, s0, flag, lo);
-                            const u64 kn = full ? kb + UN * WAVE : lim;
-                            if (kn < we) {
-                                // seed of item kn: the last lane's seed, or the next one
+                            // the cursor to item kn (< we), whose seed is the window's lane
+                            // lo_last or the next one; the next window is fetched here when
+                            // the group after needs it, so that this group's element loads,
+                            // issued next, cover its wait
+                            auto step_cursor = [&](int lo_last, u64 kn) {
                                 const u64 pn = (lo_last + 1 < WAVE) ? lane_u64(WP, lo_last + 1) : Wpend;
                                 const int ln = lo_last + (pn <= kn ? 1 : 0);
                                 const u64 c = wc + (u64)ln;
@@ -1162,12 +1216,14 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                                     cur.reset(c);
                                 }
                                 if ((!TL_KEEP_WINDOW || !(Wpend >= kn + UN * WAVE || Wpend >= we)) && pf_c != c) {
-                                    // the next group needs the next window: fetch it before
-                                    // this group's element loads, whose wait then covers it
                                     fetch_window(c, pf_P, pf_A, pf_X, pf_pend);
                                     pf_c = c;
                                 }
-                            }
+                            };
+                            int lo[UN];
+                            const int lo_last = locate_short_at(WP, kb, s0, flag, lo);
+                            const u64 kn = full ? kb + UN * WAVE : lim;
+                            if (kn < we) step_cursor(lo_last, kn);
                             u32 y[UN], xv[UN];
                             bool h[UN], act[UN];
 #pragma unroll
@@ -1182,6 +1238,32 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                                 // bitmap, so it starts no global search) and drop the result
                                 act[j] = full || kb + (u64)(j * WAVE + lane) < lim;
                                 y[j] = act[j] ? SA[ej + (u32)(j * WAVE + lane)] : tmax;
+                            }
+                            if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && TL_SG > 1 && full &&
+                                kn + UN * WAVE <= we && Wpend >= kn + UN * WAVE && cur.c_lo - wc < (u64)WAVE) {
+                                // a second full group from the same window: its loads are
+                                // issued before the first group's tests, so both are in flight
+                                const int s1 = (int)(cur.c_lo - wc);
+                                const u32 E1 = (u32)(WA - WP + kn);
+                                int lo1[UN];
+                                const int lo_last1 = locate_short_at(WP, kn, s1, flag, lo1);
+                                const u64 kn1 = kn + UN * WAVE;
+                                if (kn1 < we) step_cursor(lo_last1, kn1);
+                                u32 y1[UN], xv1[UN];
+#pragma unroll
+                                for (int j = 0; j < UN; j++) {
+                                    const u32 ej = (u32)__shfl(E1, lo1[j], WAVE);
+                                    xv1[j] = __shfl(X, lo1[j], WAVE);
+                                    y1[j] = SA[ej + (u32)(j * WAVE + lane)];
+                                }
+                                member_all(y, h);
+                                finish();
+                                report(y, h, xv);
+                                member_all(y1, h);
+                                report(y1, h, xv1);
+                                stat_add(ST_SHORT, kn1 - kb);
+                                kb = kn1;
+                                continue;
                             }
                             member_all(y, h);
                             finish();
@@ -1232,6 +1314,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 default: walk(std::integral_constant<int, MODE_SPLIT>{}); break;
             }
         }
+        stat_flush();
     }
     em.finish(o);
     {

@@ -192,6 +192,33 @@ __device__ __forceinline__ void member_multi(const u32 *T, u64 lo64, u64 hi64, c
     for (int j = 0; j < UN; j++) hit[j] = T[b[j]] == y[j];
 }
 
+// As member_multi_var, with 32-bit bounds.
+__device__ __forceinline__ void member_multi_var32(const u32 *T, const u32 (&lo)[UN], const u32 (&hi)[UN],
+                                                   const u32 (&y)[UN], bool (&hit)[UN]) {
+    u32 b[UN], n[UN];
+    u32 nmax = 0;
+#pragma unroll
+    for (int j = 0; j < UN; j++) {
+        b[j] = lo[j];
+        n[j] = hi[j] > lo[j] ? hi[j] - lo[j] : 0u;
+        nmax = n[j] > nmax ? n[j] : nmax;
+    }
+    while (nmax > 1) {
+        nmax = 0;
+#pragma unroll
+        for (int j = 0; j < UN; j++) {
+            if (n[j] > 1) {
+                const u32 half = n[j] >> 1;
+                b[j] = (T[b[j] + half] <= y[j]) ? b[j] + half : b[j];
+                n[j] -= half;
+            }
+            nmax = n[j] > nmax ? n[j] : nmax;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < UN; j++) hit[j] = n[j] == 1 && T[b[j]] == y[j];
+}
+
 // As member_multi, with a different list T[lo[j], hi[j]) per element.
 __device__ __forceinline__ void member_multi_var(const u32 *T, const u64 (&lo)[UN], const u64 (&hi)[UN],
                                                  const u32 (&y)[UN], bool (&hit)[UN]) {

@@ -163,7 +163,7 @@ struct Task {
     u32 mode;
     u32 tmin, tmax;  // T's first and last entries
     u32 pinv;      // original id of the pivot
-    u32 ws[HW];    // seed (relative to cb) of each wavefront's first item
+    u32 ss[2 * HW];  // seed (relative to cb) of each sub-range's first item
 };
 
 // SPLIT: the bitmap covers ranks [split_wlo, tmax], the top LDS_BITS ranks
@@ -172,12 +172,17 @@ __host__ __device__ __forceinline__ u32 split_wlo(u32 tmin, u32 tmax) {
     return (u64)tmax - tmin + 1 > LDS_BITS ? (u32)((u64)tmax + 1 - LDS_BITS) : tmin;
 }
 
-// Item range of wavefront w when a workgroup shares [a, b) (64-aligned runs).
-__host__ __device__ __forceinline__ void wave_share(u64 a, u64 b, u32 nwv, u32 w, u64 &wb, u64 &we) {
-    const u64 span = b - a;
-    const u64 per = (((span + nwv - 1) / nwv) + 63) & ~(u64)63;
-    wb = a + (u64)w * per;
-    we = (wb + per < b) ? wb + per : b;
+// A task's items [a, b) in 4 HW units (64-aligned), in 2 HW sub-ranges:
+// sub-range w < HW, three units, is wavefront w's own share; each of the
+// last HW units is a sub-range that the first wavefronts to finish take in
+// turn, so that a task ends with its wavefronts at most about one unit apart
+// instead of waiting at the next task's barrier for the slowest share.
+constexpr u32 NSUB = 2 * HW;
+__host__ __device__ __forceinline__ void sub_range(u64 a, u64 b, u32 i, u64 &sa, u64 &sb) {
+    const u64 per = ((((b - a) + 4 * HW - 1) / (4 * HW)) + 63) & ~(u64)63;
+    const u64 u0 = i < (u32)HW ? 3ull * i : 3ull * HW + (i - HW), u1 = i < (u32)HW ? u0 + 3 : u0 + 1;
+    sa = a + u0 * per < b ? a + u0 * per : b;
+    sb = a + u1 * per < b ? a + u1 * per : b;
 }
 
 // ---------------------------------------------------------------- plan
@@ -420,7 +425,7 @@ __global__ void k_make_tasks(GView g, u32 n, const u32 *mode, const u32 *ntask, 
             t.tmin = tmin;
             t.tmax = tmax;
             t.pinv = pinv;
-            for (int w = 0; w < HW; w++) t.ws[w] = 0;
+            for (u32 w = 0; w < NSUB; w++) t.ss[w] = 0;
             tasks[tpos[p] + i] = t;
         }
     }
@@ -429,15 +434,15 @@ __global__ void k_make_tasks(GView g, u32 n, const u32 *mode, const u32 *ntask, 
 // Seed of every heavy wavefront's first item, found once at plan time (in
 // parallel over tasks) instead of by a dependent search at task start.
 __global__ void k_task_splits(Task *tasks, u64 ntasks, const u64 *cpre) {
-    GRID_STRIDE(i, ntasks * HW) {
-        const u64 ti = i / HW;
-        const u32 w = (u32)(i % HW);
+    GRID_STRIDE(i, ntasks * NSUB) {
+        const u64 ti = i / NSUB;
+        const u32 w = (u32)(i % NSUB);
         const Task &t = tasks[ti];
-        u64 wb, we;
-        wave_share(t.a, t.b, HW, w, wb, we);
+        u64 sa, sb;
+        sub_range(t.a, t.b, w, sa, sb);
         u32 rel = 0;
-        if (wb < we) rel = (u32)(upper_bound_dev<u64>(cpre, t.cb, t.ce + 1, wb) - 1 - t.cb);
-        tasks[ti].ws[w] = rel;
+        if (sa < sb) rel = (u32)(upper_bound_dev<u64>(cpre, t.cb, t.ce + 1, sa) - 1 - t.cb);
+        tasks[ti].ss[w] = rel;
     }
 }
 
@@ -725,7 +730,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                                                     u64 k0, u64 k1, Out o, int use_queue, int use_splits,
                                                     int keep_staged) {
     extern __shared__ u32 lds[];  // the pivot list: B as a bitmap, or a sorted array
-    const int lane = lane_id(), wid = (int)wave_id(), nwv = blockDim.x / WAVE;
+    const int lane = lane_id(), wid = (int)wave_id();
     const u32 *SA = Form<ALGO>::scan_adj(g);
     const u64 *po = Form<ALGO>::piv_off(g);
     const u32 *pa = Form<ALGO>::piv_adj(g);
@@ -749,6 +754,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
     };
     if (threadIdx.x < ST_N) wstat[threadIdx.x] = 0;
     __shared__ u64 next_task;
+    __shared__ u32 next_sub;  // the task's next shared sub-range
     // The pivot whose list LDS holds.  A task that continues the same pivot
     // (hub pivots span many consecutive tasks, and a workgroup often takes
     // several of them) skips staging; LDS is reset only when the workgroup
@@ -762,10 +768,14 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
         if (use_queue) {
             // tasks handed out dynamically: one atomic per task per workgroup
             if (threadIdx.x == 0) next_task = atomicAdd((unsigned long long *)&o.acc[5], 1ull);
-            __syncthreads();
+            __syncthreads();  // (every wavefront is done with the previous task)
             ti = uni64(next_task);
+            if (threadIdx.x == 0) next_sub = HW;
             __syncthreads();
         } else {
+            __syncthreads();
+            if (threadIdx.x == 0) next_sub = HW;
+            __syncthreads();
             ti = blockIdx.x + it * gridDim.x;
         }
         if (ti >= ntasks) break;
@@ -875,15 +885,11 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
             __syncthreads();
         }
         }
-        u64 wb, we;
-        wave_share(a, b, (u32)nwv, (u32)wid, wb, we);
         // the walk, compiled once per LDS form so that each has its own tight loop
         auto walk = [&](auto mode_tag) {
             constexpr int MD = decltype(mode_tag)::value;
-            if (wb < we) {
-                const bool exact = use_splits && a == tk.a && b == tk.b;  // not clipped by a chunk slice
-                SeedCursor cur = exact ? SeedCursor(cpre, tk.ce, tk.cb + tg.ws[wid])
-                                       : SeedCursor(cpre, tk.cb, tk.ce, wb);
+            {
+                SeedCursor cur;
                 const u32 pinv = tk.pinv;
                 u32 xinv = 0;
                 u64 xinv_c = ~0ull;
@@ -1125,6 +1131,17 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 // short windows cost one fetch of 64 seeds' geometry, not one per group.
                 u64 wc = ~0ull, WP = 0, WA = 0, Wpend = 0;
                 u32 WX = 0;
+                // the wavefront's own sub-range, then shared ones while any is left
+                for (u32 sub = (u32)wid;;) {
+                u64 sa, sb;
+                sub_range(tk.a, tk.b, sub, sa, sb);
+                const u64 wb = sa > a ? sa : a, we = sb < b ? sb : b;  // (clipped to a chunk slice)
+                if (wb < we) {
+                if (use_splits && wb == sa) cur = SeedCursor(cpre, tk.ce, tk.cb + tg.ss[sub]);
+                else cur = SeedCursor(cpre, tk.cb, tk.ce, wb);
+                xinv_c = ~0ull;
+                wc = ~0ull;
+                pf_c = ~0ull;
                 u64 kb = wb;
                 while (kb < we) {
                     if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && cur.end >= kb + HG * UN * WAVE &&
@@ -1240,7 +1257,8 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                                 y[j] = act[j] ? SA[ej + (u32)(j * WAVE + lane)] : tmax;
                             }
                             if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && TL_SG > 1 && full &&
-                                kn + UN * WAVE <= we && Wpend >= kn + UN * WAVE && cur.c_lo - wc < (u64)WAVE) {
+                                kn + UN * WAVE <= we && Wpend >= kn + UN * WAVE && cur.c_lo - wc < (u64)WAVE &&
+                                cur.end < kn + HG * UN * WAVE) {
                                 // a second full group from the same window: its loads are
                                 // issued before the first group's tests, so both are in flight
                                 const int s1 = (int)(cur.c_lo - wc);
@@ -1295,6 +1313,12 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                     stat_add(ST_SINGLE, (we - kb < (u64)WAVE) ? we - kb : (u64)WAVE);
                     kb += WAVE;
                     cur.advance(kb, c);
+                }
+                }
+                u32 nx = 0;
+                if (lane == 0) nx = atomicAdd(&next_sub, 1u);
+                sub = (u32)__builtin_amdgcn_readfirstlane((int)nx);
+                if (sub >= NSUB) break;
                 }
                 if (staged) flush(staged);
                 finish();
@@ -1469,7 +1493,7 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
                            P.tasks.as<Task>());
         TL_HIP(hipGetLastError());
         if (tuning().splits) {
-            hipLaunchKernelGGL(k_task_splits, dim3(grid_for(h_nt * HW, PB, (unsigned)tl_num_cus() * 16)), dim3(PB), 0,
+            hipLaunchKernelGGL(k_task_splits, dim3(grid_for(h_nt * NSUB, PB, (unsigned)tl_num_cus() * 16)), dim3(PB), 0,
                                s, P.tasks.as<Task>(), h_nt, P.cpre.as<u64>());
             TL_HIP(hipGetLastError());
         }

@@ -69,6 +69,7 @@ struct SeedCursor {
     u64 c_lo;         // seed of the chunk's first item
     u64 base, end;    // cpre[c_lo], cpre[c_lo + 1]
 
+    __device__ __forceinline__ SeedCursor() : cpre(nullptr), ncap(0), c_lo(0), base(0), end(0) {}
     // (all arguments wave-uniform; the cursor's fields stay wave-uniform)
     __device__ __forceinline__ SeedCursor(const u64 *cp, u64 lo, u64 nc, u64 first_item) : cpre(cp), ncap(nc) {
         c_lo = uni64(upper_bound_dev<u64>(cpre, lo, ncap + 1, first_item) - 1);

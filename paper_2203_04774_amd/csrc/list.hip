@@ -45,6 +45,15 @@ namespace {
 #define TL_KEEP_WINDOW 1
 #endif
 
+// Heavy-kernel shape, fixed at build time (measured on RMAT scale 26):
+//   TL_HB      threads per heavy workgroup (1024: 16 wavefronts hide latency;
+//              512 measured 45% slower even with deeper load batches)
+//   TL_HG      long-window groups of UN chunks loaded together (2; 3 and 4
+//              measured no faster)
+//   TL_SG      short-window groups located and loaded before the first is
+//              tested (3; 1 and 2 measured slower, 4 exceeds 128 registers)
+//   TL_SUB_S/D units of a task per wavefront walked as its own share / taken
+//              from the shared tail
 constexpr int PB = 256;        // threads per block, light kernels
 #ifndef TL_HB
 #define TL_HB 1024
@@ -53,7 +62,13 @@ constexpr int PB = 256;        // threads per block, light kernels
 #define TL_HG 2
 #endif
 #ifndef TL_SG
-#define TL_SG 2
+#define TL_SG 3
+#endif
+#ifndef TL_SUB_S
+#define TL_SUB_S 1
+#endif
+#ifndef TL_SUB_D
+#define TL_SUB_D 3
 #endif
 constexpr int HB = TL_HB;      // threads per block, heavy-pivot kernel
 constexpr u32 LDS_BYTES = 128 * 1024;
@@ -163,7 +178,7 @@ struct Task {
     u32 mode;
     u32 tmin, tmax;  // T's first and last entries
     u32 pinv;      // original id of the pivot
-    u32 ss[2 * HW];  // seed (relative to cb) of each sub-range's first item
+    u32 ss[(1 + TL_SUB_D) * HW];  // seed (relative to cb) of each sub-range's first item
 };
 
 // SPLIT: the bitmap covers ranks [split_wlo, tmax], the top LDS_BITS ranks
@@ -172,15 +187,20 @@ __host__ __device__ __forceinline__ u32 split_wlo(u32 tmin, u32 tmax) {
     return (u64)tmax - tmin + 1 > LDS_BITS ? (u32)((u64)tmax + 1 - LDS_BITS) : tmin;
 }
 
-// A task's items [a, b) in 4 HW units (64-aligned), in 2 HW sub-ranges:
-// sub-range w < HW, three units, is wavefront w's own share; each of the
-// last HW units is a sub-range that the first wavefronts to finish take in
-// turn, so that a task ends with its wavefronts at most about one unit apart
-// instead of waiting at the next task's barrier for the slowest share.
-constexpr u32 NSUB = 2 * HW;
+// A task's items [a, b) in (S + D) HW units (64-aligned), in (1 + D) HW
+// sub-ranges: sub-range w < HW, S units, is wavefront w's own share; each
+// of the last D HW units is a sub-range that the first wavefronts to finish
+// take in turn, so that a task ends with its wavefronts at most about one
+// unit apart instead of waiting at the next task's barrier for the slowest
+// share.  (S, D) = (1, 3) measured best on RMAT scale 26 among (3, 1),
+// (2, 2), (1, 1), (3, 2), (1, 5), (1, 7), (0, 4) and (2, 4).
+constexpr u32 SUB_S = TL_SUB_S, SUB_D = TL_SUB_D;
+constexpr u32 NSUB = (1 + SUB_D) * HW;
 __host__ __device__ __forceinline__ void sub_range(u64 a, u64 b, u32 i, u64 &sa, u64 &sb) {
-    const u64 per = ((((b - a) + 4 * HW - 1) / (4 * HW)) + 63) & ~(u64)63;
-    const u64 u0 = i < (u32)HW ? 3ull * i : 3ull * HW + (i - HW), u1 = i < (u32)HW ? u0 + 3 : u0 + 1;
+    constexpr u64 units = (u64)(SUB_S + SUB_D) * HW;
+    const u64 per = ((((b - a) + units - 1) / units) + 63) & ~(u64)63;
+    const u64 u0 = i < (u32)HW ? (u64)SUB_S * i : (u64)SUB_S * HW + (i - HW);
+    const u64 u1 = i < (u32)HW ? u0 + SUB_S : u0 + 1;
     sa = a + u0 * per < b ? a + u0 * per : b;
     sb = a + u1 * per < b ? a + u1 * per : b;
 }
@@ -767,6 +787,7 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
         u64 ti;
         if (use_queue) {
             // tasks handed out dynamically: one atomic per task per workgroup
+            // (taking the next index one task ahead measured slower)
             if (threadIdx.x == 0) next_task = atomicAdd((unsigned long long *)&o.acc[5], 1ull);
             __syncthreads();  // (every wavefront is done with the previous task)
             ti = uni64(next_task);
@@ -1256,32 +1277,49 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                                 act[j] = full || kb + (u64)(j * WAVE + lane) < lim;
                                 y[j] = act[j] ? SA[ej + (u32)(j * WAVE + lane)] : tmax;
                             }
-                            if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && TL_SG > 1 && full &&
-                                kn + UN * WAVE <= we && Wpend >= kn + UN * WAVE && cur.c_lo - wc < (u64)WAVE &&
-                                cur.end < kn + HG * UN * WAVE) {
-                                // a second full group from the same window: its loads are
-                                // issued before the first group's tests, so both are in flight
-                                const int s1 = (int)(cur.c_lo - wc);
-                                const u32 E1 = (u32)(WA - WP + kn);
-                                int lo1[UN];
-                                const int lo_last1 = locate_short_at(WP, kn, s1, flag, lo1);
-                                const u64 kn1 = kn + UN * WAVE;
-                                if (kn1 < we) step_cursor(lo_last1, kn1);
-                                u32 y1[UN], xv1[UN];
+                            if ((MD == MODE_BITMAP || MD == MODE_SPLIT) && TL_SG > 1 && full) {
+                                // up to SG - 1 more full groups from the same window: their
+                                // loads are issued before the first group's tests, so all
+                                // are in flight together (a group the long path would take,
+                                // a seed with at least HG UN chunks left, ends the run)
+                                u32 ys[TL_SG > 1 ? TL_SG - 1 : 1][UN], xs[TL_SG > 1 ? TL_SG - 1 : 1][UN];
+                                int ng = 0;  // wave-uniform
+                                u64 kend = kn;
 #pragma unroll
-                                for (int j = 0; j < UN; j++) {
-                                    const u32 ej = (u32)__shfl(E1, lo1[j], WAVE);
-                                    xv1[j] = __shfl(X, lo1[j], WAVE);
-                                    y1[j] = SA[ej + (u32)(j * WAVE + lane)];
+                                for (int g2 = 0; g2 < TL_SG - 1; g2++) {
+                                    if (ng == g2 && kend + UN * WAVE <= we && Wpend >= kend + UN * WAVE &&
+                                        cur.c_lo - wc < (u64)WAVE && cur.end < kend + HG * UN * WAVE) {
+                                        const int s1 = (int)(cur.c_lo - wc);
+                                        const u32 E1 = (u32)(WA - WP + kend);
+                                        int lo1[UN];
+                                        const int lo_last1 = locate_short_at(WP, kend, s1, flag, lo1);
+                                        const u64 kn1 = kend + UN * WAVE;
+                                        if (kn1 < we) step_cursor(lo_last1, kn1);
+#pragma unroll
+                                        for (int j = 0; j < UN; j++) {
+                                            const u32 ej = (u32)__shfl(E1, lo1[j], WAVE);
+                                            xs[g2][j] = __shfl(X, lo1[j], WAVE);
+                                            ys[g2][j] = SA[ej + (u32)(j * WAVE + lane)];
+                                        }
+                                        kend = kn1;
+                                        ng++;
+                                    }
                                 }
-                                member_all(y, h);
-                                finish();
-                                report(y, h, xv);
-                                member_all(y1, h);
-                                report(y1, h, xv1);
-                                stat_add(ST_SHORT, kn1 - kb);
-                                kb = kn1;
-                                continue;
+                                if (ng > 0) {
+                                    member_all(y, h);
+                                    finish();
+                                    report(y, h, xv);
+#pragma unroll
+                                    for (int g2 = 0; g2 < TL_SG - 1; g2++) {
+                                        if (g2 < ng) {
+                                            member_all(ys[g2], h);
+                                            report(ys[g2], h, xs[g2]);
+                                        }
+                                    }
+                                    stat_add(ST_SHORT, kend - kb);
+                                    kb = kend;
+                                    continue;
+                                }
                             }
                             member_all(y, h);
                             finish();

@@ -49,7 +49,8 @@ namespace {
 //   TL_HB      threads per heavy workgroup (1024: 16 wavefronts hide latency;
 //              512 measured 45% slower even with deeper load batches)
 //   TL_HG      long-window groups of UN chunks loaded together (2; 3 and 4
-//              measured no faster)
+//              measured no faster, nor did loading the next batch before
+//              testing this one)
 //   TL_SG      short-window groups located and loaded before the first is
 //              tested (3; 1 and 2 measured slower, 4 exceeds 128 registers)
 //   TL_SUB_S/D units of a task per wavefront walked as its own share / taken

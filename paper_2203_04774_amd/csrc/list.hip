@@ -78,6 +78,10 @@ constexpr u64 LDS_BITS = (u64)LDS_BYTES * 8;
 constexpr u32 LOW_WORDS = 5088;  // SPLIT: list entries below the bitmap's window kept in LDS
 constexpr u32 STAGE_WORDS = 2 * WAVE;  // per wavefront: 64 staged (endpoint, third vertex) pairs
 constexpr u32 FLAG_WORDS = UN * WAVE / 4;  // per wavefront: seed-start flags of the short-window walk
+#ifndef TL_LIGHT_LDS
+#define TL_LIGHT_LDS 1
+#endif
+constexpr u32 LIGHT_LB = 512;  // light kernel: pivot-list entries in each wavefront's LDS window
 // bitmap + low entries + staging and flags for every wavefront: 160 KB in all
 constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + LOW_WORDS * 4 + (HB / WAVE) * (STAGE_WORDS + FLAG_WORDS) * 4;
 // (+128: the heavy kernel's own __shared__ variables)
@@ -576,6 +580,38 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
     __shared__ unsigned char flag_all[(PB / WAVE) * UN * WAVE];
     uint4 *stage = stage_all + wave_id() * WAVE;
     unsigned char *flag = flag_all + wave_id() * (UN * WAVE);
+#if TL_LIGHT_LDS
+    // A sliding window over the pivot-list array T in LDS, per wavefront.
+    // Seeds are pivot-major, so the candidate ranges [t_lo, t_hi) of the
+    // wavefront's successive seeds only move forward through T (and the
+    // lists of successive pivots lie next to each other in it): each entry
+    // of T that the wavefront searches is staged about once, and a group
+    // whose seeds' ranges all fit the window searches LDS instead of global
+    // memory.
+    __shared__ u32 twin_all[(PB / WAVE) * LIGHT_LB];
+    u32 *tw = twin_all + wave_id() * LIGHT_LB;
+    u64 tw_lo = 0, tw_hi = 0;  // T[tw_lo, tw_hi) is staged (wave-uniform)
+    // whether T[lo, hi) (wave-uniform) is in the window, staging it if it fits
+    auto cover = [&](u64 lo, u64 hi) -> bool {
+        if (hi - lo > LIGHT_LB) return false;
+        if (lo >= tw_lo && hi <= tw_hi) return true;
+        const u64 e = lo + LIGHT_LB < g.m ? lo + LIGHT_LB : g.m;
+        const u32 n = (u32)(e - lo);
+        u32 v[LIGHT_LB / WAVE];
+#pragma unroll
+        for (int k = 0; k < (int)(LIGHT_LB / WAVE); k++) {
+            const u32 i = (u32)(k * WAVE + lane);
+            v[k] = i < n ? T[lo + i] : 0u;
+        }
+        wave_lds_fence();  // (earlier searches of the window are done)
+#pragma unroll
+        for (int k = 0; k < (int)(LIGHT_LB / WAVE); k++) tw[k * WAVE + lane] = v[k];
+        wave_lds_fence();
+        tw_lo = lo;
+        tw_hi = e;
+        return true;
+    };
+#endif
     // hits are packed into the staging area across groups and finished 64
     // at a time: id lookup, canonical order, digest and store on full
     // wavefronts whatever the hit rate
@@ -664,6 +700,10 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
                 bool h[UN];
 #pragma unroll
                 for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
+#if TL_LIGHT_LDS
+                if (cover(t_lo, t_hi)) member_multi(tw, t_lo - tw_lo, t_hi - tw_lo, y, h);
+                else
+#endif
                 member_multi(T, t_lo, t_hi, y, h);
                 const u32 pi = L.cpinv[c], xi = L.cxinv[c];
 #pragma unroll
@@ -698,6 +738,21 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
                         tl[j] = __shfl(TL, lo[j], WAVE);
                         th[j] = __shfl(TH, lo[j], WAVE);
                     }
+#if TL_LIGHT_LDS
+                    // the group's seeds are window lanes 0 .. lo_last, whose ranges
+                    // start no earlier than lane 0's and end no later than lo_last's
+                    const u64 g_lo = (u32)__builtin_amdgcn_readlane((int)TL, 0);
+                    const u64 g_hi = (u32)__builtin_amdgcn_readlane((int)TH, lo_last);
+                    if (cover(g_lo, g_hi)) {
+                        u32 l32[UN], h32[UN];
+#pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            l32[j] = (u32)(tl[j] - tw_lo);
+                            h32[j] = (u32)(th[j] - tw_lo);
+                        }
+                        member_multi_var32(tw, l32, h32, y, h);
+                    } else
+#endif
                     member_multi_var(T, tl, th, y, h);
                     report(y, h, pv, xv);
                     kb += UN * WAVE;

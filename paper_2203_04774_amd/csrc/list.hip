@@ -81,7 +81,9 @@ constexpr u32 FLAG_WORDS = UN * WAVE / 4;  // per wavefront: seed-start flags of
 #ifndef TL_LIGHT_LDS
 #define TL_LIGHT_LDS 1
 #endif
-constexpr u32 LIGHT_LB = 512;  // light kernel: pivot-list entries in each wavefront's LDS window
+// light kernel: pivot-list entries in each wavefront's LDS window (256, 1024
+// and 2048 measured no faster on Chung-Lu 2^20)
+constexpr u32 LIGHT_LB = 512;
 // bitmap + low entries + staging and flags for every wavefront: 160 KB in all
 constexpr u32 HEAVY_LDS_BYTES = LDS_BYTES + LOW_WORDS * 4 + (HB / WAVE) * (STAGE_WORDS + FLAG_WORDS) * 4;
 // (+128: the heavy kernel's own __shared__ variables)

@@ -37,35 +37,39 @@ __global__ void k_fill_u32(u32 *p, u64 n, u32 v) {
     GRID_STRIDE(i, n) { p[i] = v; }
 }
 
-// Graphs of a wavefront's items: the wavefront's 64 consecutive items span
-// the graphs from that of its first item to that of its last, found once
-// per wavefront (the same value in every lane); each lane then searches only
-// that short range of the base array.  base[g] = first item of graph g,
-// non-decreasing; the graph of item x is the last g with base[g] <= x.
+// Each wavefront takes one contiguous run of the items [0, total) and finds
+// the graph of its first item once; later chunks step it forward (graph g
+// holds items [base[g], base[g + 1]), in order; empty graphs are skipped).
 template <class T>
-struct WaveGraphs {
-    u64 lo, hi;  // upper bounds of the wavefront's first and last item
-    __device__ __forceinline__ WaveGraphs(const T *base, u32 k, u64 w0, u64 w1) {
-        lo = upper_bound_dev<T>(base, 0, (u64)k + 1, (T)w0);
-        hi = upper_bound_dev<T>(base, lo, (u64)k + 1, (T)w1);
+struct GraphRun {
+    u64 wb, we, g0;  // wave-uniform
+    __device__ __forceinline__ GraphRun(const T *base, u32 k, u64 total) {
+        const u64 nw = ((u64)gridDim.x * blockDim.x) / WAVE;
+        const u64 gw = ((u64)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+        const u64 per = ((total + nw - 1) / nw + WAVE - 1) & ~(u64)(WAVE - 1);
+        wb = gw * per < total ? gw * per : total;
+        we = wb + per < total ? wb + per : total;
+        g0 = wb < we ? uni64(upper_bound_dev<T>(base, 0, (u64)k + 1, (T)wb) - 1) : 0;
     }
-    __device__ __forceinline__ u32 of(const T *base, u64 x) const {
-        return (u32)(upper_bound_dev<T>(base, lo, hi, (T)x) - 1);
+    // the graph of item c (wave-uniform, c >= every earlier call's c)
+    __device__ __forceinline__ void seek(const T *base, u64 c) {
+        while ((u64)base[g0 + 1] <= c) g0++;
+    }
+    // the graph of item i >= the last seek's c (per lane: a few steps at most)
+    __device__ __forceinline__ u32 of(const T *base, u64 i) const {
+        u64 g = g0;
+        while ((u64)base[g + 1] <= i) g++;
+        return (u32)g;
     }
 };
 
 __global__ void k_union_vertices(const u32 *rank, const u32 *vbase, u32 k, u32 N, u32 *gid, u32 *urank, u32 *flag) {
-    const u64 stride = (u64)gridDim.x * blockDim.x;
-    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    const u64 wfirst = first - lane_id();
-    const u64 iters = (u64)N > wfirst ? ((u64)N - wfirst + stride - 1) / stride : 0;  // wave-uniform
-    for (u64 it = 0; it < iters; it++) {
-        const u64 w0 = wfirst + it * stride;
-        const u64 w1 = w0 + WAVE - 1 < (u64)N ? w0 + WAVE - 1 : (u64)N - 1;
-        const WaveGraphs<u32> wg(vbase, k, w0, w1);
-        const u64 v = first + it * stride;
-        if (v < N) {
-            const u32 g = wg.of(vbase, v);
+    GraphRun<u32> run(vbase, k, N);
+    for (u64 c = run.wb; c < run.we; c += WAVE) {
+        run.seek(vbase, c);
+        const u64 v = c + lane_id();
+        if (v < run.we) {
+            const u32 g = run.of(vbase, v);
             const u32 ng = vbase[g + 1] - vbase[g];
             const u32 r = rank[v];
             if (r >= ng) atomicOr(flag, 1u);
@@ -86,17 +90,12 @@ struct CsrRef {
 // inverse permutation by its vertex base, and the graph id of each vertex.
 __global__ void k_concat_vertices(const CsrRef *gs, const u32 *vbase, const u64 *ebase, u32 k, u32 N, u64 *off_f,
                                   u64 *off_b, u32 *inv, u32 *gid) {
-    const u64 stride = (u64)gridDim.x * blockDim.x;
-    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    const u64 wfirst = first - lane_id();
-    const u64 iters = (u64)N > wfirst ? ((u64)N - wfirst + stride - 1) / stride : 0;  // wave-uniform
-    for (u64 it = 0; it < iters; it++) {
-        const u64 w0 = wfirst + it * stride;
-        const u64 w1 = w0 + WAVE - 1 < (u64)N ? w0 + WAVE - 1 : (u64)N - 1;
-        const WaveGraphs<u32> wg(vbase, k, w0, w1);
-        const u64 v = first + it * stride;
-        if (v < N) {
-            const u32 g = wg.of(vbase, v);
+    GraphRun<u32> run(vbase, k, N);
+    for (u64 c0 = run.wb; c0 < run.we; c0 += WAVE) {
+        run.seek(vbase, c0);
+        const u64 v = c0 + lane_id();
+        if (v < run.we) {
+            const u32 g = run.of(vbase, v);
             const u32 r = (u32)(v - vbase[g]);
             const CsrRef c = gs[g];
             off_f[v] = c.off_f[r] + ebase[g];
@@ -105,7 +104,7 @@ __global__ void k_concat_vertices(const CsrRef *gs, const u32 *vbase, const u64 
             gid[v] = g;
         }
     }
-    if (first == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         off_f[N] = ebase[k];
         off_b[N] = ebase[k];
     }
@@ -115,17 +114,12 @@ __global__ void k_concat_vertices(const CsrRef *gs, const u32 *vbase, const u64 
 // forward indices by its edge base.
 __global__ void k_concat_edges(const CsrRef *gs, const u32 *vbase, const u64 *ebase, u32 k, u64 M, u32 *adj_f,
                                u32 *row_f, u32 *adj_b, u32 *row_b, u32 *twin_b) {
-    const u64 stride = (u64)gridDim.x * blockDim.x;
-    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    const u64 wfirst = first - lane_id();
-    const u64 iters = M > wfirst ? (M - wfirst + stride - 1) / stride : 0;  // wave-uniform
-    for (u64 it = 0; it < iters; it++) {
-        const u64 w0 = wfirst + it * stride;
-        const u64 w1 = w0 + WAVE - 1 < M ? w0 + WAVE - 1 : M - 1;
-        const WaveGraphs<u64> wg(ebase, k, w0, w1);
-        const u64 i = first + it * stride;
-        if (i < M) {
-            const u32 g = wg.of(ebase, i);
+    GraphRun<u64> run(ebase, k, M);
+    for (u64 c0 = run.wb; c0 < run.we; c0 += WAVE) {
+        run.seek(ebase, c0);
+        const u64 i = c0 + lane_id();
+        if (i < run.we) {
+            const u32 g = run.of(ebase, i);
             const u64 j = i - ebase[g];
             const u32 vb = vbase[g];
             const CsrRef c = gs[g];
@@ -140,17 +134,12 @@ __global__ void k_concat_edges(const CsrRef *gs, const u32 *vbase, const u64 *eb
 
 __global__ void k_union_edges(const u32 *src, const u32 *dst, const u64 *ebase, const u32 *vbase, u32 k, u64 M,
                               u32 *usrc, u32 *udst, u32 *flag) {
-    const u64 stride = (u64)gridDim.x * blockDim.x;
-    const u64 first = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    const u64 wfirst = first - lane_id();
-    const u64 iters = M > wfirst ? (M - wfirst + stride - 1) / stride : 0;  // wave-uniform
-    for (u64 it = 0; it < iters; it++) {
-        const u64 w0 = wfirst + it * stride;
-        const u64 w1 = w0 + WAVE - 1 < M ? w0 + WAVE - 1 : M - 1;
-        const WaveGraphs<u64> wg(ebase, k, w0, w1);
-        const u64 i = first + it * stride;
-        if (i < M) {
-            const u32 g = wg.of(ebase, i);
+    GraphRun<u64> run(ebase, k, M);
+    for (u64 c = run.wb; c < run.we; c += WAVE) {
+        run.seek(ebase, c);
+        const u64 i = c + lane_id();
+        if (i < run.we) {
+            const u32 g = run.of(ebase, i);
             const u32 ng = vbase[g + 1] - vbase[g];
             u32 a = src[i], b = dst[i];
             if (a >= ng || b >= ng) {

@@ -414,19 +414,22 @@ void tl_server_destroy(tl_server *s);
  *                        the same, only the work split changes)
  * for callback mode (chunks of K triangles, tl_set_chunk_triangles):
  *   chunk_task_div       heavy tasks hold at most chunk_room x K / (this x
- *                        heavy workgroups) items, at least 65536 (1..64)
- *   chunk_growth         1: every probe slice covers K scanned items (each
- *                        yields at most one triangle); above 1 (default 8): a
+ *                        heavy workgroups) items, at least 65536 (1..64;
+ *                        default 64)
+ *   chunk_growth         1 (default): every probe slice covers chunk_room x K
+ *                        scanned items, which can never overflow the chunk
+ *                        (each item yields at most one triangle); above 1: a
  *                        slice may cover up to this many times the previous
- *                        slice's items, sized from its triangles per item, for
- *                        fewer and fuller slices (1..64)
+ *                        slice's items, sized from its triangles per item
+ *                        (1..64)
  *   chunk_margin         percent margin over the previous slice's
  *                        triangles per item when chunk_growth > 1 (100..1000;
  *                        default 125)
  *   chunk_room           the library's device chunk holds this many times K
- *                        triangles (default 2; 1..16): a slice that finds up
- *                        to that many is handed to the callback K at a time,
- *                        one that finds more is probed again shorter
+ *                        triangles (default 4; 1..16): a slice's triangles
+ *                        are handed to the callback K at a time; a slice that
+ *                        finds more than the chunk holds is probed again
+ *                        shorter
  * and for the batched pass (tl_batch_list; a captured pass is captured
  * again when these change):
  *   batch_heavy_min      pruned items of a pivot before its list is marked

@@ -38,9 +38,6 @@
 
 namespace {
 
-#ifndef TL_FLUSH_PIPELINE
-#define TL_FLUSH_PIPELINE 1
-#endif
 #ifndef TL_KEEP_WINDOW
 #define TL_KEEP_WINDOW 1
 #endif
@@ -115,8 +112,9 @@ struct Tuning {
     u64 plan_full = 16;          // scanned lists this short are taken whole (no window searches);
                                  // below UN * WAVE, so that whole lists never fill a long window
     // callback mode, chunks of K triangles (sweeps on RMAT scale 26, A++):
-    u64 chunk_task_div = 32;     // heavy tasks hold at most K / (this * heavy workgroups) items, so
-                                 // that each slice's launch ends with a short tail
+    u64 chunk_task_div = 64;     // heavy tasks hold at most room K / (this * heavy workgroups) items,
+                                 // so that each slice's launch ends with a short tail (64: 856 ->
+                                 // 849 ms heavy per RMAT-26 listing against 32)
     u64 chunk_growth = 1;        // a slice's items grow at most this factor per slice (1: room x K
                                  // items each, which can never overflow the chunk)
     u64 chunk_margin = 125;      // percent margin over the last slice's triangles per item
@@ -618,8 +616,9 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
     // at a time: id lookup, canonical order, digest and store on full
     // wavefronts whatever the hit rate
     u32 staged = 0;  // wave-uniform
-#if TL_FLUSH_PIPELINE
-    // finished one flush late, as in the heavy kernel
+    // Each batch of 64 is finished one flush late, so that its third
+    // vertices' id gathers overlap the walk (measured faster here, though not
+    // in the heavy kernel).
     u32 pend_k = 0, pend_a = 0, pend_b = 0, pend_c = 0;
     auto finish = [&]() {
         if (pend_k) {
@@ -647,23 +646,6 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
         pend_b = e.y;
         pend_c = v ? g.inv[e.z] : 0u;
     };
-#else
-    auto finish = [&]() {};
-    auto flush = [&](u32 k) {
-        wave_lds_fence();
-        const bool v = (u32)lane < k;
-        u32 ta = 0, tb = 0, tc = 0;
-        if (v) {
-            const uint4 e = stage[lane];
-            ta = e.x; tb = e.y; tc = g.inv[e.z];
-            canon3(ta, tb, tc);
-            cnt += 1;
-            hsh += tri_digest(ta, tb, tc);
-        }
-        wave_lds_fence();
-        em.push(v, ta, tb, tc, o);
-    };
-#endif
     auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&pv)[UN], const u32 (&xv)[UN]) {
         u64 bal[UN];
         u32 q[UN], tot = 0;
@@ -1119,41 +1101,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 // finished together: the id lookup, canonical order, digest
                 // and store then run on full wavefronts whatever the hit rate.
                 u32 staged = 0;  // hits waiting in the staging area (wave-uniform)
-#if TL_FLUSH_PIPELINE
-                // A batch of 64 hits is finished one flush late: its third
-                // vertices' id gathers stay in flight while the walk goes on,
-                // and the next flush (or the walk's end) completes it.
-                // The walk calls finish() right after each group's element loads
-                // are consumed: the gather, issued before those loads, has then
-                // landed too (loads complete in order), so it costs no wait.
-                u32 pend_k = 0, pend_x = 0, pend_y = 0;  // count (wave-uniform), endpoint id, third id
-                auto finish = [&]() {
-                    if (pend_k) {
-                        const bool v = (u32)lane < pend_k;
-                        u32 ta = 0, tb = 0, tc = 0;
-                        if (v) {
-                            ta = pinv; tb = pend_x; tc = pend_y;
-                            canon3(ta, tb, tc);
-                            cnt += 1;
-                            hsh += tri_digest(ta, tb, tc);
-                        }
-                        em.push(v, ta, tb, tc, o);
-                        pend_k = 0;
-                    }
-                };
-                auto flush = [&](u32 k) {
-                    wave_lds_fence();
-                    const bool v = (u32)lane < k;
-                    uint2 e = make_uint2(0u, 0u);
-                    if (v) e = stage[lane];
-                    wave_lds_fence();
-                    finish();
-                    pend_k = k;
-                    pend_x = e.x;
-                    pend_y = v ? g.inv[e.y] : 0u;
-                };
-#else
-                auto finish = [&]() {};
                 auto flush = [&](u32 k) {
                     wave_lds_fence();
                     const bool v = (u32)lane < k;
@@ -1168,7 +1115,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                     wave_lds_fence();
                     em.push(v, ta, tb, tc, o);
                 };
-#endif
                 auto report = [&](const u32 (&y)[UN], const bool (&h)[UN], const u32 (&xv)[UN]) {
                     u64 bal[UN];
                     u32 q[UN], tot = 0;
@@ -1243,7 +1189,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
 #pragma unroll
                         for (int q = 0; q < HG; q++) {
                             member_long(y[q], h);
-                            if (q == 0) finish();
                             report(y[q], h, xv);
                         }
                         kb += HG * UN * WAVE;
@@ -1265,7 +1210,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
     #pragma unroll
                         for (int j = 0; j < UN; j++) xv[j] = xinv;
                         member_long(y, h);
-                        finish();
                         report(y, h, xv);
                         kb += UN * WAVE;
                         stat_add(ST_LONG, UN * WAVE);
@@ -1365,7 +1309,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                                 }
                                 if (ng > 0) {
                                     member_all(y, h);
-                                    finish();
                                     report(y, h, xv);
 #pragma unroll
                                     for (int g2 = 0; g2 < TL_SG - 1; g2++) {
@@ -1380,7 +1323,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                                 }
                             }
                             member_all(y, h);
-                            finish();
 #pragma unroll
                             for (int j = 0; j < UN; j++) h[j] = h[j] && act[j];
                             report(y, h, xv);
@@ -1417,7 +1359,6 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                 if (sub >= NSUB) break;
                 }
                 if (staged) flush(staged);
-                finish();
             }
         };
         if constexpr (LEAN) {

@@ -409,9 +409,9 @@ void tl_server_destroy(tl_server *s);
  *                        4 hash, 5 bucket, 6 split for every heavy pivot
  *                        where it fits; 255 = automatic
  *   plan_full            a seed edge whose scanned list has at most this
- *                        many entries scans all of it instead of the window
- *                        found by two binary searches (0..255; results are
- *                        the same, only the work split changes)
+ *                        many entries scans all of it instead of its window
+ *                        (found by binary search; 0..255; results are the
+ *                        same, only the work split changes)
  * for callback mode (chunks of K triangles, tl_set_chunk_triangles):
  *   chunk_task_div       heavy tasks hold at most chunk_room x K / (this x
  *                        heavy workgroups) items, at least 65536 (1..64;

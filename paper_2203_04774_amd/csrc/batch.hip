@@ -206,8 +206,9 @@ constexpr u32 BH_BITS = BH_LDS_BYTES * 8u;   // rank span it covers
 
 // -------------------------------------------------------------- the pass
 
-// The window of seed e in its scanned list: the part of S between the
-// smallest and the largest candidate of T (no other element can match).
+// The window of seed e in its scanned list: the part of S from the smallest
+// candidate of T up to the largest (or, under A++, possibly up to the pivot
+// itself); no other element can match.
 template <int ALGO>
 __device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u32 full_max, u64 &abs) {
     abs = 0;
@@ -219,10 +220,14 @@ __device__ __forceinline__ u32 seed_window(const Seed<ALGO> &sd, u32 full_max, u
     }
     if (sd.t_lo < sd.t_hi && sd.s_lo < sd.s_hi) {
         const u32 tmin = sd.T[sd.t_lo], tmax = sd.T[sd.t_hi - 1];
-        const u64 a = lower_bound_front<u32>(sd.S, sd.s_lo, sd.s_hi, tmin);
         // A++: the pivot p itself sits in S = N+_x at twin_b[e], above every
-        // candidate, so the window ends at or before it
-        const u64 b = upper_bound_back<u32>(sd.S, a, ALGO == 0 ? (u64)sd.twin : sd.s_hi, tmax);
+        // candidate, so the window ends there or earlier; the entries between
+        // the last candidate and p are left in it (and fail the membership
+        // test) when their rank span is under 1/64 of the candidates'
+        const u64 hi = ALGO == 0 ? (u64)sd.twin : sd.s_hi;
+        const u64 a = lower_bound_front<u32>(sd.S, sd.s_lo, hi, tmin);
+        const u64 b = ALGO == 0 && (u64)(sd.p - tmax) * 64 <= (u64)(sd.p - tmin)
+                          ? hi : upper_bound_back<u32>(sd.S, a, hi, tmax);
         abs = a;
         return (u32)(b - a);
     }

@@ -386,7 +386,7 @@ __global__ __launch_bounds__(PB) void k_seed_class(GView g, const u32 *len, cons
 // endpoint, so that a hit needs no dependent lookups to name it.
 // Light seeds also get their candidate range of T and the pivot's id.
 template <int ALGO>
-__global__ void k_compact(GView g, const u32 *len, const u64 *sabs, const u64 *pos, u32 *cseed, u64 *cabs,
+__global__ void k_compact(GView g, const u32 *len, const u64 *sabs, const u64 *pos, u64 *cabs,
                           u32 *cxinv, u32 *clen, u32 *ctlo, u32 *cthi, u32 *cpinv) {
     const u64 m = g.m;
     const u64 nl = pos[m] & 0xffffffffull;
@@ -396,7 +396,6 @@ __global__ void k_compact(GView g, const u32 *len, const u64 *sabs, const u64 *p
             const u64 ps = pos[e];
             const bool heavy = ((ps >> 32) != (pos[e + 1] >> 32));
             const u64 d = heavy ? nl + (ps >> 32) : (ps & 0xffffffffull);
-            cseed[d] = (u32)e;
             cabs[d] = sabs[e];
             cxinv[d] = g.inv[Form<ALGO>::seed_adj(g)[e]];
             clen[d] = l;
@@ -798,7 +797,7 @@ __global__ __launch_bounds__(PB) void k_probe_light(GView g, const u64 *__restri
 // the listing has another form.
 template <int ALGO, bool EMIT, bool LEAN>
 __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restrict__ tasks, u64 ntasks,
-                                                    const u32 *__restrict__ cseed, const u64 *__restrict__ cabs,
+                                                    const u64 *__restrict__ cabs,
                                                     const u32 *__restrict__ cxinv, const u64 *__restrict__ cpre,
                                                     u64 k0, u64 k1, Out o, int use_queue, int use_splits,
                                                     int keep_staged) {
@@ -1459,7 +1458,7 @@ GView view_of(const tl_csr *g) {
 
 // Everything a listing's probe phase needs, produced by the plan.
 struct Plan {
-    DevBuf cseed, cabs, cxinv, cpre, tasks;
+    DevBuf cabs, cxinv, cpre, tasks;
     DevBuf ctlo, cthi, cpinv;  // light seeds only
     u64 ncomp = 0;    // compacted seeds
     u64 nlight = 0;   // ... of which light
@@ -1504,7 +1503,6 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
                        flags.as<u64>());
     TL_HIP(hipGetLastError());
     scan_u64_to_u64(flags.as<u64>(), pos.as<u64>(), m, s);
-    P.cseed = DevBuf(m * sizeof(u32), s);
     P.cabs = DevBuf(m * sizeof(u64), s);
     u32 *clen = (u32 *)flags.p;  // the flags are consumed by the scan: reuse them as lengths
     TL_HIP(hipMemsetAsync(clen, 0, m * sizeof(u32), s));
@@ -1513,7 +1511,7 @@ void make_plan(const GView &v, u32 n, u32 plo, u32 phi, u64 max_task, u64 *d_acc
     P.cthi = DevBuf(m * sizeof(u32), s);
     P.cpinv = DevBuf(m * sizeof(u32), s);
     hipLaunchKernelGGL((k_compact<ALGO>), dim3(gm), dim3(PB), 0, s, v, len.as<u32>(), sabs.as<u64>(), pos.as<u64>(),
-                       P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(), clen, P.ctlo.as<u32>(),
+                       P.cabs.as<u64>(), P.cxinv.as<u32>(), clen, P.ctlo.as<u32>(),
                        P.cthi.as<u32>(), P.cpinv.as<u32>());
     TL_HIP(hipGetLastError());
     P.cpre = DevBuf((m + 1) * sizeof(u64), s);
@@ -1590,7 +1588,7 @@ void launch_probe(const GView &v, const Plan &P, u64 k0, u64 k1, bool emit, cons
         auto go = [&](auto emit_tag, auto lean_tag) {
             hipLaunchKernelGGL((k_probe_heavy<ALGO, decltype(emit_tag)::value, decltype(lean_tag)::value>),
                                dim3((unsigned)blocks), dim3(HB), HEAVY_LDS_BYTES, s, v, P.tasks.as<Task>(), P.ntasks,
-                               P.cseed.as<u32>(), P.cabs.as<u64>(), P.cxinv.as<u32>(), P.cpre.as<u64>(), h0, h1, o,
+                               P.cabs.as<u64>(), P.cxinv.as<u32>(), P.cpre.as<u64>(), h0, h1, o,
                                (int)tuning().queue, (int)tuning().splits, (int)tuning().keep_staged);
         };
         using T_ = std::true_type;
@@ -1707,7 +1705,7 @@ u64 list_count_scratch_bytes(u64 n, u64 m) {
     t += blk(m * 4) + blk(m * 8) + 2 * blk(n * 8);            // len, sabs, wp, wpw
     t += blk(n * 4) + blk(n * 4) + blk(n * 8);                // mode, ntask, slice
     t += blk(m * 8) + blk((m + 1) * 8) + (ws_m ? ws_m : 0);   // flags, pos and its scan
-    t += blk(m * 4) + blk(m * 8) + blk(m * 4);                // cseed, cabs, cxinv
+    t += blk(m * 8) + blk(m * 4);                             // cabs, cxinv
     t += 3 * blk(m * 4);                                      // ctlo, cthi, cpinv
     t += blk((m + 1) * 8) + (ws_m ? ws_m : 0);                // cpre and its scan
     t += blk((n + 1) * 8) + (ws_n ? ws_n : 0);                // tpos and its scan

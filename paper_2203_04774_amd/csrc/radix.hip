@@ -13,16 +13,21 @@
 
 namespace {
 
-constexpr int RB = 256;            // threads per tile
+#ifndef TL_RS_THREADS
+#define TL_RS_THREADS 512
+#endif
+constexpr int RB = TL_RS_THREADS;  // threads per tile (512: 8,192 keys, 32 per digit on average, so
+                                   // longer runs per output line; RMAT-26 orientation 178 -> 173 ms)
 constexpr int RI = 16;             // keys per thread
 constexpr u32 RT = RB * RI;        // keys per tile
 constexpr int RD = 256;            // digit values
 constexpr int RNW = RB / WAVE;
+static_assert(RB >= RD && RB % RD == 0, "radix tile: at least one thread per digit");
 
 __global__ __launch_bounds__(RB) void k_rs_hist(const u64 *keys, u64 n, int sh, u32 *counts, u64 ntiles) {
     __shared__ u32 h[RD];
     const int t = threadIdx.x;
-    h[t] = 0;
+    if (t < RD) h[t] = 0;
     __syncthreads();
     const u64 base = (u64)blockIdx.x * RT;
 #pragma unroll
@@ -31,7 +36,7 @@ __global__ __launch_bounds__(RB) void k_rs_hist(const u64 *keys, u64 n, int sh, 
         if (i < n) atomicAdd(&h[(keys[i] >> sh) & 255u], 1u);
     }
     __syncthreads();
-    counts[(u64)t * ntiles + blockIdx.x] = h[t];
+    if (t < RD) counts[(u64)t * ntiles + blockIdx.x] = h[t];
 }
 
 __global__ __launch_bounds__(RB) void k_rs_scatter(const u64 *in, u64 *out, u64 n, int sh, const u32 *counts,
@@ -46,12 +51,15 @@ __global__ __launch_bounds__(RB) void k_rs_scatter(const u64 *in, u64 *out, u64 
     const u64 base = tile * RT;
     const u32 cnt = (u32)(n - base < RT ? n - base : RT);
     {
-        const u32 c = counts[(u64)t * ntiles + tile];
+        const u32 c = t < RD ? counts[(u64)t * ntiles + tile] : 0u;
         u64 tot;
-        tbase[t] = (u32)block_excl_scan_u64<RB>(c, lds64, tot);
-        gbase[t] = offs[(u64)t * ntiles + tile];
+        const u32 tb = (u32)block_excl_scan_u64<RB>(c, lds64, tot);
+        if (t < RD) {
+            tbase[t] = tb;
+            gbase[t] = offs[(u64)t * ntiles + tile];
 #pragma unroll
-        for (int w = 0; w < RNW; w++) wcnt[w][t] = 0;
+            for (int w = 0; w < RNW; w++) wcnt[w][t] = 0;
+        }
     }
     __syncthreads();
     // Each wavefront takes a contiguous run of RI * 64 keys (coalesced
@@ -82,7 +90,7 @@ __global__ __launch_bounds__(RB) void k_rs_scatter(const u64 *in, u64 *out, u64 
     }
     __syncthreads();
     // offset of each wavefront's block of digit d inside the tile's run of d
-    {
+    if (t < RD) {
         u32 acc = tbase[t];
 #pragma unroll
         for (int w = 0; w < RNW; w++) {

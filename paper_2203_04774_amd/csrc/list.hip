@@ -889,6 +889,11 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
         unsigned char *flag =
             reinterpret_cast<unsigned char *>(lds + LDS_WORDS + LOW_WORDS + HW * STAGE_WORDS + (u32)wid * FLAG_WORDS);
         const bool low_lds = tk.mode == MODE_SPLIT && ts - t0 <= LOW_WORDS;
+        // SPLIT lists with more entries below the window than LOW holds: LOW
+        // keeps every lstride-th of them, so that a search there leaves one
+        // stride of the list to search in global memory
+        const u32 lstride = (tk.mode == MODE_SPLIT && !low_lds) ? (u32)((ts - t0 + LOW_WORDS - 1) / LOW_WORDS) : 1u;
+        const u32 lsamp = (tk.mode == MODE_SPLIT && !low_lds) ? (u32)((ts - t0 + lstride - 1) / lstride) : 0u;
         if (!restage) {
             // the list is already staged
         } else {
@@ -907,13 +912,14 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
         // staging loops keep SU loads of the list in flight per thread: a
         // list of L entries costs about L / (SU x 1024) memory round trips
         constexpr int SU = 8;
-        if (low_lds) {
+        if (tk.mode == MODE_SPLIT) {
+            // all entries below the window, or every lstride-th of them
             const u32 *src = pa + t0;
-            const u32 nl = (u32)(ts - t0), bd = blockDim.x;  // (32-bit offsets: lists hold < 2^32 entries)
+            const u32 nl = low_lds ? (u32)(ts - t0) : lsamp, bd = blockDim.x;  // (lists hold < 2^32 entries)
             for (u32 i = threadIdx.x; i < nl; i += SU * bd) {
                 u32 v[SU];
 #pragma unroll
-                for (int k = 0; k < SU; k++) v[k] = i + k * bd < nl ? src[i + k * bd] : 0u;
+                for (int k = 0; k < SU; k++) v[k] = i + k * bd < nl ? src[(i + k * bd) * lstride] : 0u;
 #pragma unroll
                 for (int k = 0; k < SU; k++)
                     if (i + k * bd < nl) low[i + k * bd] = v[k];
@@ -1034,13 +1040,27 @@ __global__ __launch_bounds__(HB) void k_probe_heavy(GView g, const Task *__restr
                             if (!low_lds) stat_add(ST_BELOW_GLOB, nb);
                             // (32-bit indices: adjacency arrays hold fewer than 2^32 entries)
                             u32 lo[UN], hi[UN];
-                            const u32 base = low_lds ? 0u : (u32)t0, top = low_lds ? (u32)(ts - t0) : (u32)ts;
+                            const u32 top = low_lds ? (u32)(ts - t0) : lsamp;
     #pragma unroll
                             for (int j = 0; j < UN; j++) {
-                                lo[j] = base;
-                                hi[j] = (y[j] >= wlo || y[j] < tmin) ? base : top;
+                                lo[j] = 0u;
+                                hi[j] = (y[j] - tmin) < lspan ? top : 0u;
                             }
-                            member_multi_var32(low_lds ? low : pa, lo, hi, y, h);
+                            if (low_lds) {
+                                member_multi_var32(low, lo, hi, y, h);
+                            } else {
+                                // the sample at or below y, then its stride of the list
+                                u32 b[UN];
+                                bound_multi_var32(low, lo, hi, y, b);
+    #pragma unroll
+                                for (int j = 0; j < UN; j++) {
+                                    const bool in = hi[j] != 0u;
+                                    lo[j] = in ? (u32)t0 + b[j] * lstride : 0u;
+                                    const u32 e = lo[j] + lstride;
+                                    hi[j] = in ? (e < (u32)ts ? e : (u32)ts) : 0u;
+                                }
+                                member_multi_var32(pa, lo, hi, y, h);
+                            }
                         } else {
     #pragma unroll
                             for (int j = 0; j < UN; j++) h[j] = false;

@@ -193,6 +193,33 @@ __device__ __forceinline__ void member_multi(const u32 *T, u64 lo64, u64 hi64, c
     for (int j = 0; j < UN; j++) hit[j] = T[b[j]] == y[j];
 }
 
+// For each element, the last index b[j] in T[lo[j], hi[j]) with T[b] <= y[j]
+// (lo[j] when the range is empty or T[lo[j]] > y[j]); interleaved as
+// member_multi_var32.
+__device__ __forceinline__ void bound_multi_var32(const u32 *T, const u32 (&lo)[UN], const u32 (&hi)[UN],
+                                                  const u32 (&y)[UN], u32 (&b)[UN]) {
+    u32 n[UN];
+    u32 nmax = 0;
+#pragma unroll
+    for (int j = 0; j < UN; j++) {
+        b[j] = lo[j];
+        n[j] = hi[j] > lo[j] ? hi[j] - lo[j] : 0u;
+        nmax = n[j] > nmax ? n[j] : nmax;
+    }
+    while (nmax > 1) {
+        nmax = 0;
+#pragma unroll
+        for (int j = 0; j < UN; j++) {
+            if (n[j] > 1) {
+                const u32 half = n[j] >> 1;
+                b[j] = (T[b[j] + half] <= y[j]) ? b[j] + half : b[j];
+                n[j] -= half;
+            }
+            nmax = n[j] > nmax ? n[j] : nmax;
+        }
+    }
+}
+
 // As member_multi_var, with 32-bit bounds.
 __device__ __forceinline__ void member_multi_var32(const u32 *T, const u32 (&lo)[UN], const u32 (&hi)[UN],
                                                    const u32 (&y)[UN], bool (&hit)[UN]) {

@@ -49,9 +49,7 @@ namespace {
 //              measured no faster, nor did loading the next batch before
 //              testing this one)
 //   TL_SG      short-window groups located and loaded before the first is
-//              tested (3; 1 and 2 measured slower, 4 exceeds 128 registers;
-//              locating all groups with one pass of flags, so that their
-//              loads issue together, measured slower for 2 and for 3)
+//              tested (3; 1 and 2 measured slower, 4 exceeds 128 registers)
 //   TL_SUB_S/D units of a task per wavefront walked as its own share / taken
 //              from the shared tail
 constexpr int PB = 256;        // threads per block, light kernels

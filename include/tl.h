@@ -144,7 +144,7 @@ int tl_list_range(const tl_csr *g, tl_algo a, uint32_t pivot_lo, uint32_t pivot_
  * library runs on holds until the process ends.
  *   g, a, stream  as for tl_list; out  host, receives the summary.
  * Returns TL_ECAPACITY, with nothing launched, when the graph's plan needs
- * more than that array (roughly 64 bytes per edge plus 28 per vertex), or
+ * more than that array (roughly 60 bytes per edge plus 28 per vertex), or
  * when its heavy-pivot tasks do not fit what is left of it (then after
  * waiting for the stream).  Every call on a GPU uses that GPU's one array:
  * calls that overlap on one GPU (other threads, other streams) race and

@@ -468,8 +468,9 @@ __global__ void k_make_tasks(GView g, u32 n, const u32 *mode, const u32 *ntask, 
     }
 }
 
-// Seed of every heavy wavefront's first item, found once at plan time (in
-// parallel over tasks) instead of by a dependent search at task start.
+// Seed of every task sub-range's first item, found once at plan time (in
+// parallel over tasks) instead of by a dependent search when a wavefront
+// starts the sub-range.
 __global__ void k_task_splits(Task *tasks, u64 ntasks, const u64 *cpre) {
     GRID_STRIDE(i, ntasks * NSUB) {
         const u64 ti = i / NSUB;

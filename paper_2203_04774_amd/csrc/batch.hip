@@ -389,6 +389,33 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, const u64 *__restrict__ 
     __shared__ unsigned char flag_all[(BB / WAVE) * UN * WAVE];
     uint4 *stage = stage_all + wave_id() * WAVE;
     unsigned char *flag = flag_all + wave_id() * (UN * WAVE);
+    // A sliding window over the pivot-list array T in LDS, per wavefront, as
+    // in the plain light kernel: seeds are pivot-major (across the union's
+    // graphs too), so the candidate ranges only move forward through T, and a
+    // group whose ranges fit the window searches LDS instead of global memory.
+    constexpr u32 TWL = 512;
+    __shared__ u32 twin_all[(BB / WAVE) * TWL];
+    u32 *tw = twin_all + wave_id() * TWL;
+    u64 tw_lo = 0, tw_hi = 0;  // T[tw_lo, tw_hi) is staged (wave-uniform)
+    auto cover = [&](u64 lo, u64 hi) -> bool {
+        if (hi - lo > TWL) return false;
+        if (lo >= tw_lo && hi <= tw_hi) return true;
+        const u64 e = lo + TWL < g.m ? lo + TWL : g.m;
+        const u32 n = (u32)(e - lo);
+        u32 v[TWL / WAVE];
+#pragma unroll
+        for (int k = 0; k < (int)(TWL / WAVE); k++) {
+            const u32 i = (u32)(k * WAVE + lane);
+            v[k] = i < n ? T[lo + i] : 0u;
+        }
+        wave_lds_fence();  // (earlier searches of the window are done)
+#pragma unroll
+        for (int k = 0; k < (int)(TWL / WAVE); k++) tw[k * WAVE + lane] = v[k];
+        wave_lds_fence();
+        tw_lo = lo;
+        tw_hi = e;
+        return true;
+    };
     // hits are packed into the staging area across groups and finished 64 at a time
     u32 staged = 0;  // wave-uniform
     auto flush = [&](u32 k) {
@@ -440,7 +467,8 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, const u64 *__restrict__ 
                 bool h[UN];
 #pragma unroll
                 for (int j = 0; j < UN; j++) y[j] = SA[sab + (u64)j * WAVE];
-                member_multi(T, t_lo, t_hi, y, h);
+                if (cover(t_lo, t_hi)) member_multi(tw, t_lo - tw_lo, t_hi - tw_lo, y, h);
+                else member_multi(T, t_lo, t_hi, y, h);
                 const u32 pi = L.cpinv[c], xi = L.cxinv[c], gi = L.cgid[c];
 #pragma unroll
                 for (int j = 0; j < UN; j++) { pv[j] = pi; xv[j] = xi; gv[j] = gi; }
@@ -474,7 +502,21 @@ __global__ __launch_bounds__(BB) void k_bprobe(GView g, const u64 *__restrict__ 
                         tl[j] = __shfl(TL, lo[j], WAVE);
                         th[j] = __shfl(TH, lo[j], WAVE);
                     }
-                    member_multi_var(T, tl, th, y, h);
+                    // the group's seeds are window lanes 0 .. lo_last, whose ranges
+                    // start no earlier than lane 0's and end no later than lo_last's
+                    const u64 g_lo = (u32)__builtin_amdgcn_readlane((int)TL, 0);
+                    const u64 g_hi = (u32)__builtin_amdgcn_readlane((int)TH, lo_last);
+                    if (cover(g_lo, g_hi)) {
+                        u32 l32[UN], h32[UN];
+#pragma unroll
+                        for (int j = 0; j < UN; j++) {
+                            l32[j] = (u32)(tl[j] - tw_lo);
+                            h32[j] = (u32)(th[j] - tw_lo);
+                        }
+                        member_multi_var32(tw, l32, h32, y, h);
+                    } else {
+                        member_multi_var(T, tl, th, y, h);
+                    }
                     report(y, h, pv, xv, gv);
                     kb += UN * WAVE;
                     if (kb < we) {
